@@ -1,0 +1,72 @@
+"""Differentiable FP64 transcriptions of the oracle for gradient checks.
+
+TEST INFRASTRUCTURE ONLY (same rule as the rest of ``oracle/``).
+
+The paper does not differentiate its filter.  These plain PyTorch (CPU,
+float64) transcriptions of eqs. (1)-(2) and of Algorithm 1 with fixed
+centers let autograd provide reference gradients with respect to the image
+f, the guide p, sigma_r and sigma_s.  Centers are constants (stop-gradient).
+"""
+from __future__ import annotations
+
+import torch
+import torch.nn.functional as F
+
+
+def _omega2(S, sigma_s, spatial):
+    j = torch.arange(-S, S + 1, dtype=torch.float64)
+    if spatial == "box":
+        return torch.ones(2 * S + 1, 2 * S + 1, dtype=torch.float64)
+    return torch.exp(-(j[:, None] ** 2 + j[None, :] ** 2) / (2.0 * sigma_s ** 2))
+
+
+def fast_filter_torch(f, p, centers, sigma_s, sigma_r, S, spatial="gaussian",
+                      full_rank=True):
+    """Algorithm 1 with given centers: b = phi(mu - p), c = A^+ b, the
+    convolutions of eqs. (13)-(14), the ratio of eqs. (15)-(16).
+
+    f: (n,H,W), p: (rho,H,W), centers: (K,rho), sigma_r / sigma_s: scalars or
+    0-d tensors (may require grad).  A^+ = A^-1 when ``full_rank``.
+    Returns (g, r_hat)."""
+    n, H, W = f.shape
+    rho = p.shape[0]
+    mu = torch.as_tensor(centers, dtype=torch.float64)
+    K = mu.shape[0]
+    X = p.reshape(rho, -1).T
+    d2 = ((X[:, None, :] - mu[None, :, :]) ** 2).sum(-1)
+    B = torch.exp(-d2 / (2.0 * sigma_r ** 2))
+    dm = ((mu[:, None, :] - mu[None, :, :]) ** 2).sum(-1)
+    A = torch.exp(-dm / (2.0 * sigma_r ** 2))
+    P = torch.linalg.inv(A) if full_rank else torch.linalg.pinv(A, hermitian=True)
+    C = B @ P.T
+    Fl = f.reshape(n, -1)
+    U = torch.cat([B.T[:, None, :] * Fl[None, :, :], B.T[:, None, :]], dim=1)
+    w = _omega2(S, sigma_s, spatial)
+    V = F.conv2d(U.reshape(K * (n + 1), 1, H, W), w[None, None], padding=S)
+    V = V.reshape(K, n + 1, H * W)
+    v = (C.T[:, None, :] * V).sum(0)
+    return (v[:n] / v[n]).reshape(n, H, W), v[n].reshape(H, W)
+
+
+def bruteforce_torch(f, p, sigma_s, sigma_r, S, spatial="gaussian"):
+    """Eqs. (1)-(2) with out-of-domain samples excluded.  Returns (g, eta)."""
+    n, H, W = f.shape
+    fp = F.pad(f[None], (S, S, S, S))[0]
+    pp = F.pad(p[None], (S, S, S, S))[0]
+    inside = F.pad(torch.ones(1, 1, H, W, dtype=torch.float64), (S, S, S, S))[0, 0]
+    num = torch.zeros_like(f)
+    eta = torch.zeros(H, W, dtype=torch.float64)
+    for jy in range(-S, S + 1):
+        for jx in range(-S, S + 1):
+            # the sample q = i - j, read from the zero-padded copies
+            ys, xs = slice(S - jy, S - jy + H), slice(S - jx, S - jx + W)
+            if spatial == "box":
+                w = 1.0
+            else:
+                w = torch.exp(torch.as_tensor(-(jy * jy + jx * jx), dtype=torch.float64)
+                              / (2.0 * sigma_s ** 2))
+            ph = torch.exp(-((pp[:, ys, xs] - p) ** 2).sum(0) / (2.0 * sigma_r ** 2))
+            wt = w * ph * inside[ys, xs]
+            num = num + wt * fp[:, ys, xs]
+            eta = eta + wt
+    return num / eta, eta
