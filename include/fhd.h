@@ -1,0 +1,205 @@
+/*
+ * fhd.h - C ABI of the MI355X (gfx950) fast high-dimensional bilateral and
+ * nonlocal-means filter of Nair & Chaudhury, "Fast High-Dimensional Bilateral
+ * and Nonlocal Means Filtering" (IEEE TIP).
+ *
+ * The filter (Sec. I-A, eqs. (1)-(2)) smooths an image f : Omega -> R^n under
+ * the control of a guide p : Omega -> R^rho:
+ *     g(i) = sum_{j in W} w(j) phi(p(i-j) - p(i)) f(i-j) / eta(i),
+ *     eta(i) = sum_{j in W} w(j) phi(p(i-j) - p(i)),   W = [-S, S]^2,
+ * with a Gaussian range kernel phi(x) = exp(-|x|^2 / 2 sigma_r^2) and a
+ * Gaussian (bilateral) or box (nonlocal means) spatial kernel w (Sec. IV).
+ * The library computes the approximation of Algorithm 1 (Sec. II-B): cluster
+ * the guide vectors into K centers (bisecting K-means, Sec. II-C), solve the
+ * K x K least-squares system of eqs. (11)-(12) once, form the per-pixel
+ * weights and coefficients, run the (n+1)K spatial convolutions of
+ * eqs. (13)-(14) and recombine per pixel, eqs. (15)-(16).
+ *
+ * Conventions for every call:
+ *  - Images are planar (C, H, W), row-major, FP32, in DEVICE memory of the
+ *    context's GPU ("device" below).  "host" marks host memory.
+ *  - Window samples outside the image are excluded from both sums (the
+ *    convolved images are zero-extended).  Kernels are unnormalised (peak 1).
+ *    S is the half-width of the window (W = [-S, S]^2).
+ *  - All device work is enqueued on the context's stream.  Calls that return
+ *    host results (info, centers, gradients of scalars) synchronise that
+ *    stream before returning; the others return with work in flight.
+ *  - The caller owns every buffer it passes in.  The library never frees
+ *    them.  It keeps its own device workspace inside the context (grown on
+ *    demand, freed by fhd_destroy) unless the caller supplies one with
+ *    fhd_set_workspace, in which case it allocates no device memory at all.
+ *  - Errors are reported through the return value only; nothing is thrown
+ *    and nothing aborts across this boundary.  fhd_last_error() gives a
+ *    message.  Output contents are unspecified when a call fails.
+ *  - Outputs must not alias inputs (FHD_EINVAL where detected); `guide` may
+ *    alias `f` (the self-guided bilateral filter).
+ */
+#ifndef FHD_H
+#define FHD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fhd_ctx fhd_ctx;
+
+typedef enum {
+    FHD_OK = 0,
+    FHD_EINVAL = -1,        /* bad argument (sizes, sigmas, NULL, aliasing) */
+    FHD_ENOMEM = -2,        /* device/host allocation failed or caller workspace too small */
+    FHD_EHIP = -3,          /* a HIP runtime error */
+    FHD_ENUMERIC = -4,      /* strict mode: a non-positive normaliser or non-finite output */
+    FHD_EUNSUPPORTED = -5   /* valid but outside what this build implements */
+} fhd_status;
+
+enum { FHD_SPATIAL_GAUSSIAN = 0, FHD_SPATIAL_BOX = 1 };
+/* Precision of the point-to-center distance contraction (weights step only;
+ * convolutions and normalisation stay FP32). */
+enum { FHD_CONTRACT_FP32 = 0, FHD_CONTRACT_BF16 = 1, FHD_CONTRACT_FP16 = 2 };
+/* Coefficients: least squares c = A^+ b (eqs. (11)-(12)) or the hard
+ * cluster indicator of eq. (17), which gives eq. (18). */
+enum { FHD_COEF_LSQ = 0, FHD_COEF_HARD = 1 };
+
+/* Limits of this build. */
+#define FHD_MAX_K 128        /* clusters */
+#define FHD_MAX_RHO 64       /* guide dimensions */
+#define FHD_MAX_N 64         /* image channels */
+#define FHD_MAX_RADIUS 128   /* window half-width S */
+
+typedef struct {
+    float sigma_s;        /* Gaussian spatial std (pixels), > 0; ignored for box */
+    int radius;           /* S; < 0 means ceil(3 sigma_s) (Sec. IV); required (>= 0) for box */
+    float sigma_r;        /* range std, > 0; +INFINITY allowed (phi == 1) */
+    int K;                /* requested clusters, 1..FHD_MAX_K; fewer are used when the
+                             guide has fewer distinct vectors (reported as K_eff) */
+    int spatial;          /* FHD_SPATIAL_* */
+    int contract;         /* FHD_CONTRACT_* */
+    int coef;             /* FHD_COEF_* */
+    int kmeans_max_iter;  /* 2-means assignment steps per split (default 20) */
+    double pinv_rtol;     /* <= 0: singular values above K * s_max * 2^-52 are kept
+                             (the MATLAB pinv default); else rtol * s_max */
+    int strict;           /* nonzero: FHD_ENUMERIC if a normaliser is <= 0 or an output
+                             is not finite (needs a synchronising check) */
+} fhd_params;
+
+/* Diagnostics of one call (host struct, filled when non-NULL). */
+typedef struct {
+    int K_eff;              /* clusters actually used */
+    int pinv_rank;          /* rank kept by the pseudo-inverse */
+    int kmeans_rounds;      /* batched split rounds run on the GPU */
+    int kmeans_splits;      /* 2-means splits computed (committed or not) */
+    double E_K;             /* clustering error, eq. (20) */
+    double cond_A;          /* s_max / s_min over the kept singular values of A */
+    double pinv_norm;       /* largest |entry| of A^+ */
+    float ms_cluster;       /* wall time of the clustering (host clock) */
+    float ms_solve;         /* wall time of the K x K solve */
+    float ms_filter;        /* wall time from the solve to the end of the filter passes
+                               (only when the call synchronises) */
+} fhd_info;
+
+/* Fill `p` with defaults: sigma_s 3, radius -1, sigma_r 0.1, K 16, Gaussian,
+ * FP32 contraction, least-squares coefficients, 20 iterations, MATLAB pinv
+ * tolerance, not strict. */
+void fhd_default_params(fhd_params* p);
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t
+ * to enqueue on (NULL: the null stream).  The stream stays the caller's. */
+fhd_status fhd_create(fhd_ctx** ctx, int device, void* hip_stream);
+fhd_status fhd_destroy(fhd_ctx* ctx);
+fhd_status fhd_set_stream(fhd_ctx* ctx, void* hip_stream);
+/* Message of the last failure on this context ("" if none).  Valid until the
+ * next call on the context. */
+const char* fhd_last_error(const fhd_ctx* ctx);
+
+/* Device workspace (bytes) that fhd_filter needs for one image of this
+ * shape with these parameters (an upper bound for the other calls). */
+fhd_status fhd_workspace_size(const fhd_params* p, int n, int rho, int H, int W,
+                              size_t* bytes);
+/* Hand the library a caller-owned device buffer of `bytes` bytes (aligned to
+ * 256 B) to use as workspace instead of its own; NULL reverts to the
+ * library's own.  Calls whose need exceeds it fail with FHD_ENOMEM. */
+fhd_status fhd_set_workspace(fhd_ctx* ctx, void* dev, size_t bytes);
+
+/* Step 1 of Algorithm 1: bisecting K-means of the range space eq. (8)
+ * (Sec. II-C), on the GPU with FP64 centroid and distance arithmetic.
+ * The leaf with the largest SSE (sum of squared distances to its centroid;
+ * ties: lower heap id, root 1, children 2h and 2h+1) is split by 2-means
+ * seeded with a = the member farthest from the centroid and b = the member
+ * farthest from a (ties: lowest pixel index); x joins a's child iff
+ * |x - c_a|^2 <= |x - c_b|^2; at most `max_iter` assignment steps, stopping
+ * when no label changes.  Splitting stops at K leaves or when no leaf has two
+ * distinct members.
+ *   guide   device, rho x H x W.
+ *   centers host, K x rho FP32, row-major: the K_eff leaf centroids in heap-id
+ *           order (rows K_eff..K-1 untouched).
+ *   labels  device, H x W int32 cluster index per pixel, or NULL.
+ *   K_eff   host, number of clusters produced.
+ * Synchronises. */
+fhd_status fhd_cluster(fhd_ctx* ctx, const float* guide, int rho, int H, int W, int K,
+                       int max_iter, float* centers, int* labels, int* K_eff,
+                       fhd_info* info);
+
+/* Step 2 of Algorithm 1 on its own: A_kl = phi(mu_k - mu_l) (eq. (12)) and its
+ * pseudo-inverse in FP64 (symmetric eigen-decomposition, singular values
+ * |lambda| above the tolerance of fhd_params.pinv_rtol kept).
+ *   centers host K x rho FP32;  Apinv host K x K FP64 (row-major), or NULL;
+ *   A host K x K FP64 or NULL;  rank host or NULL. */
+fhd_status fhd_pinv(const float* centers, int K, int rho, double sigma_r, double rtol,
+                    double* A, double* Apinv, int* rank, double* cond);
+
+/* Steps 2-5 of Algorithm 1 with given centers: the K x K solve, the weights
+ * b_k(i) = phi(mu_k - p(i)) and coefficients c(i) = A^+ b(i), the
+ * convolutions of eqs. (13)-(14) and the recombination of eqs. (15)-(16).
+ *   f       device n x H x W;  guide device rho x H x W (may equal f).
+ *   centers host K x rho FP32.
+ *   out     device n x H x W: g_hat = v / r_hat.
+ *   den     device H x W: the normaliser r_hat of eq. (16), or NULL.
+ *   labels  device H x W cluster index per pixel; required for FHD_COEF_HARD,
+ *           else ignored (may be NULL).
+ * Returns with the filter in flight unless `info` or strict mode asks for
+ * host results. */
+fhd_status fhd_filter_centers(fhd_ctx* ctx, const float* f, int n, const float* guide,
+                              int rho, int H, int W, const float* centers, int K,
+                              const int* labels, const fhd_params* p, float* out,
+                              float* den, fhd_info* info);
+
+/* The whole of Algorithm 1: fhd_cluster then fhd_filter_centers.
+ *   centers_out host K x rho FP32 (the K_eff centers used), or NULL.
+ *   den         device H x W normaliser, or NULL.
+ * Synchronises once per clustering round (the greedy split selection runs on
+ * the host); returns with the filter passes in flight unless `info` or strict
+ * mode asks for host results. */
+fhd_status fhd_filter(fhd_ctx* ctx, const float* f, int n, const float* guide, int rho,
+                      int H, int W, const fhd_params* p, float* out, float* centers_out,
+                      float* den, fhd_info* info);
+
+/* The brute-force filter of eqs. (1)-(2) on the GPU (FP32), the reference
+ * the approximation is measured against.  out device n x H x W; den device
+ * H x W (eta) or NULL. */
+fhd_status fhd_bruteforce(fhd_ctx* ctx, const float* f, int n, const float* guide, int rho,
+                          int H, int W, const fhd_params* p, float* out, float* den);
+
+/* Stage timing with HIP events on the context's stream (for benchmarks).
+ * While enabled, every call records an event pair around each stage's
+ * kernels; fhd_timing_read returns, per stage, the summed elapsed
+ * milliseconds and the number of recorded launches since the last read, then
+ * forgets them (it synchronises the stream).  Stages: */
+enum {
+    FHD_STAGE_CLUSTER = 0,  /* all clustering kernels of one call (first to last) */
+    FHD_STAGE_WEIGHTS = 1,  /* weights pass (materialised b and c planes) */
+    FHD_STAGE_ROW = 2,      /* row pass of the convolutions */
+    FHD_STAGE_COL = 3,      /* column pass with the recombination */
+    FHD_STAGE_BRUTE = 4,    /* brute force */
+    FHD_NUM_STAGES = 5
+};
+fhd_status fhd_timing_enable(fhd_ctx* ctx, int enable);
+/* ms and launches: host arrays of FHD_NUM_STAGES entries. */
+fhd_status fhd_timing_read(fhd_ctx* ctx, double* ms, int* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FHD_H */

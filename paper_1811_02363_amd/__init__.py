@@ -1,0 +1,285 @@
+"""MI355X (gfx950) fast high-dimensional bilateral and nonlocal-means filtering.
+
+Python binding of ``libfhd.so`` (C ABI in ``include/fhd.h``).  This module only
+marshals arguments: every step of the filter runs in the library's HIP
+kernels and host code.  PyTorch supplies device memory and the current HIP
+stream.  Importing works without a GPU; calling a filter needs the built
+library and a GPU and fails loudly otherwise (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import threading
+
+import torch
+
+__all__ = [
+    "FHDError", "Params", "Info", "load", "lib_path", "symbols",
+    "filter", "filter_centers", "cluster", "pinv", "bruteforce",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+lib_path = os.path.join(_HERE, "libfhd.so")
+
+FHD_OK, FHD_EINVAL, FHD_ENOMEM, FHD_EHIP, FHD_ENUMERIC, FHD_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+_STATUS = {0: "FHD_OK", -1: "FHD_EINVAL", -2: "FHD_ENOMEM", -3: "FHD_EHIP",
+           -4: "FHD_ENUMERIC", -5: "FHD_EUNSUPPORTED"}
+SPATIAL = {"gaussian": 0, "box": 1}
+CONTRACT = {"fp32": 0, "bf16": 1, "fp16": 2}
+COEF = {"lsq": 0, "hard": 1}
+
+# Every entry point declared in include/fhd.h.
+symbols = [
+    "fhd_default_params", "fhd_create", "fhd_destroy", "fhd_set_stream", "fhd_last_error",
+    "fhd_workspace_size", "fhd_set_workspace", "fhd_cluster", "fhd_pinv",
+    "fhd_filter_centers", "fhd_filter", "fhd_bruteforce", "fhd_timing_enable", "fhd_timing_read",
+]
+STAGES = ("cluster", "weights", "row", "col", "brute")
+
+
+class FHDError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("sigma_s", ctypes.c_float), ("radius", ctypes.c_int), ("sigma_r", ctypes.c_float),
+        ("K", ctypes.c_int), ("spatial", ctypes.c_int), ("contract", ctypes.c_int),
+        ("coef", ctypes.c_int), ("kmeans_max_iter", ctypes.c_int), ("pinv_rtol", ctypes.c_double),
+        ("strict", ctypes.c_int),
+    ]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("K_eff", ctypes.c_int), ("pinv_rank", ctypes.c_int), ("kmeans_rounds", ctypes.c_int),
+        ("kmeans_splits", ctypes.c_int), ("E_K", ctypes.c_double), ("cond_A", ctypes.c_double),
+        ("pinv_norm", ctypes.c_double), ("ms_cluster", ctypes.c_float),
+        ("ms_solve", ctypes.c_float), ("ms_filter", ctypes.c_float),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+_lock = threading.Lock()
+_ctxs = {}
+
+
+def load():
+    """Load ``libfhd.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(lib_path):
+            raise FHDError(FHD_EUNSUPPORTED,
+                           f"{lib_path} is missing: build it with `python -m paper_1811_02363_amd.build`")
+        lib = ctypes.CDLL(lib_path)
+        P, V, I, F, D = ctypes.POINTER, ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.c_double
+        pp = P(Params)
+        pi = P(Info)
+        sig = {
+            "fhd_default_params": (None, [pp]),
+            "fhd_create": (I, [P(V), I, V]),
+            "fhd_destroy": (I, [V]),
+            "fhd_set_stream": (I, [V, V]),
+            "fhd_last_error": (ctypes.c_char_p, [V]),
+            "fhd_workspace_size": (I, [pp, I, I, I, I, P(ctypes.c_size_t)]),
+            "fhd_set_workspace": (I, [V, V, ctypes.c_size_t]),
+            "fhd_cluster": (I, [V, V, I, I, I, I, I, V, V, P(I), pi]),
+            "fhd_pinv": (I, [V, I, I, D, D, V, V, P(I), P(D)]),
+            "fhd_filter_centers": (I, [V, V, I, V, I, I, I, V, I, V, pp, V, V, pi]),
+            "fhd_filter": (I, [V, V, I, V, I, I, I, pp, V, V, V, pi]),
+            "fhd_bruteforce": (I, [V, V, I, V, I, I, I, pp, V, V]),
+            "fhd_timing_enable": (I, [V, I]),
+            "fhd_timing_read": (I, [V, P(D), P(I)]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _ctx(device: int):
+    lib = load()
+    c = _ctxs.get(device)
+    if c is None:
+        h = ctypes.c_void_p()
+        _check(lib.fhd_create(ctypes.byref(h), device, None), None)
+        c = h
+        _ctxs[device] = c
+    stream = torch.cuda.current_stream(device).cuda_stream
+    _check(lib.fhd_set_stream(c, ctypes.c_void_p(stream)), c)
+    return c
+
+
+def _check(status, ctx):
+    if status != FHD_OK:
+        msg = load().fhd_last_error(ctx).decode() if ctx is not None else ""
+        raise FHDError(status, msg)
+
+
+def _dev(t, name, dtype=torch.float32):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise FHDError(FHD_EINVAL, f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise FHDError(FHD_EINVAL, f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise FHDError(FHD_EINVAL, f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def make_params(sigma_s=3.0, sigma_r=0.1, K=16, spatial="gaussian", radius=None,
+                contract="fp32", coef="lsq", kmeans_max_iter=20, pinv_rtol=0.0, strict=False):
+    p = Params()
+    load().fhd_default_params(ctypes.byref(p))
+    p.sigma_s = float(sigma_s if sigma_s is not None else 1.0)
+    p.radius = -1 if radius is None else int(radius)
+    p.sigma_r = float(sigma_r)
+    p.K = int(K)
+    p.spatial = SPATIAL[spatial]
+    p.contract = CONTRACT[contract]
+    p.coef = COEF[coef]
+    p.kmeans_max_iter = int(kmeans_max_iter)
+    p.pinv_rtol = float(pinv_rtol)
+    p.strict = 1 if strict else 0
+    return p
+
+
+def _shape(f, guide):
+    if not isinstance(f, torch.Tensor) or not f.is_cuda:
+        raise FHDError(FHD_EINVAL, "images must be CUDA (HIP) tensors; there is no CPU path")
+    if f.dim() != 3:
+        raise FHDError(FHD_EINVAL, "images are (C, H, W)")
+    g = f if guide is None else guide
+    if g.dim() != 3 or g.shape[1:] != f.shape[1:]:
+        raise FHDError(FHD_EINVAL, "guide must be (rho, H, W) with the image's H, W")
+    return f.shape[0], g.shape[0], f.shape[1], f.shape[2], g
+
+
+def filter(f, guide=None, sigma_s=3.0, sigma_r=0.1, K=16, spatial="gaussian", radius=None,
+           contract="fp32", coef="lsq", kmeans_max_iter=20, return_den=False,
+           return_centers=False, info=False, strict=False):
+    """Algorithm 1 end to end: returns g_hat (n, H, W) [, den (H, W)]
+    [, centers (K_eff, rho) on the host] [, info dict]."""
+    n, rho, H, W, g = _shape(f, guide)
+    ctx = _ctx(f.device.index)
+    p = make_params(sigma_s, sigma_r, K, spatial, radius, contract, coef, kmeans_max_iter,
+                    strict=strict)
+    out = torch.empty_like(f)
+    den = torch.empty((H, W), device=f.device, dtype=torch.float32) if return_den else None
+    cen = torch.zeros((K, rho), dtype=torch.float32)
+    inf = Info()
+    _check(load().fhd_filter(ctx, _dev(f, "f"), n, _dev(g, "guide"), rho, H, W, ctypes.byref(p),
+                             _dev(out, "out"), ctypes.c_void_p(cen.data_ptr()),
+                             _dev(den, "den") if den is not None else None,
+                             ctypes.byref(inf) if (info or return_centers) else None), ctx)
+    res = [out]
+    if return_den:
+        res.append(den)
+    if return_centers:
+        res.append(cen[:inf.K_eff].clone())
+    if info:
+        res.append(inf.as_dict())
+    return res[0] if len(res) == 1 else tuple(res)
+
+
+def filter_centers(f, guide, centers, sigma_s=3.0, sigma_r=0.1, spatial="gaussian", radius=None,
+                   contract="fp32", coef="lsq", labels=None, return_den=False, info=False,
+                   strict=False):
+    """Steps 2-5 with given centers (host or device (K, rho) float32)."""
+    n, rho, H, W, g = _shape(f, guide)
+    ctx = _ctx(f.device.index)
+    c = torch.as_tensor(centers, dtype=torch.float32).detach().cpu().contiguous()
+    K = c.shape[0]
+    if c.dim() != 2 or c.shape[1] != rho:
+        raise FHDError(FHD_EINVAL, "centers must be (K, rho)")
+    p = make_params(sigma_s, sigma_r, K, spatial, radius, contract, coef, strict=strict)
+    out = torch.empty_like(f)
+    den = torch.empty((H, W), device=f.device, dtype=torch.float32) if return_den else None
+    inf = Info()
+    lab = _dev(labels, "labels", torch.int32) if labels is not None else None
+    _check(load().fhd_filter_centers(ctx, _dev(f, "f"), n, _dev(g, "guide"), rho, H, W,
+                                     ctypes.c_void_p(c.data_ptr()), K, lab, ctypes.byref(p),
+                                     _dev(out, "out"),
+                                     _dev(den, "den") if den is not None else None,
+                                     ctypes.byref(inf) if info else None), ctx)
+    res = [out]
+    if return_den:
+        res.append(den)
+    if info:
+        res.append(inf.as_dict())
+    return res[0] if len(res) == 1 else tuple(res)
+
+
+def cluster(guide, K, max_iter=20, labels=False):
+    """Bisecting K-means of the guide vectors: (centers (K_eff, rho) host float32
+    [, labels (H, W) int32 device], info)."""
+    rho, H, W = guide.shape
+    ctx = _ctx(guide.device.index)
+    cen = torch.zeros((K, rho), dtype=torch.float32)
+    lab = torch.empty((H, W), device=guide.device, dtype=torch.int32) if labels else None
+    keff = ctypes.c_int()
+    inf = Info()
+    _check(load().fhd_cluster(ctx, _dev(guide, "guide"), rho, H, W, int(K), int(max_iter),
+                              ctypes.c_void_p(cen.data_ptr()),
+                              _dev(lab, "labels", torch.int32) if lab is not None else None,
+                              ctypes.byref(keff), ctypes.byref(inf)), ctx)
+    cen = cen[:keff.value].clone()
+    if labels:
+        return cen, lab, inf.as_dict()
+    return cen, inf.as_dict()
+
+
+def pinv(centers, sigma_r, rtol=0.0):
+    """The K x K solve on the host (FP64): (A, A^+, rank, cond) as float64 tensors."""
+    c = torch.as_tensor(centers, dtype=torch.float32).contiguous()
+    K, rho = c.shape
+    A = torch.empty((K, K), dtype=torch.float64)
+    P = torch.empty((K, K), dtype=torch.float64)
+    rank = ctypes.c_int()
+    cond = ctypes.c_double()
+    st = load().fhd_pinv(ctypes.c_void_p(c.data_ptr()), K, rho, float(sigma_r), float(rtol),
+                         ctypes.c_void_p(A.data_ptr()), ctypes.c_void_p(P.data_ptr()),
+                         ctypes.byref(rank), ctypes.byref(cond))
+    _check(st, None)
+    return A, P, rank.value, cond.value
+
+
+def bruteforce(f, guide=None, sigma_s=3.0, sigma_r=0.1, spatial="gaussian", radius=None,
+               return_den=False):
+    """Eqs. (1)-(2) directly on the GPU (FP32)."""
+    n, rho, H, W, g = _shape(f, guide)
+    ctx = _ctx(f.device.index)
+    p = make_params(sigma_s, sigma_r, 1, spatial, radius)
+    out = torch.empty_like(f)
+    den = torch.empty((H, W), device=f.device, dtype=torch.float32) if return_den else None
+    _check(load().fhd_bruteforce(ctx, _dev(f, "f"), n, _dev(g, "guide"), rho, H, W,
+                                 ctypes.byref(p), _dev(out, "out"),
+                                 _dev(den, "den") if den is not None else None), ctx)
+    return (out, den) if return_den else out
+
+
+def timing_enable(device=0, enable=True):
+    """Record HIP events around each stage of later calls on `device`."""
+    ctx = _ctx(device)
+    _check(load().fhd_timing_enable(ctx, 1 if enable else 0), ctx)
+
+
+def timing_read(device=0):
+    """{stage: (total ms, launches)} since the last read (synchronises)."""
+    ctx = _ctx(device)
+    ms = (ctypes.c_double * len(STAGES))()
+    n = (ctypes.c_int * len(STAGES))()
+    _check(load().fhd_timing_read(ctx, ms, n), ctx)
+    return {s: (ms[i], n[i]) for i, s in enumerate(STAGES)}

@@ -1,0 +1,520 @@
+// The C ABI of include/fhd.h: argument checks, workspace, orchestration of
+// the steps of Algorithm 1, and conversion of failures into status codes.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "fhd_internal.h"
+
+namespace fhd {
+
+Arena Ctx::arena(size_t need) {
+    Arena a;
+    if (ext_ws != nullptr) {
+        FHD_REQUIRE(need <= ext_bytes, FHD_ENOMEM, "caller workspace too small");
+        a.base = static_cast<char*>(ext_ws);
+        a.cap = ext_bytes;
+        return a;
+    }
+    if (own_bytes < need) {
+        if (own_ws != nullptr) {
+            FHD_HIP(hipStreamSynchronize(stream));
+            FHD_HIP(hipFree(own_ws));
+            own_ws = nullptr;
+            own_bytes = 0;
+        }
+        const size_t bytes = align_up(need + need / 8, 1 << 20);
+        if (hipMalloc(&own_ws, bytes) != hipSuccess) {
+            own_ws = nullptr;
+            (void)hipGetLastError();
+            throw Error(FHD_ENOMEM, "device workspace allocation failed");
+        }
+        own_bytes = bytes;
+    }
+    a.base = static_cast<char*>(own_ws);
+    a.cap = own_bytes;
+    return a;
+}
+
+void* Ctx::host_stage(int slot, size_t bytes) {
+    if (pinned_pending[slot]) {
+        FHD_HIP(hipEventSynchronize(pinned_ev[slot]));
+        pinned_pending[slot] = false;
+    }
+    if (pinned_bytes[slot] < bytes) {
+        if (pinned[slot] != nullptr) FHD_HIP(hipHostFree(pinned[slot]));
+        pinned[slot] = nullptr;
+        pinned_bytes[slot] = 0;
+        const size_t b = align_up(std::max<size_t>(bytes, 1 << 16), 1 << 16);
+        if (hipHostMalloc(&pinned[slot], b, hipHostMallocDefault) != hipSuccess) {
+            pinned[slot] = nullptr;
+            (void)hipGetLastError();
+            throw Error(FHD_ENOMEM, "pinned host allocation failed");
+        }
+        pinned_bytes[slot] = b;
+    }
+    if (pinned_ev[slot] == nullptr) FHD_HIP(hipEventCreateWithFlags(&pinned_ev[slot], hipEventDisableTiming));
+    return pinned[slot];
+}
+
+void Ctx::stage_done(int slot) {
+    FHD_HIP(hipEventRecord(pinned_ev[slot], stream));
+    pinned_pending[slot] = true;
+}
+
+hipEvent_t Ctx::take_event() {
+    if (!ev_pool.empty()) {
+        hipEvent_t e = ev_pool.back();
+        ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    FHD_HIP(hipEventCreate(&e));
+    return e;
+}
+
+hipEvent_t Ctx::stage_begin() {
+    if (!timing) return nullptr;
+    hipEvent_t e = take_event();
+    FHD_HIP(hipEventRecord(e, stream));
+    return e;
+}
+
+void Ctx::stage_end(int stage, hipEvent_t begin) {
+    if (!timing || begin == nullptr) return;
+    hipEvent_t e = take_event();
+    FHD_HIP(hipEventRecord(e, stream));
+    ev_rec[stage].emplace_back(begin, e);
+}
+
+void Ctx::release() {
+    if (stream != nullptr || true) (void)hipStreamSynchronize(stream);
+    if (own_ws != nullptr) (void)hipFree(own_ws);
+    own_ws = nullptr;
+    for (auto& v : ev_rec)
+        for (auto& pr : v) {
+            ev_pool.push_back(pr.first);
+            ev_pool.push_back(pr.second);
+        }
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    ev_pool.clear();
+    for (int s = 0; s < 3; ++s) {
+        if (pinned[s] != nullptr) (void)hipHostFree(pinned[s]);
+        if (pinned_ev[s] != nullptr) (void)hipEventDestroy(pinned_ev[s]);
+        pinned[s] = nullptr;
+        pinned_ev[s] = nullptr;
+    }
+}
+
+namespace {
+
+using clk = std::chrono::steady_clock;
+double ms_since(clk::time_point t0) {
+    return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) FHD_HIP(hipSetDevice(dev));
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+int resolve_radius(const fhd_params& p) {
+    if (p.radius >= 0) return p.radius;
+    return (int)std::ceil(3.0 * (double)p.sigma_s - 1e-9);
+}
+
+void check_params(const fhd_params* p, int n, int rho, int H, int W) {
+    FHD_REQUIRE(p != nullptr, FHD_EINVAL, "params is NULL");
+    FHD_REQUIRE(n >= 1 && rho >= 1 && H >= 1 && W >= 1, FHD_EINVAL, "n, rho, H, W must be >= 1");
+    FHD_REQUIRE(n <= FHD_MAX_N, FHD_EUNSUPPORTED, "n exceeds FHD_MAX_N");
+    FHD_REQUIRE(rho <= FHD_MAX_RHO, FHD_EUNSUPPORTED, "rho exceeds FHD_MAX_RHO");
+    FHD_REQUIRE((long long)H * W < (1LL << 31), FHD_EUNSUPPORTED, "image has 2^31 pixels or more");
+    FHD_REQUIRE(p->spatial == FHD_SPATIAL_GAUSSIAN || p->spatial == FHD_SPATIAL_BOX, FHD_EINVAL,
+                "unknown spatial kernel");
+    if (p->spatial == FHD_SPATIAL_GAUSSIAN)
+        FHD_REQUIRE(p->sigma_s > 0.0f && std::isfinite(p->sigma_s), FHD_EINVAL, "sigma_s must be > 0");
+    else
+        FHD_REQUIRE(p->radius >= 0, FHD_EINVAL, "the box kernel needs radius >= 0");
+    FHD_REQUIRE(p->sigma_r > 0.0f && !std::isnan(p->sigma_r), FHD_EINVAL, "sigma_r must be > 0");
+    FHD_REQUIRE(p->K >= 1 && p->K <= FHD_MAX_K, FHD_EINVAL, "K must be in [1, FHD_MAX_K]");
+    FHD_REQUIRE((long long)p->K <= (long long)H * W, FHD_EINVAL, "K exceeds the number of pixels");
+    FHD_REQUIRE(p->coef == FHD_COEF_LSQ || p->coef == FHD_COEF_HARD, FHD_EINVAL, "unknown coef");
+    FHD_REQUIRE(p->contract == FHD_CONTRACT_FP32 || p->contract == FHD_CONTRACT_BF16 ||
+                    p->contract == FHD_CONTRACT_FP16,
+                FHD_EINVAL, "unknown contraction precision");
+    FHD_REQUIRE(p->kmeans_max_iter >= 1, FHD_EINVAL, "kmeans_max_iter must be >= 1");
+    const int S = resolve_radius(*p);
+    FHD_REQUIRE(S >= 0 && S <= FHD_MAX_RADIUS, FHD_EUNSUPPORTED, "radius exceeds FHD_MAX_RADIUS");
+}
+
+FilterPlan make_plan(const fhd_params& p, int n, int rho, int H, int W, int K) {
+    FilterPlan fp{};
+    fp.n = n;
+    fp.rho = rho;
+    fp.H = H;
+    fp.W = W;
+    fp.K = K;
+    fp.S = resolve_radius(p);
+    fp.spatial = p.spatial;
+    fp.contract = p.contract;
+    fp.coef = p.coef;
+    fp.sigma_s = p.sigma_s;
+    fp.sigma_r = p.sigma_r;
+    fp.N = (long long)H * W;
+    fp.Wp = (int)align_up((size_t)W, 4);
+    fp.materialize = rho > 8 || p.contract != FHD_CONTRACT_FP32;
+    return fp;
+}
+
+bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
+    if (a == nullptr || b == nullptr) return false;
+    const char* x = static_cast<const char*>(a);
+    const char* y = static_cast<const char*>(b);
+    return x < y + nb && y < x + na;
+}
+
+// The K x K solve on FP32 centers: A, A^+ (FP64) and its FP32 copy.
+PinvResult solve(const float* centers, int K, int rho, double sigma_r, double rtol, std::vector<float>& P32) {
+    std::vector<double> A((size_t)K * K), P((size_t)K * K);
+    kernel_matrix(centers, K, rho, sigma_r, A.data());
+    PinvResult r = pinv_symmetric(A.data(), K, rtol, P.data());
+    P32.resize((size_t)K * K);
+    for (size_t q = 0; q < P.size(); ++q) P32[q] = (float)P[q];
+    return r;
+}
+
+template <class F>
+fhd_status guarded(fhd_ctx* ctx, F&& body) {
+    if (ctx == nullptr) return FHD_EINVAL;
+    ctx->impl.err.clear();
+    try {
+        DeviceGuard g(ctx->impl.device);
+        body(ctx->impl);
+        return FHD_OK;
+    } catch (const Error& e) {
+        ctx->impl.err = e.what();
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        ctx->impl.err = "host allocation failed";
+        return FHD_ENOMEM;
+    } catch (const std::exception& e) {
+        ctx->impl.err = e.what();
+        return FHD_EINVAL;
+    } catch (...) {
+        ctx->impl.err = "unknown failure";
+        return FHD_EINVAL;
+    }
+}
+
+// Counts of non-positive normalisers and non-finite outputs (strict mode).
+__global__ void check_output(const float* out, long long count, const float* den, long long N,
+                             unsigned long long* bad) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long b = 0;
+    if (i < count && !isfinite(out[i])) b = 1;
+    if (den != nullptr && i < N && !(den[i] > 0.0f)) b = 1;
+    if (b) atomicAdd(bad, 1ull);
+}
+
+void strict_check(Ctx& c, Arena& ws, const float* out, long long count, const float* den, long long N) {
+    unsigned long long* bad = ws.take<unsigned long long>(1);
+    FHD_HIP(hipMemsetAsync(bad, 0, sizeof(unsigned long long), c.stream));
+    hipLaunchKernelGGL(check_output, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, c.stream, out,
+                       count, den, N, bad);
+    FHD_HIP(hipGetLastError());
+    unsigned long long h = 0;
+    FHD_HIP(hipMemcpyAsync(&h, bad, sizeof(h), hipMemcpyDeviceToHost, c.stream));
+    FHD_HIP(hipStreamSynchronize(c.stream));
+    FHD_REQUIRE(h == 0, FHD_ENUMERIC, "non-positive normaliser or non-finite output");
+}
+
+void fill_info(fhd_info* info, int K_eff, const PinvResult& pr, double E_K, int rounds, int splits,
+               double ms_cluster, double ms_solve, double ms_filter) {
+    if (info == nullptr) return;
+    info->K_eff = K_eff;
+    info->pinv_rank = pr.rank;
+    info->kmeans_rounds = rounds;
+    info->kmeans_splits = splits;
+    info->E_K = E_K;
+    info->cond_A = pr.cond;
+    info->pinv_norm = pr.max_abs;
+    info->ms_cluster = (float)ms_cluster;
+    info->ms_solve = (float)ms_solve;
+    info->ms_filter = (float)ms_filter;
+}
+
+}  // namespace
+}  // namespace fhd
+
+using namespace fhd;
+
+extern "C" {
+
+void fhd_default_params(fhd_params* p) {
+    if (p == nullptr) return;
+    std::memset(p, 0, sizeof(*p));
+    p->sigma_s = 3.0f;
+    p->radius = -1;
+    p->sigma_r = 0.1f;
+    p->K = 16;
+    p->spatial = FHD_SPATIAL_GAUSSIAN;
+    p->contract = FHD_CONTRACT_FP32;
+    p->coef = FHD_COEF_LSQ;
+    p->kmeans_max_iter = 20;
+    p->pinv_rtol = 0.0;
+    p->strict = 0;
+}
+
+fhd_status fhd_create(fhd_ctx** out, int device, void* hip_stream) {
+    if (out == nullptr) return FHD_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
+        (void)hipGetLastError();
+        return device < 0 ? FHD_EINVAL : FHD_EHIP;
+    }
+    fhd_ctx* c = new (std::nothrow) fhd_ctx();
+    if (c == nullptr) return FHD_ENOMEM;
+    c->impl.device = device;
+    c->impl.stream = static_cast<hipStream_t>(hip_stream);
+    *out = c;
+    return FHD_OK;
+}
+
+fhd_status fhd_destroy(fhd_ctx* ctx) {
+    if (ctx == nullptr) return FHD_EINVAL;
+    {
+        int prev = -1;
+        (void)hipGetDevice(&prev);
+        (void)hipSetDevice(ctx->impl.device);
+        ctx->impl.release();
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+    delete ctx;
+    return FHD_OK;
+}
+
+fhd_status fhd_set_stream(fhd_ctx* ctx, void* hip_stream) {
+    return guarded(ctx, [&](Ctx& c) {
+        // the staging slots may still feed copies on the old stream
+        for (int s = 0; s < 3; ++s)
+            if (c.pinned_pending[s]) {
+                FHD_HIP(hipEventSynchronize(c.pinned_ev[s]));
+                c.pinned_pending[s] = false;
+            }
+        c.stream = static_cast<hipStream_t>(hip_stream);
+    });
+}
+
+const char* fhd_last_error(const fhd_ctx* ctx) {
+    if (ctx == nullptr) return "context is NULL";
+    return ctx->impl.err.c_str();
+}
+
+fhd_status fhd_workspace_size(const fhd_params* p, int n, int rho, int H, int W, size_t* bytes) {
+    if (bytes == nullptr) return FHD_EINVAL;
+    try {
+        check_params(p, n, rho, H, W);
+        const FilterPlan fp = make_plan(*p, n, rho, H, W, p->K);
+        size_t b = kmeans_workspace(fp.N, rho, p->K);
+        b += filter_workspace(fp);
+        b += align_up(sizeof(int) * (size_t)fp.N, 256);  // labels
+        b += 4096;                                       // strict-mode counter, slack
+        *bytes = b;
+        return FHD_OK;
+    } catch (const Error& e) {
+        return e.status;
+    } catch (...) {
+        return FHD_EINVAL;
+    }
+}
+
+fhd_status fhd_set_workspace(fhd_ctx* ctx, void* dev, size_t bytes) {
+    return guarded(ctx, [&](Ctx& c) {
+        FHD_REQUIRE(dev == nullptr || (reinterpret_cast<uintptr_t>(dev) & 255) == 0, FHD_EINVAL,
+                    "workspace must be 256-byte aligned");
+        FHD_HIP(hipStreamSynchronize(c.stream));
+        c.ext_ws = dev;
+        c.ext_bytes = dev ? bytes : 0;
+    });
+}
+
+fhd_status fhd_cluster(fhd_ctx* ctx, const float* guide, int rho, int H, int W, int K, int max_iter,
+                       float* centers, int* labels, int* K_eff, fhd_info* info) {
+    return guarded(ctx, [&](Ctx& c) {
+        FHD_REQUIRE(guide != nullptr && centers != nullptr, FHD_EINVAL, "NULL pointer");
+        FHD_REQUIRE(rho >= 1 && H >= 1 && W >= 1, FHD_EINVAL, "rho, H, W must be >= 1");
+        FHD_REQUIRE(rho <= FHD_MAX_RHO, FHD_EUNSUPPORTED, "rho exceeds FHD_MAX_RHO");
+        const long long N = (long long)H * W;
+        FHD_REQUIRE(K >= 1 && K <= FHD_MAX_K && K <= N, FHD_EINVAL, "K out of range");
+        Arena ws = c.arena(kmeans_workspace(N, rho, K));
+        const auto t0 = clk::now();
+        KmResult km;
+        kmeans_run(c, ws, guide, rho, N, K, max_iter, labels, km);
+        for (size_t q = 0; q < km.centers.size(); ++q) centers[q] = (float)km.centers[q];
+        if (K_eff) *K_eff = km.K_eff;
+        FHD_HIP(hipStreamSynchronize(c.stream));
+        if (info) {
+            std::memset(info, 0, sizeof(*info));
+            info->K_eff = km.K_eff;
+            info->E_K = km.E_K;
+            info->kmeans_rounds = km.rounds;
+            info->kmeans_splits = km.splits;
+            info->ms_cluster = (float)ms_since(t0);
+        }
+    });
+}
+
+fhd_status fhd_pinv(const float* centers, int K, int rho, double sigma_r, double rtol, double* A,
+                    double* Apinv, int* rank, double* cond) {
+    if (centers == nullptr || K < 1 || K > FHD_MAX_K || rho < 1 || rho > FHD_MAX_RHO || !(sigma_r > 0.0))
+        return FHD_EINVAL;
+    try {
+        std::vector<double> a((size_t)K * K), p((size_t)K * K);
+        kernel_matrix(centers, K, rho, sigma_r, a.data());
+        const PinvResult r = pinv_symmetric(a.data(), K, rtol, p.data());
+        if (A) std::memcpy(A, a.data(), sizeof(double) * a.size());
+        if (Apinv) std::memcpy(Apinv, p.data(), sizeof(double) * p.size());
+        if (rank) *rank = r.rank;
+        if (cond) *cond = r.cond;
+        return FHD_OK;
+    } catch (...) {
+        return FHD_ENOMEM;
+    }
+}
+
+fhd_status fhd_filter_centers(fhd_ctx* ctx, const float* f, int n, const float* guide, int rho, int H,
+                              int W, const float* centers, int K, const int* labels, const fhd_params* p,
+                              float* out, float* den, fhd_info* info) {
+    return guarded(ctx, [&](Ctx& c) {
+        check_params(p, n, rho, H, W);
+        FHD_REQUIRE(f && guide && centers && out, FHD_EINVAL, "NULL pointer");
+        FHD_REQUIRE(K >= 1 && K <= FHD_MAX_K, FHD_EINVAL, "K must be in [1, FHD_MAX_K]");
+        FHD_REQUIRE(p->coef != FHD_COEF_HARD || labels != nullptr, FHD_EINVAL, "hard coefficients need labels");
+        const long long N = (long long)H * W;
+        FHD_REQUIRE(!ranges_overlap(out, sizeof(float) * N * n, f, sizeof(float) * N * n) &&
+                        !ranges_overlap(out, sizeof(float) * N * n, guide, sizeof(float) * N * rho) &&
+                        !ranges_overlap(den, sizeof(float) * N, f, sizeof(float) * N * n) &&
+                        !ranges_overlap(den, sizeof(float) * N, guide, sizeof(float) * N * rho) &&
+                        !ranges_overlap(den, sizeof(float) * N, out, sizeof(float) * N * n),
+                    FHD_EINVAL, "outputs alias inputs");
+        const FilterPlan fp = make_plan(*p, n, rho, H, W, K);
+        Arena ws = c.arena(filter_workspace(fp) + 4096);
+        const auto t0 = clk::now();
+        std::vector<float> P32;
+        const PinvResult pr = solve(centers, K, rho, p->sigma_r, p->pinv_rtol, P32);
+        const double ms_solve = ms_since(t0);
+        const auto t1 = clk::now();
+        filter_run(c, ws, fp, f, guide, centers, P32.data(), labels, out, den);
+        if (p->strict) strict_check(c, ws, out, N * n, den, N);
+        double ms_filter = 0.0;
+        if (info) {
+            FHD_HIP(hipStreamSynchronize(c.stream));
+            ms_filter = ms_since(t1);
+        }
+        fill_info(info, K, pr, 0.0, 0, 0, 0.0, ms_solve, ms_filter);
+    });
+}
+
+fhd_status fhd_filter(fhd_ctx* ctx, const float* f, int n, const float* guide, int rho, int H, int W,
+                      const fhd_params* p, float* out, float* centers_out, float* den, fhd_info* info) {
+    return guarded(ctx, [&](Ctx& c) {
+        check_params(p, n, rho, H, W);
+        FHD_REQUIRE(f && guide && out, FHD_EINVAL, "NULL pointer");
+        const long long N = (long long)H * W;
+        FHD_REQUIRE(!ranges_overlap(out, sizeof(float) * N * n, f, sizeof(float) * N * n) &&
+                        !ranges_overlap(out, sizeof(float) * N * n, guide, sizeof(float) * N * rho) &&
+                        !ranges_overlap(den, sizeof(float) * N, f, sizeof(float) * N * n) &&
+                        !ranges_overlap(den, sizeof(float) * N, guide, sizeof(float) * N * rho) &&
+                        !ranges_overlap(den, sizeof(float) * N, out, sizeof(float) * N * n),
+                    FHD_EINVAL, "outputs alias inputs");
+        size_t need = 0;
+        {
+            const FilterPlan fp0 = make_plan(*p, n, rho, H, W, p->K);
+            need = kmeans_workspace(N, rho, p->K) + filter_workspace(fp0) +
+                   align_up(sizeof(int) * (size_t)N, 256) + 4096;
+        }
+        Arena ws = c.arena(need);
+        const bool hard = p->coef == FHD_COEF_HARD;
+        int* labels = hard ? ws.take<int>((size_t)N) : nullptr;
+        const auto t0 = clk::now();
+        KmResult km;
+        {
+            Arena kws = ws;  // the clustering scratch is dead once the centers are known
+            kmeans_run(c, kws, guide, rho, N, p->K, p->kmeans_max_iter, labels, km);
+        }
+        const double ms_cluster = ms_since(t0);
+        const int K = km.K_eff;
+        std::vector<float> c32((size_t)K * rho);
+        for (size_t q = 0; q < c32.size(); ++q) c32[q] = (float)km.centers[q];
+        if (centers_out) std::memcpy(centers_out, c32.data(), sizeof(float) * c32.size());
+        const auto t1 = clk::now();
+        std::vector<float> P32;
+        const PinvResult pr = solve(c32.data(), K, rho, p->sigma_r, p->pinv_rtol, P32);
+        const double ms_solve = ms_since(t1);
+        const auto t2 = clk::now();
+        const FilterPlan fp = make_plan(*p, n, rho, H, W, K);
+        filter_run(c, ws, fp, f, guide, c32.data(), P32.data(), labels, out, den);
+        if (p->strict) strict_check(c, ws, out, N * n, den, N);
+        double ms_filter = 0.0;
+        if (info) {
+            FHD_HIP(hipStreamSynchronize(c.stream));
+            ms_filter = ms_since(t2);
+        }
+        fill_info(info, K, pr, km.E_K, km.rounds, km.splits, ms_cluster, ms_solve, ms_filter);
+    });
+}
+
+fhd_status fhd_bruteforce(fhd_ctx* ctx, const float* f, int n, const float* guide, int rho, int H, int W,
+                          const fhd_params* p, float* out, float* den) {
+    return guarded(ctx, [&](Ctx& c) {
+        check_params(p, n, rho, H, W);
+        FHD_REQUIRE(f && guide && out, FHD_EINVAL, "NULL pointer");
+        const long long N = (long long)H * W;
+        FHD_REQUIRE(!ranges_overlap(out, sizeof(float) * N * n, f, sizeof(float) * N * n) &&
+                        !ranges_overlap(out, sizeof(float) * N * n, guide, sizeof(float) * N * rho),
+                    FHD_EINVAL, "outputs alias inputs");
+        const FilterPlan fp = make_plan(*p, n, rho, H, W, 1);
+        bruteforce_run(c, fp, f, guide, out, den);
+        if (p->strict) {
+            Arena ws = c.arena(4096);
+            strict_check(c, ws, out, N * n, den, N);
+        }
+    });
+}
+
+fhd_status fhd_timing_enable(fhd_ctx* ctx, int enable) {
+    return guarded(ctx, [&](Ctx& c) { c.timing = enable != 0; });
+}
+
+fhd_status fhd_timing_read(fhd_ctx* ctx, double* ms, int* launches) {
+    return guarded(ctx, [&](Ctx& c) {
+        FHD_REQUIRE(ms != nullptr && launches != nullptr, FHD_EINVAL, "NULL pointer");
+        FHD_HIP(hipStreamSynchronize(c.stream));
+        for (int s = 0; s < FHD_NUM_STAGES; ++s) {
+            double tot = 0.0;
+            for (auto& pr : c.ev_rec[s]) {
+                float t = 0.0f;
+                FHD_HIP(hipEventElapsedTime(&t, pr.first, pr.second));
+                tot += t;
+                c.ev_pool.push_back(pr.first);
+                c.ev_pool.push_back(pr.second);
+            }
+            ms[s] = tot;
+            launches[s] = (int)c.ev_rec[s].size();
+            c.ev_rec[s].clear();
+        }
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,132 @@
+// Internal declarations shared by the HIP sources of libfhd.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/fhd.h"
+
+namespace fhd {
+
+// A failure inside the library; converted to a status code at the C ABI.
+struct Error : std::runtime_error {
+    fhd_status status;
+    Error(fhd_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+#define FHD_HIP(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            throw ::fhd::Error(FHD_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define FHD_REQUIRE(cond, status, msg)                         \
+    do {                                                       \
+        if (!(cond)) throw ::fhd::Error((status), (msg));      \
+    } while (0)
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Bump allocator over one device buffer.  Every slice is 256-byte aligned.
+struct Arena {
+    char* base = nullptr;
+    size_t cap = 0;
+    size_t used = 0;
+    template <class T>
+    T* take(size_t count) {
+        size_t off = align_up(used, 256);
+        size_t bytes = align_up(count * sizeof(T), 256);
+        if (base != nullptr && off + bytes > cap)
+            throw Error(FHD_ENOMEM, "workspace too small");
+        used = off + bytes;
+        return base ? reinterpret_cast<T*>(base + off) : nullptr;
+    }
+};
+
+struct Ctx;
+
+// ---- clustering (kmeans.hip) ------------------------------------------------
+struct KmResult {
+    int K_eff = 0;
+    int rounds = 0;
+    int splits = 0;
+    double E_K = 0.0;
+    std::vector<double> centers;   // K_eff x rho, FP64 leaf centroids in heap order
+};
+// Workspace bytes for clustering N points of dimension rho into <= K leaves.
+size_t kmeans_workspace(long long N, int rho, int K);
+void kmeans_run(Ctx& c, Arena& ws, const float* guide, int rho, long long N, int K,
+                int max_iter, int* labels, KmResult& out);
+
+// ---- K x K solve (linalg.cpp) ----------------------------------------------
+struct PinvResult {
+    int rank = 0;
+    double cond = 0.0;
+    double max_abs = 0.0;
+};
+// A (K x K, row-major) = phi(mu_k - mu_l) from FP32 centers promoted to FP64.
+void kernel_matrix(const float* centers, int K, int rho, double sigma_r, double* A);
+// Pseudo-inverse of the symmetric A by cyclic Jacobi; rtol <= 0: K * 2^-52.
+PinvResult pinv_symmetric(const double* A, int K, double rtol, double* P);
+
+// ---- filter passes (filter.hip) --------------------------------------------
+struct FilterPlan {
+    int n, rho, H, W, K, S, spatial, contract, coef;
+    float sigma_s, sigma_r;
+    long long N;
+    int Wp;                // row pitch of the intermediate planes (floats)
+    bool materialize;      // B and C planes are computed by a separate pass
+};
+size_t filter_workspace(const FilterPlan& fp);
+void filter_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const float* guide,
+                const float* centers_host, const float* Pfp32_host, const int* labels,
+                float* out, float* den);
+void bruteforce_run(Ctx& c, const FilterPlan& fp, const float* f, const float* guide,
+                    float* out, float* den);
+
+// ---- context ---------------------------------------------------------------
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    // library-owned workspace
+    void* own_ws = nullptr;
+    size_t own_bytes = 0;
+    // caller-owned workspace
+    void* ext_ws = nullptr;
+    size_t ext_bytes = 0;
+    // pinned host staging slots (0: clustering, 1: filter uploads, 2: misc);
+    // each slot's event marks the end of the last copy that read it
+    void* pinned[3] = {nullptr, nullptr, nullptr};
+    size_t pinned_bytes[3] = {0, 0, 0};
+    hipEvent_t pinned_ev[3] = {nullptr, nullptr, nullptr};
+    bool pinned_pending[3] = {false, false, false};
+
+    // stage timing (fhd_timing_enable)
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_rec[FHD_NUM_STAGES];
+    hipEvent_t take_event();
+    // Records the start of `stage` now; returns the event (null when off).
+    hipEvent_t stage_begin();
+    void stage_end(int stage, hipEvent_t begin);
+
+    Arena arena(size_t need);
+    // A pinned buffer of at least `bytes`, safe to overwrite (waits for the
+    // copies enqueued from it before the last stage_done(slot)).
+    void* host_stage(int slot, size_t bytes);
+    void stage_done(int slot);
+    void release();
+};
+
+}  // namespace fhd
+
+struct fhd_ctx {
+    fhd::Ctx impl;
+};

@@ -1,0 +1,865 @@
+// Steps 3-5 of Algorithm 1 (Sec. II-B) on gfx950: range weights and
+// coefficients, the (n+1)K spatial convolutions of eqs. (13)-(14) and the
+// recombination of eqs. (15)-(16), plus the brute-force filter of
+// eqs. (1)-(2).
+//
+// The convolutions run as two passes over (n+1)K FP32 planes:
+//   row pass:    for every cluster l, U_l = g_l * [f, 1] is formed on the fly
+//                from the guide and filtered along x (LDS-staged halo row);
+//                the K(n+1) row-filtered planes are written once;
+//   column pass: reads them once, filters along y, and recombines per pixel
+//                with weight h_l(i), writing g_hat and the normaliser.
+// For least-squares coefficients c = A^+ b the pair (g, h) is (c, b): since
+// A^+ is symmetric, sum_k c_k(i) b_k(i-j) = sum_l b_l(i) c_l(i-j), so the
+// recombination of eqs. (15)-(16) equals sum_l b_l(i) (w * c_l [f,1])(i) and
+// only the cheap b_l(i) is needed where the output is formed.  For the hard
+// assignment of eq. (17) the pair is (b, 1[s(i) = l]) (the form of Alg. 1).
+// The Gaussian window is separable and zero extension commutes with the row
+// pass, so the two 1-D passes equal the 2-D window sum.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "fhd_internal.h"
+
+namespace fhd {
+namespace {
+
+constexpr int RT = 256;       // threads per block
+constexpr int MAXS_T = 32;    // radii with unrolled register-window kernels
+constexpr int R_ROW = 8;      // outputs per thread, row pass
+constexpr int R_COL = 8;      // outputs per thread, column pass
+constexpr int TXC = 64;       // column-pass tile width
+constexpr int TYC = R_COL * (RT / TXC);   // column-pass tile height
+constexpr int CG = 4;         // channels per column-pass group
+constexpr int RHO_INLINE = 8; // guides up to this dimension get inline weights
+
+struct FA {
+    const float* f;
+    const float* p;
+    const float* mu;    // K x rho
+    const float* P;     // K x K, symmetric (least-squares coefficients)
+    const float* Bpl;   // K planes of b, or null (weights computed inline)
+    const float* Cpl;   // K planes of c, or null
+    const int* labels;  // hard assignment
+    float* planes;      // K(n+1) row-filtered planes, pitch Wp, S zero rows above and below
+    float* out;
+    float* den;
+    int n, rho, K, H, W, Wp, S, coef, tx, xcd_groups;
+    long long N, Np;    // pixels; stride of the B / C planes
+    long long Pp;       // stride of the intermediate planes: H + 2S rows of Wp, row y at y + S
+    float inv2s2;       // 1 / (2 sigma_r^2), 0 for sigma_r = inf
+    float w[FHD_MAX_RADIUS + 1];  // 1-D spatial taps w[|j|]
+};
+
+__device__ __forceinline__ int pidx(int i) { return i + (i >> 5); }  // LDS skew vs bank conflicts
+
+// ---------------------------------------------------------------------------
+// Row pass, phase 1: the convolved factor g_l (c_l or b_l) and f on the halo
+// run [x0 - S, x0 + tx + S) of row y, zero outside the image, into LDS.
+//   cs[l * csp + pidx(h)], fs[ch * csp + pidx(h)]; scratch bs[h * (K+1) + m].
+__device__ void row_factors(const FA& a, int y, int x0, int hw, int csp, float* cs, float* fs,
+                            float* bs) {
+    const int K = a.K, rho = a.rho, n = a.n;
+    const long long rowoff = (long long)y * a.W;
+    for (int h = threadIdx.x; h < hw; h += RT) {
+        const int x = x0 - a.S + h;
+        const bool in = x >= 0 && x < a.W;
+        for (int ch = 0; ch < n; ++ch)
+            fs[ch * csp + pidx(h)] = in ? a.f[(long long)ch * a.N + rowoff + x] : 0.0f;
+    }
+    if (a.Bpl != nullptr) {  // weights materialised by the weights pass
+        const float* src = a.coef == FHD_COEF_HARD ? a.Bpl : a.Cpl;
+        const long long prow = (long long)y * a.Wp;
+        for (int t = threadIdx.x; t < hw * K; t += RT) {
+            const int l = t / hw, h = t - l * hw;
+            const int x = x0 - a.S + h;
+            const bool in = x >= 0 && x < a.W;
+            cs[l * csp + pidx(h)] = in ? src[(long long)l * a.Np + prow + x] : 0.0f;
+        }
+        __syncthreads();
+        return;
+    }
+    // b_m(h) = phi(mu_m - p(h)) for the halo pixels
+    for (int h = threadIdx.x; h < hw; h += RT) {
+        const int x = x0 - a.S + h;
+        const bool in = x >= 0 && x < a.W;
+        float pr[RHO_INLINE];
+#pragma unroll
+        for (int r = 0; r < RHO_INLINE; ++r)
+            pr[r] = (in && r < rho) ? a.p[(long long)r * a.N + rowoff + x] : 0.0f;
+        for (int m = 0; m < K; ++m) {
+            float d2 = 0.0f;
+#pragma unroll
+            for (int r = 0; r < RHO_INLINE; ++r) {
+                if (r < rho) {
+                    const float d = pr[r] - a.mu[m * rho + r];
+                    d2 = fmaf(d, d, d2);
+                }
+            }
+            bs[h * (K + 1) + m] = in ? __expf(-d2 * a.inv2s2) : 0.0f;
+        }
+    }
+    __syncthreads();
+    if (a.coef == FHD_COEF_HARD) {
+        for (int t = threadIdx.x; t < hw * K; t += RT) {
+            const int l = t / hw, h = t - l * hw;
+            cs[l * csp + pidx(h)] = bs[h * (K + 1) + l];
+        }
+        __syncthreads();
+        return;
+    }
+    // c(h) = A^+ b(h), eight coefficients per task
+    const int groups = (K + 7) >> 3;
+    for (int t = threadIdx.x; t < hw * groups; t += RT) {
+        const int g = t / hw, h = t - g * hw;
+        float acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = 0.0f;
+        const float* brow = bs + h * (K + 1);
+        for (int m = 0; m < K; ++m) {
+            const float bv = brow[m];
+            const float* prow = a.P + (long long)m * K + g * 8;  // P symmetric: P[l][m] = P[m][l]
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (g * 8 + q < K) acc[q] = fmaf(prow[q], bv, acc[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (g * 8 + q < K) cs[(g * 8 + q) * csp + pidx(h)] = acc[q];
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void store_row(const FA& a, float* dst, int x, const float* o, int R) {
+    // dst points at (plane, row y, column 0)
+    if (x + R <= a.W && (a.Wp & 3) == 0 && (R & 3) == 0) {
+        for (int t = 0; t < R; t += 4)
+            *reinterpret_cast<float4*>(dst + x + t) = make_float4(o[t], o[t + 1], o[t + 2], o[t + 3]);
+    } else {
+        for (int t = 0; t < R; ++t)
+            if (x + t < a.W) dst[x + t] = o[t];
+    }
+}
+
+// Gaussian row pass, radius S known at compile time: each task filters R
+// outputs of one cluster from a register window of R + 2S inputs.
+template <int S>
+__global__ __launch_bounds__(RT) void row_gauss(FA a) {
+    extern __shared__ float lds[];
+    constexpr int R = R_ROW;
+    constexpr int WIN = R + 2 * S;
+    const int y = blockIdx.y;
+    const int x0 = blockIdx.x * a.tx;
+    const int hw = a.tx + 2 * S;
+    const int csp = pidx(hw - 1) + 1;
+    float* cs = lds;
+    float* fs = cs + a.K * csp;
+    float* bs = fs + a.n * csp;
+    row_factors(a, y, x0, hw, csp, cs, fs, bs);
+    const int nseg = a.tx / R;
+    const int n = a.n;
+    for (int task = threadIdx.x; task < a.K * nseg; task += RT) {
+        const int l = task / nseg, seg = task - l * nseg;
+        const int x = x0 + seg * R;
+        if (x >= a.W) continue;
+        float cw[WIN];
+#pragma unroll
+        for (int q = 0; q < WIN; ++q) cw[q] = cs[l * csp + pidx(seg * R + q)];
+        float o[R];
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            float s = a.w[0] * cw[t + S];
+#pragma unroll
+            for (int j = 1; j <= S; ++j) s = fmaf(a.w[j], cw[t + S - j] + cw[t + S + j], s);
+            o[t] = s;
+        }
+        const long long rowp = (long long)(y + S) * a.Wp;
+        float* base = a.planes + (long long)l * (n + 1) * a.Pp + rowp;
+        store_row(a, base + (long long)n * a.Pp, x, o, R);
+        for (int ch = 0; ch < n; ++ch) {
+            float u[WIN];
+#pragma unroll
+            for (int q = 0; q < WIN; ++q) u[q] = cw[q] * fs[ch * csp + pidx(seg * R + q)];
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                float s = a.w[0] * u[t + S];
+#pragma unroll
+                for (int j = 1; j <= S; ++j) s = fmaf(a.w[j], u[t + S - j] + u[t + S + j], s);
+                o[t] = s;
+            }
+            store_row(a, base + (long long)ch * a.Pp, x, o, R);
+        }
+    }
+}
+
+// Row pass for any radius: box kernel as a running sum, Gaussian tap by tap.
+template <bool BOX>
+__global__ __launch_bounds__(RT) void row_generic(FA a) {
+    extern __shared__ float lds[];
+    constexpr int R = 16;
+    const int S = a.S;
+    const int y = blockIdx.y;
+    const int x0 = blockIdx.x * a.tx;
+    const int hw = a.tx + 2 * S;
+    const int csp = pidx(hw - 1) + 1;
+    float* cs = lds;
+    float* fs = cs + a.K * csp;
+    float* bs = fs + a.n * csp;
+    row_factors(a, y, x0, hw, csp, cs, fs, bs);
+    const int nseg = a.tx / R;
+    const int n = a.n;
+    for (int task = threadIdx.x; task < a.K * nseg * (n + 1); task += RT) {
+        const int ch = task % (n + 1);
+        const int rest = task / (n + 1);
+        const int l = rest / nseg, seg = rest - l * nseg;
+        const int x = x0 + seg * R;
+        if (x >= a.W) continue;
+        const float* cl = cs + l * csp;
+        const float* fc = fs + (ch < n ? ch : 0) * csp;
+        auto U = [&](int h) { return ch < n ? cl[pidx(h)] * fc[pidx(h)] : cl[pidx(h)]; };
+        float o[R];
+        const int h0 = seg * R;  // halo index of the window start for output x
+        if (BOX) {
+            float s = 0.0f;
+            for (int q = 0; q <= 2 * S; ++q) s += U(h0 + q);
+            o[0] = s;
+#pragma unroll
+            for (int t = 1; t < R; ++t) {
+                s += U(h0 + t + 2 * S) - U(h0 + t - 1);
+                o[t] = s;
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                float s = a.w[0] * U(h0 + t + S);
+                for (int j = 1; j <= S; ++j) s = fmaf(a.w[j], U(h0 + t + S - j) + U(h0 + t + S + j), s);
+                o[t] = s;
+            }
+        }
+        float* dst = a.planes + ((long long)l * (n + 1) + ch) * a.Pp + (long long)(y + S) * a.Wp;
+        store_row(a, dst, x, o, R);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Column pass with the recombination of eqs. (15)-(16) fused in.
+
+struct ColTile {
+    int x, y0, bx0, by0;
+    bool block_active;  // the block maps to a tile
+    bool active;        // this thread's column is inside the image
+};
+
+__device__ __forceinline__ ColTile col_tile(const FA& a, int ty) {
+    // XCD-aware order: consecutive blocks on one XCD take vertically adjacent
+    // tiles, so the S-row halos they share stay in that XCD's L2.
+    const int gx = (a.W + TXC - 1) / TXC, gy = (a.H + ty - 1) / ty;
+    const int total = gx * gy;
+    const int per = a.xcd_groups;  // blocks per XCD
+    const int b = blockIdx.x;
+    const int t = (b & 7) * per + (b >> 3);
+    ColTile c;
+    c.block_active = t < total;
+    const int bx = t / gy, by = t - bx * gy;
+    c.bx0 = bx * TXC;
+    c.by0 = by * ty;
+    c.x = c.bx0 + (threadIdx.x & (TXC - 1));
+    c.y0 = c.by0 + (threadIdx.x / TXC) * (ty / (RT / TXC));
+    c.active = c.block_active && c.x < a.W;
+    return c;
+}
+
+// Guide values of the tile's pixels (inline weights only): sp[r][row][col].
+__device__ __forceinline__ void col_stage_guide(const FA& a, int bx0, int by0, int ty, float* sp) {
+    if (a.Bpl != nullptr || a.coef == FHD_COEF_HARD) return;
+    const int cnt = a.rho * ty * TXC;
+    for (int t = threadIdx.x; t < cnt; t += RT) {
+        const int r = t / (ty * TXC), rem = t - r * ty * TXC;
+        const int yy = by0 + rem / TXC, xx = bx0 + (rem & (TXC - 1));
+        sp[t] = (yy < a.H && xx < a.W) ? a.p[(long long)r * a.N + (long long)yy * a.W + xx] : 0.0f;
+    }
+}
+
+// Recombination weight h_l of the R outputs of a thread: b_l(i) for the
+// least-squares coefficients, the cluster indicator for the hard variant.
+// Weight modes of the column pass.
+enum { WM_INLINE = 0, WM_PLANES = 1, WM_HARD = 2 };
+
+template <int R, int MODE>
+__device__ __forceinline__ void recomb_weights(const FA& a, int l, int x, int y0, int ly0, int lx, int ty,
+                                               const float* sp, const int (&lab)[R], float (&hl)[R]) {
+    if (MODE == WM_HARD) {
+#pragma unroll
+        for (int t = 0; t < R; ++t) hl[t] = lab[t] == l ? 1.0f : 0.0f;
+    } else if (MODE == WM_PLANES) {
+        const float* bp = a.Bpl + (long long)l * a.Np + (long long)y0 * a.Wp + x;
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            hl[t] = (y0 + t < a.H && x < a.W) ? *bp : 0.0f;
+            bp += a.Wp;
+        }
+    } else {
+        float d2[R];
+#pragma unroll
+        for (int t = 0; t < R; ++t) d2[t] = 0.0f;
+        for (int r = 0; r < a.rho; ++r) {
+            const float m = a.mu[l * a.rho + r];
+            const float* row = sp + (r * ty + ly0) * TXC + lx;
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                const float d = row[t * TXC] - m;
+                d2[t] = fmaf(d, d, d2[t]);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < R; ++t) hl[t] = __expf(-d2[t] * a.inv2s2);
+    }
+}
+
+template <int R, int MODE>
+__device__ __forceinline__ void col_load_labels(const FA& a, int x, int y0, int (&lab)[R]) {
+#pragma unroll
+    for (int t = 0; t < R; ++t)
+        lab[t] = (MODE == WM_HARD && y0 + t < a.H && x < a.W) ? a.labels[(long long)(y0 + t) * a.W + x] : -1;
+}
+
+template <int R>
+__device__ __forceinline__ void col_finish(const FA& a, int x, int y0, int g, const float (&acc)[CG][R],
+                                           float (&dv)[R]) {
+    const int n = a.n;
+    if (g == 0) {
+#pragma unroll
+        for (int t = 0; t < R; ++t) dv[t] = 1.0f / acc[0][t];
+        if (a.den != nullptr) {
+            float* dp = a.den + (long long)y0 * a.W + x;
+            for (int t = 0; t < R && y0 + t < a.H; ++t) {
+                *dp = acc[0][t];
+                dp += a.W;
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < CG; ++c) {
+        const int gi = g * CG + c;
+        if (gi > n) break;
+        if (gi == 0) continue;
+        float* op = a.out + (long long)(gi - 1) * a.N + (long long)y0 * a.W + x;
+        for (int t = 0; t < R && y0 + t < a.H; ++t) {
+            *op = acc[c][t] * dv[t];
+            op += a.W;
+        }
+    }
+}
+
+// Column pass.  A block owns a tile of TXC columns x ty rows; for every
+// plane (cluster l, channel) in turn it stages the tile's rows plus the 2S
+// halo rows in LDS (double-buffered: the next plane's rows are in flight from
+// global memory while the current one is filtered), and every thread filters
+// R consecutive rows of one column from a register window.
+__device__ __forceinline__ int plane_index(int n, int g, int l, int c) {
+    const int gi = g * CG + c;
+    return l * (n + 1) + (gi == 0 ? n : gi - 1);
+}
+
+// successor of (g, l, c) in the visiting order; false at the end
+__device__ __forceinline__ bool plane_next(int n, int K, int& g, int& l, int& c) {
+    const int groups = (n + 1 + CG - 1) / CG;
+    ++c;
+    if (c < CG && g * CG + c <= n) return true;
+    c = 0;
+    if (++l < K) return true;
+    l = 0;
+    return ++g < groups;
+}
+
+template <int S, int MODE>
+__global__ __launch_bounds__(RT) void col_gauss(FA a) {
+    constexpr int R = R_COL;
+    constexpr int TY = TYC;
+    constexpr int ROWS = TY + 2 * S;
+    constexpr int PER = (ROWS * TXC + RT - 1) / RT;  // staged values per thread and plane
+    constexpr int WIN = R + 2 * S;
+    __shared__ float tbuf[2][PER * RT];
+    extern __shared__ float sp[];
+    const ColTile tile = col_tile(a, TY);
+    if (!tile.block_active) return;
+    if (MODE == WM_INLINE) col_stage_guide(a, tile.bx0, tile.by0, TY, sp);
+    const int n = a.n, K = a.K;
+    const int lx = threadIdx.x & (TXC - 1), tr = threadIdx.x / TXC;
+    const int x = tile.x, y0 = tile.y0;
+    const int ly0 = tr * R;
+    // staging: thread loads rows tr, tr+4, ... of the tile at column lx
+    const long long tile_off = (long long)tile.by0 * a.Wp + tile.bx0 + tr * (long long)a.Wp + lx;
+    const long long step = (long long)(RT / TXC) * a.Wp;
+    auto fetch = [&](int plane, float (&pre)[PER]) {
+        const float* src = a.planes + (long long)plane * a.Pp + tile_off;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            pre[k] = (tr + k * (RT / TXC) < ROWS) ? *src : 0.0f;
+            src += step;
+        }
+    };
+    auto stash = [&](float* dst, const float (&pre)[PER]) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) dst[k * RT + threadIdx.x] = pre[k];
+    };
+    int lab[R];
+    col_load_labels<R, MODE>(a, x, y0, lab);
+    float pre[PER];
+    fetch(plane_index(n, 0, 0, 0), pre);
+    stash(tbuf[0], pre);
+    __syncthreads();
+    int buf = 0;
+    const int groups = (n + 1 + CG - 1) / CG;
+    float dv[R];
+    for (int g = 0; g < groups; ++g) {
+        float acc[CG][R];
+#pragma unroll
+        for (int c = 0; c < CG; ++c)
+#pragma unroll
+            for (int t = 0; t < R; ++t) acc[c][t] = 0.0f;
+        for (int l = 0; l < K; ++l) {
+            float hl[R];
+            recomb_weights<R, MODE>(a, l, x, y0, ly0, lx, TY, sp, lab, hl);
+#pragma unroll
+            for (int c = 0; c < CG; ++c) {
+                if (g * CG + c > n) break;
+                int ng = g, nl = l, nc = c;
+                const bool more = plane_next(n, K, ng, nl, nc);
+                if (more) fetch(plane_index(n, ng, nl, nc), pre);
+                // filter the staged plane: tile row ly0 + q holds image row y0 - S + q
+                const float* col = tbuf[buf] + ly0 * TXC + lx;
+                float win[WIN];
+#pragma unroll
+                for (int q = 0; q < WIN; ++q) win[q] = col[q * TXC];
+#pragma unroll
+                for (int t = 0; t < R; ++t) {
+                    float s = a.w[0] * win[t + S];
+#pragma unroll
+                    for (int j = 1; j <= S; ++j) s = fmaf(a.w[j], win[t + S - j] + win[t + S + j], s);
+                    acc[c][t] = fmaf(hl[t], s, acc[c][t]);
+                }
+                if (more) stash(tbuf[buf ^ 1], pre);
+                __syncthreads();
+                buf ^= 1;
+            }
+        }
+        if (tile.active) col_finish<R>(a, x, y0, g, acc, dv);
+    }
+}
+
+// Column pass for any radius (box as a running sum, Gaussian tap by tap),
+// single-buffered tile in dynamic LDS after the guide tile.
+template <bool BOX, int MODE>
+__global__ __launch_bounds__(RT) void col_generic(FA a) {
+    constexpr int R = 16;
+    constexpr int TY = R * (RT / TXC);
+    extern __shared__ float sp[];
+    const ColTile tile = col_tile(a, TY);
+    if (!tile.block_active) return;
+    if (MODE == WM_INLINE) col_stage_guide(a, tile.bx0, tile.by0, TY, sp);
+    float* tb = sp + (MODE == WM_INLINE ? a.rho * TY * TXC : 0);
+    const int n = a.n, K = a.K, S = a.S;
+    const int rows = TY + 2 * S;
+    const int lx = threadIdx.x & (TXC - 1), tr = threadIdx.x / TXC;
+    const int x = tile.x, y0 = tile.y0;
+    const int ly0 = tr * R;
+    int lab[R];
+    col_load_labels<R, MODE>(a, x, y0, lab);
+    const int groups = (n + 1 + CG - 1) / CG;
+    float dv[R];
+    for (int g = 0; g < groups; ++g) {
+        float acc[CG][R];
+#pragma unroll
+        for (int c = 0; c < CG; ++c)
+#pragma unroll
+            for (int t = 0; t < R; ++t) acc[c][t] = 0.0f;
+        for (int l = 0; l < K; ++l) {
+            float hl[R];
+            recomb_weights<R, MODE>(a, l, x, y0, ly0, lx, TY, sp, lab, hl);
+#pragma unroll
+            for (int c = 0; c < CG; ++c) {
+                if (g * CG + c > n) break;
+                const int plane = plane_index(n, g, l, c);
+                __syncthreads();  // previous plane fully consumed
+                const float* src = a.planes + (long long)plane * a.Pp + (long long)tile.by0 * a.Wp + tile.bx0;
+                for (int e = threadIdx.x; e < rows * TXC; e += RT)
+                    tb[e] = src[(long long)(e / TXC) * a.Wp + (e & (TXC - 1))];
+                __syncthreads();
+                const float* col = tb + ly0 * TXC + lx;  // tile row ly0 + q = image row y0 - S + q
+                if (BOX) {
+                    float s = 0.0f;
+                    for (int q = 0; q <= 2 * S; ++q) s += col[q * TXC];
+                    acc[c][0] = fmaf(hl[0], s, acc[c][0]);
+#pragma unroll
+                    for (int t = 1; t < R; ++t) {
+                        s += col[(t + 2 * S) * TXC] - col[(t - 1) * TXC];
+                        acc[c][t] = fmaf(hl[t], s, acc[c][t]);
+                    }
+                } else {
+#pragma unroll
+                    for (int t = 0; t < R; ++t) {
+                        float s = a.w[0] * col[(t + S) * TXC];
+                        for (int j = 1; j <= S; ++j)
+                            s = fmaf(a.w[j], col[(t + S - j) * TXC] + col[(t + S + j) * TXC], s);
+                        acc[c][t] = fmaf(hl[t], s, acc[c][t]);
+                    }
+                }
+            }
+        }
+        if (tile.active) col_finish<R>(a, x, y0, g, acc, dv);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Weights pass (guides with more than RHO_INLINE dimensions): B and C planes.
+// One block per run of `tx` pixels of a row; distances accumulated over
+// eight-dimension chunks of the guide.
+__global__ __launch_bounds__(RT) void weights_fp32(FA a, float* Bpl, float* Cpl) {
+    extern __shared__ float lds[];
+    const int K = a.K, rho = a.rho;
+    const int y = blockIdx.y, x0 = blockIdx.x * a.tx;
+    const int hw = a.tx;
+    float* bs = lds;  // hw x (K+1)
+    const long long rowoff = (long long)y * a.W;
+    for (int h = threadIdx.x; h < hw; h += RT)
+        for (int m = 0; m < K; ++m) bs[h * (K + 1) + m] = 0.0f;
+    for (int r0 = 0; r0 < rho; r0 += 8) {
+        for (int h = threadIdx.x; h < hw; h += RT) {
+            const int x = x0 + h;
+            const bool in = x < a.W;
+            float pr[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r)
+                pr[r] = (in && r0 + r < rho) ? a.p[(long long)(r0 + r) * a.N + rowoff + x] : 0.0f;
+            for (int m = 0; m < K; ++m) {
+                float d2 = bs[h * (K + 1) + m];
+#pragma unroll
+                for (int r = 0; r < 8; ++r)
+                    if (r0 + r < rho) {
+                        const float d = pr[r] - a.mu[m * rho + r0 + r];
+                        d2 = fmaf(d, d, d2);
+                    }
+                bs[h * (K + 1) + m] = d2;
+            }
+        }
+    }
+    for (int h = threadIdx.x; h < hw; h += RT)
+        for (int m = 0; m < K; ++m) bs[h * (K + 1) + m] = __expf(-bs[h * (K + 1) + m] * a.inv2s2);
+    __syncthreads();
+    const long long prow = (long long)y * a.Wp;
+    for (int t = threadIdx.x; t < hw * K; t += RT) {
+        const int l = t / hw, h = t - l * hw;
+        if (x0 + h < a.W) Bpl[(long long)l * a.Np + prow + x0 + h] = bs[h * (K + 1) + l];
+    }
+    if (Cpl == nullptr) return;
+    const int groups = (K + 7) >> 3;
+    for (int t = threadIdx.x; t < hw * groups; t += RT) {
+        const int g = t / hw, h = t - g * hw;
+        if (x0 + h >= a.W) continue;
+        float acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = 0.0f;
+        const float* brow = bs + h * (K + 1);
+        for (int m = 0; m < K; ++m) {
+            const float bv = brow[m];
+            const float* prow2 = a.P + (long long)m * K + g * 8;
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (g * 8 + q < K) acc[q] = fmaf(prow2[q], bv, acc[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (g * 8 + q < K) Cpl[(long long)(g * 8 + q) * a.Np + prow + x0 + h] = acc[q];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Brute force, eqs. (1)-(2): one thread per output pixel, window read from a
+// 16 x 16-output LDS tile with halo when it fits, else from global memory.
+__global__ __launch_bounds__(RT) void brute_lds(FA a) {
+    extern __shared__ float lds[];
+    const int S = a.S, n = a.n, rho = a.rho;
+    const int T = 16, L = T + 2 * S;
+    const int bx = blockIdx.x * T, by = blockIdx.y * T;
+    const int C = rho + n;
+    for (int t = threadIdx.x; t < L * L; t += RT) {
+        const int yy = by - S + t / L, xx = bx - S + t % L;
+        const bool in = yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
+        const long long off = (long long)yy * a.W + xx;
+        for (int c = 0; c < rho; ++c) lds[c * L * L + t] = in ? a.p[(long long)c * a.N + off] : 0.0f;
+        for (int c = 0; c < n; ++c) lds[(rho + c) * L * L + t] = in ? a.f[(long long)c * a.N + off] : 0.0f;
+        if (!in) lds[C * L * L + t] = 0.0f; else lds[C * L * L + t] = 1.0f;
+    }
+    __syncthreads();
+    const int ly = threadIdx.x / T, lx = threadIdx.x % T;
+    const int y = by + ly, x = bx + lx;
+    if (y >= a.H || x >= a.W) return;
+    const int ci = (ly + S) * L + (lx + S);
+    float pc[FHD_MAX_RHO > 16 ? 16 : FHD_MAX_RHO];
+    for (int c = 0; c < rho && c < 16; ++c) pc[c] = lds[c * L * L + ci];
+    float num[16];
+    for (int c = 0; c < 16; ++c) num[c] = 0.0f;
+    float eta = 0.0f;
+    for (int jy = -S; jy <= S; ++jy) {
+        const float wy = a.w[jy < 0 ? -jy : jy];
+        const int rowi = (ly + S - jy) * L;
+        for (int jx = -S; jx <= S; ++jx) {
+            const int q = rowi + (lx + S - jx);
+            const float inside = lds[C * L * L + q];
+            float d2 = 0.0f;
+            for (int c = 0; c < rho; ++c) {
+                const float d = lds[c * L * L + q] - pc[c];
+                d2 = fmaf(d, d, d2);
+            }
+            const float wgt = inside * wy * a.w[jx < 0 ? -jx : jx] * __expf(-d2 * a.inv2s2);
+            for (int c = 0; c < n; ++c) num[c] = fmaf(wgt, lds[(rho + c) * L * L + q], num[c]);
+            eta += wgt;
+        }
+    }
+    const long long off = (long long)y * a.W + x;
+    for (int c = 0; c < n; ++c) a.out[(long long)c * a.N + off] = num[c] / eta;
+    if (a.den) a.den[off] = eta;
+}
+
+__global__ __launch_bounds__(RT) void brute_global(FA a) {
+    const int x = blockIdx.x * 16 + (threadIdx.x & 15);
+    const int y = blockIdx.y * 16 + (threadIdx.x >> 4);
+    if (x >= a.W || y >= a.H) return;
+    const int S = a.S, n = a.n, rho = a.rho;
+    const long long i = (long long)y * a.W + x;
+    float eta = 0.0f;
+    for (int c = 0; c < n; ++c) a.out[(long long)c * a.N + i] = 0.0f;
+    for (int jy = -S; jy <= S; ++jy) {
+        const int yy = y - jy;
+        if (yy < 0 || yy >= a.H) continue;
+        const float wy = a.w[jy < 0 ? -jy : jy];
+        for (int jx = -S; jx <= S; ++jx) {
+            const int xx = x - jx;
+            if (xx < 0 || xx >= a.W) continue;
+            const long long q = (long long)yy * a.W + xx;
+            float d2 = 0.0f;
+            for (int c = 0; c < rho; ++c) {
+                const float d = a.p[(long long)c * a.N + q] - a.p[(long long)c * a.N + i];
+                d2 = fmaf(d, d, d2);
+            }
+            const float wgt = wy * a.w[jx < 0 ? -jx : jx] * __expf(-d2 * a.inv2s2);
+            for (int c = 0; c < n; ++c) a.out[(long long)c * a.N + i] += wgt * a.f[(long long)c * a.N + q];
+            eta += wgt;
+        }
+    }
+    for (int c = 0; c < n; ++c) a.out[(long long)c * a.N + i] /= eta;
+    if (a.den) a.den[i] = eta;
+}
+
+// ---------------------------------------------------------------------------
+// dispatch tables for the unrolled radii
+
+using KernFn = void (*)(FA);
+
+template <int S>
+struct Tables {
+    static void fill(KernFn* row, KernFn (*col)[3]) {
+        row[S] = row_gauss<S>;
+        col[S][WM_INLINE] = col_gauss<S, WM_INLINE>;
+        col[S][WM_PLANES] = col_gauss<S, WM_PLANES>;
+        col[S][WM_HARD] = col_gauss<S, WM_HARD>;
+        Tables<S - 1>::fill(row, col);
+    }
+};
+template <>
+struct Tables<0> {
+    static void fill(KernFn*, KernFn (*)[3]) {}
+};
+
+struct Dispatch {
+    KernFn row[MAXS_T + 1];
+    KernFn col[MAXS_T + 1][3];
+    Dispatch() {
+        row[0] = nullptr;
+        col[0][0] = col[0][1] = col[0][2] = nullptr;
+        Tables<MAXS_T>::fill(row, col);
+    }
+};
+
+const Dispatch& dispatch() {
+    static Dispatch d;
+    return d;
+}
+
+FA make_args(const FilterPlan& fp) {
+    FA a;
+    std::memset(&a, 0, sizeof(a));
+    a.n = fp.n;
+    a.rho = fp.rho;
+    a.K = fp.K;
+    a.H = fp.H;
+    a.W = fp.W;
+    a.Wp = fp.Wp;
+    a.S = fp.S;
+    a.coef = fp.coef;
+    a.N = fp.N;
+    a.Np = (long long)fp.H * fp.Wp;
+    a.Pp = (long long)(fp.H + 2 * fp.S) * fp.Wp;
+    a.inv2s2 = std::isinf(fp.sigma_r) ? 0.0f : (float)(1.0 / (2.0 * (double)fp.sigma_r * fp.sigma_r));
+    for (int j = 0; j <= fp.S; ++j)
+        a.w[j] = fp.spatial == FHD_SPATIAL_BOX
+                     ? 1.0f
+                     : (float)std::exp(-(double)j * j / (2.0 * (double)fp.sigma_s * fp.sigma_s));
+    return a;
+}
+
+// Intermediate planes: K(n+1) planes of (H + 2S) x Wp, plus slack rows read
+// (and discarded) by the last column tile.
+size_t plane_floats(const FilterPlan& fp) {
+    const size_t Pp = (size_t)(fp.H + 2 * fp.S) * fp.Wp;
+    return (size_t)fp.K * (fp.n + 1) * Pp + (size_t)64 * fp.Wp + 64;
+}
+
+int row_tx(int K) { return K <= 32 ? 256 : (K <= 64 ? 128 : 64); }
+
+size_t row_lds_bytes(const FilterPlan& fp, int tx) {
+    const int hw = tx + 2 * fp.S;
+    const int csp = hw + ((hw - 1) >> 5) + 1;
+    size_t fl = (size_t)fp.K * csp + (size_t)fp.n * csp;
+    if (!fp.materialize) fl += (size_t)hw * (fp.K + 1);
+    return fl * sizeof(float);
+}
+
+}  // namespace
+
+size_t filter_workspace(const FilterPlan& fp) {
+    Arena probe;
+    const long long Np = (long long)fp.H * fp.Wp;
+    probe.take<float>(plane_floats(fp));
+    if (fp.materialize) {
+        probe.take<float>((size_t)fp.K * Np);
+        probe.take<float>((size_t)fp.K * Np);
+    }
+    probe.take<float>((size_t)fp.K * fp.rho);
+    probe.take<float>((size_t)fp.K * fp.K);
+    return probe.used;
+}
+
+void filter_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const float* guide,
+                const float* centers_host, const float* Pfp32_host, const int* labels, float* out,
+                float* den) {
+    const long long Np = (long long)fp.H * fp.Wp;
+    float* planes = ws.take<float>(plane_floats(fp));
+    float* Bpl = nullptr;
+    float* Cpl = nullptr;
+    if (fp.materialize) {
+        Bpl = ws.take<float>((size_t)fp.K * Np);
+        Cpl = ws.take<float>((size_t)fp.K * Np);
+    }
+    float* mu = ws.take<float>((size_t)fp.K * fp.rho);
+    float* P = ws.take<float>((size_t)fp.K * fp.K);
+    hipStream_t st = c.stream;
+    // stage centers and A^+ through pinned memory (async, stream ordered)
+    const size_t kb = sizeof(float) * fp.K * fp.rho, pb = sizeof(float) * fp.K * fp.K;
+    char* hs = static_cast<char*>(c.host_stage(1, align_up(kb, 256) + pb));
+    std::memcpy(hs, centers_host, kb);
+    std::memcpy(hs + align_up(kb, 256), Pfp32_host, pb);
+    FHD_HIP(hipMemcpyAsync(mu, hs, kb, hipMemcpyHostToDevice, st));
+    FHD_HIP(hipMemcpyAsync(P, hs + align_up(kb, 256), pb, hipMemcpyHostToDevice, st));
+    c.stage_done(1);
+
+    FA a = make_args(fp);
+    a.f = f;
+    a.p = guide;
+    a.mu = mu;
+    a.P = P;
+    a.labels = labels;
+    a.planes = planes;
+    a.out = out;
+    a.den = den;
+
+    if (fp.materialize) {
+        const int tx = 128;
+        a.tx = tx;
+        const size_t lds = sizeof(float) * (size_t)tx * (fp.K + 1);
+        FHD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(weights_fp32),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipEvent_t tw = c.stage_begin();
+        hipLaunchKernelGGL(weights_fp32, dim3((fp.W + tx - 1) / tx, fp.H), dim3(RT), lds, st, a, Bpl,
+                           fp.coef == FHD_COEF_HARD ? nullptr : Cpl);
+        c.stage_end(FHD_STAGE_WEIGHTS, tw);
+        FHD_HIP(hipGetLastError());
+        a.Bpl = Bpl;
+        a.Cpl = Cpl;
+    }
+
+    // the S zero rows above and below every intermediate plane
+    if (fp.S > 0) {
+        const size_t pitch = sizeof(float) * (size_t)(fp.H + 2 * fp.S) * fp.Wp;
+        const size_t width = sizeof(float) * (size_t)fp.S * fp.Wp;
+        const size_t planes_n = (size_t)fp.K * (fp.n + 1);
+        FHD_HIP(hipMemset2DAsync(planes, pitch, 0, width, planes_n, st));
+        FHD_HIP(hipMemset2DAsync(planes + (size_t)(fp.H + fp.S) * fp.Wp, pitch, 0, width, planes_n, st));
+    }
+
+    // row pass
+    const bool box = fp.spatial == FHD_SPATIAL_BOX;
+    const bool unrolled = !box && fp.S >= 1 && fp.S <= MAXS_T;
+    int tx = row_tx(fp.K);
+    size_t lds = row_lds_bytes(fp, tx);
+    while (lds > 150 * 1024 && tx > 16) {
+        tx /= 2;
+        lds = row_lds_bytes(fp, tx);
+    }
+    FHD_REQUIRE(lds <= 160 * 1024, FHD_EUNSUPPORTED, "row pass does not fit in LDS");
+    a.tx = tx;
+    const dim3 rg((fp.W + tx - 1) / tx, fp.H);
+    KernFn rowk = unrolled ? dispatch().row[fp.S] : (box ? row_generic<true> : row_generic<false>);
+    FHD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(rowk),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipEvent_t tr = c.stage_begin();
+    hipLaunchKernelGGL(rowk, rg, dim3(RT), lds, st, a);
+    c.stage_end(FHD_STAGE_ROW, tr);
+    FHD_HIP(hipGetLastError());
+
+    // column pass + recombination
+    const int ty = unrolled ? TYC : 16 * (RT / TXC);
+    const int gx = (fp.W + TXC - 1) / TXC, gy = (fp.H + ty - 1) / ty;
+    const int total = gx * gy;
+    const int per = (total + 7) / 8;
+    a.xcd_groups = per;
+    const dim3 cg(per * 8);
+    size_t clds = (fp.materialize || fp.coef == FHD_COEF_HARD) ? 0 : sizeof(float) * fp.rho * ty * TXC;
+    if (!unrolled) clds += sizeof(float) * (size_t)(ty + 2 * fp.S) * TXC;
+    const int mode = fp.coef == FHD_COEF_HARD ? WM_HARD : (fp.materialize ? WM_PLANES : WM_INLINE);
+    static const KernFn gen[2][3] = {
+        {col_generic<false, WM_INLINE>, col_generic<false, WM_PLANES>, col_generic<false, WM_HARD>},
+        {col_generic<true, WM_INLINE>, col_generic<true, WM_PLANES>, col_generic<true, WM_HARD>}};
+    KernFn colk = unrolled ? dispatch().col[fp.S][mode] : gen[box ? 1 : 0][mode];
+    FHD_REQUIRE(clds <= 150 * 1024, FHD_EUNSUPPORTED, "column pass does not fit in LDS");
+    FHD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(colk),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)clds));
+    hipEvent_t tc = c.stage_begin();
+    hipLaunchKernelGGL(colk, cg, dim3(RT), clds, st, a);
+    c.stage_end(FHD_STAGE_COL, tc);
+    FHD_HIP(hipGetLastError());
+}
+
+void bruteforce_run(Ctx& c, const FilterPlan& fp, const float* f, const float* guide, float* out,
+                    float* den) {
+    FA a = make_args(fp);
+    a.f = f;
+    a.p = guide;
+    a.out = out;
+    a.den = den;
+    const int L = 16 + 2 * fp.S;
+    const size_t lds = sizeof(float) * (size_t)L * L * (fp.rho + fp.n + 1);
+    const dim3 g((fp.W + 15) / 16, (fp.H + 15) / 16);
+    hipEvent_t tb = c.stage_begin();
+    if (lds <= 64 * 1024 && fp.rho <= 16 && fp.n <= 16) {
+        hipLaunchKernelGGL(brute_lds, g, dim3(RT), lds, c.stream, a);
+    } else {
+        hipLaunchKernelGGL(brute_global, g, dim3(RT), 0, c.stream, a);
+    }
+    c.stage_end(FHD_STAGE_BRUTE, tb);
+    FHD_HIP(hipGetLastError());
+}
+
+}  // namespace fhd

@@ -1,0 +1,97 @@
+"""The C ABI library on the CPU: it loads, exports every entry point that
+include/fhd.h declares, validates arguments, and its host-side K x K solve
+(eq. (12)) matches the oracle's pseudo-inverse.  No GPU is used."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1811_02363_amd as fhd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "fhd.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fhd_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = fhd.load()
+    declared = _declared()
+    assert len(declared) >= 10
+    for name in declared:
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", fhd.lib_path], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\b(fhd_[a-z_0-9]+)\b", out))
+    assert set(declared) <= exported
+    assert sorted(declared) == sorted(fhd.symbols)
+
+
+def test_default_params():
+    p = fhd.make_params()
+    assert p.radius == -1 and p.K == 16 and p.kmeans_max_iter == 20 and p.contract == 0
+
+
+def test_workspace_size_validation():
+    lib = fhd.load()
+    n = ctypes.c_size_t()
+    p = fhd.make_params(sigma_s=5.0, sigma_r=0.12, K=32)
+    assert lib.fhd_workspace_size(ctypes.byref(p), 3, 3, 2048, 2048, ctypes.byref(n)) == 0
+    # K(n+1) planes of (H + 2S) x W floats dominate
+    assert n.value >= 32 * 4 * (2048 + 30) * 2048 * 4
+    bad = [dict(K=0), dict(K=200), dict(sigma_r=0.0), dict(sigma_r=float("nan")),
+           dict(sigma_s=0.0)]
+    for kw in bad:
+        args = dict(sigma_s=3.0, sigma_r=0.1, K=8)
+        args.update(kw)
+        q = fhd.make_params(**args)
+        assert lib.fhd_workspace_size(ctypes.byref(q), 3, 3, 64, 64, ctypes.byref(n)) == fhd.FHD_EINVAL
+    q = fhd.make_params(K=8, spatial="box")          # box without a radius
+    assert lib.fhd_workspace_size(ctypes.byref(q), 3, 3, 64, 64, ctypes.byref(n)) == fhd.FHD_EINVAL
+    q = fhd.make_params(K=8)
+    assert lib.fhd_workspace_size(ctypes.byref(q), 3, 65, 64, 64, ctypes.byref(n)) == fhd.FHD_EUNSUPPORTED
+    assert lib.fhd_workspace_size(ctypes.byref(q), 0, 3, 64, 64, ctypes.byref(n)) == fhd.FHD_EINVAL
+    q = fhd.make_params(K=8, sigma_s=100.0)          # S = 300 > FHD_MAX_RADIUS
+    assert lib.fhd_workspace_size(ctypes.byref(q), 3, 3, 64, 64, ctypes.byref(n)) == fhd.FHD_EUNSUPPORTED
+    q = fhd.make_params(K=8, sigma_r=float("inf"))   # phi == 1 is allowed
+    assert lib.fhd_workspace_size(ctypes.byref(q), 3, 3, 64, 64, ctypes.byref(n)) == 0
+
+
+@pytest.mark.parametrize("K,sr", [(1, 0.1), (7, 0.1), (32, 0.12), (64, 0.2), (16, float("inf"))])
+def test_pinv_matches_oracle(K, sr):
+    rng = np.random.default_rng(K)
+    rho = 3 if K != 64 else 32
+    mu = rng.uniform(size=(K, rho)).astype(np.float32)
+    A, P, rank, cond = fhd.pinv(mu, sr)
+    A_ref = oracle.kernel_matrix(mu.astype(np.float64), sr)
+    P_ref, rank_ref, s = oracle.pinv(A_ref)
+    assert rank == rank_ref
+    assert np.abs(A.numpy() - A_ref).max() < 1e-15
+    scale = max(1.0, np.abs(P_ref).max())
+    assert np.abs(P.numpy() - P_ref).max() < 1e-9 * scale * max(1.0, s[0] / s[rank_ref - 1])
+
+
+def test_pinv_duplicate_centers_rank():
+    mu = np.array([[0.1, 0.2, 0.3], [0.1, 0.2, 0.3], [0.5, 0.5, 0.5], [0.9, 0.1, 0.4]], np.float32)
+    A, P, rank, cond = fhd.pinv(mu, 0.2)
+    assert rank == 3
+    A = A.numpy()
+    P = P.numpy()
+    assert np.abs(A @ P @ A - A).max() < 1e-12
+    assert np.abs(P @ A @ P - P).max() < 1e-12
+
+
+def test_filter_without_gpu_fails_loudly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    x = torch.zeros(3, 8, 8)
+    with pytest.raises(fhd.FHDError):
+        fhd.filter(x, sigma_s=1.0, sigma_r=0.1, K=2)
