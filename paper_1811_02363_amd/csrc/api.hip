@@ -172,7 +172,7 @@ FilterPlan make_plan(const fhd_params& p, int n, int rho, int H, int W, int K) {
     fp.sigma_r = p.sigma_r;
     fp.N = (long long)H * W;
     fp.Wp = (int)align_up((size_t)W, 4);
-    fp.materialize = rho > 8 || p.contract != FHD_CONTRACT_FP32;
+    fp.materialize = rho > 8 || K > 32 || p.contract != FHD_CONTRACT_FP32;
     return fp;
 }
 

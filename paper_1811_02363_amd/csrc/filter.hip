@@ -56,10 +56,15 @@ __device__ __forceinline__ int pidx(int i) { return i + (i >> 5); }  // LDS skew
 
 // ---------------------------------------------------------------------------
 // Row pass, phase 1: the convolved factor g_l (c_l or b_l) and f on the halo
-// run [x0 - S, x0 + tx + S) of row y, zero outside the image, into LDS.
-//   cs[l * csp + pidx(h)], fs[ch * csp + pidx(h)]; scratch bs[h * (K+1) + m].
+// run [x0 - S, x0 + tx + S) of row y, zero outside the image, into LDS:
+//   cs[l * csp + pidx(h)], fs[ch * csp + pidx(h)].
+// Inline weights (rho <= RHO_INLINE, K <= KMAX_INLINE): one thread per halo
+// pixel computes b_m = phi(mu_m - p) for every center and accumulates
+// c = A^+ b in registers (A^+ read from LDS as broadcasts).
+constexpr int KMAX_INLINE = 32;
+
 __device__ void row_factors(const FA& a, int y, int x0, int hw, int csp, float* cs, float* fs,
-                            float* bs) {
+                            float* smu, float* sP) {
     const int K = a.K, rho = a.rho, n = a.n;
     const long long rowoff = (long long)y * a.W;
     for (int h = threadIdx.x; h < hw; h += RT) {
@@ -80,7 +85,10 @@ __device__ void row_factors(const FA& a, int y, int x0, int hw, int csp, float* 
         __syncthreads();
         return;
     }
-    // b_m(h) = phi(mu_m - p(h)) for the halo pixels
+    for (int t = threadIdx.x; t < K * rho; t += RT) smu[t] = a.mu[t];
+    for (int t = threadIdx.x; t < K * K; t += RT) sP[t] = a.P[t];
+    __syncthreads();
+    const bool hard = a.coef == FHD_COEF_HARD;
     for (int h = threadIdx.x; h < hw; h += RT) {
         const int x = x0 - a.S + h;
         const bool in = x >= 0 && x < a.W;
@@ -88,45 +96,33 @@ __device__ void row_factors(const FA& a, int y, int x0, int hw, int csp, float* 
 #pragma unroll
         for (int r = 0; r < RHO_INLINE; ++r)
             pr[r] = (in && r < rho) ? a.p[(long long)r * a.N + rowoff + x] : 0.0f;
+        float c[KMAX_INLINE];
+#pragma unroll
+        for (int l = 0; l < KMAX_INLINE; ++l) c[l] = 0.0f;
         for (int m = 0; m < K; ++m) {
             float d2 = 0.0f;
 #pragma unroll
             for (int r = 0; r < RHO_INLINE; ++r) {
                 if (r < rho) {
-                    const float d = pr[r] - a.mu[m * rho + r];
+                    const float d = pr[r] - smu[m * rho + r];
                     d2 = fmaf(d, d, d2);
                 }
             }
-            bs[h * (K + 1) + m] = in ? __expf(-d2 * a.inv2s2) : 0.0f;
-        }
-    }
-    __syncthreads();
-    if (a.coef == FHD_COEF_HARD) {
-        for (int t = threadIdx.x; t < hw * K; t += RT) {
-            const int l = t / hw, h = t - l * hw;
-            cs[l * csp + pidx(h)] = bs[h * (K + 1) + l];
-        }
-        __syncthreads();
-        return;
-    }
-    // c(h) = A^+ b(h), eight coefficients per task
-    const int groups = (K + 7) >> 3;
-    for (int t = threadIdx.x; t < hw * groups; t += RT) {
-        const int g = t / hw, h = t - g * hw;
-        float acc[8];
+            const float b = in ? __expf(-d2 * a.inv2s2) : 0.0f;
+            if (hard) {
+                cs[m * csp + pidx(h)] = b;
+            } else {
+                const float* prow = sP + m * K;  // P symmetric: column m = row m
 #pragma unroll
-        for (int q = 0; q < 8; ++q) acc[q] = 0.0f;
-        const float* brow = bs + h * (K + 1);
-        for (int m = 0; m < K; ++m) {
-            const float bv = brow[m];
-            const float* prow = a.P + (long long)m * K + g * 8;  // P symmetric: P[l][m] = P[m][l]
-#pragma unroll
-            for (int q = 0; q < 8; ++q)
-                if (g * 8 + q < K) acc[q] = fmaf(prow[q], bv, acc[q]);
+                for (int l = 0; l < KMAX_INLINE; ++l)
+                    if (l < K) c[l] = fmaf(prow[l], b, c[l]);
+            }
         }
+        if (!hard) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
-            if (g * 8 + q < K) cs[(g * 8 + q) * csp + pidx(h)] = acc[q];
+            for (int l = 0; l < KMAX_INLINE; ++l)
+                if (l < K) cs[l * csp + pidx(h)] = c[l];
+        }
     }
     __syncthreads();
 }
@@ -155,8 +151,9 @@ __global__ __launch_bounds__(RT) void row_gauss(FA a) {
     const int csp = pidx(hw - 1) + 1;
     float* cs = lds;
     float* fs = cs + a.K * csp;
-    float* bs = fs + a.n * csp;
-    row_factors(a, y, x0, hw, csp, cs, fs, bs);
+    float* smu = fs + a.n * csp;
+    float* sP = smu + a.K * a.rho;
+    row_factors(a, y, x0, hw, csp, cs, fs, smu, sP);
     const int nseg = a.tx / R;
     const int n = a.n;
     for (int task = threadIdx.x; task < a.K * nseg; task += RT) {
@@ -205,8 +202,9 @@ __global__ __launch_bounds__(RT) void row_generic(FA a) {
     const int csp = pidx(hw - 1) + 1;
     float* cs = lds;
     float* fs = cs + a.K * csp;
-    float* bs = fs + a.n * csp;
-    row_factors(a, y, x0, hw, csp, cs, fs, bs);
+    float* smu = fs + a.n * csp;
+    float* sP = smu + a.K * a.rho;
+    row_factors(a, y, x0, hw, csp, cs, fs, smu, sP);
     const int nseg = a.tx / R;
     const int n = a.n;
     for (int task = threadIdx.x; task < a.K * nseg * (n + 1); task += RT) {
@@ -717,13 +715,19 @@ size_t plane_floats(const FilterPlan& fp) {
     return (size_t)fp.K * (fp.n + 1) * Pp + (size_t)64 * fp.Wp + 64;
 }
 
-int row_tx(int K) { return K <= 32 ? 256 : (K <= 64 ? 128 : 64); }
+// Row-pass run length: the halo run tx + 2S fits the 256 threads when the
+// radius allows, so the per-pixel coefficient work is one round.
+int row_tx(int K, int S, int R) {
+    int tx = (RT - 2 * S) / R * R;
+    if (tx < 64) tx = K <= 32 ? 256 : 128;
+    return tx;
+}
 
 size_t row_lds_bytes(const FilterPlan& fp, int tx) {
     const int hw = tx + 2 * fp.S;
     const int csp = hw + ((hw - 1) >> 5) + 1;
     size_t fl = (size_t)fp.K * csp + (size_t)fp.n * csp;
-    if (!fp.materialize) fl += (size_t)hw * (fp.K + 1);
+    if (!fp.materialize) fl += (size_t)fp.K * fp.rho + (size_t)fp.K * fp.K;
     return fl * sizeof(float);
 }
 
@@ -802,10 +806,11 @@ void filter_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const f
     // row pass
     const bool box = fp.spatial == FHD_SPATIAL_BOX;
     const bool unrolled = !box && fp.S >= 1 && fp.S <= MAXS_T;
-    int tx = row_tx(fp.K);
+    const int rR = unrolled ? R_ROW : 16;
+    int tx = row_tx(fp.K, fp.S, rR);
     size_t lds = row_lds_bytes(fp, tx);
-    while (lds > 150 * 1024 && tx > 16) {
-        tx /= 2;
+    while (lds > 150 * 1024 && tx > 4 * rR) {
+        tx = std::max(4 * rR, tx / 2 / rR * rR);
         lds = row_lds_bytes(fp, tx);
     }
     FHD_REQUIRE(lds <= 160 * 1024, FHD_EUNSUPPORTED, "row pass does not fit in LDS");

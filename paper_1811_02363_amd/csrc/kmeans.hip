@@ -1,21 +1,27 @@
 // Bisecting K-means of the range space (Algorithm 1, step 1; Sec. II-C) on
 // the GPU.
 //
-// Design: the guide vectors are packed point-major (AoS) together with their
-// pixel index, and every cluster is kept as a contiguous range of that array
-// (two ping-pong copies; a split stably partitions its range into the other
-// copy).  Splits are computed in batched rounds: each round computes, for all
-// leaves that the greedy largest-SSE rule may still pick, the 2-means split
-// (seeds, Lloyd steps, children's SSE, partition) with one launch per pass for
-// all of them.  The host then commits splits greedily and plans the next
-// round; this is the only host synchronisation, once per round.
+// Design.  The guide vectors are packed point-major (AoS) with their pixel
+// index, and every cluster is a contiguous range of that array (two ping-pong
+// copies; a split stably partitions its range into the other copy).  Splits
+// are computed in batched rounds: each round computes the 2-means split of
+// every leaf the greedy largest-SSE rule may still pick (seeds, assignment
+// steps, children's SSE, partition), one launch per pass for all of them.
+// The host commits splits greedily between rounds; that is the only host
+// synchronisation, once per round.
 //
-// Arithmetic: distances and centroid sums in FP64, reduced in a fixed order
-// (per-lane sequential, fixed shuffle tree, then blocks in index order), so a
-// run is deterministic.  No floating-point atomics.  A block's lanes are laid
-// out dimension-parallel: LP = next power of two >= rho lanes per point.
+// Passes stream the member points once and write one partial record per
+// block; a one-block-per-job finalize kernel reduces the records and updates
+// the job's state.  Labels are never stored: the assignment is a pure
+// function of the point and the job's two centers, so the pass that needs the
+// final labels (split statistics, partition) recomputes them bit for bit.
+//
+// Arithmetic: distances and centroid sums in FP64 from the FP32 points, in a
+// fixed reduction order (per lane sequential, fixed shuffle tree, waves in
+// order, blocks in order), so a run is deterministic.  No floating-point
+// atomics.  Lanes are laid out LP per point, each lane holding up to eight
+// consecutive dimensions (LP = 1 for rho <= 8).
 #include <algorithm>
-#include <chrono>
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -28,64 +34,113 @@ namespace {
 
 constexpr int KT = 256;          // threads per block
 constexpr int KWAVES = KT / 64;  // waves per block
-constexpr int KITERS = 32;       // point groups per block and pass
+constexpr int KITERS = 16;       // point groups per block and pass
+constexpr int DPL = 8;           // dimensions per lane
 
 // per-job integer state
-enum { JI_START, JI_COUNT, JI_BUF, JI_CONV, JI_PARITY, JI_ITERS, JI_FIRST, JI_NBLK, JI_NA, JI_W = 12 };
+enum { JI_START, JI_COUNT, JI_BUF, JI_STOP, JI_STEPS, JI_FIRST, JI_NBLK, JI_NA, JI_W = 8 };
 // per-job FP64 results
-enum { JD_MAXD, JD_SSEA, JD_SSEB, JD_NA, JD_NB, JD_SPLA, JD_SPLB, JD_W = 8 };
+enum { JD_SSEA, JD_SSEB, JD_NA, JD_NB, JD_SPLA, JD_SPLB, JD_W = 6 };
 
 struct KmArgs {
     float* pts[2];
     int* idx[2];
-    unsigned char* side[2];
     const int4* btab;  // per block: job, first point, point count, rank within job (or label)
-    int* blkA;         // per block: members assigned to the first child
-    double* part;      // per block partials, pw doubles each
+    int* blkA;         // per block: members of the first child (split pass)
+    double* part;      // per block records, pw doubles each
     int* ji;           // per job ints, JI_W each
     double* jm;        // per job centroid (rho)
-    double* ca;        // per job first seed / child centroid (rho)
-    double* cb;        // per job second seed / child centroid (rho)
+    double* ca;        // per job current centers (first / second child), rho each
+    double* cb;
+    double* la;        // per job centers of the latest accepted assignment
+    double* lb;
+    double* fa;        // per job centers whose assignment gives the final labels
+    double* fb;
     double* jd;        // per job results, JD_W each
-    unsigned* done;    // per job finished-block counters (zero between passes)
     int rho;
     int pw;
 };
 
+// ---------------------------------------------------------------------------
+// lane layout
+
 template <int LP>
-__device__ inline double sum_over_point(double v) {
+struct Lanes {
+    static constexpr int PPW = 64 / LP;  // points per wave
+    int lane, wave, sub, pw, d0;
+    __device__ Lanes() {
+        lane = threadIdx.x & 63;
+        wave = threadIdx.x >> 6;
+        sub = lane & (LP - 1);
+        pw = lane / LP;
+        d0 = sub * DPL;
+    }
+};
+
+// this lane's dimensions of point `pos` (zero beyond rho)
+__device__ __forceinline__ void load_dims(const float* pts, long long pos, int rho, int d0, double (&x)[DPL]) {
+    const float* p = pts + pos * rho;
 #pragma unroll
-    for (int o = 1; o < LP; o <<= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    for (int k = 0; k < DPL; ++k) x[k] = (d0 + k < rho) ? (double)p[d0 + k] : 0.0;
 }
 
-// Reduce `v` over the lanes of the block that hold the same dimension
-// (lane % LP); thread t < LP receives the total for dimension t.  OP: 0 sum,
-// 1 min, 2 max.  Fixed order: shuffle tree, then waves 0..3.
-template <int LP, int OP>
-__device__ inline double block_reduce_dims(double v, double (*red)[64]) {
+__device__ __forceinline__ void load_center(const double* c, int rho, int d0, double (&v)[DPL]) {
 #pragma unroll
-    for (int o = LP; o < 64; o <<= 1) {
-        double w = __shfl_xor(v, o, 64);
-        v = OP == 0 ? v + w : (OP == 1 ? fmin(v, w) : fmax(v, w));
-    }
+    for (int k = 0; k < DPL; ++k) v[k] = (d0 + k < rho) ? c[d0 + k] : 0.0;
+}
+
+// |x - c|^2 over the point's dimensions: sequential over a lane's dimensions
+// (separately rounded products and sums), then a shuffle tree over its LP lanes.
+template <int LP>
+__device__ __forceinline__ double dist2(const double (&x)[DPL], const double (&c)[DPL], int rho, int d0) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < DPL; ++k)
+        if (d0 + k < rho) {
+            const double t = __dsub_rn(x[k], c[k]);
+            s = __dadd_rn(s, __dmul_rn(t, t));
+        }
+#pragma unroll
+    for (int o = 1; o < LP; o <<= 1) s = __dadd_rn(s, __shfl_xor(s, o, 64));
+    return s;
+}
+
+// The assignment rule: first child iff |x - c_a|^2 <= |x - c_b|^2.
+template <int LP>
+__device__ __forceinline__ bool to_first(const double (&x)[DPL], const double (&a)[DPL], const double (&b)[DPL],
+                                         int rho, int d0) {
+    return dist2<LP>(x, a, rho, d0) <= dist2<LP>(x, b, rho, d0);
+}
+
+template <int OP>
+__device__ __forceinline__ double op2(double u, double v) {
+    return OP == 0 ? u + v : (OP == 1 ? fmin(u, v) : fmax(u, v));
+}
+
+// Block reduction of per-lane dimension values (lanes with equal `sub` hold
+// the same dimensions); thread t < rho writes the total of dimension t to out[t].
+template <int LP, int OP>
+__device__ __forceinline__ void block_dims(double (&v)[DPL], double (*red)[64], int rho, double* out) {
+#pragma unroll
+    for (int k = 0; k < DPL; ++k)
+#pragma unroll
+        for (int o = LP; o < 64; o <<= 1) v[k] = op2<OP>(v[k], __shfl_xor(v[k], o, 64));
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     __syncthreads();
-    if (lane < LP) red[wave][lane] = v;
+    if (lane < LP)
+#pragma unroll
+        for (int k = 0; k < DPL; ++k)
+            if (lane * DPL + k < 64) red[wave][lane * DPL + k] = v[k];
     __syncthreads();
-    double r = 0.0;
-    if (threadIdx.x < LP) {
-        r = red[0][threadIdx.x];
-        for (int q = 1; q < KWAVES; ++q) {
-            double w = red[q][threadIdx.x];
-            r = OP == 0 ? r + w : (OP == 1 ? fmin(r, w) : fmax(r, w));
-        }
+    if (threadIdx.x < rho) {
+        double r = red[0][threadIdx.x];
+        for (int q = 1; q < KWAVES; ++q) r = op2<OP>(r, red[q][threadIdx.x]);
+        out[threadIdx.x] = r;
     }
-    return r;
 }
 
-// Sum of `v` over every lane of the block; valid in thread 0.
-__device__ inline double block_sum_all(double v, double (*red)[64]) {
+// Sum over every lane of the block, result in thread 0.
+__device__ __forceinline__ double block_sum(double v, double (*red)[64]) {
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -98,117 +153,139 @@ __device__ inline double block_sum_all(double v, double (*red)[64]) {
     return r;
 }
 
-// True in every thread of the block that is the last of its job to finish
-// this pass.  Partials written before the call are visible to that block.
-__device__ inline bool last_block(unsigned* done, int job, int nblk) {
-    __shared__ int s_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned prev = __hip_atomic_fetch_add(&done[job], 1u, __ATOMIC_ACQ_REL,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (prev == (unsigned)(nblk - 1)) ? 1 : 0;
+// Finalize helper: res[e] = reduction over the job's blocks of record entry
+// e0 + e, for e < E, with the operation opof(e) (0 sum, 1 min, 2 max).  The
+// work is spread over the block in a fixed order (a group of threads per
+// entry, blocks strided over the group, then the group's results in order).
+template <class OpOf>
+__device__ void reduce_records(const double* part, int first, int nblk, int pw, int e0, int E, OpOf opof,
+                               double* tmp, double* res) {
+    for (int base = 0; base < E; base += KT) {
+        const int Ec = min(KT, E - base);
+        const int G = KT / Ec;  // threads per entry
+        const int t = threadIdx.x;
+        if (t < Ec * G) {
+            const int e = base + t / G, sub = t % G;
+            const int op = opof(e);
+            double acc = op == 0 ? 0.0 : (op == 1 ? INFINITY : -INFINITY);
+            for (int b = sub; b < nblk; b += G) {
+                const double w = part[(long long)(first + b) * pw + e0 + e];
+                acc = op == 0 ? acc + w : (op == 1 ? fmin(acc, w) : fmax(acc, w));
+            }
+            tmp[t] = acc;
+        }
+        __syncthreads();
+        if (t < Ec) {
+            const int e = base + t;
+            const int op = opof(e);
+            double r = tmp[t * G];
+            for (int s = 1; s < G; ++s) {
+                const double w = tmp[t * G + s];
+                r = op == 0 ? r + w : (op == 1 ? fmin(r, w) : fmax(r, w));
+            }
+            res[e] = r;
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    const bool last = s_last != 0;
-    if (last) {
-        __threadfence();
-        if (threadIdx.x == 0) done[job] = 0u;
-    }
-    return last;
 }
 
 // ---------------------------------------------------------------------------
+// passes
 
-__global__ __launch_bounds__(KT) void km_pack(const float* __restrict__ guide, int rho,
-                                              long long N, float* __restrict__ pts,
-                                              int* __restrict__ idx) {
+__global__ __launch_bounds__(KT) void km_pack(const float* __restrict__ guide, int rho, long long N,
+                                              float* __restrict__ pts, int* __restrict__ idx) {
     const long long i = (long long)blockIdx.x * KT + threadIdx.x;
     if (i >= N) return;
     for (int d = 0; d < rho; ++d) pts[i * rho + d] = guide[(long long)d * N + i];
     idx[i] = (int)i;
 }
 
-// Centroid (sum / count) and per-dimension min/max of each job's members.
+// Member sums and per-dimension min/max.  Record: sum[rho], min[rho], max[rho].
 template <int LP>
 __global__ __launch_bounds__(KT) void km_stats(KmArgs a) {
     __shared__ double red[KWAVES][64];
     const int4 bt = a.btab[blockIdx.x];
     const int job = bt.x, s = bt.y, cnt = bt.z;
-    const int* ji = a.ji + job * JI_W;
-    const float* pts = a.pts[ji[JI_BUF]];
+    const float* pts = a.pts[a.ji[job * JI_W + JI_BUF]];
     const int rho = a.rho;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int d = lane & (LP - 1), pw = lane / LP;
-    constexpr int PPW = 64 / LP;
-    double sum = 0.0, mn = INFINITY, mx = -INFINITY;
-    for (int base = 0; base < cnt; base += KWAVES * PPW) {
-        const int p = base + wave * PPW + pw;
-        if (p < cnt && d < rho) {
-            const double x = pts[(long long)(s + p) * rho + d];
-            sum += x;
-            mn = fmin(mn, x);
-            mx = fmax(mx, x);
-        }
+    const Lanes<LP> L;
+    double sum[DPL], mn[DPL], mx[DPL];
+#pragma unroll
+    for (int k = 0; k < DPL; ++k) {
+        sum[k] = 0.0;
+        mn[k] = INFINITY;
+        mx[k] = -INFINITY;
     }
-    double* part = a.part + (long long)blockIdx.x * a.pw;
-    const double tsum = block_reduce_dims<LP, 0>(sum, red);
-    const double tmn = block_reduce_dims<LP, 1>(mn, red);
-    const double tmx = block_reduce_dims<LP, 2>(mx, red);
-    if (threadIdx.x < rho) {
-        part[threadIdx.x] = tsum;
-        part[rho + threadIdx.x] = tmn;
-        part[2 * rho + threadIdx.x] = tmx;
+    for (int base = 0; base < cnt; base += KWAVES * L.PPW) {
+        const int p = base + L.wave * L.PPW + L.pw;
+        if (p >= cnt) continue;
+        double x[DPL];
+        load_dims(pts, s + p, rho, L.d0, x);
+#pragma unroll
+        for (int k = 0; k < DPL; ++k)
+            if (L.d0 + k < rho) {
+                sum[k] += x[k];
+                mn[k] = fmin(mn[k], x[k]);
+                mx[k] = fmax(mx[k], x[k]);
+            }
     }
-    if (!last_block(a.done, job, ji[JI_NBLK])) return;
-    __shared__ int s_split;
-    if (threadIdx.x == 0) s_split = 0;
-    __syncthreads();
-    if (threadIdx.x < rho) {
-        const int t = threadIdx.x;
-        double S = 0.0, lo = INFINITY, hi = -INFINITY;
-        for (int b = ji[JI_FIRST]; b < ji[JI_FIRST] + ji[JI_NBLK]; ++b) {
-            const double* pb = a.part + (long long)b * a.pw;
-            S += pb[t];
-            lo = fmin(lo, pb[rho + t]);
-            hi = fmax(hi, pb[2 * rho + t]);
-        }
-        a.jm[job * rho + t] = S / (double)ji[JI_COUNT];
-        if (hi != lo) atomicOr(&s_split, 1);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) a.jd[job * JD_W + JD_SPLA] = (double)s_split;
+    double* rec = a.part + (long long)blockIdx.x * a.pw;
+    block_dims<LP, 0>(sum, red, rho, rec);
+    block_dims<LP, 1>(mn, red, rho, rec + rho);
+    block_dims<LP, 2>(mx, red, rho, rec + 2 * rho);
 }
 
-// Seed search: the member farthest from the centroid (which == 0, stored in
-// ca) or from the first seed (which == 1, stored in cb); ties -> lowest pixel
-// index.
+// SSE of the whole job around its centroid jm.  Record: sse.
+template <int LP>
+__global__ __launch_bounds__(KT) void km_sse1(KmArgs a) {
+    __shared__ double red[KWAVES][64];
+    const int4 bt = a.btab[blockIdx.x];
+    const int job = bt.x, s = bt.y, cnt = bt.z;
+    const float* pts = a.pts[a.ji[job * JI_W + JI_BUF]];
+    const int rho = a.rho;
+    const Lanes<LP> L;
+    double c[DPL];
+    load_center(a.jm + job * rho, rho, L.d0, c);
+    double e = 0.0;
+    for (int base = 0; base < cnt; base += KWAVES * L.PPW) {
+        const int p = base + L.wave * L.PPW + L.pw;
+        if (p >= cnt) continue;
+        double x[DPL];
+        load_dims(pts, s + p, rho, L.d0, x);
+#pragma unroll
+        for (int k = 0; k < DPL; ++k)
+            if (L.d0 + k < rho) {
+                const double t = x[k] - c[k];
+                e += t * t;
+            }
+    }
+    const double tot = block_sum(e, red);
+    if (threadIdx.x == 0) a.part[(long long)blockIdx.x * a.pw] = tot;
+}
+
+// Seed search: the member farthest from the centroid (which == 0) or from the
+// first seed (which == 1); ties -> lowest pixel index.  Record: d, pixel, pos.
 template <int LP>
 __global__ __launch_bounds__(KT) void km_far(KmArgs a, int which) {
     __shared__ double rb[KWAVES];
     __shared__ int ri[KWAVES], rp[KWAVES];
     const int4 bt = a.btab[blockIdx.x];
     const int job = bt.x, s = bt.y, cnt = bt.z;
-    const int* ji = a.ji + job * JI_W;
-    const float* pts = a.pts[ji[JI_BUF]];
-    const int* idx = a.idx[ji[JI_BUF]];
+    const int buf = a.ji[job * JI_W + JI_BUF];
+    const float* pts = a.pts[buf];
+    const int* idx = a.idx[buf];
     const int rho = a.rho;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int d = lane & (LP - 1), pw = lane / LP;
-    constexpr int PPW = 64 / LP;
-    const double* ref = (which == 0 ? a.jm : a.ca) + job * rho;
-    const double r = d < rho ? ref[d] : 0.0;
+    const Lanes<LP> L;
+    double r[DPL];
+    load_center((which == 0 ? a.jm : a.ca) + job * rho, rho, L.d0, r);
     double best = -1.0;
     int bidx = INT_MAX, bpos = -1;
-    for (int base = 0; base < cnt; base += KWAVES * PPW) {
-        const int p = base + wave * PPW + pw;
+    for (int base = 0; base < cnt; base += KWAVES * L.PPW) {
+        const int p = base + L.wave * L.PPW + L.pw;
         const bool valid = p < cnt;
-        double t = 0.0;
-        if (valid && d < rho) {
-            const double x = pts[(long long)(s + p) * rho + d];
-            t = (x - r) * (x - r);
-        }
-        t = sum_over_point<LP>(t);
+        double x[DPL];
+        load_dims(pts, valid ? s + p : s, rho, L.d0, x);
+        const double t = dist2<LP>(x, r, rho, L.d0);
         if (valid) {
             const int pi = idx[s + p];
             if (t > best || (t == best && pi < bidx)) {
@@ -229,13 +306,12 @@ __global__ __launch_bounds__(KT) void km_far(KmArgs a, int which) {
             bpos = op;
         }
     }
-    if (lane == 0) {
-        rb[wave] = best;
-        ri[wave] = bidx;
-        rp[wave] = bpos;
+    if (L.lane == 0) {
+        rb[L.wave] = best;
+        ri[L.wave] = bidx;
+        rp[L.wave] = bpos;
     }
     __syncthreads();
-    double* part = a.part + (long long)blockIdx.x * a.pw;
     if (threadIdx.x == 0) {
         for (int q = 1; q < KWAVES; ++q)
             if (rb[q] > best || (rb[q] == best && ri[q] < bidx)) {
@@ -243,240 +319,131 @@ __global__ __launch_bounds__(KT) void km_far(KmArgs a, int which) {
                 bidx = ri[q];
                 bpos = rp[q];
             }
-        part[0] = best;
-        part[1] = (double)bidx;
-        part[2] = (double)bpos;
-    }
-    if (!last_block(a.done, job, ji[JI_NBLK])) return;
-    __shared__ int s_pos;
-    if (threadIdx.x == 0) {
-        double B = -1.0;
-        int I = INT_MAX, P = -1;
-        for (int b = ji[JI_FIRST]; b < ji[JI_FIRST] + ji[JI_NBLK]; ++b) {
-            const double* pb = a.part + (long long)b * a.pw;
-            const int bi = (int)pb[1];
-            if (pb[0] > B || (pb[0] == B && bi < I)) {
-                B = pb[0];
-                I = bi;
-                P = (int)pb[2];
-            }
-        }
-        s_pos = P;
-        if (which == 0) a.jd[job * JD_W + JD_MAXD] = B;
-    }
-    __syncthreads();
-    if (threadIdx.x < rho) {
-        double* dst = (which == 0 ? a.ca : a.cb) + job * rho;
-        dst[threadIdx.x] = pts[(long long)s_pos * rho + threadIdx.x];
+        double* rec = a.part + (long long)blockIdx.x * a.pw;
+        rec[0] = best;
+        rec[1] = (double)bidx;
+        rec[2] = (double)bpos;
     }
 }
 
-// One 2-means assignment step: x joins the first child iff
-// |x - c_a|^2 <= |x - c_b|^2; then the children's centroids are updated.  The
-// labels of step `it` go to side[it & 1]; the previous step's labels are in
-// side[(it + 1) & 1].
+// One assignment step with the current centers (ca, cb).
+// Record: sumA[rho], sumB[rho], nA, nB.
 template <int LP>
-__global__ __launch_bounds__(KT) void km_lloyd(KmArgs a, int it, int T) {
+__global__ __launch_bounds__(KT) void km_lloyd(KmArgs a) {
     __shared__ double red[KWAVES][64];
     const int4 bt = a.btab[blockIdx.x];
     const int job = bt.x, s = bt.y, cnt = bt.z;
-    int* ji = a.ji + job * JI_W;
-    if (ji[JI_CONV]) return;
+    const int* ji = a.ji + job * JI_W;
+    if (ji[JI_STOP]) return;
     const float* pts = a.pts[ji[JI_BUF]];
     const int rho = a.rho;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int d = lane & (LP - 1), pw = lane / LP;
-    constexpr int PPW = 64 / LP;
-    const double ca = d < rho ? a.ca[job * rho + d] : 0.0;
-    const double cb = d < rho ? a.cb[job * rho + d] : 0.0;
-    unsigned char* snew = a.side[it & 1];
-    const unsigned char* sold = a.side[(it + 1) & 1];
-    double sa = 0.0, sb = 0.0, na = 0.0, nb = 0.0, ch = 0.0;
-    for (int base = 0; base < cnt; base += KWAVES * PPW) {
-        const int p = base + wave * PPW + pw;
+    const Lanes<LP> L;
+    double ca[DPL], cb[DPL], sa[DPL], sb[DPL];
+    load_center(a.ca + job * rho, rho, L.d0, ca);
+    load_center(a.cb + job * rho, rho, L.d0, cb);
+#pragma unroll
+    for (int k = 0; k < DPL; ++k) sa[k] = sb[k] = 0.0;
+    double na = 0.0, nb = 0.0;
+    for (int base = 0; base < cnt; base += KWAVES * L.PPW) {
+        const int p = base + L.wave * L.PPW + L.pw;
         const bool valid = p < cnt;
-        double x = 0.0, ta = 0.0, tb = 0.0;
-        if (valid && d < rho) {
-            x = pts[(long long)(s + p) * rho + d];
-            ta = (x - ca) * (x - ca);
-            tb = (x - cb) * (x - cb);
-        }
-        ta = sum_over_point<LP>(ta);
-        tb = sum_over_point<LP>(tb);
+        double x[DPL];
+        load_dims(pts, valid ? s + p : s, rho, L.d0, x);
+        const bool A = to_first<LP>(x, ca, cb, rho, L.d0);
         if (valid) {
-            const bool toA = ta <= tb;
-            if (toA) sa += x; else sb += x;
-            if (d == 0) {
-                const unsigned char ns = toA ? 0 : 1;
-                if (toA) na += 1.0; else nb += 1.0;
-                if (it > 0 && sold[s + p] != ns) ch += 1.0;
-                snew[s + p] = ns;
+#pragma unroll
+            for (int k = 0; k < DPL; ++k) {
+                if (A) sa[k] += x[k];
+                else sb[k] += x[k];
+            }
+            if (L.sub == 0) {
+                if (A) na += 1.0;
+                else nb += 1.0;
             }
         }
     }
-    const double tsa = block_reduce_dims<LP, 0>(sa, red);
-    const double tsb = block_reduce_dims<LP, 0>(sb, red);
-    const double tna = block_sum_all(na, red);
-    const double tnb = block_sum_all(nb, red);
-    const double tch = block_sum_all(ch, red);
-    double* part = a.part + (long long)blockIdx.x * a.pw;
-    if (threadIdx.x < rho) {
-        part[threadIdx.x] = tsa;
-        part[rho + threadIdx.x] = tsb;
-    }
+    double* rec = a.part + (long long)blockIdx.x * a.pw;
+    block_dims<LP, 0>(sa, red, rho, rec);
+    block_dims<LP, 0>(sb, red, rho, rec + rho);
+    const double tna = block_sum(na, red);
+    const double tnb = block_sum(nb, red);
     if (threadIdx.x == 0) {
-        part[2 * rho] = tna;
-        part[2 * rho + 1] = tnb;
-        part[2 * rho + 2] = tch;
-    }
-    if (!last_block(a.done, job, ji[JI_NBLK])) return;
-    __shared__ double s_na, s_nb;
-    __shared__ int s_update;
-    const int first = ji[JI_FIRST], nblk = ji[JI_NBLK];
-    if (threadIdx.x == 0) {
-        double NA = 0.0, NB = 0.0, CH = 0.0;
-        for (int b = first; b < first + nblk; ++b) {
-            const double* pb = a.part + (long long)b * a.pw;
-            NA += pb[2 * rho];
-            NB += pb[2 * rho + 1];
-            CH += pb[2 * rho + 2];
-        }
-        int update = 0;
-        if (it > 0 && CH == 0.0) {
-            ji[JI_CONV] = 1;  // no label changed: centroids already match
-            ji[JI_PARITY] = it & 1;
-        } else if (NA == 0.0 || NB == 0.0) {
-            ji[JI_CONV] = 1;  // a child would be empty: keep the previous step
-            ji[JI_PARITY] = (it + 1) & 1;
-        } else {
-            update = 1;
-            ji[JI_PARITY] = it & 1;
-            ji[JI_ITERS] = it + 1;
-            if (it == T - 1) ji[JI_CONV] = 1;
-        }
-        s_na = NA;
-        s_nb = NB;
-        s_update = update;
-    }
-    __syncthreads();
-    if (s_update && threadIdx.x < rho) {
-        const int t = threadIdx.x;
-        double SA = 0.0, SB = 0.0;
-        for (int b = first; b < first + nblk; ++b) {
-            const double* pb = a.part + (long long)b * a.pw;
-            SA += pb[t];
-            SB += pb[rho + t];
-        }
-        a.ca[job * rho + t] = SA / s_na;
-        a.cb[job * rho + t] = SB / s_nb;
+        rec[2 * rho] = tna;
+        rec[2 * rho + 1] = tnb;
     }
 }
 
-// SSE, member counts and per-dimension min/max of the two children (split
-// mode: labels side[parity], centroids ca/cb) or of the whole job (single
-// mode: every member in the first group, centroid jm).
+// Final labels (assignment with fa, fb): per child member count, SSE around
+// the child's centroid (ca / cb) and per-dimension min/max.
+// Record: sseA, sseB, nA, nB, minA[rho], maxA[rho], minB[rho], maxB[rho].
 template <int LP>
-__global__ __launch_bounds__(KT) void km_sse(KmArgs a, int single) {
+__global__ __launch_bounds__(KT) void km_split(KmArgs a) {
     __shared__ double red[KWAVES][64];
     const int4 bt = a.btab[blockIdx.x];
     const int job = bt.x, s = bt.y, cnt = bt.z;
-    int* ji = a.ji + job * JI_W;
-    const float* pts = a.pts[ji[JI_BUF]];
+    const float* pts = a.pts[a.ji[job * JI_W + JI_BUF]];
     const int rho = a.rho;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int d = lane & (LP - 1), pw = lane / LP;
-    constexpr int PPW = 64 / LP;
-    const double ca = d < rho ? (single ? a.jm : a.ca)[job * rho + d] : 0.0;
-    const double cb = (d < rho && !single) ? a.cb[job * rho + d] : 0.0;
-    const unsigned char* sd = a.side[ji[JI_PARITY]];
+    const Lanes<LP> L;
+    double fa[DPL], fb[DPL], ma[DPL], mb[DPL];
+    load_center(a.fa + job * rho, rho, L.d0, fa);
+    load_center(a.fb + job * rho, rho, L.d0, fb);
+    load_center(a.ca + job * rho, rho, L.d0, ma);
+    load_center(a.cb + job * rho, rho, L.d0, mb);
+    double lo_a[DPL], hi_a[DPL], lo_b[DPL], hi_b[DPL];
+#pragma unroll
+    for (int k = 0; k < DPL; ++k) {
+        lo_a[k] = lo_b[k] = INFINITY;
+        hi_a[k] = hi_b[k] = -INFINITY;
+    }
     double ea = 0.0, eb = 0.0, na = 0.0, nb = 0.0;
-    double mna = INFINITY, mxa = -INFINITY, mnb = INFINITY, mxb = -INFINITY;
-    for (int base = 0; base < cnt; base += KWAVES * PPW) {
-        const int p = base + wave * PPW + pw;
-        if (p >= cnt) continue;
-        const bool inB = single ? false : (sd[s + p] != 0);
-        if (d < rho) {
-            const double x = pts[(long long)(s + p) * rho + d];
-            if (inB) {
-                eb += (x - cb) * (x - cb);
-                mnb = fmin(mnb, x);
-                mxb = fmax(mxb, x);
+    for (int base = 0; base < cnt; base += KWAVES * L.PPW) {
+        const int p = base + L.wave * L.PPW + L.pw;
+        const bool valid = p < cnt;
+        double x[DPL];
+        load_dims(pts, valid ? s + p : s, rho, L.d0, x);
+        const bool A = to_first<LP>(x, fa, fb, rho, L.d0);
+        if (!valid) continue;
+#pragma unroll
+        for (int k = 0; k < DPL; ++k) {
+            if (L.d0 + k >= rho) continue;
+            if (A) {
+                const double t = x[k] - ma[k];
+                ea += t * t;
+                lo_a[k] = fmin(lo_a[k], x[k]);
+                hi_a[k] = fmax(hi_a[k], x[k]);
             } else {
-                ea += (x - ca) * (x - ca);
-                mna = fmin(mna, x);
-                mxa = fmax(mxa, x);
+                const double t = x[k] - mb[k];
+                eb += t * t;
+                lo_b[k] = fmin(lo_b[k], x[k]);
+                hi_b[k] = fmax(hi_b[k], x[k]);
             }
         }
-        if (d == 0) {
-            if (inB) nb += 1.0; else na += 1.0;
+        if (L.sub == 0) {
+            if (A) na += 1.0;
+            else nb += 1.0;
         }
     }
-    const double tea = block_sum_all(ea, red);
-    const double teb = block_sum_all(eb, red);
-    const double tna = block_sum_all(na, red);
-    const double tnb = block_sum_all(nb, red);
-    const double t0 = block_reduce_dims<LP, 1>(mna, red);
-    const double t1 = block_reduce_dims<LP, 2>(mxa, red);
-    const double t2 = block_reduce_dims<LP, 1>(mnb, red);
-    const double t3 = block_reduce_dims<LP, 2>(mxb, red);
-    double* part = a.part + (long long)blockIdx.x * a.pw;
+    double* rec = a.part + (long long)blockIdx.x * a.pw;
+    const double tea = block_sum(ea, red);
+    const double teb = block_sum(eb, red);
+    const double tna = block_sum(na, red);
+    const double tnb = block_sum(nb, red);
     if (threadIdx.x == 0) {
-        part[0] = tea;
-        part[1] = teb;
-        part[2] = tna;
-        part[3] = tnb;
+        rec[0] = tea;
+        rec[1] = teb;
+        rec[2] = tna;
+        rec[3] = tnb;
         a.blkA[blockIdx.x] = (int)tna;
     }
-    if (threadIdx.x < rho) {
-        part[4 + threadIdx.x] = t0;
-        part[4 + rho + threadIdx.x] = t1;
-        part[4 + 2 * rho + threadIdx.x] = t2;
-        part[4 + 3 * rho + threadIdx.x] = t3;
-    }
-    if (!last_block(a.done, job, ji[JI_NBLK])) return;
-    __shared__ int s_sa, s_sb;
-    const int first = ji[JI_FIRST], nblk = ji[JI_NBLK];
-    if (threadIdx.x == 0) {
-        s_sa = 0;
-        s_sb = 0;
-    }
-    __syncthreads();
-    if (threadIdx.x < rho) {
-        const int t = threadIdx.x;
-        double lo_a = INFINITY, hi_a = -INFINITY, lo_b = INFINITY, hi_b = -INFINITY;
-        for (int b = first; b < first + nblk; ++b) {
-            const double* pb = a.part + (long long)b * a.pw;
-            lo_a = fmin(lo_a, pb[4 + t]);
-            hi_a = fmax(hi_a, pb[4 + rho + t]);
-            lo_b = fmin(lo_b, pb[4 + 2 * rho + t]);
-            hi_b = fmax(hi_b, pb[4 + 3 * rho + t]);
-        }
-        if (hi_a > lo_a) atomicOr(&s_sa, 1);
-        if (hi_b > lo_b) atomicOr(&s_sb, 1);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double EA = 0.0, EB = 0.0, NA = 0.0, NB = 0.0;
-        for (int b = first; b < first + nblk; ++b) {
-            const double* pb = a.part + (long long)b * a.pw;
-            EA += pb[0];
-            EB += pb[1];
-            NA += pb[2];
-            NB += pb[3];
-        }
-        double* jd = a.jd + job * JD_W;
-        jd[JD_SSEA] = s_sa ? EA : 0.0;  // a single-valued group has SSE exactly 0
-        jd[JD_SSEB] = s_sb ? EB : 0.0;
-        jd[JD_NA] = NA;
-        jd[JD_NB] = NB;
-        jd[JD_SPLA] = s_sa;
-        jd[JD_SPLB] = s_sb;
-        ji[JI_NA] = (int)NA;
-    }
+    block_dims<LP, 1>(lo_a, red, rho, rec + 4);
+    block_dims<LP, 2>(hi_a, red, rho, rec + 4 + rho);
+    block_dims<LP, 1>(lo_b, red, rho, rec + 4 + 2 * rho);
+    block_dims<LP, 2>(hi_b, red, rho, rec + 4 + 3 * rho);
 }
 
 // Stable partition of each job's range by the final labels into the other
 // copy: first-child members first, both groups in their original order.
+template <int LP>
 __global__ __launch_bounds__(KT) void km_scatter(KmArgs a) {
     __shared__ int red[KWAVES];
     __shared__ int s_offA, s_offB, s_wa[KWAVES], s_wb[KWAVES];
@@ -490,14 +457,16 @@ __global__ __launch_bounds__(KT) void km_scatter(KmArgs a) {
     int* idst = a.idx[1 - buf];
     const int rho = a.rho;
     const int start = ji[JI_START], NA = ji[JI_NA], first = ji[JI_FIRST];
-    const unsigned char* sd = a.side[ji[JI_PARITY]];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const Lanes<LP> L;
+    double fa[DPL], fb[DPL];
+    load_center(a.fa + job * rho, rho, L.d0, fa);
+    load_center(a.fb + job * rho, rho, L.d0, fb);
     // members of the first child in the earlier blocks of this job
     int acc = 0;
     for (int q = threadIdx.x; q < rank; q += KT) acc += a.blkA[first + q];
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
-    if (lane == 0) red[wave] = acc;
+    if (L.lane == 0) red[L.wave] = acc;
     __syncthreads();
     if (threadIdx.x == 0) {
         int t = 0;
@@ -507,23 +476,28 @@ __global__ __launch_bounds__(KT) void km_scatter(KmArgs a) {
     }
     __syncthreads();
     int offA = s_offA, offB = s_offB;
-    for (int base = 0; base < cnt; base += KT) {
-        const int p = base + threadIdx.x;
+    // each step visits KWAVES * PPW consecutive points: wave w takes the w-th
+    // run of PPW, lane group pw its pw-th point
+    for (int base = 0; base < cnt; base += KWAVES * L.PPW) {
+        const int p = base + L.wave * L.PPW + L.pw;
         const bool valid = p < cnt;
-        const bool inA = valid && sd[s + p] == 0;
-        const bool inB = valid && !inA;
-        const unsigned long long ma = __ballot(inA);
-        const unsigned long long mb = __ballot(inB);
-        const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-        const int ra = __popcll(ma & below), rb = __popcll(mb & below);
-        if (lane == 0) {
-            s_wa[wave] = __popcll(ma);
-            s_wb[wave] = __popcll(mb);
+        double x[DPL];
+        load_dims(src, valid ? s + p : s, rho, L.d0, x);
+        const bool A = to_first<LP>(x, fa, fb, rho, L.d0);
+        const bool lead = valid && L.sub == 0;
+        const unsigned long long ma = __ballot(lead && A);
+        const unsigned long long mb = __ballot(lead && !A);
+        const int rl = L.lane & ~(LP - 1);  // the point's lead lane
+        const unsigned long long bl = (rl == 0) ? 0ull : (~0ull >> (64 - rl));
+        const int ra = __popcll(ma & bl), rb = __popcll(mb & bl);
+        if (L.lane == 0) {
+            s_wa[L.wave] = __popcll(ma);
+            s_wb[L.wave] = __popcll(mb);
         }
         __syncthreads();
         int pa = 0, pb = 0, ta = 0, tb = 0;
         for (int q = 0; q < KWAVES; ++q) {
-            if (q < wave) {
+            if (q < L.wave) {
                 pa += s_wa[q];
                 pb += s_wb[q];
             }
@@ -531,10 +505,11 @@ __global__ __launch_bounds__(KT) void km_scatter(KmArgs a) {
             tb += s_wb[q];
         }
         if (valid) {
-            const int to = inA ? offA + pa + ra : offB + pb + rb;
-            for (int dd = 0; dd < rho; ++dd)
-                dst[(long long)to * rho + dd] = src[(long long)(s + p) * rho + dd];
-            idst[to] = isrc[s + p];
+            const int to = A ? offA + pa + ra : offB + pb + rb;
+#pragma unroll
+            for (int k = 0; k < DPL; ++k)
+                if (L.d0 + k < rho) dst[(long long)to * rho + L.d0 + k] = src[(long long)(s + p) * rho + L.d0 + k];
+            if (L.sub == 0) idst[to] = isrc[s + p];
         }
         offA += ta;
         offB += tb;
@@ -548,6 +523,176 @@ __global__ __launch_bounds__(KT) void km_labels(KmArgs a, int* __restrict__ labe
     const int job = bt.x, s = bt.y, cnt = bt.z, lab = bt.w;
     const int* idx = a.idx[a.ji[job * JI_W + JI_BUF]];
     for (int p = threadIdx.x; p < cnt; p += KT) labels[idx[s + p]] = lab;
+}
+
+// ---------------------------------------------------------------------------
+// finalize kernels: one block per job
+
+__global__ __launch_bounds__(KT) void fin_stats(KmArgs a) {
+    __shared__ double tmp[KT];
+    __shared__ double res[3 * FHD_MAX_RHO];
+    const int job = blockIdx.x, rho = a.rho;
+    const int* ji = a.ji + job * JI_W;
+    reduce_records(a.part, ji[JI_FIRST], ji[JI_NBLK], a.pw, 0, 3 * rho,
+                   [rho](int e) { return e < rho ? 0 : (e < 2 * rho ? 1 : 2); }, tmp, res);
+    if (threadIdx.x < rho) a.jm[job * rho + threadIdx.x] = res[threadIdx.x] / (double)ji[JI_COUNT];
+    if (threadIdx.x == 0) {
+        int split = 0;
+        for (int t = 0; t < rho; ++t) split |= res[2 * rho + t] != res[rho + t];
+        a.jd[job * JD_W + JD_SPLA] = split;
+    }
+}
+
+__global__ __launch_bounds__(KT) void fin_sse1(KmArgs a) {
+    __shared__ double tmp[KT];
+    __shared__ double res[1];
+    const int job = blockIdx.x;
+    const int* ji = a.ji + job * JI_W;
+    reduce_records(a.part, ji[JI_FIRST], ji[JI_NBLK], a.pw, 0, 1, [](int) { return 0; }, tmp, res);
+    if (threadIdx.x == 0) a.jd[job * JD_W + JD_SSEA] = res[0];
+}
+
+__global__ __launch_bounds__(KT) void fin_far(KmArgs a, int which) {
+    __shared__ double rb[KWAVES];
+    __shared__ int ri[KWAVES], rp[KWAVES];
+    __shared__ int s_pos;
+    const int job = blockIdx.x, rho = a.rho;
+    const int* ji = a.ji + job * JI_W;
+    const int first = ji[JI_FIRST], nblk = ji[JI_NBLK];
+    double B = -1.0;
+    int I = INT_MAX, P = -1;
+    for (int b = threadIdx.x; b < nblk; b += KT) {
+        const double* rec = a.part + (long long)(first + b) * a.pw;
+        const int bi = (int)rec[1];
+        if (rec[0] > B || (rec[0] == B && bi < I)) {
+            B = rec[0];
+            I = bi;
+            P = (int)rec[2];
+        }
+    }
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const double ob = __shfl_xor(B, o, 64);
+        const int oi = __shfl_xor(I, o, 64);
+        const int op = __shfl_xor(P, o, 64);
+        if (ob > B || (ob == B && oi < I)) {
+            B = ob;
+            I = oi;
+            P = op;
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        rb[wave] = B;
+        ri[wave] = I;
+        rp[wave] = P;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < KWAVES; ++q)
+            if (rb[q] > B || (rb[q] == B && ri[q] < I)) {
+                B = rb[q];
+                I = ri[q];
+                P = rp[q];
+            }
+        s_pos = P;
+    }
+    __syncthreads();
+    const float* pts = a.pts[ji[JI_BUF]];
+    if (threadIdx.x < rho)
+        (which == 0 ? a.ca : a.cb)[job * rho + threadIdx.x] = pts[(long long)s_pos * rho + threadIdx.x];
+}
+
+// The 2-means state machine after one assignment step (m = means of the new
+// labels):
+//   a child would be empty  -> stop; final labels = assignment with la/lb;
+//   m equals ca/cb, step>=1 -> converged; final labels = assignment with ca/cb;
+//   otherwise               -> la/lb = ca/cb, ca/cb = m; after max_iter steps
+//                              stop with final labels = assignment with la/lb.
+// Equal means from a fixed summation order follow from equal labels, and
+// equal means make the next assignment repeat the current one, so this stops
+// with the labels and centers of the label-change rule.
+__global__ __launch_bounds__(KT) void fin_lloyd(KmArgs a, int T) {
+    __shared__ double tmp[KT];
+    __shared__ double res[2 * FHD_MAX_RHO + 2];
+    __shared__ int s_act;
+    const int job = blockIdx.x, rho = a.rho;
+    int* ji = a.ji + job * JI_W;
+    if (ji[JI_STOP]) return;
+    reduce_records(a.part, ji[JI_FIRST], ji[JI_NBLK], a.pw, 0, 2 * rho + 2, [](int) { return 0; }, tmp, res);
+    double* ca = a.ca + job * rho;
+    double* cb = a.cb + job * rho;
+    const double NA = res[2 * rho], NB = res[2 * rho + 1];
+    const int steps = ji[JI_STEPS];
+    if (threadIdx.x == 0) {
+        int act;
+        if (NA == 0.0 || NB == 0.0) {
+            act = 0;  // keep the previous step
+        } else {
+            bool same = steps >= 1;
+            for (int t = 0; t < rho && same; ++t) same = (res[t] / NA == ca[t]) && (res[rho + t] / NB == cb[t]);
+            act = same ? 1 : 2;
+        }
+        s_act = act;
+    }
+    __syncthreads();
+    const int act = s_act;
+    if (threadIdx.x < rho) {
+        const int t = threadIdx.x;
+        if (act == 0) {
+            a.fa[job * rho + t] = a.la[job * rho + t];
+            a.fb[job * rho + t] = a.lb[job * rho + t];
+        } else if (act == 1) {
+            a.fa[job * rho + t] = ca[t];
+            a.fb[job * rho + t] = cb[t];
+        } else {
+            const double oa = ca[t], ob = cb[t];
+            a.la[job * rho + t] = oa;
+            a.lb[job * rho + t] = ob;
+            ca[t] = res[t] / NA;
+            cb[t] = res[rho + t] / NB;
+            a.fa[job * rho + t] = oa;  // final if this was the last allowed step
+            a.fb[job * rho + t] = ob;
+        }
+    }
+    if (threadIdx.x == 0) {
+        if (act != 2) {
+            ji[JI_STOP] = 1;
+        } else {
+            ji[JI_STEPS] = steps + 1;
+            if (steps + 1 >= T) ji[JI_STOP] = 1;
+        }
+    }
+}
+
+__global__ __launch_bounds__(KT) void fin_split(KmArgs a) {
+    __shared__ double tmp[KT];
+    __shared__ double res[4 + 4 * FHD_MAX_RHO];
+    const int job = blockIdx.x, rho = a.rho;
+    int* ji = a.ji + job * JI_W;
+    reduce_records(
+        a.part, ji[JI_FIRST], ji[JI_NBLK], a.pw, 0, 4 + 4 * rho,
+        [rho](int e) {
+            if (e < 4) return 0;
+            const int q = (e - 4) / rho;
+            return (q == 0 || q == 2) ? 1 : 2;
+        },
+        tmp, res);
+    if (threadIdx.x == 0) {
+        int sa = 0, sb = 0;
+        for (int t = 0; t < rho; ++t) {
+            sa |= res[4 + rho + t] > res[4 + t];
+            sb |= res[4 + 3 * rho + t] > res[4 + 2 * rho + t];
+        }
+        double* jd = a.jd + job * JD_W;
+        jd[JD_SSEA] = sa ? res[0] : 0.0;  // a single-valued group has SSE exactly 0
+        jd[JD_SSEB] = sb ? res[1] : 0.0;
+        jd[JD_NA] = res[2];
+        jd[JD_NB] = res[3];
+        jd[JD_SPLA] = sa;
+        jd[JD_SPLB] = sb;
+        ji[JI_NA] = (int)res[2];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -574,86 +719,66 @@ bool heap_less(const std::string& a, const std::string& b) {
 
 int lanes_per_point(int rho) {
     int lp = 1;
-    while (lp < rho) lp <<= 1;
+    while (lp * DPL < rho) lp <<= 1;
     return lp;
 }
-
-struct KmBuffers {
-    float* pts[2];
-    int* idx[2];
-    unsigned char* side[2];
-    int4* btab;
-    int* blkA;
-    double* part;
-    int* ji;
-    double *jm, *ca, *cb, *jd;
-    unsigned* done;
-    long long maxBlocks;
-    int maxJobs;
-};
 
 long long chunk_points(int rho) { return (long long)KITERS * KWAVES * (64 / lanes_per_point(rho)); }
 
 long long max_blocks(long long N, int rho, int K) { return N / chunk_points(rho) + 2LL * K + 4; }
+
+int record_width(int rho) { return 4 * rho + 8; }
+
+struct KmBuffers {
+    float* pts[2];
+    int* idx[2];
+    int4* btab;
+    int* blkA;
+    double* part;
+    int* ji;
+    double *jm, *ca, *cb, *la, *lb, *fa, *fb, *jd;
+    long long maxBlocks;
+    int maxJobs;
+};
 
 KmBuffers carve(Arena& ws, long long N, int rho, int K) {
     KmBuffers b{};
     b.maxJobs = std::max(2 * K, 4);
     b.maxBlocks = max_blocks(N, rho, K);
     for (int q = 0; q < 2; ++q) {
-        b.pts[q] = ws.take<float>((size_t)N * rho);
+        b.pts[q] = ws.take<float>((size_t)N * rho + 64);
         b.idx[q] = ws.take<int>((size_t)N);
-        b.side[q] = ws.take<unsigned char>((size_t)N);
     }
     b.btab = ws.take<int4>((size_t)b.maxBlocks);
     b.blkA = ws.take<int>((size_t)b.maxBlocks);
-    b.part = ws.take<double>((size_t)b.maxBlocks * (4 * rho + 8));
+    b.part = ws.take<double>((size_t)b.maxBlocks * record_width(rho));
     b.ji = ws.take<int>((size_t)b.maxJobs * JI_W);
-    b.jm = ws.take<double>((size_t)b.maxJobs * rho);
-    b.ca = ws.take<double>((size_t)b.maxJobs * rho);
-    b.cb = ws.take<double>((size_t)b.maxJobs * rho);
+    double** dv[] = {&b.jm, &b.ca, &b.cb, &b.la, &b.lb, &b.fa, &b.fb};
+    for (double** p : dv) *p = ws.take<double>((size_t)b.maxJobs * rho);
     b.jd = ws.take<double>((size_t)b.maxJobs * JD_W);
-    b.done = ws.take<unsigned>((size_t)b.maxJobs);
     return b;
 }
 
-template <int LP>
-struct Passes {
-    static void stats(dim3 g, hipStream_t s, const KmArgs& a) {
-        hipLaunchKernelGGL(km_stats<LP>, g, dim3(KT), 0, s, a);
-    }
-    static void far(dim3 g, hipStream_t s, const KmArgs& a, int which) {
-        hipLaunchKernelGGL(km_far<LP>, g, dim3(KT), 0, s, a, which);
-    }
-    static void lloyd(dim3 g, hipStream_t s, const KmArgs& a, int it, int T) {
-        hipLaunchKernelGGL(km_lloyd<LP>, g, dim3(KT), 0, s, a, it, T);
-    }
-    static void sse(dim3 g, hipStream_t s, const KmArgs& a, int single) {
-        hipLaunchKernelGGL(km_sse<LP>, g, dim3(KT), 0, s, a, single);
-    }
-};
-
-struct Dispatch {
-    void (*stats)(dim3, hipStream_t, const KmArgs&);
-    void (*far)(dim3, hipStream_t, const KmArgs&, int);
-    void (*lloyd)(dim3, hipStream_t, const KmArgs&, int, int);
-    void (*sse)(dim3, hipStream_t, const KmArgs&, int);
-};
+enum { P_STATS, P_SSE1, P_FAR, P_LLOYD, P_SPLIT, P_SCATTER };
 
 template <int LP>
-Dispatch make_dispatch() {
-    return Dispatch{&Passes<LP>::stats, &Passes<LP>::far, &Passes<LP>::lloyd, &Passes<LP>::sse};
+void launch_lp(int which, dim3 g, hipStream_t s, const KmArgs& a, int arg) {
+    switch (which) {
+        case P_STATS: hipLaunchKernelGGL(km_stats<LP>, g, dim3(KT), 0, s, a); break;
+        case P_SSE1: hipLaunchKernelGGL(km_sse1<LP>, g, dim3(KT), 0, s, a); break;
+        case P_FAR: hipLaunchKernelGGL(km_far<LP>, g, dim3(KT), 0, s, a, arg); break;
+        case P_LLOYD: hipLaunchKernelGGL(km_lloyd<LP>, g, dim3(KT), 0, s, a); break;
+        case P_SPLIT: hipLaunchKernelGGL(km_split<LP>, g, dim3(KT), 0, s, a); break;
+        default: hipLaunchKernelGGL(km_scatter<LP>, g, dim3(KT), 0, s, a); break;
+    }
 }
 
-Dispatch dispatch_for(int rho) {
-    switch (lanes_per_point(rho)) {
-        case 1: return make_dispatch<1>();
-        case 2: return make_dispatch<2>();
-        case 4: return make_dispatch<4>();
-        case 8: return make_dispatch<8>();
-        case 16: return make_dispatch<16>();
-        case 32: return make_dispatch<32>();
-        default: return make_dispatch<64>();
+void launch_pass(int lp, int which, dim3 g, hipStream_t s, const KmArgs& a, int arg = 0) {
+    switch (lp) {
+        case 1: launch_lp<1>(which, g, s, a, arg); break;
+        case 2: launch_lp<2>(which, g, s, a, arg); break;
+        case 4: launch_lp<4>(which, g, s, a, arg); break;
+        default: launch_lp<8>(which, g, s, a, arg); break;
     }
 }
 
@@ -675,20 +800,18 @@ size_t kmeans_workspace(long long N, int rho, int K) {
     return probe.used;
 }
 
-void kmeans_run(Ctx& c, Arena& ws, const float* guide, int rho, long long N, int K, int max_iter,
-                int* labels, KmResult& out) {
+void kmeans_run(Ctx& c, Arena& ws, const float* guide, int rho, long long N, int K, int max_iter, int* labels,
+                KmResult& out) {
     FHD_REQUIRE(N >= 1 && N < (1LL << 31), FHD_EINVAL, "image too large for clustering");
     FHD_REQUIRE(rho >= 1 && rho <= FHD_MAX_RHO, FHD_EUNSUPPORTED, "guide dimension out of range");
     FHD_REQUIRE(K >= 1 && K <= FHD_MAX_K, FHD_EINVAL, "K out of range");
     FHD_REQUIRE(max_iter >= 1, FHD_EINVAL, "kmeans_max_iter must be >= 1");
     KmBuffers B = carve(ws, N, rho, K);
-    const Dispatch D = dispatch_for(rho);
+    const int LP = lanes_per_point(rho);
     const long long CH = chunk_points(rho);
     hipStream_t st = c.stream;
 
-    // pinned staging: block table + per-job state
-    const size_t stage_bytes = align_up(sizeof(int4) * B.maxBlocks, 256) +
-                               align_up(sizeof(int) * B.maxJobs * JI_W, 256) +
+    const size_t stage_bytes = align_up(sizeof(int4) * B.maxBlocks, 256) + align_up(sizeof(int) * B.maxJobs * JI_W, 256) +
                                3 * align_up(sizeof(double) * B.maxJobs * rho, 256) +
                                align_up(sizeof(double) * B.maxJobs * JD_W, 256);
     char* hs = static_cast<char*>(c.host_stage(0, stage_bytes));
@@ -712,7 +835,6 @@ void kmeans_run(Ctx& c, Arena& ws, const float* guide, int rho, long long N, int
     for (int q = 0; q < 2; ++q) {
         a.pts[q] = B.pts[q];
         a.idx[q] = B.idx[q];
-        a.side[q] = B.side[q];
     }
     a.btab = B.btab;
     a.blkA = B.blkA;
@@ -721,15 +843,16 @@ void kmeans_run(Ctx& c, Arena& ws, const float* guide, int rho, long long N, int
     a.jm = B.jm;
     a.ca = B.ca;
     a.cb = B.cb;
+    a.la = B.la;
+    a.lb = B.lb;
+    a.fa = B.fa;
+    a.fb = B.fb;
     a.jd = B.jd;
-    a.done = B.done;
     a.rho = rho;
-    a.pw = 4 * rho + 8;
+    a.pw = record_width(rho);
 
     hipEvent_t t_begin = c.stage_begin();
-    FHD_HIP(hipMemsetAsync(B.done, 0, sizeof(unsigned) * B.maxJobs, st));
-    hipLaunchKernelGGL(km_pack, dim3((unsigned)((N + KT - 1) / KT)), dim3(KT), 0, st, guide, rho,
-                       N, B.pts[0], B.idx[0]);
+    hipLaunchKernelGGL(km_pack, dim3((unsigned)((N + KT - 1) / KT)), dim3(KT), 0, st, guide, rho, N, B.pts[0], B.idx[0]);
     FHD_HIP(hipGetLastError());
 
     // Upload jobs (ranges of leaves) and their block table; returns #blocks.
@@ -755,11 +878,9 @@ void kmeans_run(Ctx& c, Arena& ws, const float* guide, int rho, long long N, int
         }
         FHD_REQUIRE(nb <= B.maxBlocks, FHD_EINVAL, "internal: block table overflow");
         FHD_HIP(hipMemcpyAsync(B.btab, H.btab, sizeof(int4) * nb, hipMemcpyHostToDevice, st));
-        FHD_HIP(hipMemcpyAsync(B.ji, H.ji, sizeof(int) * JI_W * jobs.size(), hipMemcpyHostToDevice,
-                               st));
+        FHD_HIP(hipMemcpyAsync(B.ji, H.ji, sizeof(int) * JI_W * jobs.size(), hipMemcpyHostToDevice, st));
         if (with_mean)
-            FHD_HIP(hipMemcpyAsync(B.jm, H.jm, sizeof(double) * rho * jobs.size(),
-                                   hipMemcpyHostToDevice, st));
+            FHD_HIP(hipMemcpyAsync(B.jm, H.jm, sizeof(double) * rho * jobs.size(), hipMemcpyHostToDevice, st));
         return nb;
     };
 
@@ -775,8 +896,10 @@ void kmeans_run(Ctx& c, Arena& ws, const float* guide, int rho, long long N, int
     {
         std::vector<Leaf*> jobs{root};
         const int nb = upload(jobs, false, false);
-        D.stats(dim3(nb), st, a);
-        D.sse(dim3(nb), st, a, 1);
+        launch_pass(LP, P_STATS, dim3(nb), st, a);
+        hipLaunchKernelGGL(fin_stats, dim3(1), dim3(KT), 0, st, a);
+        launch_pass(LP, P_SSE1, dim3(nb), st, a);
+        hipLaunchKernelGGL(fin_sse1, dim3(1), dim3(KT), 0, st, a);
         FHD_HIP(hipGetLastError());
         FHD_HIP(hipMemcpyAsync(H.jm, B.jm, sizeof(double) * rho, hipMemcpyDeviceToHost, st));
         FHD_HIP(hipMemcpyAsync(H.jd, B.jd, sizeof(double) * JD_W, hipMemcpyDeviceToHost, st));
@@ -807,12 +930,18 @@ void kmeans_run(Ctx& c, Arena& ws, const float* guide, int rho, long long N, int
         if (!jobs.empty()) {
             FHD_REQUIRE((int)jobs.size() <= B.maxJobs, FHD_EINVAL, "internal: too many jobs");
             const int nb = upload(jobs, true, false);
-            const dim3 g(nb);
-            D.far(g, st, a, 0);
-            D.far(g, st, a, 1);
-            for (int it = 0; it < max_iter; ++it) D.lloyd(g, st, a, it, max_iter);
-            D.sse(g, st, a, 0);
-            hipLaunchKernelGGL(km_scatter, g, dim3(KT), 0, st, a);
+            const dim3 g(nb), gj((unsigned)jobs.size());
+            launch_pass(LP, P_FAR, g, st, a, 0);
+            hipLaunchKernelGGL(fin_far, gj, dim3(KT), 0, st, a, 0);
+            launch_pass(LP, P_FAR, g, st, a, 1);
+            hipLaunchKernelGGL(fin_far, gj, dim3(KT), 0, st, a, 1);
+            for (int it = 0; it < max_iter; ++it) {
+                launch_pass(LP, P_LLOYD, g, st, a);
+                hipLaunchKernelGGL(fin_lloyd, gj, dim3(KT), 0, st, a, max_iter);
+            }
+            launch_pass(LP, P_SPLIT, g, st, a);
+            hipLaunchKernelGGL(fin_split, gj, dim3(KT), 0, st, a);
+            launch_pass(LP, P_SCATTER, g, st, a);
             FHD_HIP(hipGetLastError());
             const size_t J = jobs.size();
             FHD_HIP(hipMemcpyAsync(H.ca, B.ca, sizeof(double) * rho * J, hipMemcpyDeviceToHost, st));
@@ -870,8 +999,7 @@ void kmeans_run(Ctx& c, Arena& ws, const float* guide, int rho, long long N, int
         if (!any) break;
     }
 
-    std::sort(leaves.begin(), leaves.end(),
-              [](const Leaf* x, const Leaf* y) { return heap_less(x->heap, y->heap); });
+    std::sort(leaves.begin(), leaves.end(), [](const Leaf* x, const Leaf* y) { return heap_less(x->heap, y->heap); });
     out.K_eff = (int)leaves.size();
     out.rounds = rounds;
     out.splits = splits;
