@@ -35,7 +35,8 @@ namespace {
 constexpr int KT = 256;          // threads per block
 constexpr int KWAVES = KT / 64;  // waves per block
 constexpr int KITERS = 16;       // point groups per block and pass
-constexpr int DPL = 8;           // dimensions per lane
+constexpr int DPL = 8;           // dimensions per lane (at most)
+constexpr int UNR = 4;           // points per lane group in flight per step
 
 // per-job integer state
 enum { JI_START, JI_COUNT, JI_BUF, JI_STOP, JI_STEPS, JI_FIRST, JI_NBLK, JI_NA, JI_W = 8 };
@@ -64,7 +65,7 @@ struct KmArgs {
 // ---------------------------------------------------------------------------
 // lane layout
 
-template <int LP>
+template <int LP, int D>
 struct Lanes {
     static constexpr int PPW = 64 / LP;  // points per wave
     int lane, wave, sub, pw, d0;
@@ -73,29 +74,31 @@ struct Lanes {
         wave = threadIdx.x >> 6;
         sub = lane & (LP - 1);
         pw = lane / LP;
-        d0 = sub * DPL;
+        d0 = sub * D;
     }
 };
 
 // this lane's dimensions of point `pos` (zero beyond rho)
-__device__ __forceinline__ void load_dims(const float* pts, long long pos, int rho, int d0, double (&x)[DPL]) {
+template <int D>
+__device__ __forceinline__ void load_dims(const float* pts, long long pos, int rho, int d0, double (&x)[D]) {
     const float* p = pts + pos * rho;
 #pragma unroll
-    for (int k = 0; k < DPL; ++k) x[k] = (d0 + k < rho) ? (double)p[d0 + k] : 0.0;
+    for (int k = 0; k < D; ++k) x[k] = (d0 + k < rho) ? (double)p[d0 + k] : 0.0;
 }
 
-__device__ __forceinline__ void load_center(const double* c, int rho, int d0, double (&v)[DPL]) {
+template <int D>
+__device__ __forceinline__ void load_center(const double* c, int rho, int d0, double (&v)[D]) {
 #pragma unroll
-    for (int k = 0; k < DPL; ++k) v[k] = (d0 + k < rho) ? c[d0 + k] : 0.0;
+    for (int k = 0; k < D; ++k) v[k] = (d0 + k < rho) ? c[d0 + k] : 0.0;
 }
 
 // |x - c|^2 over the point's dimensions: sequential over a lane's dimensions
 // (separately rounded products and sums), then a shuffle tree over its LP lanes.
-template <int LP>
-__device__ __forceinline__ double dist2(const double (&x)[DPL], const double (&c)[DPL], int rho, int d0) {
+template <int LP, int D>
+__device__ __forceinline__ double dist2(const double (&x)[D], const double (&c)[D], int rho, int d0) {
     double s = 0.0;
 #pragma unroll
-    for (int k = 0; k < DPL; ++k)
+    for (int k = 0; k < D; ++k)
         if (d0 + k < rho) {
             const double t = __dsub_rn(x[k], c[k]);
             s = __dadd_rn(s, __dmul_rn(t, t));
@@ -106,10 +109,10 @@ __device__ __forceinline__ double dist2(const double (&x)[DPL], const double (&c
 }
 
 // The assignment rule: first child iff |x - c_a|^2 <= |x - c_b|^2.
-template <int LP>
-__device__ __forceinline__ bool to_first(const double (&x)[DPL], const double (&a)[DPL], const double (&b)[DPL],
-                                         int rho, int d0) {
-    return dist2<LP>(x, a, rho, d0) <= dist2<LP>(x, b, rho, d0);
+template <int LP, int D>
+__device__ __forceinline__ bool to_first(const double (&x)[D], const double (&a)[D], const double (&b)[D], int rho,
+                                         int d0) {
+    return dist2<LP, D>(x, a, rho, d0) <= dist2<LP, D>(x, b, rho, d0);
 }
 
 template <int OP>
@@ -119,18 +122,18 @@ __device__ __forceinline__ double op2(double u, double v) {
 
 // Block reduction of per-lane dimension values (lanes with equal `sub` hold
 // the same dimensions); thread t < rho writes the total of dimension t to out[t].
-template <int LP, int OP>
-__device__ __forceinline__ void block_dims(double (&v)[DPL], double (*red)[64], int rho, double* out) {
+template <int LP, int D, int OP>
+__device__ __forceinline__ void block_dims(double (&v)[D], double (*red)[64], int rho, double* out) {
 #pragma unroll
-    for (int k = 0; k < DPL; ++k)
+    for (int k = 0; k < D; ++k)
 #pragma unroll
         for (int o = LP; o < 64; o <<= 1) v[k] = op2<OP>(v[k], __shfl_xor(v[k], o, 64));
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     __syncthreads();
     if (lane < LP)
 #pragma unroll
-        for (int k = 0; k < DPL; ++k)
-            if (lane * DPL + k < 64) red[wave][lane * DPL + k] = v[k];
+        for (int k = 0; k < D; ++k)
+            if (lane * D + k < 64) red[wave][lane * D + k] = v[k];
     __syncthreads();
     if (threadIdx.x < rho) {
         double r = red[0][threadIdx.x];
@@ -201,17 +204,17 @@ __global__ __launch_bounds__(KT) void km_pack(const float* __restrict__ guide, i
 }
 
 // Member sums and per-dimension min/max.  Record: sum[rho], min[rho], max[rho].
-template <int LP>
+template <int LP, int D>
 __global__ __launch_bounds__(KT) void km_stats(KmArgs a) {
     __shared__ double red[KWAVES][64];
     const int4 bt = a.btab[blockIdx.x];
     const int job = bt.x, s = bt.y, cnt = bt.z;
     const float* pts = a.pts[a.ji[job * JI_W + JI_BUF]];
     const int rho = a.rho;
-    const Lanes<LP> L;
-    double sum[DPL], mn[DPL], mx[DPL];
+    const Lanes<LP, D> L;
+    double sum[D], mn[D], mx[D];
 #pragma unroll
-    for (int k = 0; k < DPL; ++k) {
+    for (int k = 0; k < D; ++k) {
         sum[k] = 0.0;
         mn[k] = INFINITY;
         mx[k] = -INFINITY;
@@ -219,10 +222,10 @@ __global__ __launch_bounds__(KT) void km_stats(KmArgs a) {
     for (int base = 0; base < cnt; base += KWAVES * L.PPW) {
         const int p = base + L.wave * L.PPW + L.pw;
         if (p >= cnt) continue;
-        double x[DPL];
+        double x[D];
         load_dims(pts, s + p, rho, L.d0, x);
 #pragma unroll
-        for (int k = 0; k < DPL; ++k)
+        for (int k = 0; k < D; ++k)
             if (L.d0 + k < rho) {
                 sum[k] += x[k];
                 mn[k] = fmin(mn[k], x[k]);
@@ -230,30 +233,30 @@ __global__ __launch_bounds__(KT) void km_stats(KmArgs a) {
             }
     }
     double* rec = a.part + (long long)blockIdx.x * a.pw;
-    block_dims<LP, 0>(sum, red, rho, rec);
-    block_dims<LP, 1>(mn, red, rho, rec + rho);
-    block_dims<LP, 2>(mx, red, rho, rec + 2 * rho);
+    block_dims<LP, D, 0>(sum, red, rho, rec);
+    block_dims<LP, D, 1>(mn, red, rho, rec + rho);
+    block_dims<LP, D, 2>(mx, red, rho, rec + 2 * rho);
 }
 
 // SSE of the whole job around its centroid jm.  Record: sse.
-template <int LP>
+template <int LP, int D>
 __global__ __launch_bounds__(KT) void km_sse1(KmArgs a) {
     __shared__ double red[KWAVES][64];
     const int4 bt = a.btab[blockIdx.x];
     const int job = bt.x, s = bt.y, cnt = bt.z;
     const float* pts = a.pts[a.ji[job * JI_W + JI_BUF]];
     const int rho = a.rho;
-    const Lanes<LP> L;
-    double c[DPL];
+    const Lanes<LP, D> L;
+    double c[D];
     load_center(a.jm + job * rho, rho, L.d0, c);
     double e = 0.0;
     for (int base = 0; base < cnt; base += KWAVES * L.PPW) {
         const int p = base + L.wave * L.PPW + L.pw;
         if (p >= cnt) continue;
-        double x[DPL];
+        double x[D];
         load_dims(pts, s + p, rho, L.d0, x);
 #pragma unroll
-        for (int k = 0; k < DPL; ++k)
+        for (int k = 0; k < D; ++k)
             if (L.d0 + k < rho) {
                 const double t = x[k] - c[k];
                 e += t * t;
@@ -265,7 +268,7 @@ __global__ __launch_bounds__(KT) void km_sse1(KmArgs a) {
 
 // Seed search: the member farthest from the centroid (which == 0) or from the
 // first seed (which == 1); ties -> lowest pixel index.  Record: d, pixel, pos.
-template <int LP>
+template <int LP, int D>
 __global__ __launch_bounds__(KT) void km_far(KmArgs a, int which) {
     __shared__ double rb[KWAVES];
     __shared__ int ri[KWAVES], rp[KWAVES];
@@ -275,23 +278,29 @@ __global__ __launch_bounds__(KT) void km_far(KmArgs a, int which) {
     const float* pts = a.pts[buf];
     const int* idx = a.idx[buf];
     const int rho = a.rho;
-    const Lanes<LP> L;
-    double r[DPL];
+    const Lanes<LP, D> L;
+    double r[D];
     load_center((which == 0 ? a.jm : a.ca) + job * rho, rho, L.d0, r);
     double best = -1.0;
     int bidx = INT_MAX, bpos = -1;
-    for (int base = 0; base < cnt; base += KWAVES * L.PPW) {
-        const int p = base + L.wave * L.PPW + L.pw;
-        const bool valid = p < cnt;
-        double x[DPL];
-        load_dims(pts, valid ? s + p : s, rho, L.d0, x);
-        const double t = dist2<LP>(x, r, rho, L.d0);
-        if (valid) {
-            const int pi = idx[s + p];
-            if (t > best || (t == best && pi < bidx)) {
-                best = t;
-                bidx = pi;
-                bpos = s + p;
+    for (int base = 0; base < cnt; base += UNR * KWAVES * L.PPW) {
+        double x[UNR][D];
+        int pp[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            pp[u] = base + (u * KWAVES + L.wave) * L.PPW + L.pw;
+            load_dims(pts, pp[u] < cnt ? s + pp[u] : s, rho, L.d0, x[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const double t = dist2<LP, D>(x[u], r, rho, L.d0);
+            if (pp[u] < cnt) {
+                const int pi = idx[s + pp[u]];
+                if (t > best || (t == best && pi < bidx)) {
+                    best = t;
+                    bidx = pi;
+                    bpos = s + pp[u];
+                }
             }
         }
     }
@@ -328,7 +337,7 @@ __global__ __launch_bounds__(KT) void km_far(KmArgs a, int which) {
 
 // One assignment step with the current centers (ca, cb).
 // Record: sumA[rho], sumB[rho], nA, nB.
-template <int LP>
+template <int LP, int D>
 __global__ __launch_bounds__(KT) void km_lloyd(KmArgs a) {
     __shared__ double red[KWAVES][64];
     const int4 bt = a.btab[blockIdx.x];
@@ -337,34 +346,42 @@ __global__ __launch_bounds__(KT) void km_lloyd(KmArgs a) {
     if (ji[JI_STOP]) return;
     const float* pts = a.pts[ji[JI_BUF]];
     const int rho = a.rho;
-    const Lanes<LP> L;
-    double ca[DPL], cb[DPL], sa[DPL], sb[DPL];
+    const Lanes<LP, D> L;
+    double ca[D], cb[D], sa[D], sb[D];
     load_center(a.ca + job * rho, rho, L.d0, ca);
     load_center(a.cb + job * rho, rho, L.d0, cb);
 #pragma unroll
-    for (int k = 0; k < DPL; ++k) sa[k] = sb[k] = 0.0;
+    for (int k = 0; k < D; ++k) sa[k] = sb[k] = 0.0;
     double na = 0.0, nb = 0.0;
-    for (int base = 0; base < cnt; base += KWAVES * L.PPW) {
-        const int p = base + L.wave * L.PPW + L.pw;
-        const bool valid = p < cnt;
-        double x[DPL];
-        load_dims(pts, valid ? s + p : s, rho, L.d0, x);
-        const bool A = to_first<LP>(x, ca, cb, rho, L.d0);
-        if (valid) {
+    // UNR points per lane group per step, all loads issued before use
+    for (int base = 0; base < cnt; base += UNR * KWAVES * L.PPW) {
+        double x[UNR][D];
+        bool valid[UNR];
 #pragma unroll
-            for (int k = 0; k < DPL; ++k) {
-                if (A) sa[k] += x[k];
-                else sb[k] += x[k];
-            }
-            if (L.sub == 0) {
-                if (A) na += 1.0;
-                else nb += 1.0;
+        for (int u = 0; u < UNR; ++u) {
+            const int p = base + (u * KWAVES + L.wave) * L.PPW + L.pw;
+            valid[u] = p < cnt;
+            load_dims(pts, valid[u] ? s + p : s, rho, L.d0, x[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const bool A = to_first<LP, D>(x[u], ca, cb, rho, L.d0);
+            if (valid[u]) {
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    if (A) sa[k] += x[u][k];
+                    else sb[k] += x[u][k];
+                }
+                if (L.sub == 0) {
+                    if (A) na += 1.0;
+                    else nb += 1.0;
+                }
             }
         }
     }
     double* rec = a.part + (long long)blockIdx.x * a.pw;
-    block_dims<LP, 0>(sa, red, rho, rec);
-    block_dims<LP, 0>(sb, red, rho, rec + rho);
+    block_dims<LP, D, 0>(sa, red, rho, rec);
+    block_dims<LP, D, 0>(sb, red, rho, rec + rho);
     const double tna = block_sum(na, red);
     const double tnb = block_sum(nb, red);
     if (threadIdx.x == 0) {
@@ -376,51 +393,58 @@ __global__ __launch_bounds__(KT) void km_lloyd(KmArgs a) {
 // Final labels (assignment with fa, fb): per child member count, SSE around
 // the child's centroid (ca / cb) and per-dimension min/max.
 // Record: sseA, sseB, nA, nB, minA[rho], maxA[rho], minB[rho], maxB[rho].
-template <int LP>
+template <int LP, int D>
 __global__ __launch_bounds__(KT) void km_split(KmArgs a) {
     __shared__ double red[KWAVES][64];
     const int4 bt = a.btab[blockIdx.x];
     const int job = bt.x, s = bt.y, cnt = bt.z;
     const float* pts = a.pts[a.ji[job * JI_W + JI_BUF]];
     const int rho = a.rho;
-    const Lanes<LP> L;
-    double fa[DPL], fb[DPL], ma[DPL], mb[DPL];
+    const Lanes<LP, D> L;
+    double fa[D], fb[D], ma[D], mb[D];
     load_center(a.fa + job * rho, rho, L.d0, fa);
     load_center(a.fb + job * rho, rho, L.d0, fb);
     load_center(a.ca + job * rho, rho, L.d0, ma);
     load_center(a.cb + job * rho, rho, L.d0, mb);
-    double lo_a[DPL], hi_a[DPL], lo_b[DPL], hi_b[DPL];
+    double lo_a[D], hi_a[D], lo_b[D], hi_b[D];
 #pragma unroll
-    for (int k = 0; k < DPL; ++k) {
+    for (int k = 0; k < D; ++k) {
         lo_a[k] = lo_b[k] = INFINITY;
         hi_a[k] = hi_b[k] = -INFINITY;
     }
     double ea = 0.0, eb = 0.0, na = 0.0, nb = 0.0;
-    for (int base = 0; base < cnt; base += KWAVES * L.PPW) {
-        const int p = base + L.wave * L.PPW + L.pw;
-        const bool valid = p < cnt;
-        double x[DPL];
-        load_dims(pts, valid ? s + p : s, rho, L.d0, x);
-        const bool A = to_first<LP>(x, fa, fb, rho, L.d0);
-        if (!valid) continue;
+    for (int base = 0; base < cnt; base += UNR * KWAVES * L.PPW) {
+        double x[UNR][D];
+        bool valid[UNR];
 #pragma unroll
-        for (int k = 0; k < DPL; ++k) {
-            if (L.d0 + k >= rho) continue;
-            if (A) {
-                const double t = x[k] - ma[k];
-                ea += t * t;
-                lo_a[k] = fmin(lo_a[k], x[k]);
-                hi_a[k] = fmax(hi_a[k], x[k]);
-            } else {
-                const double t = x[k] - mb[k];
-                eb += t * t;
-                lo_b[k] = fmin(lo_b[k], x[k]);
-                hi_b[k] = fmax(hi_b[k], x[k]);
-            }
+        for (int u = 0; u < UNR; ++u) {
+            const int p = base + (u * KWAVES + L.wave) * L.PPW + L.pw;
+            valid[u] = p < cnt;
+            load_dims(pts, valid[u] ? s + p : s, rho, L.d0, x[u]);
         }
-        if (L.sub == 0) {
-            if (A) na += 1.0;
-            else nb += 1.0;
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const bool A = to_first<LP, D>(x[u], fa, fb, rho, L.d0);
+            if (!valid[u]) continue;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                if (L.d0 + k >= rho) continue;
+                if (A) {
+                    const double t = x[u][k] - ma[k];
+                    ea += t * t;
+                    lo_a[k] = fmin(lo_a[k], x[u][k]);
+                    hi_a[k] = fmax(hi_a[k], x[u][k]);
+                } else {
+                    const double t = x[u][k] - mb[k];
+                    eb += t * t;
+                    lo_b[k] = fmin(lo_b[k], x[u][k]);
+                    hi_b[k] = fmax(hi_b[k], x[u][k]);
+                }
+            }
+            if (L.sub == 0) {
+                if (A) na += 1.0;
+                else nb += 1.0;
+            }
         }
     }
     double* rec = a.part + (long long)blockIdx.x * a.pw;
@@ -435,15 +459,15 @@ __global__ __launch_bounds__(KT) void km_split(KmArgs a) {
         rec[3] = tnb;
         a.blkA[blockIdx.x] = (int)tna;
     }
-    block_dims<LP, 1>(lo_a, red, rho, rec + 4);
-    block_dims<LP, 2>(hi_a, red, rho, rec + 4 + rho);
-    block_dims<LP, 1>(lo_b, red, rho, rec + 4 + 2 * rho);
-    block_dims<LP, 2>(hi_b, red, rho, rec + 4 + 3 * rho);
+    block_dims<LP, D, 1>(lo_a, red, rho, rec + 4);
+    block_dims<LP, D, 2>(hi_a, red, rho, rec + 4 + rho);
+    block_dims<LP, D, 1>(lo_b, red, rho, rec + 4 + 2 * rho);
+    block_dims<LP, D, 2>(hi_b, red, rho, rec + 4 + 3 * rho);
 }
 
 // Stable partition of each job's range by the final labels into the other
 // copy: first-child members first, both groups in their original order.
-template <int LP>
+template <int LP, int D>
 __global__ __launch_bounds__(KT) void km_scatter(KmArgs a) {
     __shared__ int red[KWAVES];
     __shared__ int s_offA, s_offB, s_wa[KWAVES], s_wb[KWAVES];
@@ -457,8 +481,8 @@ __global__ __launch_bounds__(KT) void km_scatter(KmArgs a) {
     int* idst = a.idx[1 - buf];
     const int rho = a.rho;
     const int start = ji[JI_START], NA = ji[JI_NA], first = ji[JI_FIRST];
-    const Lanes<LP> L;
-    double fa[DPL], fb[DPL];
+    const Lanes<LP, D> L;
+    double fa[D], fb[D];
     load_center(a.fa + job * rho, rho, L.d0, fa);
     load_center(a.fb + job * rho, rho, L.d0, fb);
     // members of the first child in the earlier blocks of this job
@@ -481,9 +505,9 @@ __global__ __launch_bounds__(KT) void km_scatter(KmArgs a) {
     for (int base = 0; base < cnt; base += KWAVES * L.PPW) {
         const int p = base + L.wave * L.PPW + L.pw;
         const bool valid = p < cnt;
-        double x[DPL];
+        double x[D];
         load_dims(src, valid ? s + p : s, rho, L.d0, x);
-        const bool A = to_first<LP>(x, fa, fb, rho, L.d0);
+        const bool A = to_first<LP, D>(x, fa, fb, rho, L.d0);
         const bool lead = valid && L.sub == 0;
         const unsigned long long ma = __ballot(lead && A);
         const unsigned long long mb = __ballot(lead && !A);
@@ -507,7 +531,7 @@ __global__ __launch_bounds__(KT) void km_scatter(KmArgs a) {
         if (valid) {
             const int to = A ? offA + pa + ra : offB + pb + rb;
 #pragma unroll
-            for (int k = 0; k < DPL; ++k)
+            for (int k = 0; k < D; ++k)
                 if (L.d0 + k < rho) dst[(long long)to * rho + L.d0 + k] = src[(long long)(s + p) * rho + L.d0 + k];
             if (L.sub == 0) idst[to] = isrc[s + p];
         }
@@ -761,25 +785,26 @@ KmBuffers carve(Arena& ws, long long N, int rho, int K) {
 
 enum { P_STATS, P_SSE1, P_FAR, P_LLOYD, P_SPLIT, P_SCATTER };
 
-template <int LP>
+template <int LP, int D>
 void launch_lp(int which, dim3 g, hipStream_t s, const KmArgs& a, int arg) {
     switch (which) {
-        case P_STATS: hipLaunchKernelGGL(km_stats<LP>, g, dim3(KT), 0, s, a); break;
-        case P_SSE1: hipLaunchKernelGGL(km_sse1<LP>, g, dim3(KT), 0, s, a); break;
-        case P_FAR: hipLaunchKernelGGL(km_far<LP>, g, dim3(KT), 0, s, a, arg); break;
-        case P_LLOYD: hipLaunchKernelGGL(km_lloyd<LP>, g, dim3(KT), 0, s, a); break;
-        case P_SPLIT: hipLaunchKernelGGL(km_split<LP>, g, dim3(KT), 0, s, a); break;
-        default: hipLaunchKernelGGL(km_scatter<LP>, g, dim3(KT), 0, s, a); break;
+        case P_STATS: hipLaunchKernelGGL((km_stats<LP, D>), g, dim3(KT), 0, s, a); break;
+        case P_SSE1: hipLaunchKernelGGL((km_sse1<LP, D>), g, dim3(KT), 0, s, a); break;
+        case P_FAR: hipLaunchKernelGGL((km_far<LP, D>), g, dim3(KT), 0, s, a, arg); break;
+        case P_LLOYD: hipLaunchKernelGGL((km_lloyd<LP, D>), g, dim3(KT), 0, s, a); break;
+        case P_SPLIT: hipLaunchKernelGGL((km_split<LP, D>), g, dim3(KT), 0, s, a); break;
+        default: hipLaunchKernelGGL((km_scatter<LP, D>), g, dim3(KT), 0, s, a); break;
     }
 }
 
-void launch_pass(int lp, int which, dim3 g, hipStream_t s, const KmArgs& a, int arg = 0) {
-    switch (lp) {
-        case 1: launch_lp<1>(which, g, s, a, arg); break;
-        case 2: launch_lp<2>(which, g, s, a, arg); break;
-        case 4: launch_lp<4>(which, g, s, a, arg); break;
-        default: launch_lp<8>(which, g, s, a, arg); break;
-    }
+// lane layout by guide dimension: one lane per point with four or eight
+// dimensions, or LP lanes of eight dimensions each
+void launch_pass(int rho, int which, dim3 g, hipStream_t s, const KmArgs& a, int arg = 0) {
+    if (rho <= 4) launch_lp<1, 4>(which, g, s, a, arg);
+    else if (rho <= 8) launch_lp<1, 8>(which, g, s, a, arg);
+    else if (rho <= 16) launch_lp<2, 8>(which, g, s, a, arg);
+    else if (rho <= 32) launch_lp<4, 8>(which, g, s, a, arg);
+    else launch_lp<8, 8>(which, g, s, a, arg);
 }
 
 // Host staging layout (pinned): block table, job ints, job doubles.
@@ -807,7 +832,6 @@ void kmeans_run(Ctx& c, Arena& ws, const float* guide, int rho, long long N, int
     FHD_REQUIRE(K >= 1 && K <= FHD_MAX_K, FHD_EINVAL, "K out of range");
     FHD_REQUIRE(max_iter >= 1, FHD_EINVAL, "kmeans_max_iter must be >= 1");
     KmBuffers B = carve(ws, N, rho, K);
-    const int LP = lanes_per_point(rho);
     const long long CH = chunk_points(rho);
     hipStream_t st = c.stream;
 
@@ -896,9 +920,9 @@ void kmeans_run(Ctx& c, Arena& ws, const float* guide, int rho, long long N, int
     {
         std::vector<Leaf*> jobs{root};
         const int nb = upload(jobs, false, false);
-        launch_pass(LP, P_STATS, dim3(nb), st, a);
+        launch_pass(rho, P_STATS, dim3(nb), st, a);
         hipLaunchKernelGGL(fin_stats, dim3(1), dim3(KT), 0, st, a);
-        launch_pass(LP, P_SSE1, dim3(nb), st, a);
+        launch_pass(rho, P_SSE1, dim3(nb), st, a);
         hipLaunchKernelGGL(fin_sse1, dim3(1), dim3(KT), 0, st, a);
         FHD_HIP(hipGetLastError());
         FHD_HIP(hipMemcpyAsync(H.jm, B.jm, sizeof(double) * rho, hipMemcpyDeviceToHost, st));
@@ -931,17 +955,17 @@ void kmeans_run(Ctx& c, Arena& ws, const float* guide, int rho, long long N, int
             FHD_REQUIRE((int)jobs.size() <= B.maxJobs, FHD_EINVAL, "internal: too many jobs");
             const int nb = upload(jobs, true, false);
             const dim3 g(nb), gj((unsigned)jobs.size());
-            launch_pass(LP, P_FAR, g, st, a, 0);
+            launch_pass(rho, P_FAR, g, st, a, 0);
             hipLaunchKernelGGL(fin_far, gj, dim3(KT), 0, st, a, 0);
-            launch_pass(LP, P_FAR, g, st, a, 1);
+            launch_pass(rho, P_FAR, g, st, a, 1);
             hipLaunchKernelGGL(fin_far, gj, dim3(KT), 0, st, a, 1);
             for (int it = 0; it < max_iter; ++it) {
-                launch_pass(LP, P_LLOYD, g, st, a);
+                launch_pass(rho, P_LLOYD, g, st, a);
                 hipLaunchKernelGGL(fin_lloyd, gj, dim3(KT), 0, st, a, max_iter);
             }
-            launch_pass(LP, P_SPLIT, g, st, a);
+            launch_pass(rho, P_SPLIT, g, st, a);
             hipLaunchKernelGGL(fin_split, gj, dim3(KT), 0, st, a);
-            launch_pass(LP, P_SCATTER, g, st, a);
+            launch_pass(rho, P_SCATTER, g, st, a);
             FHD_HIP(hipGetLastError());
             const size_t J = jobs.size();
             FHD_HIP(hipMemcpyAsync(H.ca, B.ca, sizeof(double) * rho * J, hipMemcpyDeviceToHost, st));
