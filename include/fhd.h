@@ -181,6 +181,20 @@ fhd_status fhd_filter(fhd_ctx* ctx, const float* f, int n, const float* guide, i
 fhd_status fhd_bruteforce(fhd_ctx* ctx, const float* f, int n, const float* guide, int rho,
                           int H, int W, const fhd_params* p, float* out, float* den);
 
+/* The guide of nonlocal means (Sec. I-A; PCA of patches as in Sec. IV-C):
+ * every pixel's patch x (patch x patch x n values, half-sample symmetric
+ * extension at the borders, flattened in (dy, dx, channel) order) is
+ * projected onto the `dims` leading eigenvectors of the patch covariance
+ * (1/N normalised, FP64 on the host):  guide_d(i) = sum_j (x_j(i) - mean_j) V_jd.
+ * Each eigenvector's largest-magnitude component is made positive.
+ *   f        device n x H x W;  patch odd, patch*patch*n <= 160;
+ *   dims     1 .. min(patch*patch*n, FHD_MAX_RHO);
+ *   guide    device dims x H x W (output);
+ *   eigvals  host, patch*patch*n covariance eigenvalues in descending order, or NULL.
+ * Synchronises (the eigen-decomposition runs on the host between kernels). */
+fhd_status fhd_nlm_guide(fhd_ctx* ctx, const float* f, int n, int H, int W, int patch, int dims,
+                         float* guide, double* eigvals);
+
 /* Stage timing with HIP events on the context's stream (for benchmarks).
  * While enabled, every call records an event pair around each stage's
  * kernels; fhd_timing_read returns, per stage, the summed elapsed

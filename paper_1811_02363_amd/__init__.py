@@ -34,7 +34,8 @@ COEF = {"lsq": 0, "hard": 1}
 symbols = [
     "fhd_default_params", "fhd_create", "fhd_destroy", "fhd_set_stream", "fhd_last_error",
     "fhd_workspace_size", "fhd_set_workspace", "fhd_cluster", "fhd_pinv",
-    "fhd_filter_centers", "fhd_filter", "fhd_bruteforce", "fhd_timing_enable", "fhd_timing_read",
+    "fhd_filter_centers", "fhd_filter", "fhd_bruteforce", "fhd_nlm_guide", "fhd_timing_enable",
+    "fhd_timing_read",
 ]
 STAGES = ("cluster", "weights", "row", "col", "brute")
 
@@ -99,6 +100,7 @@ def load():
             "fhd_filter_centers": (I, [V, V, I, V, I, I, I, V, I, V, pp, V, V, pi]),
             "fhd_filter": (I, [V, V, I, V, I, I, I, pp, V, V, V, pi]),
             "fhd_bruteforce": (I, [V, V, I, V, I, I, I, pp, V, V]),
+            "fhd_nlm_guide": (I, [V, V, I, I, I, I, I, V, V]),
             "fhd_timing_enable": (I, [V, I]),
             "fhd_timing_read": (I, [V, P(D), P(I)]),
         }
@@ -268,6 +270,21 @@ def bruteforce(f, guide=None, sigma_s=3.0, sigma_r=0.1, spatial="gaussian", radi
                                  ctypes.byref(p), _dev(out, "out"),
                                  _dev(den, "den") if den is not None else None), ctx)
     return (out, den) if return_den else out
+
+
+def nlm_guide(f, patch=5, dims=16, eigvals=False):
+    """Patch-PCA guide of nonlocal means: (dims, H, W) float32 on the device
+    [, covariance eigenvalues (float64, descending)]."""
+    if not isinstance(f, torch.Tensor) or not f.is_cuda or f.dim() != 3:
+        raise FHDError(FHD_EINVAL, "f must be a (C, H, W) CUDA (HIP) tensor")
+    n, H, W = f.shape
+    ctx = _ctx(f.device.index)
+    g = torch.empty((dims, H, W), device=f.device, dtype=torch.float32)
+    D = patch * patch * n
+    ev = torch.zeros(D, dtype=torch.float64)
+    _check(load().fhd_nlm_guide(ctx, _dev(f, "f"), n, H, W, int(patch), int(dims), _dev(g, "guide"),
+                                ctypes.c_void_p(ev.data_ptr()) if eigvals else None), ctx)
+    return (g, ev) if eigvals else g
 
 
 def timing_enable(device=0, enable=True):

@@ -493,6 +493,21 @@ fhd_status fhd_bruteforce(fhd_ctx* ctx, const float* f, int n, const float* guid
     });
 }
 
+fhd_status fhd_nlm_guide(fhd_ctx* ctx, const float* f, int n, int H, int W, int patch, int dims, float* guide,
+                         double* eigvals) {
+    return guarded(ctx, [&](Ctx& c) {
+        FHD_REQUIRE(f != nullptr && guide != nullptr, FHD_EINVAL, "NULL pointer");
+        FHD_REQUIRE(n >= 1 && H >= 1 && W >= 1 && patch >= 1, FHD_EINVAL, "n, H, W, patch must be >= 1");
+        FHD_REQUIRE((long long)H * W < (1LL << 31), FHD_EUNSUPPORTED, "image has 2^31 pixels or more");
+        const long long N = (long long)H * W;
+        FHD_REQUIRE(!ranges_overlap(guide, sizeof(float) * N * dims, f, sizeof(float) * N * n), FHD_EINVAL,
+                    "guide aliases the image");
+        Arena ws = c.arena(nlm_workspace(n, H, W, patch, dims));
+        nlm_guide_run(c, ws, f, n, H, W, patch, dims, guide, eigvals);
+        if (eigvals) FHD_HIP(hipStreamSynchronize(c.stream));
+    });
+}
+
 fhd_status fhd_timing_enable(fhd_ctx* ctx, int enable) {
     return guarded(ctx, [&](Ctx& c) { c.timing = enable != 0; });
 }

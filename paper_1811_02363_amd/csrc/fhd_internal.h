@@ -72,8 +72,11 @@ struct PinvResult {
 };
 // A (K x K, row-major) = phi(mu_k - mu_l) from FP32 centers promoted to FP64.
 void kernel_matrix(const float* centers, int K, int rho, double sigma_r, double* A);
-// Pseudo-inverse of the symmetric A by cyclic Jacobi; rtol <= 0: K * 2^-52.
+// Pseudo-inverse of the symmetric A; rtol <= 0: K * 2^-52 relative to s_max.
 PinvResult pinv_symmetric(const double* A, int K, double rtol, double* P);
+// Symmetric eigen-decomposition (t destroyed): eigenvalues lam (unsorted),
+// column i of v (row-major n x n) the i-th unit eigenvector.
+void sym_eigen(std::vector<double>& t, int n, std::vector<double>& lam, std::vector<double>& v);
 
 // ---- filter passes (filter.hip) --------------------------------------------
 struct FilterPlan {
@@ -89,6 +92,11 @@ void filter_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const f
                 float* out, float* den);
 void bruteforce_run(Ctx& c, const FilterPlan& fp, const float* f, const float* guide,
                     float* out, float* den);
+
+// ---- nonlocal-means guide (nlm.hip) ----------------------------------------
+size_t nlm_workspace(int n, int H, int W, int m, int dims);
+void nlm_guide_run(Ctx& c, Arena& ws, const float* f, int n, int H, int W, int m, int dims, float* guide,
+                   double* eigvals);
 
 // ---- context ---------------------------------------------------------------
 struct Ctx {

@@ -574,6 +574,146 @@ __global__ __launch_bounds__(RT) void weights_fp32(FA a, float* Bpl, float* Cpl)
 }
 
 // ---------------------------------------------------------------------------
+// Weights pass with the point-to-center distance as a matrix contraction on
+// the matrix cores: D = |p~|^2 + |mu~|^2 - 2 p~ . mu~, where p~ = round(p - o)
+// and mu~ = round(mu - o) are BF16 or FP16 values (o is the mean of the
+// centers: distances do not change under a common shift, and the shift keeps
+// the rounded coordinates small).  Products of 16-bit values are exact in the
+// FP32 accumulator, and the norms are taken from the same rounded values, so
+// D is the distance between the rounded points up to FP32 accumulation; it is
+// clamped at 0.  b = exp(-D / 2 sigma_r^2) in FP32, c = A^+ b in FP32.
+// A block handles 64 pixels of a row, each wave 16 of them against all
+// centers, 16 centers per 16x16x16 product (dims in chunks of 16).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef short i16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+
+constexpr int MW_PIX = 64;                      // pixels per block
+constexpr int MW_RHO = FHD_MAX_RHO;             // padded dims
+constexpr int MW_K = FHD_MAX_K;
+
+__device__ __forceinline__ unsigned short to_bf16(float x) {
+    // round to nearest even (finite inputs)
+    const unsigned u = __float_as_uint(x);
+    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float from_bf16(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+template <bool BF16>
+__device__ __forceinline__ unsigned short round16(float x) {
+    if (BF16) return to_bf16(x);
+    const _Float16 h = (_Float16)x;
+    return *reinterpret_cast<const unsigned short*>(&h);
+}
+template <bool BF16>
+__device__ __forceinline__ float widen16(unsigned short v) {
+    if (BF16) return from_bf16(v);
+    return (float)*reinterpret_cast<const _Float16*>(&v);
+}
+
+template <bool BF16>
+__global__ __launch_bounds__(RT) void weights_mfma(FA a, float* Bpl, float* Cpl, const float* offs) {
+    __shared__ unsigned short smu[MW_K * MW_RHO];  // rounded centers, dims padded with 0
+    __shared__ float smn[MW_K];                    // |mu~|^2
+    __shared__ float spn[MW_PIX];                  // |p~|^2
+    __shared__ float sb[MW_PIX * (MW_K + 1)];      // b for the block's pixels
+    const int K = a.K, rho = a.rho;
+    const int rp = (rho + 15) & ~15;               // dims rounded up to whole chunks
+    const int y = blockIdx.y, x0 = blockIdx.x * MW_PIX;
+    for (int t = threadIdx.x; t < K * rp; t += RT) {
+        const int k = t / rp, d = t - k * rp;
+        smu[k * MW_RHO + d] = d < rho ? round16<BF16>(a.mu[k * rho + d] - offs[d]) : (unsigned short)0;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < K; k += RT) {
+        float s = 0.0f;
+        for (int d = 0; d < rho; ++d) {
+            const float v = widen16<BF16>(smu[k * MW_RHO + d]);
+            s = fmaf(v, v, s);
+        }
+        smn[k] = s;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = lane & 15, kq = lane >> 4;       // fragment row / dim quad
+    const int pix = wave * 16 + i;                 // this lane's pixel for the A fragment
+    const int x = x0 + pix;
+    const bool inx = x < a.W;
+    const long long off = (long long)y * a.W + x;
+    // A fragments: pixel pix, dims 16c + 4kq + e
+    unsigned short af[MW_RHO / 4];
+    float pn = 0.0f;
+#pragma unroll
+    for (int c = 0; c < MW_RHO / 16; ++c)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int d = 16 * c + 4 * kq + e;
+            unsigned short v = 0;
+            if (16 * c < rp && d < rho && inx) v = round16<BF16>(a.p[(long long)d * a.N + off] - offs[d]);
+            af[4 * c + e] = v;
+            const float w = widen16<BF16>(v);
+            pn = fmaf(w, w, pn);
+        }
+    pn += __shfl_xor(pn, 16, 64);
+    pn += __shfl_xor(pn, 32, 64);
+    if (kq == 0) spn[pix] = pn;
+    __syncthreads();
+    for (int t0 = 0; t0 < K; t0 += 16) {
+        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        const int cen = t0 + i;                    // B fragment column (center)
+#pragma unroll
+        for (int c = 0; c < MW_RHO / 16; ++c) {
+            if (16 * c >= rp) break;
+            i16x4 av, bv;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                av[e] = (short)af[4 * c + e];
+                bv[e] = cen < K ? (short)smu[cen * MW_RHO + 16 * c + 4 * kq + e] : (short)0;
+            }
+            if (BF16) {
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+            } else {
+                acc = __builtin_amdgcn_mfma_f32_16x16x16f16(*reinterpret_cast<f16x4*>(&av),
+                                                            *reinterpret_cast<f16x4*>(&bv), acc, 0, 0, 0);
+            }
+        }
+        // acc[e] = p~(pixel wave*16 + 4kq + e) . mu~(center t0 + i)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int pr = wave * 16 + 4 * kq + e;
+            if (cen < K) {
+                const float d2 = fmaxf(spn[pr] + smn[cen] - 2.0f * acc[e], 0.0f);
+                sb[pr * (MW_K + 1) + cen] = __expf(-d2 * a.inv2s2);
+            }
+        }
+    }
+    __syncthreads();
+    const long long prow = (long long)y * a.Wp;
+    for (int t = threadIdx.x; t < MW_PIX * K; t += RT) {
+        const int l = t / MW_PIX, h = t - l * MW_PIX;
+        if (x0 + h < a.W) Bpl[(long long)l * a.Np + prow + x0 + h] = sb[h * (MW_K + 1) + l];
+    }
+    if (Cpl == nullptr) return;
+    const int groups = (K + 7) >> 3;
+    for (int t = threadIdx.x; t < MW_PIX * groups; t += RT) {
+        const int g = t / MW_PIX, h = t - g * MW_PIX;
+        if (x0 + h >= a.W) continue;
+        float acc2[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc2[q] = 0.0f;
+        for (int m = 0; m < K; ++m) {
+            const float bv = sb[h * (MW_K + 1) + m];
+            const float* prow2 = a.P + (long long)m * K + g * 8;
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (g * 8 + q < K) acc2[q] = fmaf(prow2[q], bv, acc2[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (g * 8 + q < K) Cpl[(long long)(g * 8 + q) * a.Np + prow + x0 + h] = acc2[q];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Brute force, eqs. (1)-(2): one thread per output pixel, window read from a
 // 16 x 16-output LDS tile with halo when it fits, else from global memory.
 __global__ __launch_bounds__(RT) void brute_lds(FA a) {
@@ -743,6 +883,7 @@ size_t filter_workspace(const FilterPlan& fp) {
     }
     probe.take<float>((size_t)fp.K * fp.rho);
     probe.take<float>((size_t)fp.K * fp.K);
+    probe.take<float>((size_t)fp.rho);
     return probe.used;
 }
 
@@ -759,14 +900,24 @@ void filter_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const f
     }
     float* mu = ws.take<float>((size_t)fp.K * fp.rho);
     float* P = ws.take<float>((size_t)fp.K * fp.K);
+    float* offs = ws.take<float>((size_t)fp.rho);
     hipStream_t st = c.stream;
-    // stage centers and A^+ through pinned memory (async, stream ordered)
+    // stage centers, A^+ and the contraction offset (mean of the centers)
+    // through pinned memory (async, stream ordered)
     const size_t kb = sizeof(float) * fp.K * fp.rho, pb = sizeof(float) * fp.K * fp.K;
-    char* hs = static_cast<char*>(c.host_stage(1, align_up(kb, 256) + pb));
+    const size_t ob = sizeof(float) * fp.rho;
+    char* hs = static_cast<char*>(c.host_stage(1, align_up(kb, 256) + align_up(pb, 256) + ob));
     std::memcpy(hs, centers_host, kb);
     std::memcpy(hs + align_up(kb, 256), Pfp32_host, pb);
+    float* ho = reinterpret_cast<float*>(hs + align_up(kb, 256) + align_up(pb, 256));
+    for (int d = 0; d < fp.rho; ++d) {
+        double s = 0.0;
+        for (int k = 0; k < fp.K; ++k) s += centers_host[(size_t)k * fp.rho + d];
+        ho[d] = (float)(s / fp.K);
+    }
     FHD_HIP(hipMemcpyAsync(mu, hs, kb, hipMemcpyHostToDevice, st));
     FHD_HIP(hipMemcpyAsync(P, hs + align_up(kb, 256), pb, hipMemcpyHostToDevice, st));
+    FHD_HIP(hipMemcpyAsync(offs, ho, ob, hipMemcpyHostToDevice, st));
     c.stage_done(1);
 
     FA a = make_args(fp);
@@ -779,7 +930,20 @@ void filter_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const f
     a.out = out;
     a.den = den;
 
-    if (fp.materialize) {
+    if (fp.materialize && fp.contract != FHD_CONTRACT_FP32) {
+        hipEvent_t tw = c.stage_begin();
+        const dim3 g((fp.W + MW_PIX - 1) / MW_PIX, fp.H);
+        if (fp.contract == FHD_CONTRACT_BF16)
+            hipLaunchKernelGGL(weights_mfma<true>, g, dim3(RT), 0, st, a, Bpl,
+                               fp.coef == FHD_COEF_HARD ? nullptr : Cpl, offs);
+        else
+            hipLaunchKernelGGL(weights_mfma<false>, g, dim3(RT), 0, st, a, Bpl,
+                               fp.coef == FHD_COEF_HARD ? nullptr : Cpl, offs);
+        FHD_HIP(hipGetLastError());
+        c.stage_end(FHD_STAGE_WEIGHTS, tw);
+        a.Bpl = Bpl;
+        a.Cpl = Cpl;
+    } else if (fp.materialize) {
         const int tx = 128;
         a.tx = tx;
         const size_t lds = sizeof(float) * (size_t)tx * (fp.K + 1);

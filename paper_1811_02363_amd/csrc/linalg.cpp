@@ -1,9 +1,9 @@
 // The K x K least-squares solve of Algorithm 1 (eqs. (11)-(12)): the kernel
 // matrix A_kl = phi(mu_k - mu_l) and its Moore-Penrose pseudo-inverse, in FP64
-// on the host.  A is symmetric, so its singular values are |eigenvalues| and
-// A^+ = sum over kept eigenpairs of v v^T / lambda.  The eigen-decomposition
-// is the cyclic Jacobi method (rotations zeroing one off-diagonal pair at a
-// time, swept until the off-diagonal mass is negligible).
+// on the host, and the symmetric eigen-decomposition it uses (also used for the
+// patch covariance of the nonlocal-means guide).  A is symmetric, so its
+// singular values are |eigenvalues| and A^+ = sum over kept eigenpairs of
+// v v^T / lambda.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -30,61 +30,108 @@ void kernel_matrix(const float* centers, int K, int rho, double sigma_r, double*
     }
 }
 
-namespace {
-
-// Eigen-decomposition of the symmetric K x K matrix `a` (destroyed): on return
-// lam[i] are the eigenvalues and column i of v (row-major K x K) the
-// corresponding unit eigenvector.
-void jacobi_eigen(std::vector<double>& a, int K, std::vector<double>& lam, std::vector<double>& v) {
-    v.assign((size_t)K * K, 0.0);
-    for (int i = 0; i < K; ++i) v[(size_t)i * K + i] = 1.0;
-    double fro = 0.0;
-    for (double x : a) fro += x * x;
-    fro = std::sqrt(fro);
-    for (int sweep = 0; sweep < 64; ++sweep) {
-        double off = 0.0;
-        for (int p = 0; p < K; ++p)
-            for (int q = p + 1; q < K; ++q) off += a[(size_t)p * K + q] * a[(size_t)p * K + q];
-        if (std::sqrt(2.0 * off) <= 1e-16 * fro || off == 0.0) break;
-        for (int p = 0; p < K - 1; ++p) {
-            for (int q = p + 1; q < K; ++q) {
-                const double apq = a[(size_t)p * K + q];
-                if (apq == 0.0) continue;
-                const double app = a[(size_t)p * K + p], aqq = a[(size_t)q * K + q];
-                // rotation angle that zeroes a_pq: tan(theta) = t
-                const double tau = (aqq - app) / (2.0 * apq);
-                const double t = (tau >= 0.0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
-                const double c = 1.0 / std::sqrt(1.0 + t * t), s = t * c;
-                // a <- J^T a J, J = identity but J_pp = J_qq = c, J_pq = s, J_qp = -s
-                for (int k = 0; k < K; ++k) {
-                    const double akp = a[(size_t)k * K + p], akq = a[(size_t)k * K + q];
-                    a[(size_t)k * K + p] = c * akp - s * akq;
-                    a[(size_t)k * K + q] = s * akp + c * akq;
-                }
-                for (int k = 0; k < K; ++k) {
-                    const double apk = a[(size_t)p * K + k], aqk = a[(size_t)q * K + k];
-                    a[(size_t)p * K + k] = c * apk - s * aqk;
-                    a[(size_t)q * K + k] = s * apk + c * aqk;
-                }
-                a[(size_t)p * K + q] = 0.0;
-                a[(size_t)q * K + p] = 0.0;
-                for (int k = 0; k < K; ++k) {
-                    const double vkp = v[(size_t)k * K + p], vkq = v[(size_t)k * K + q];
-                    v[(size_t)k * K + p] = c * vkp - s * vkq;
-                    v[(size_t)k * K + q] = s * vkp + c * vkq;
-                }
+// Eigen-decomposition of a symmetric n x n matrix (row-major, destroyed):
+// Householder reduction to tridiagonal form, then implicit symmetric QR steps
+// with the Wilkinson shift, the Givens rotations applied to the band of the
+// tridiagonal matrix (plus its one-element bulge) and accumulated into the
+// orthogonal factor.  On return lam[i] are the eigenvalues and column i of v
+// (row-major n x n) the corresponding unit eigenvectors (unsorted).
+void sym_eigen(std::vector<double>& t, int n, std::vector<double>& lam, std::vector<double>& v) {
+    auto T = [&](int i, int j) -> double& { return t[(size_t)i * n + j]; };
+    v.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) v[(size_t)i * n + i] = 1.0;
+    auto Q = [&](int i, int j) -> double& { return v[(size_t)i * n + j]; };
+    // --- Householder: T <- H T H on the trailing block, Q <- Q H
+    std::vector<double> x(n), p(n), q(n);
+    for (int k = 0; k + 2 < n; ++k) {
+        const int m = n - k - 1;
+        double xn = 0.0;
+        for (int i = 0; i < m; ++i) {
+            x[i] = T(k + 1 + i, k);
+            xn += x[i] * x[i];
+        }
+        xn = std::sqrt(xn);
+        if (xn == 0.0) continue;
+        const double alpha = x[0] >= 0.0 ? -xn : xn;
+        x[0] -= alpha;  // x is now the reflector v
+        double vn = 0.0;
+        for (int i = 0; i < m; ++i) vn += x[i] * x[i];
+        if (vn == 0.0) continue;
+        const double beta = 2.0 / vn;
+        double vp = 0.0;
+        for (int i = 0; i < m; ++i) {
+            double s = 0.0;
+            for (int j = 0; j < m; ++j) s += T(k + 1 + i, k + 1 + j) * x[j];
+            p[i] = beta * s;
+            vp += x[i] * p[i];
+        }
+        const double kk = vp / vn;
+        for (int i = 0; i < m; ++i) q[i] = p[i] - kk * x[i];
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) T(k + 1 + i, k + 1 + j) -= x[i] * q[j] + q[i] * x[j];
+        T(k + 1, k) = T(k, k + 1) = alpha;
+        for (int i = 1; i < m; ++i) T(k + 1 + i, k) = T(k, k + 1 + i) = 0.0;
+        for (int r = 0; r < n; ++r) {
+            double s = 0.0;
+            for (int j = 0; j < m; ++j) s += Q(r, k + 1 + j) * x[j];
+            s *= beta;
+            for (int j = 0; j < m; ++j) Q(r, k + 1 + j) -= s * x[j];
+        }
+    }
+    // --- implicit symmetric QR with Wilkinson shifts
+    const double eps = 0x1p-52;
+    auto rot = [&](int k, int lo, int hi, double c, double s) {
+        // T <- G^T T G, G = rotation in the (k, k+1) plane, G_kk = G_k+1,k+1 = c, G_k,k+1 = s
+        const int j0 = std::max(lo, k - 1), j1 = std::min(hi, k + 2);
+        for (int j = j0; j <= j1; ++j) {
+            const double a = T(k, j), b = T(k + 1, j);
+            T(k, j) = c * a - s * b;
+            T(k + 1, j) = s * a + c * b;
+        }
+        for (int i = j0; i <= j1; ++i) {
+            const double a = T(i, k), b = T(i, k + 1);
+            T(i, k) = c * a - s * b;
+            T(i, k + 1) = s * a + c * b;
+        }
+        for (int r = 0; r < n; ++r) {
+            const double a = Q(r, k), b = Q(r, k + 1);
+            Q(r, k) = c * a - s * b;
+            Q(r, k + 1) = s * a + c * b;
+        }
+    };
+    int hi = n - 1, guard = 0;
+    while (hi > 0 && guard < 64 * n) {
+        if (std::fabs(T(hi, hi - 1)) <= eps * (std::fabs(T(hi - 1, hi - 1)) + std::fabs(T(hi, hi)))) {
+            T(hi, hi - 1) = T(hi - 1, hi) = 0.0;
+            --hi;
+            continue;
+        }
+        int lo = hi - 1;
+        while (lo > 0 && std::fabs(T(lo, lo - 1)) > eps * (std::fabs(T(lo - 1, lo - 1)) + std::fabs(T(lo, lo)))) --lo;
+        if (lo > 0) T(lo, lo - 1) = T(lo - 1, lo) = 0.0;
+        ++guard;
+        const double dd = 0.5 * (T(hi - 1, hi - 1) - T(hi, hi));
+        const double ee = T(hi, hi - 1);
+        const double den = dd + (dd >= 0.0 ? 1.0 : -1.0) * std::hypot(dd, ee);
+        const double mu = T(hi, hi) - ee * ee / den;
+        double xx = T(lo, lo) - mu, zz = T(lo + 1, lo);
+        for (int k = lo; k < hi; ++k) {
+            const double r = std::hypot(xx, zz);
+            const double c = r == 0.0 ? 1.0 : xx / r, s = r == 0.0 ? 0.0 : -zz / r;
+            rot(k, lo, hi, c, s);
+            if (k + 1 < hi) {
+                xx = T(k + 1, k);
+                zz = T(k + 2, k);
             }
         }
     }
-    lam.resize(K);
-    for (int i = 0; i < K; ++i) lam[i] = a[(size_t)i * K + i];
+    lam.resize(n);
+    for (int i = 0; i < n; ++i) lam[i] = T(i, i);
 }
-
-}  // namespace
 
 PinvResult pinv_symmetric(const double* A, int K, double rtol, double* P) {
     std::vector<double> a(A, A + (size_t)K * K), lam, v;
-    jacobi_eigen(a, K, lam, v);
+    sym_eigen(a, K, lam, v);
     double smax = 0.0;
     for (double x : lam) smax = std::max(smax, std::fabs(x));
     const double tol = (rtol > 0.0 ? rtol : (double)K * 0x1p-52) * smax;
