@@ -175,6 +175,30 @@ fhd_status fhd_filter(fhd_ctx* ctx, const float* f, int n, const float* guide, i
                       int H, int W, const fhd_params* p, float* out, float* centers_out,
                       float* den, fhd_info* info);
 
+/* Adjoint of fhd_filter_centers for least-squares coefficients (the paper
+ * does not differentiate its filter; this is the exact gradient of the
+ * computation of Algorithm 1 steps 2-5 with the centers held fixed).  Given
+ * G = dL/dg_hat it returns dL/df, dL/dguide and dL/dsigma_r; the weights are
+ * recomputed from the guide in FP32 (never stored by the forward call), so the
+ * gradient is that of the FP32 contraction whatever `p->contract` says.  The
+ * sigma_r term through A^+ holds the rank decision of the pseudo-inverse fixed
+ * (see fhd_pinv).
+ *   f, guide, centers, K, p  as passed to fhd_filter_centers (p->coef must be
+ *            FHD_COEF_LSQ; K <= 64; radius 1..32; Gaussian or box window).
+ *   out, den device: g_hat and r_hat returned by that forward call.
+ *   grad_out device n x H x W: G.
+ *   grad_f   device n x H x W output, or NULL.
+ *   grad_guide device rho x H x W output, or NULL.  When the guide is the
+ *            image (joint filtering of f by itself), dL/df is the sum of the
+ *            two outputs.
+ *   grad_sigma_r host, one double, or NULL.  Synchronises when non-NULL.
+ * Gradient outputs must not alias inputs.  Workspace: five K-plane sets plus
+ * the intermediate planes of the forward call. */
+fhd_status fhd_filter_backward(fhd_ctx* ctx, const float* f, int n, const float* guide, int rho,
+                               int H, int W, const float* centers, int K, const fhd_params* p,
+                               const float* out, const float* den, const float* grad_out,
+                               float* grad_f, float* grad_guide, double* grad_sigma_r);
+
 /* The brute-force filter of eqs. (1)-(2) on the GPU (FP32), the reference
  * the approximation is measured against.  out device n x H x W; den device
  * H x W (eta) or NULL. */

@@ -70,3 +70,42 @@ def bruteforce_torch(f, p, sigma_s, sigma_r, S, spatial="gaussian"):
             num = num + wt * fp[:, ys, xs]
             eta = eta + wt
     return num / eta, eta
+
+
+def sigma_r_shares(f, p, centers, sigma_s, sigma_r, S, G, spatial="gaussian", full_rank=True):
+    """Per-pixel split of dL/dsigma_r for L = <G, g>, in FP64:
+    share_b(i) = sum_k dL/db_k(i) * db_k(i)/dsigma_r (the weights' own
+    dependence) and share_A(i) = dL/dc(i) . (dA^+/dsigma_r) b(i) (the pseudo-
+    inverse's).  Their sum over pixels is the total gradient; the sum of their
+    magnitudes sizes the rounding error of any evaluation of that total."""
+    n, H, W = f.shape
+    rho = p.shape[0]
+    f = torch.as_tensor(f, dtype=torch.float64)
+    p = torch.as_tensor(p, dtype=torch.float64)
+    mu = torch.as_tensor(centers, dtype=torch.float64)
+    X = p.reshape(rho, -1).T
+    d2 = ((X[:, None, :] - mu[None, :, :]) ** 2).sum(-1)
+    dm = ((mu[:, None, :] - mu[None, :, :]) ** 2).sum(-1)
+
+    def pinv_of(s):
+        A = torch.exp(-dm / (2.0 * s ** 2))
+        return torch.linalg.inv(A) if full_rank else torch.linalg.pinv(A, hermitian=True)
+
+    s0 = torch.tensor(float(sigma_r), dtype=torch.float64)
+    B = torch.exp(-d2 / (2.0 * s0 ** 2)).requires_grad_(True)
+    P = pinv_of(s0)
+    C = B @ P.T
+    C.retain_grad()
+    Fl = f.reshape(n, -1)
+    U = torch.cat([B.T[:, None, :] * Fl[None, :, :], B.T[:, None, :]], dim=1)
+    w = _omega2(S, sigma_s, spatial)
+    K = mu.shape[0]
+    V = F.conv2d(U.reshape(K * (n + 1), 1, H, W), w[None, None], padding=S).reshape(K, n + 1, H * W)
+    v = (C.T[:, None, :] * V).sum(0)
+    g = v[:n] / v[n]
+    (g * torch.as_tensor(G, dtype=torch.float64).reshape(n, -1)).sum().backward()
+    dB = B.detach() * d2 / float(sigma_r) ** 3
+    share_b = (B.grad * dB).sum(1)
+    M = torch.autograd.functional.jacobian(pinv_of, s0)
+    share_A = (C.grad * (B.detach() @ M.T)).sum(1)
+    return share_b.numpy(), share_A.numpy()

@@ -17,7 +17,8 @@ import torch
 
 __all__ = [
     "FHDError", "Params", "Info", "load", "lib_path", "symbols",
-    "filter", "filter_centers", "cluster", "pinv", "bruteforce",
+    "filter", "filter_centers", "filter_backward", "FilterFunction", "filter_autograd",
+    "cluster", "pinv", "bruteforce", "nlm_guide",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -34,8 +35,8 @@ COEF = {"lsq": 0, "hard": 1}
 symbols = [
     "fhd_default_params", "fhd_create", "fhd_destroy", "fhd_set_stream", "fhd_last_error",
     "fhd_workspace_size", "fhd_set_workspace", "fhd_cluster", "fhd_pinv",
-    "fhd_filter_centers", "fhd_filter", "fhd_bruteforce", "fhd_nlm_guide", "fhd_timing_enable",
-    "fhd_timing_read",
+    "fhd_filter_centers", "fhd_filter", "fhd_filter_backward", "fhd_bruteforce", "fhd_nlm_guide",
+    "fhd_timing_enable", "fhd_timing_read",
 ]
 STAGES = ("cluster", "weights", "row", "col", "brute")
 
@@ -99,6 +100,7 @@ def load():
             "fhd_pinv": (I, [V, I, I, D, D, V, V, P(I), P(D)]),
             "fhd_filter_centers": (I, [V, V, I, V, I, I, I, V, I, V, pp, V, V, pi]),
             "fhd_filter": (I, [V, V, I, V, I, I, I, pp, V, V, V, pi]),
+            "fhd_filter_backward": (I, [V, V, I, V, I, I, I, V, I, pp, V, V, V, V, V, P(D)]),
             "fhd_bruteforce": (I, [V, V, I, V, I, I, I, pp, V, V]),
             "fhd_nlm_guide": (I, [V, V, I, I, I, I, I, V, V]),
             "fhd_timing_enable": (I, [V, I]),
@@ -222,6 +224,72 @@ def filter_centers(f, guide, centers, sigma_s=3.0, sigma_r=0.1, spatial="gaussia
     if info:
         res.append(inf.as_dict())
     return res[0] if len(res) == 1 else tuple(res)
+
+
+def filter_backward(f, guide, centers, out, den, grad_out, sigma_s=3.0, sigma_r=0.1,
+                    spatial="gaussian", radius=None, need_f=True, need_guide=True, need_sigma_r=True):
+    """Adjoint of :func:`filter_centers` (least-squares coefficients): given
+    G = dL/dg_hat and the forward call's (g_hat, r_hat), returns
+    (dL/df or None, dL/dguide or None, dL/dsigma_r as float or None)."""
+    n, rho, H, W, g = _shape(f, guide)
+    ctx = _ctx(f.device.index)
+    c = torch.as_tensor(centers, dtype=torch.float32).detach().cpu().contiguous()
+    K = c.shape[0]
+    if c.dim() != 2 or c.shape[1] != rho:
+        raise FHDError(FHD_EINVAL, "centers must be (K, rho)")
+    p = make_params(sigma_s, sigma_r, K, spatial, radius)
+    gf = torch.empty_like(f) if need_f else None
+    gg = torch.empty_like(g) if need_guide else None
+    gs = ctypes.c_double(0.0)
+    _check(load().fhd_filter_backward(
+        ctx, _dev(f, "f"), n, _dev(g, "guide"), rho, H, W, ctypes.c_void_p(c.data_ptr()), K,
+        ctypes.byref(p), _dev(out, "out"), _dev(den, "den"), _dev(grad_out, "grad_out"),
+        _dev(gf, "grad_f") if gf is not None else None,
+        _dev(gg, "grad_guide") if gg is not None else None,
+        ctypes.byref(gs) if need_sigma_r else None), ctx)
+    return gf, gg, (gs.value if need_sigma_r else None)
+
+
+class FilterFunction(torch.autograd.Function):
+    """g_hat = filter_centers(f, guide, centers) with gradients with respect to
+    f, guide and sigma_r (a 0-d tensor) from the library's adjoint; the
+    centers are constants.  Pass the same tensor as f and guide for joint
+    filtering of an image by itself: autograd adds the two contributions."""
+
+    @staticmethod
+    def forward(ctx, f, guide, sigma_r, centers, sigma_s, spatial, radius, contract):
+        sr = float(sigma_r)
+        out, den = filter_centers(f.detach(), guide.detach(), centers, sigma_s=sigma_s, sigma_r=sr,
+                                  spatial=spatial, radius=radius, contract=contract, return_den=True)
+        ctx.save_for_backward(f, guide, out, den)
+        ctx.conf = (centers, sigma_s, sr, spatial, radius)
+        ctx.sr_tensor = isinstance(sigma_r, torch.Tensor)
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        f, guide, out, den = ctx.saved_tensors
+        centers, sigma_s, sr, spatial, radius = ctx.conf
+        need_f, need_g, need_s = ctx.needs_input_grad[0], ctx.needs_input_grad[1], ctx.needs_input_grad[2]
+        gf, gg, gs = filter_backward(f.detach(), guide.detach(), centers, out, den,
+                                     grad_out.contiguous(), sigma_s=sigma_s, sigma_r=sr,
+                                     spatial=spatial, radius=radius, need_f=need_f, need_guide=need_g,
+                                     need_sigma_r=need_s and ctx.sr_tensor)
+        gsr = None
+        if need_s and ctx.sr_tensor:
+            gsr = torch.tensor(gs, dtype=torch.float32)
+        return gf, gg, gsr, None, None, None, None, None
+
+
+def filter_autograd(f, guide=None, sigma_s=3.0, sigma_r=0.1, K=16, spatial="gaussian",
+                    radius=None, contract="fp32", centers=None, kmeans_max_iter=20):
+    """Differentiable Algorithm 1: the centers come from the bisecting K-means
+    of the (detached) guide unless given, then :class:`FilterFunction`.
+    ``sigma_r`` may be a 0-d tensor that requires grad."""
+    g = f if guide is None else guide
+    if centers is None:
+        centers, _ = cluster(g.detach(), K, max_iter=kmeans_max_iter)
+    return FilterFunction.apply(f, g, sigma_r, centers, sigma_s, spatial, radius, contract)
 
 
 def cluster(guide, K, max_iter=20, labels=False):

@@ -475,6 +475,39 @@ fhd_status fhd_filter(fhd_ctx* ctx, const float* f, int n, const float* guide, i
     });
 }
 
+fhd_status fhd_filter_backward(fhd_ctx* ctx, const float* f, int n, const float* guide, int rho, int H, int W,
+                               const float* centers, int K, const fhd_params* p, const float* out,
+                               const float* den, const float* grad_out, float* grad_f, float* grad_guide,
+                               double* grad_sigma_r) {
+    return guarded(ctx, [&](Ctx& c) {
+        check_params(p, n, rho, H, W);
+        FHD_REQUIRE(f && guide && centers && out && den && grad_out, FHD_EINVAL, "NULL pointer");
+        FHD_REQUIRE(K >= 1 && K <= 64, FHD_EUNSUPPORTED, "the adjoint supports K in [1, 64]");
+        FHD_REQUIRE(p->coef == FHD_COEF_LSQ, FHD_EUNSUPPORTED, "the adjoint covers least-squares coefficients");
+        const long long N = (long long)H * W;
+        const size_t fb = sizeof(float) * N * n, gb = sizeof(float) * N * rho, db = sizeof(float) * N;
+        auto clash = [&](const void* o, size_t ob) {
+            return ranges_overlap(o, ob, f, fb) || ranges_overlap(o, ob, guide, gb) ||
+                   ranges_overlap(o, ob, out, fb) || ranges_overlap(o, ob, den, db) ||
+                   ranges_overlap(o, ob, grad_out, fb);
+        };
+        FHD_REQUIRE(!clash(grad_f, fb) && !clash(grad_guide, gb) && !ranges_overlap(grad_f, fb, grad_guide, gb),
+                    FHD_EINVAL, "gradient outputs alias inputs or each other");
+        FilterPlan fp = make_plan(*p, n, rho, H, W, K);
+        fp.contract = FHD_CONTRACT_FP32;
+        fp.materialize = true;
+        Arena ws = c.arena(adjoint_workspace(fp) + 4096);
+        std::vector<float> P32;
+        (void)solve(centers, K, rho, p->sigma_r, p->pinv_rtol, P32);
+        std::vector<double> M((size_t)K * K);
+        pinv_sigma_derivative(centers, K, rho, p->sigma_r, p->pinv_rtol, M.data());
+        std::vector<float> M32(M.size());
+        for (size_t q = 0; q < M.size(); ++q) M32[q] = (float)M[q];
+        adjoint_run(c, ws, fp, f, guide, centers, P32.data(), M32.data(), out, den, grad_out, grad_f, grad_guide,
+                    grad_sigma_r);
+    });
+}
+
 fhd_status fhd_bruteforce(fhd_ctx* ctx, const float* f, int n, const float* guide, int rho, int H, int W,
                           const fhd_params* p, float* out, float* den) {
     return guarded(ctx, [&](Ctx& c) {

@@ -74,6 +74,7 @@ struct PinvResult {
 void kernel_matrix(const float* centers, int K, int rho, double sigma_r, double* A);
 // Pseudo-inverse of the symmetric A; rtol <= 0: K * 2^-52 relative to s_max.
 PinvResult pinv_symmetric(const double* A, int K, double rtol, double* P);
+void pinv_sigma_derivative(const float* centers, int K, int rho, double sigma_r, double rtol, double* M);
 // Symmetric eigen-decomposition (t destroyed): eigenvalues lam (unsorted),
 // column i of v (row-major n x n) the i-th unit eigenvector.
 void sym_eigen(std::vector<double>& t, int n, std::vector<double>& lam, std::vector<double>& v);
@@ -92,6 +93,10 @@ void filter_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const f
                 float* out, float* den);
 void bruteforce_run(Ctx& c, const FilterPlan& fp, const float* f, const float* guide,
                     float* out, float* den);
+size_t adjoint_workspace(const FilterPlan& fp);
+void adjoint_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const float* guide,
+                 const float* centers_host, const float* Pfp32_host, const float* M_host, const float* out,
+                 const float* den, const float* gout, float* gradf, float* gradp, double* gsig);
 
 // ---- nonlocal-means guide (nlm.hip) ----------------------------------------
 size_t nlm_workspace(int n, int H, int W, int m, int dims);

@@ -45,6 +45,15 @@ struct FA {
     float* planes;      // K(n+1) row-filtered planes, pitch Wp, S zero rows above and below
     float* out;
     float* den;
+    // adjoint
+    int fmode;          // row pass vector: 0 = [f, 1], 1 = [G / r, -(G . g_hat) / r]
+    int factor_b;       // row pass factor: 0 = c (or b for the hard variant), 1 = b
+    const float* gout;  // G = dL/dg_hat (n planes)
+    const float* gimg;  // g_hat (n planes)
+    const float* gden;  // r_hat
+    float* beta;        // K planes
+    float* gamma;       // K planes
+    float* gradf;       // n planes or null
     int n, rho, K, H, W, Wp, S, coef, tx, xcd_groups;
     long long N, Np;    // pixels; stride of the B / C planes
     long long Pp;       // stride of the intermediate planes: H + 2S rows of Wp, row y at y + S
@@ -70,11 +79,24 @@ __device__ void row_factors(const FA& a, int y, int x0, int hw, int csp, float* 
     for (int h = threadIdx.x; h < hw; h += RT) {
         const int x = x0 - a.S + h;
         const bool in = x >= 0 && x < a.W;
-        for (int ch = 0; ch < n; ++ch)
-            fs[ch * csp + pidx(h)] = in ? a.f[(long long)ch * a.N + rowoff + x] : 0.0f;
+        if (a.fmode == 0) {
+            for (int ch = 0; ch < n; ++ch)
+                fs[ch * csp + pidx(h)] = in ? a.f[(long long)ch * a.N + rowoff + x] : 0.0f;
+            fs[n * csp + pidx(h)] = in ? 1.0f : 0.0f;
+        } else {
+            // adjoint vector: dL/dv = G / r, dL/dr = -(G . g_hat) / r
+            const float inv = in ? 1.0f / a.gden[rowoff + x] : 0.0f;
+            float dr = 0.0f;
+            for (int ch = 0; ch < n; ++ch) {
+                const float gv = in ? a.gout[(long long)ch * a.N + rowoff + x] : 0.0f;
+                fs[ch * csp + pidx(h)] = gv * inv;
+                dr = fmaf(gv, in ? a.gimg[(long long)ch * a.N + rowoff + x] : 0.0f, dr);
+            }
+            fs[n * csp + pidx(h)] = -dr * inv;
+        }
     }
     if (a.Bpl != nullptr) {  // weights materialised by the weights pass
-        const float* src = a.coef == FHD_COEF_HARD ? a.Bpl : a.Cpl;
+        const float* src = (a.coef == FHD_COEF_HARD || a.factor_b) ? a.Bpl : a.Cpl;
         const long long prow = (long long)y * a.Wp;
         for (int t = threadIdx.x; t < hw * K; t += RT) {
             const int l = t / hw, h = t - l * hw;
@@ -151,7 +173,7 @@ __global__ __launch_bounds__(RT) void row_gauss(FA a) {
     const int csp = pidx(hw - 1) + 1;
     float* cs = lds;
     float* fs = cs + a.K * csp;
-    float* smu = fs + a.n * csp;
+    float* smu = fs + (a.n + 1) * csp;
     float* sP = smu + a.K * a.rho;
     row_factors(a, y, x0, hw, csp, cs, fs, smu, sP);
     const int nseg = a.tx / R;
@@ -164,12 +186,25 @@ __global__ __launch_bounds__(RT) void row_gauss(FA a) {
 #pragma unroll
         for (int q = 0; q < WIN; ++q) cw[q] = cs[l * csp + pidx(seg * R + q)];
         float o[R];
+        if (a.fmode == 0) {  // last vector entry: the constant 1
 #pragma unroll
-        for (int t = 0; t < R; ++t) {
-            float s = a.w[0] * cw[t + S];
+            for (int t = 0; t < R; ++t) {
+                float s = a.w[0] * cw[t + S];
 #pragma unroll
-            for (int j = 1; j <= S; ++j) s = fmaf(a.w[j], cw[t + S - j] + cw[t + S + j], s);
-            o[t] = s;
+                for (int j = 1; j <= S; ++j) s = fmaf(a.w[j], cw[t + S - j] + cw[t + S + j], s);
+                o[t] = s;
+            }
+        } else {
+            float u[WIN];
+#pragma unroll
+            for (int q = 0; q < WIN; ++q) u[q] = cw[q] * fs[n * csp + pidx(seg * R + q)];
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                float s = a.w[0] * u[t + S];
+#pragma unroll
+                for (int j = 1; j <= S; ++j) s = fmaf(a.w[j], u[t + S - j] + u[t + S + j], s);
+                o[t] = s;
+            }
         }
         const long long rowp = (long long)(y + S) * a.Wp;
         float* base = a.planes + (long long)l * (n + 1) * a.Pp + rowp;
@@ -202,7 +237,7 @@ __global__ __launch_bounds__(RT) void row_generic(FA a) {
     const int csp = pidx(hw - 1) + 1;
     float* cs = lds;
     float* fs = cs + a.K * csp;
-    float* smu = fs + a.n * csp;
+    float* smu = fs + (a.n + 1) * csp;
     float* sP = smu + a.K * a.rho;
     row_factors(a, y, x0, hw, csp, cs, fs, smu, sP);
     const int nseg = a.tx / R;
@@ -214,8 +249,8 @@ __global__ __launch_bounds__(RT) void row_generic(FA a) {
         const int x = x0 + seg * R;
         if (x >= a.W) continue;
         const float* cl = cs + l * csp;
-        const float* fc = fs + (ch < n ? ch : 0) * csp;
-        auto U = [&](int h) { return ch < n ? cl[pidx(h)] * fc[pidx(h)] : cl[pidx(h)]; };
+        const float* fc = fs + ch * csp;
+        auto U = [&](int h) { return (ch < n || a.fmode != 0) ? cl[pidx(h)] * fc[pidx(h)] : cl[pidx(h)]; };
         float o[R];
         const int h0 = seg * R;  // halo index of the window start for output x
         if (BOX) {
@@ -507,6 +542,242 @@ __global__ __launch_bounds__(RT) void col_generic(FA a) {
             }
         }
         if (tile.active) col_finish<R>(a, x, y0, g, acc, dv);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint column passes.  Same staging and filtering as the forward column
+// pass; the epilogue per cluster l and pixel i is
+//   BETA:  beta_l(i)  = Y(i) . Q_l(i),  Y = [G / r, -(G . g_hat) / r]
+//          (Q_l = w * (c_l [f, 1]) recomputed: dL/db_l from the recombination)
+//   GAMMA: gamma_l(i) = [f(i), 1] . Z_l(i)  and  dL/df(i) += c_l(i) Z_l(i)[0:n]
+//          (Z_l = w * (b_l Y): the adjoint of the convolution applied to
+//          dL/dQ_l = b_l Y; w is symmetric and zero-extended, so its adjoint is
+//          itself)
+enum { AM_BETA = 0, AM_GAMMA = 1 };
+
+template <int S, int MODE>
+__global__ __launch_bounds__(RT) void col_adj(FA a) {
+    constexpr int R = R_COL;
+    constexpr int TY = TYC;
+    constexpr int ROWS = TY + 2 * S;
+    constexpr int PER = (ROWS * TXC + RT - 1) / RT;
+    constexpr int WIN = R + 2 * S;
+    __shared__ float tbuf[2][PER * RT];
+    const ColTile tile = col_tile(a, TY);
+    if (!tile.block_active) return;
+    const int n = a.n, K = a.K;
+    const int lx = threadIdx.x & (TXC - 1), tr = threadIdx.x / TXC;
+    const int x = tile.x, y0 = tile.y0;
+    const int ly0 = tr * R;
+    const long long tile_off = (long long)tile.by0 * a.Wp + tile.bx0 + tr * (long long)a.Wp + lx;
+    const long long step = (long long)(RT / TXC) * a.Wp;
+    auto fetch = [&](int plane, float (&pre)[PER]) {
+        const float* src = a.planes + (long long)plane * a.Pp + tile_off;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            pre[k] = (tr + k * (RT / TXC) < ROWS) ? *src : 0.0f;
+            src += step;
+        }
+    };
+    auto stash = [&](float* dst, const float (&pre)[PER]) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) dst[k * RT + threadIdx.x] = pre[k];
+    };
+    float pre[PER];
+    fetch(plane_index(n, 0, 0, 0), pre);
+    stash(tbuf[0], pre);
+    __syncthreads();
+    int buf = 0;
+    const int groups = (n + 1 + CG - 1) / CG;
+    const bool act = tile.active;
+    for (int g = 0; g < groups; ++g) {
+        // the group's entries of the per-pixel vector (Y for BETA, [f, 1] for GAMMA)
+        float vec[CG][R];
+#pragma unroll
+        for (int c = 0; c < CG; ++c) {
+            const int gi = g * CG + c;
+            const int ch = gi == 0 ? n : gi - 1;
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                float v = 0.0f;
+                if (act && gi <= n && y0 + t < a.H) {
+                    const long long off = (long long)(y0 + t) * a.W + x;
+                    if (MODE == AM_BETA) {
+                        const float inv = 1.0f / a.gden[off];
+                        if (ch < n) {
+                            v = a.gout[(long long)ch * a.N + off] * inv;
+                        } else {
+                            float dr = 0.0f;
+                            for (int q = 0; q < n; ++q)
+                                dr = fmaf(a.gout[(long long)q * a.N + off], a.gimg[(long long)q * a.N + off], dr);
+                            v = -dr * inv;
+                        }
+                    } else {
+                        v = ch < n ? a.f[(long long)ch * a.N + off] : 1.0f;
+                    }
+                }
+                vec[c][t] = v;
+            }
+        }
+        float fbar[CG][R];
+#pragma unroll
+        for (int c = 0; c < CG; ++c)
+#pragma unroll
+            for (int t = 0; t < R; ++t) fbar[c][t] = 0.0f;
+        for (int l = 0; l < K; ++l) {
+            float acc[R], cl[R];
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                acc[t] = 0.0f;
+                cl[t] = (MODE == AM_GAMMA && act && y0 + t < a.H)
+                            ? a.Cpl[(long long)l * a.Np + (long long)(y0 + t) * a.Wp + x]
+                            : 0.0f;
+            }
+#pragma unroll
+            for (int c = 0; c < CG; ++c) {
+                const int gi = g * CG + c;
+                if (gi > n) break;
+                int ng = g, nl = l, nc = c;
+                const bool more = plane_next(n, K, ng, nl, nc);
+                if (more) fetch(plane_index(n, ng, nl, nc), pre);
+                const float* col = tbuf[buf] + ly0 * TXC + lx;
+                float win[WIN];
+#pragma unroll
+                for (int q = 0; q < WIN; ++q) win[q] = col[q * TXC];
+#pragma unroll
+                for (int t = 0; t < R; ++t) {
+                    float s = a.w[0] * win[t + S];
+#pragma unroll
+                    for (int j = 1; j <= S; ++j) s = fmaf(a.w[j], win[t + S - j] + win[t + S + j], s);
+                    acc[t] = fmaf(vec[c][t], s, acc[t]);
+                    if (MODE == AM_GAMMA && gi > 0) fbar[c][t] = fmaf(cl[t], s, fbar[c][t]);
+                }
+                if (more) stash(tbuf[buf ^ 1], pre);
+                __syncthreads();
+                buf ^= 1;
+            }
+            if (act) {
+                float* dst = (MODE == AM_BETA ? a.beta : a.gamma) + (long long)l * a.Np + (long long)y0 * a.Wp + x;
+                for (int t = 0; t < R && y0 + t < a.H; ++t) {
+                    *dst = (g == 0 ? 0.0f : *dst) + acc[t];
+                    dst += a.Wp;
+                }
+            }
+        }
+        if (MODE == AM_GAMMA && act && a.gradf != nullptr) {
+#pragma unroll
+            for (int c = 0; c < CG; ++c) {
+                const int gi = g * CG + c;
+                if (gi > n) break;
+                if (gi == 0) continue;
+                float* op = a.gradf + (long long)(gi - 1) * a.N + (long long)y0 * a.W + x;
+                for (int t = 0; t < R && y0 + t < a.H; ++t) {
+                    *op = fbar[c][t];
+                    op += a.W;
+                }
+            }
+        }
+    }
+}
+
+// Per-pixel end of the adjoint: dL/db = beta + A^+ gamma (A^+ symmetric),
+// dL/dp = sum_l dL/db_l b_l (-2 s)(p - mu_l) with s = 1 / (2 sigma_r^2), and
+// this pixel's share of dL/dsigma_r:
+//   sum_l dL/db_l b_l |p - mu_l|^2 / sigma_r^3  +  gamma . (M b),
+// M = d(A^+)/dsigma_r (K x K, formed on the host).  One launch covers the
+// clusters l in [l0, l0 + 32) (dL/dp is linear in the per-cluster terms, so a
+// second launch adds its share); the FP64 shares are summed per block in a
+// fixed order.
+constexpr int KF = 32;
+
+__global__ __launch_bounds__(RT) void adj_final(FA a, const float* __restrict__ Md, float sig3inv, int l0,
+                                                int accumulate, float* __restrict__ gradp,
+                                                double* __restrict__ part) {
+    __shared__ float sP[KF * 64], sA[KF * 64];
+    __shared__ float smu[KF * FHD_MAX_RHO];
+    __shared__ double red[RT / 64];
+    const int K = a.K, rho = a.rho;
+    const int kl = min(KF, K - l0);
+    for (int t = threadIdx.x; t < kl * K; t += RT) {
+        sP[t] = a.P[(long long)l0 * K + t];
+        sA[t] = Md[(long long)l0 * K + t];
+    }
+    for (int t = threadIdx.x; t < kl * rho; t += RT) smu[t] = a.mu[(long long)l0 * rho + t];
+    __syncthreads();
+    const long long i = (long long)blockIdx.x * RT + threadIdx.x;
+    const bool valid = i < a.N;
+    const int y = valid ? (int)(i / a.W) : 0, x = valid ? (int)(i % a.W) : 0;
+    const long long po = (long long)y * a.Wp + x;
+    float pg[KF], ac[KF];
+#pragma unroll
+    for (int l = 0; l < KF; ++l) pg[l] = ac[l] = 0.0f;
+    for (int m = 0; m < K; ++m) {
+        const float gm = valid ? a.gamma[(long long)m * a.Np + po] : 0.0f;
+        const float bm = valid ? a.Bpl[(long long)m * a.Np + po] : 0.0f;
+#pragma unroll
+        for (int l = 0; l < KF; ++l)
+            if (l < kl) {
+                pg[l] = fmaf(sP[l * K + m], gm, pg[l]);
+                ac[l] = fmaf(sA[l * K + m], bm, ac[l]);
+            }
+    }
+    // weights w_l = dL/db_l * b_l
+    double sig = 0.0;
+    float wsum = 0.0f;
+#pragma unroll
+    for (int l = 0; l < KF; ++l) {
+        if (l >= kl) break;
+        const long long pl = (long long)(l0 + l) * a.Np + po;
+        const float bl = valid ? a.Bpl[pl] : 0.0f;
+        const float bb = (valid ? a.beta[pl] : 0.0f) + pg[l];
+        const float w = bb * bl;
+        const float gl = valid ? a.gamma[pl] : 0.0f;
+        float d2 = 0.0f;
+        for (int r = 0; r < rho; ++r) {
+            const float d = (valid ? a.p[(long long)r * a.N + i] : 0.0f) - smu[l * rho + r];
+            d2 = fmaf(d, d, d2);
+        }
+        sig += (double)w * d2 * sig3inv + (double)gl * ac[l];
+        pg[l] = w;  // reuse: w_l
+        wsum += w;
+    }
+    if (valid && gradp != nullptr) {
+        const float m2s = -2.0f * a.inv2s2;
+        for (int r = 0; r < rho; ++r) {
+            float s = 0.0f;
+#pragma unroll
+            for (int l = 0; l < KF; ++l)
+                if (l < kl) s = fmaf(pg[l], smu[l * rho + r], s);
+            const float pr = a.p[(long long)r * a.N + i];
+            float* gp = gradp + (long long)r * a.N + i;
+            const float v = m2s * (pr * wsum - s);
+            *gp = accumulate ? *gp + v : v;
+        }
+    }
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) sig += __shfl_xor(sig, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sig;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int q = 0; q < RT / 64; ++q) t += red[q];
+        part[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(RT) void sum_blocks(const double* __restrict__ part, int nb, double* __restrict__ out) {
+    __shared__ double red[RT / 64];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += RT) s += part[b];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int q = 0; q < RT / 64; ++q) t += red[q];
+        *out = t;
     }
 }
 
@@ -811,13 +1082,29 @@ struct Tables<0> {
     static void fill(KernFn*, KernFn (*)[3]) {}
 };
 
+template <int S>
+struct AdjTables {
+    static void fill(KernFn (*adj)[2]) {
+        adj[S][AM_BETA] = col_adj<S, AM_BETA>;
+        adj[S][AM_GAMMA] = col_adj<S, AM_GAMMA>;
+        AdjTables<S - 1>::fill(adj);
+    }
+};
+template <>
+struct AdjTables<0> {
+    static void fill(KernFn (*)[2]) {}
+};
+
 struct Dispatch {
     KernFn row[MAXS_T + 1];
     KernFn col[MAXS_T + 1][3];
+    KernFn adj[MAXS_T + 1][2];
     Dispatch() {
         row[0] = nullptr;
         col[0][0] = col[0][1] = col[0][2] = nullptr;
+        adj[0][0] = adj[0][1] = nullptr;
         Tables<MAXS_T>::fill(row, col);
+        AdjTables<MAXS_T>::fill(adj);
     }
 };
 
@@ -866,7 +1153,7 @@ int row_tx(int K, int S, int R) {
 size_t row_lds_bytes(const FilterPlan& fp, int tx) {
     const int hw = tx + 2 * fp.S;
     const int csp = hw + ((hw - 1) >> 5) + 1;
-    size_t fl = (size_t)fp.K * csp + (size_t)fp.n * csp;
+    size_t fl = (size_t)fp.K * csp + (size_t)(fp.n + 1) * csp;
     if (!fp.materialize) fl += (size_t)fp.K * fp.rho + (size_t)fp.K * fp.K;
     return fl * sizeof(float);
 }
@@ -1009,6 +1296,128 @@ void filter_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const f
     hipLaunchKernelGGL(colk, cg, dim3(RT), clds, st, a);
     c.stage_end(FHD_STAGE_COL, tc);
     FHD_HIP(hipGetLastError());
+}
+
+size_t adjoint_workspace(const FilterPlan& fp) {
+    Arena probe;
+    const long long Np = (long long)fp.H * fp.Wp;
+    probe.take<float>(plane_floats(fp));
+    for (int q = 0; q < 4; ++q) probe.take<float>((size_t)fp.K * Np);
+    probe.take<float>((size_t)fp.K * fp.rho);
+    probe.take<float>((size_t)fp.K * fp.K);
+    probe.take<float>((size_t)fp.K * fp.K);
+    probe.take<double>(2 * ((size_t)(fp.N + RT - 1) / RT) + 1);
+    return probe.used;
+}
+
+void adjoint_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const float* guide,
+                 const float* centers_host, const float* Pfp32_host, const float* M_host, const float* out,
+                 const float* den, const float* gout, float* gradf, float* gradp, double* gsig) {
+    FHD_REQUIRE(fp.S >= 1 && fp.S <= MAXS_T, FHD_EUNSUPPORTED, "the adjoint supports radii 1..32");
+    FHD_REQUIRE(fp.K <= 64, FHD_EUNSUPPORTED, "the adjoint supports K <= 64");
+    FHD_REQUIRE(fp.coef == FHD_COEF_LSQ, FHD_EUNSUPPORTED, "the adjoint covers least-squares coefficients");
+    FHD_REQUIRE(fp.materialize, FHD_EINVAL, "internal: adjoint plan must materialise weights");
+    const long long Np = (long long)fp.H * fp.Wp;
+    float* planes = ws.take<float>(plane_floats(fp));
+    float* Bpl = ws.take<float>((size_t)fp.K * Np);
+    float* Cpl = ws.take<float>((size_t)fp.K * Np);
+    float* beta = ws.take<float>((size_t)fp.K * Np);
+    float* gamma = ws.take<float>((size_t)fp.K * Np);
+    float* mu = ws.take<float>((size_t)fp.K * fp.rho);
+    float* P = ws.take<float>((size_t)fp.K * fp.K);
+    float* Md = ws.take<float>((size_t)fp.K * fp.K);
+    const int nb = (int)((fp.N + RT - 1) / RT);
+    double* part = ws.take<double>(2 * (size_t)nb + 1);
+    hipStream_t st = c.stream;
+    const size_t kb = sizeof(float) * fp.K * fp.rho, pb = sizeof(float) * fp.K * fp.K;
+    char* hs = static_cast<char*>(c.host_stage(1, align_up(kb, 256) + 2 * align_up(pb, 256)));
+    std::memcpy(hs, centers_host, kb);
+    std::memcpy(hs + align_up(kb, 256), Pfp32_host, pb);
+    std::memcpy(hs + align_up(kb, 256) + align_up(pb, 256), M_host, pb);
+    FHD_HIP(hipMemcpyAsync(mu, hs, kb, hipMemcpyHostToDevice, st));
+    FHD_HIP(hipMemcpyAsync(P, hs + align_up(kb, 256), pb, hipMemcpyHostToDevice, st));
+    FHD_HIP(hipMemcpyAsync(Md, hs + align_up(kb, 256) + align_up(pb, 256), pb, hipMemcpyHostToDevice, st));
+    c.stage_done(1);
+
+    FA a = make_args(fp);
+    a.f = f;
+    a.p = guide;
+    a.mu = mu;
+    a.P = P;
+    a.planes = planes;
+    a.gout = gout;
+    a.gimg = out;
+    a.gden = den;
+    a.beta = beta;
+    a.gamma = gamma;
+    a.gradf = gradf;
+    // weights recomputed from the guide (never stored by the forward call)
+    {
+        const int tx = 128;
+        a.tx = tx;
+        const size_t lds = sizeof(float) * (size_t)tx * (fp.K + 1);
+        FHD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(weights_fp32),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipEvent_t tw = c.stage_begin();
+        hipLaunchKernelGGL(weights_fp32, dim3((fp.W + tx - 1) / tx, fp.H), dim3(RT), lds, st, a, Bpl, Cpl);
+        c.stage_end(FHD_STAGE_WEIGHTS, tw);
+        FHD_HIP(hipGetLastError());
+    }
+    a.Bpl = Bpl;
+    a.Cpl = Cpl;
+    {
+        const size_t pitch = sizeof(float) * (size_t)(fp.H + 2 * fp.S) * fp.Wp;
+        const size_t width = sizeof(float) * (size_t)fp.S * fp.Wp;
+        const size_t planes_n = (size_t)fp.K * (fp.n + 1);
+        FHD_HIP(hipMemset2DAsync(planes, pitch, 0, width, planes_n, st));
+        FHD_HIP(hipMemset2DAsync(planes + (size_t)(fp.H + fp.S) * fp.Wp, pitch, 0, width, planes_n, st));
+    }
+    int tx = row_tx(fp.K, fp.S, R_ROW);
+    size_t lds = row_lds_bytes(fp, tx);
+    while (lds > 150 * 1024 && tx > 4 * R_ROW) {
+        tx = std::max(4 * R_ROW, tx / 2 / R_ROW * R_ROW);
+        lds = row_lds_bytes(fp, tx);
+    }
+    FHD_REQUIRE(lds <= 160 * 1024, FHD_EUNSUPPORTED, "row pass does not fit in LDS");
+    a.tx = tx;
+    const dim3 rg((fp.W + tx - 1) / tx, fp.H);
+    KernFn rowk = dispatch().row[fp.S];
+    FHD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(rowk), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds));
+    const int gx = (fp.W + TXC - 1) / TXC, gy = (fp.H + TYC - 1) / TYC;
+    const int per = (gx * gy + 7) / 8;
+    a.xcd_groups = per;
+    const dim3 cg(per * 8);
+    // dL/db_l from the recombination: recompute Q_l = w * (c_l [f, 1])
+    a.fmode = 0;
+    a.factor_b = 0;
+    hipEvent_t t0 = c.stage_begin();
+    hipLaunchKernelGGL(rowk, rg, dim3(RT), lds, st, a);
+    c.stage_end(FHD_STAGE_ROW, t0);
+    t0 = c.stage_begin();
+    hipLaunchKernelGGL(dispatch().adj[fp.S][AM_BETA], cg, dim3(RT), 0, st, a);
+    c.stage_end(FHD_STAGE_COL, t0);
+    // the adjoint convolution of dL/dQ_l = b_l Y
+    a.fmode = 1;
+    a.factor_b = 1;
+    t0 = c.stage_begin();
+    hipLaunchKernelGGL(rowk, rg, dim3(RT), lds, st, a);
+    c.stage_end(FHD_STAGE_ROW, t0);
+    t0 = c.stage_begin();
+    hipLaunchKernelGGL(dispatch().adj[fp.S][AM_GAMMA], cg, dim3(RT), 0, st, a);
+    c.stage_end(FHD_STAGE_COL, t0);
+    FHD_HIP(hipGetLastError());
+    const float sig3inv = std::isinf(fp.sigma_r) ? 0.0f : (float)(1.0 / ((double)fp.sigma_r * fp.sigma_r * fp.sigma_r));
+    const int halves = (fp.K + KF - 1) / KF;
+    for (int h = 0; h < halves; ++h)
+        hipLaunchKernelGGL(adj_final, dim3(nb), dim3(RT), 0, st, a, Md, sig3inv, h * KF, h, gradp,
+                           part + (size_t)h * nb);
+    hipLaunchKernelGGL(sum_blocks, dim3(1), dim3(RT), 0, st, part, halves * nb, part + (size_t)halves * nb);
+    FHD_HIP(hipGetLastError());
+    if (gsig != nullptr) {
+        FHD_HIP(hipMemcpyAsync(gsig, part + (size_t)halves * nb, sizeof(double), hipMemcpyDeviceToHost, st));
+        FHD_HIP(hipStreamSynchronize(st));
+    }
 }
 
 void bruteforce_run(Ctx& c, const FilterPlan& fp, const float* f, const float* guide, float* out,

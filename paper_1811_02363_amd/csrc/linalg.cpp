@@ -153,4 +153,70 @@ PinvResult pinv_symmetric(const double* A, int K, double rtol, double* P) {
     return r;
 }
 
+// dA^+/dsigma_r for A_kl = exp(-|mu_k - mu_l|^2 / (2 sigma_r^2)), with the
+// kept eigenpairs of A held fixed (the rank decision of pinv_symmetric).
+// A^+ = F(A) with the spectral function g(lam) = 1/lam on kept eigenvalues
+// and 0 on dropped ones, so dF = V (D o (V^T dA V)) V^T with the divided
+// differences D_ij = (g(lam_i) - g(lam_j)) / (lam_i - lam_j) (g' on equal
+// pairs): -1/(lam_i lam_j) for two kept, 1/(lam_i (lam_i - lam_j)) for kept i
+// and dropped j, 0 for two dropped.  dA/dsigma_r = A o |mu_k - mu_l|^2 / sigma_r^3.
+void pinv_sigma_derivative(const float* centers, int K, int rho, double sigma_r, double rtol, double* M) {
+    std::fill(M, M + (size_t)K * K, 0.0);
+    if (std::isinf(sigma_r)) return;
+    std::vector<double> A((size_t)K * K), dA((size_t)K * K);
+    kernel_matrix(centers, K, rho, sigma_r, A.data());
+    const double s3 = sigma_r * sigma_r * sigma_r;
+    for (int k = 0; k < K; ++k)
+        for (int l = 0; l < K; ++l) {
+            double d2 = 0.0;
+            for (int t = 0; t < rho; ++t) {
+                const double d = (double)centers[(size_t)k * rho + t] - (double)centers[(size_t)l * rho + t];
+                d2 += d * d;
+            }
+            dA[(size_t)k * K + l] = A[(size_t)k * K + l] * d2 / s3;
+        }
+    std::vector<double> lam, V;
+    sym_eigen(A, K, lam, V);
+    double smax = 0.0;
+    for (double x : lam) smax = std::max(smax, std::fabs(x));
+    const double tol = (rtol > 0.0 ? rtol : (double)K * 0x1p-52) * smax;
+    std::vector<char> kept(K);
+    for (int i = 0; i < K; ++i) kept[i] = std::fabs(lam[i]) > tol;
+    // E = V^T dA V, then E_ij *= D_ij, then M = V E V^T
+    std::vector<double> T((size_t)K * K, 0.0), E((size_t)K * K, 0.0);
+    for (int k = 0; k < K; ++k)
+        for (int j = 0; j < K; ++j) {
+            double s = 0.0;
+            for (int l = 0; l < K; ++l) s += dA[(size_t)k * K + l] * V[(size_t)l * K + j];
+            T[(size_t)k * K + j] = s;
+        }
+    for (int i = 0; i < K; ++i)
+        for (int j = 0; j < K; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < K; ++k) s += V[(size_t)k * K + i] * T[(size_t)k * K + j];
+            double d;
+            if (kept[i] && kept[j])
+                d = -1.0 / (lam[i] * lam[j]);
+            else if (kept[i])
+                d = 1.0 / (lam[i] * (lam[i] - lam[j]));
+            else if (kept[j])
+                d = 1.0 / (lam[j] * (lam[j] - lam[i]));
+            else
+                d = 0.0;
+            E[(size_t)i * K + j] = s * d;
+        }
+    for (int k = 0; k < K; ++k)
+        for (int j = 0; j < K; ++j) {
+            double s = 0.0;
+            for (int i = 0; i < K; ++i) s += V[(size_t)k * K + i] * E[(size_t)i * K + j];
+            T[(size_t)k * K + j] = s;
+        }
+    for (int k = 0; k < K; ++k)
+        for (int l = 0; l < K; ++l) {
+            double s = 0.0;
+            for (int j = 0; j < K; ++j) s += T[(size_t)k * K + j] * V[(size_t)l * K + j];
+            M[(size_t)k * K + l] = s;
+        }
+}
+
 }  // namespace fhd
