@@ -1,20 +1,28 @@
 """Throughput of the fast high-dimensional filter on one MI355X.
 
 One step = one whole call of Algorithm 1 on the 2048x2048 RGB bilateral
-workload (sigma_s = 5, S = 15, sigma_r = 0.12, K = 32): bisecting K-means of
-the guide, the K x K solve, weights and coefficients, the 4K row-filtered
-planes and the column pass with the recombination.  Inputs are resident in
-HBM before the timed region.
+workload (sigma_s = 5, S = 15, sigma_r = 0.12, K = 32, guide = image):
+bisecting K-means of the guide, the K x K solve, weights and coefficients, the
+4K row-filtered planes and the column pass with the recombination.  Inputs
+are resident in HBM before the timed region.
 
-Prints one JSON line with the throughput (Mpix/s), the roofline of the
-dominant kernel (algorithmic bytes per launch / HIP-event duration on the
-library's stream), and the FP64 CPU oracle timed on a bounded crop of the same
-workload.
+Prints one JSON line: the forward throughput (Mpix/s) as `value`; the
+approximation quality (PSNR of eq. (21) against the GPU brute-force filter of
+eqs. (1)-(2)) and the brute force's own throughput; forward + adjoint
+throughput on the same workload; the FP32 and BF16 forms of the distance
+contraction on the 512x512x32 hyperspectral workload (Mpix/s and PSNR each);
+the roofline of the dominant kernel (algorithmic bytes and FLOPs per launch /
+HIP-event duration on the library's stream); and the FP64 CPU oracle timed on
+a bounded crop of the same workload.
+
+`--copy-calibration` instead runs a plain device copy of known size (the
+reference for scaling rocprofv3's FETCH_SIZE / WRITE_SIZE counters).
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -22,12 +30,14 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, published
-PROFILE_NOTE = "profiles/"
+METRIC = "Mpix/s (fwd; fwd+bwd) at stated PSNR vs brute force, BF16 vs FP32 form"
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
+FP32_VECTOR_PEAK = 157.3     # TFLOP/s, MI355X published FP32 vector (packed FMA)
 
-# HBM bytes per launch of the column pass, measured with rocprofv3 --pmc
-# (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), for the
-# kernel as it is in this tree; None when not measured for this version.
+# HBM bytes per launch of the row pass at the 2048x2048 workload from
+# rocprofv3 --pmc (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel
+# calibration) for the row kernel as it is in this tree; None when the counters
+# have not been taken for this version of the kernel.
 MEASURED_TRAFFIC = None
 
 
@@ -37,8 +47,19 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--quick", action="store_true",
+                    help="forward timing only (no quality, adjoint or precision legs)")
     ap.add_argument("--cpu-crop", type=int, default=512)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="run a device copy of MIB MiB three times and exit")
     return ap.parse_args()
+
+
+def psnr(a, b):
+    """Eq. (21): -10 log10 of the channel-summed squared error per pixel."""
+    d = (a.double() - b.double())
+    mse = float((d * d).sum()) / (a.shape[-1] * a.shape[-2])
+    return float("inf") if mse == 0 else -10.0 * math.log10(mse)
 
 
 def cpu_baseline(f, cfg, crop):
@@ -57,12 +78,51 @@ def cpu_baseline(f, cfg, crop):
                       f"of the same input and parameters ({dt:.1f} s)"}
 
 
+def timed(torch, fn, reps):
+    """Median wall time (ms) of fn() over reps, synchronised around each call."""
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1000.0)
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def copy_calibration(mib):
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.rand(n, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "reps": 3}))
+
+
+def row_col_models(n, rho, K, S):
+    """Algorithmic bytes and FLOPs per output pixel of the two passes (FP32).
+    FIR: a symmetric (2S+1)-tap filter costs S + 1 multiplies and 2S adds."""
+    fir = K * (n + 1) * (3 * S + 1)
+    weights = 2 * rho * K + K                   # distances and scaling (exp not counted)
+    row_flops = weights + 2 * K * K + K * n + fir   # + c = A^+ b and c [f, 1]
+    col_flops = weights + fir + 2 * K * (n + 1) + n  # + recombination and division
+    row_bytes = 4 * (n + rho + K * (n + 1))
+    col_bytes = 4 * (K * (n + 1) + rho + n)
+    return {"row": (row_bytes, row_flops), "col": (col_bytes, col_flops)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path "
               f"(asked for --gpus {args.gpus})", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     import numpy as np
     import torch
 
@@ -70,13 +130,14 @@ def main():
     import synth
 
     cfg = synth.CONFIGS[1]
-    H, W, n, K = cfg["H"], cfg["W"], cfg["n"], cfg["K"]
+    H, W, n, K, S = cfg["H"], cfg["W"], cfg["n"], cfg["K"], cfg["S"]
+    ss, sr = cfg["sigma_s"], cfg["sigma_r"]
     f = synth.config_input(1)
     x = torch.from_numpy(f).cuda()
     torch.cuda.synchronize()
 
     def step():
-        return fhd.filter(x, sigma_s=cfg["sigma_s"], sigma_r=cfg["sigma_r"], K=K, radius=cfg["S"])
+        return fhd.filter(x, sigma_s=ss, sigma_r=sr, K=K, radius=S)
 
     for _ in range(args.warmup):
         step()
@@ -98,19 +159,27 @@ def main():
     # dominant kernel: the longer of the two convolution passes
     avg = {s: (ms / cnt if cnt else 0.0) for s, (ms, cnt) in stages.items()}
     dom = "col" if avg["col"] >= avg["row"] else "row"
-    rho = n
-    bytes_per_px = 4 * (K * (n + 1) + n + rho)      # planes + image/guide (+ output, same size)
-    alg_bytes = bytes_per_px * N
-    achieved = alg_bytes / (avg[dom] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": f"{dom} pass", "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": MEASURED_TRAFFIC,
-                "bytes_per_launch": alg_bytes, "avg_ms": round(avg[dom], 4),
-                "launches": stages[dom][1]}
+    models = row_col_models(n, n, K, S)
+    bpx, fpx = models[dom]
+    sec = avg[dom] * 1e-3
+    gbs = bpx * N / sec / 1e9
+    tfs = fpx * N / sec / 1e12
+    # the row pass is VALU-bound (its counters show VALU busy, HBM at a fraction
+    # of peak); the column pass is reported against HBM
+    if dom == "row":
+        roofline = {"bound": "alu", "achieved": round(tfs, 2), "peak": FP32_VECTOR_PEAK,
+                    "unit": "TFLOP/s", "frac": round(tfs / FP32_VECTOR_PEAK, 4)}
+    else:
+        roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    roofline.update({"traffic": MEASURED_TRAFFIC, "kernel": f"{dom} pass",
+                     "flops_per_launch": fpx * N, "bytes_per_launch": bpx * N,
+                     "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "avg_ms": round(avg[dom], 4), "launches": stages[dom][1]})
     breakdown = {s: round(avg[s], 4) for s in avg if stages[s][1]}
 
     res = {
-        "metric": "Mpix/s (fwd), fast filter, FP32",
+        "metric": METRIC,
         "value": round(value, 2),
         "unit": "Mpix/s",
         "n_gpus": 1,
@@ -123,13 +192,57 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "bf_rgb_2048: 2048x2048 RGB bilateral, guide = image, "
-                               "sigma_s 5 (S 15), sigma_r 0.12, K 32, forward",
-                   "H": H, "W": W, "n": n, "rho": rho, "K": K, "S": cfg["S"],
-                   "sigma_s": cfg["sigma_s"], "sigma_r": cfg["sigma_r"]},
+                               "sigma_s 5 (S 15), sigma_r 0.12, K 32, forward, FP32 form",
+                   "H": H, "W": W, "n": n, "rho": n, "K": K, "S": S,
+                   "sigma_s": ss, "sigma_r": sr},
         "stage_ms": breakdown,
         "roofline": roofline,
     }
-    if not args.no_cpu:
+
+    if not args.quick:
+        # quality: eq. (21) against the GPU brute force of eqs. (1)-(2)
+        brute = fhd.bruteforce(x, sigma_s=ss, sigma_r=sr, radius=S)
+        ms_brute = timed(torch, lambda: fhd.bruteforce(x, sigma_s=ss, sigma_r=sr, radius=S), 5)
+        res["quality"] = {"psnr_vs_brute_db": round(psnr(out, brute), 2),
+                          "brute_force_mpix_s": round(N / ms_brute / 1e3, 1),
+                          "brute_force_ms": round(ms_brute, 3)}
+
+        # forward + hand-written adjoint (image and guide gradients, sigma_r)
+        G = torch.from_numpy(np.random.default_rng(7).standard_normal(f.shape).astype(np.float32)).cuda()
+
+        def fb():
+            o, d, c = fhd.filter(x, sigma_s=ss, sigma_r=sr, K=K, radius=S, return_den=True,
+                                 return_centers=True)
+            fhd.filter_backward(x, x, c, o, d, G, sigma_s=ss, sigma_r=sr, radius=S)
+
+        fb()
+        ms_fb = timed(torch, fb, max(3, args.steps // 4))
+        res["fwd_bwd"] = {"mpix_s": round(N / ms_fb / 1e3, 2), "ms_per_step": round(ms_fb, 3),
+                          "note": "one forward call plus one adjoint call (dL/df, dL/dguide, "
+                                  "dL/dsigma_r), same workload"}
+
+        # BF16 vs FP32 contraction on the 512x512x32 hyperspectral workload
+        c2 = synth.CONFIGS[2]
+        h = torch.from_numpy(synth.config_input(2)).cuda()
+        ref2 = fhd.bruteforce(h, sigma_s=c2["sigma_s"], sigma_r=c2["sigma_r"], radius=c2["S"])
+        ms_b2 = timed(torch, lambda: fhd.bruteforce(h, sigma_s=c2["sigma_s"], sigma_r=c2["sigma_r"],
+                                                    radius=c2["S"]), 3)
+        N2 = c2["H"] * c2["W"]
+        forms = {"workload": "hyper_512: 512x512x32 bands, guide = image, sigma_s 4 (S 12), "
+                             "sigma_r 0.2, K 64",
+                 "brute_force_mpix_s": round(N2 / ms_b2 / 1e3, 1)}
+        outs = {}
+        for form in ("fp32", "bf16"):
+            run = lambda: fhd.filter(h, sigma_s=c2["sigma_s"], sigma_r=c2["sigma_r"], K=c2["K"],
+                                     radius=c2["S"], contract=form)
+            outs[form] = run()
+            ms2 = timed(torch, run, 5)
+            forms[form] = {"mpix_s": round(N2 / ms2 / 1e3, 2),
+                           "psnr_vs_brute_db": round(psnr(outs[form], ref2), 2)}
+        forms["bf16_vs_fp32_max_abs"] = float((outs["bf16"] - outs["fp32"]).abs().max())
+        res["forms"] = forms
+
+    if not args.no_cpu and not args.quick:
         res["cpu_baseline"] = cpu_baseline(f, cfg, args.cpu_crop)
     print(json.dumps(res))
 

@@ -61,7 +61,10 @@ struct FA {
     float w[FHD_MAX_RADIUS + 1];  // 1-D spatial taps w[|j|]
 };
 
-__device__ __forceinline__ int pidx(int i) { return i + (i >> 5); }  // LDS skew vs bank conflicts
+// LDS skew: one pad word after every R_ROW = 8 entries.  A thread's window
+// starting at h0 = 8 seg sits at 9 seg + q + q / 8, so a run of lanes reads
+// with stride 9 words (no bank conflicts) at compile-time offsets from one base.
+__device__ __forceinline__ int pidx(int i) { return i + (i >> 3); }
 
 // ---------------------------------------------------------------------------
 // Row pass, phase 1: the convolved factor g_l (c_l or b_l) and f on the halo
@@ -107,8 +110,16 @@ __device__ void row_factors(const FA& a, int y, int x0, int hw, int csp, float* 
         __syncthreads();
         return;
     }
-    for (int t = threadIdx.x; t < K * rho; t += RT) smu[t] = a.mu[t];
-    for (int t = threadIdx.x; t < K * K; t += RT) sP[t] = a.P[t];
+    // zero-padded copies (K x RHO_INLINE centers, K x KMAX_INLINE rows of A^+)
+    // keep the unrolled loops below free of per-element bounds branches
+    for (int t = threadIdx.x; t < K * RHO_INLINE; t += RT) {
+        const int m = t / RHO_INLINE, r = t - m * RHO_INLINE;
+        smu[t] = r < rho ? a.mu[m * rho + r] : 0.0f;
+    }
+    for (int t = threadIdx.x; t < K * KMAX_INLINE; t += RT) {
+        const int m = t / KMAX_INLINE, l = t - m * KMAX_INLINE;
+        sP[t] = l < K ? a.P[m * K + l] : 0.0f;
+    }
     __syncthreads();
     const bool hard = a.coef == FHD_COEF_HARD;
     for (int h = threadIdx.x; h < hw; h += RT) {
@@ -124,26 +135,28 @@ __device__ void row_factors(const FA& a, int y, int x0, int hw, int csp, float* 
         for (int m = 0; m < K; ++m) {
             float d2 = 0.0f;
 #pragma unroll
-            for (int r = 0; r < RHO_INLINE; ++r) {
-                if (r < rho) {
-                    const float d = pr[r] - smu[m * rho + r];
-                    d2 = fmaf(d, d, d2);
-                }
+            for (int r = 0; r < RHO_INLINE; ++r) {  // padded entries are 0 - 0
+                const float d = pr[r] - smu[m * RHO_INLINE + r];
+                d2 = fmaf(d, d, d2);
             }
             const float b = in ? __expf(-d2 * a.inv2s2) : 0.0f;
             if (hard) {
                 cs[m * csp + pidx(h)] = b;
             } else {
-                const float* prow = sP + m * K;  // P symmetric: column m = row m
+                const float* prow = sP + m * KMAX_INLINE;  // P symmetric: column m = row m
 #pragma unroll
-                for (int l = 0; l < KMAX_INLINE; ++l)
-                    if (l < K) c[l] = fmaf(prow[l], b, c[l]);
+                for (int l = 0; l < KMAX_INLINE; ++l) c[l] = fmaf(prow[l], b, c[l]);
             }
         }
         if (!hard) {
+            if (K == KMAX_INLINE) {
 #pragma unroll
-            for (int l = 0; l < KMAX_INLINE; ++l)
-                if (l < K) cs[l * csp + pidx(h)] = c[l];
+                for (int l = 0; l < KMAX_INLINE; ++l) cs[l * csp + pidx(h)] = c[l];
+            } else {
+#pragma unroll
+                for (int l = 0; l < KMAX_INLINE; ++l)
+                    if (l < K) cs[l * csp + pidx(h)] = c[l];
+            }
         }
     }
     __syncthreads();
@@ -174,7 +187,7 @@ __global__ __launch_bounds__(RT) void row_gauss(FA a) {
     float* cs = lds;
     float* fs = cs + a.K * csp;
     float* smu = fs + (a.n + 1) * csp;
-    float* sP = smu + a.K * a.rho;
+    float* sP = smu + a.K * RHO_INLINE;
     row_factors(a, y, x0, hw, csp, cs, fs, smu, sP);
     const int nseg = a.tx / R;
     const int n = a.n;
@@ -183,8 +196,10 @@ __global__ __launch_bounds__(RT) void row_gauss(FA a) {
         const int x = x0 + seg * R;
         if (x >= a.W) continue;
         float cw[WIN];
+        static_assert(R == 8, "the LDS skew assumes 8 outputs per task");
+        const int wb = seg * (R + 1);  // pidx(seg * R)
 #pragma unroll
-        for (int q = 0; q < WIN; ++q) cw[q] = cs[l * csp + pidx(seg * R + q)];
+        for (int q = 0; q < WIN; ++q) cw[q] = cs[l * csp + wb + q + (q >> 3)];
         float o[R];
         if (a.fmode == 0) {  // last vector entry: the constant 1
 #pragma unroll
@@ -197,7 +212,7 @@ __global__ __launch_bounds__(RT) void row_gauss(FA a) {
         } else {
             float u[WIN];
 #pragma unroll
-            for (int q = 0; q < WIN; ++q) u[q] = cw[q] * fs[n * csp + pidx(seg * R + q)];
+            for (int q = 0; q < WIN; ++q) u[q] = cw[q] * fs[n * csp + wb + q + (q >> 3)];
 #pragma unroll
             for (int t = 0; t < R; ++t) {
                 float s = a.w[0] * u[t + S];
@@ -212,7 +227,7 @@ __global__ __launch_bounds__(RT) void row_gauss(FA a) {
         for (int ch = 0; ch < n; ++ch) {
             float u[WIN];
 #pragma unroll
-            for (int q = 0; q < WIN; ++q) u[q] = cw[q] * fs[ch * csp + pidx(seg * R + q)];
+            for (int q = 0; q < WIN; ++q) u[q] = cw[q] * fs[ch * csp + wb + q + (q >> 3)];
 #pragma unroll
             for (int t = 0; t < R; ++t) {
                 float s = a.w[0] * u[t + S];
@@ -238,7 +253,7 @@ __global__ __launch_bounds__(RT) void row_generic(FA a) {
     float* cs = lds;
     float* fs = cs + a.K * csp;
     float* smu = fs + (a.n + 1) * csp;
-    float* sP = smu + a.K * a.rho;
+    float* sP = smu + a.K * RHO_INLINE;
     row_factors(a, y, x0, hw, csp, cs, fs, smu, sP);
     const int nseg = a.tx / R;
     const int n = a.n;
@@ -1152,9 +1167,9 @@ int row_tx(int K, int S, int R) {
 
 size_t row_lds_bytes(const FilterPlan& fp, int tx) {
     const int hw = tx + 2 * fp.S;
-    const int csp = hw + ((hw - 1) >> 5) + 1;
+    const int csp = hw + ((hw - 1) >> 3);  // pidx(hw - 1) + 1
     size_t fl = (size_t)fp.K * csp + (size_t)(fp.n + 1) * csp;
-    if (!fp.materialize) fl += (size_t)fp.K * fp.rho + (size_t)fp.K * fp.K;
+    if (!fp.materialize) fl += (size_t)fp.K * (RHO_INLINE + KMAX_INLINE);
     return fl * sizeof(float);
 }
 

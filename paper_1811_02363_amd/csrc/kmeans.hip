@@ -19,8 +19,10 @@
 // Arithmetic: distances and centroid sums in FP64 from the FP32 points, in a
 // fixed reduction order (per lane sequential, fixed shuffle tree, waves in
 // order, blocks in order), so a run is deterministic.  No floating-point
-// atomics.  Lanes are laid out LP per point, each lane holding up to eight
-// consecutive dimensions (LP = 1 for rho <= 8).
+// atomics.  Lanes are laid out LP per point, each lane holding D consecutive
+// dimensions (LP = 1 for rho <= 8).  Points are packed at a stride of LP * D
+// floats with the dimensions beyond rho set to zero (centers too), so every
+// load is unconditional and the padded terms add exactly 0.0 to distances.
 #include <algorithm>
 #include <climits>
 #include <cmath>
@@ -60,6 +62,7 @@ struct KmArgs {
     double* jd;        // per job results, JD_W each
     int rho;
     int pw;
+    int ps;            // point stride in floats (LP * D of the launched layout)
 };
 
 // ---------------------------------------------------------------------------
@@ -78,12 +81,12 @@ struct Lanes {
     }
 };
 
-// this lane's dimensions of point `pos` (zero beyond rho)
-template <int D>
-__device__ __forceinline__ void load_dims(const float* pts, long long pos, int rho, int d0, double (&x)[D]) {
-    const float* p = pts + pos * rho;
+// this lane's dimensions of point `pos` (stored zeros beyond rho)
+template <int LP, int D>
+__device__ __forceinline__ void load_dims(const float* pts, long long pos, int d0, double (&x)[D]) {
+    const float* p = pts + pos * (LP * D) + d0;
 #pragma unroll
-    for (int k = 0; k < D; ++k) x[k] = (d0 + k < rho) ? (double)p[d0 + k] : 0.0;
+    for (int k = 0; k < D; ++k) x[k] = (double)p[k];
 }
 
 template <int D>
@@ -98,11 +101,10 @@ template <int LP, int D>
 __device__ __forceinline__ double dist2(const double (&x)[D], const double (&c)[D], int rho, int d0) {
     double s = 0.0;
 #pragma unroll
-    for (int k = 0; k < D; ++k)
-        if (d0 + k < rho) {
-            const double t = __dsub_rn(x[k], c[k]);
-            s = __dadd_rn(s, __dmul_rn(t, t));
-        }
+    for (int k = 0; k < D; ++k) {  // beyond rho: (0 - 0)^2 added to s >= +0 leaves s unchanged
+        const double t = __dsub_rn(x[k], c[k]);
+        s = __dadd_rn(s, __dmul_rn(t, t));
+    }
 #pragma unroll
     for (int o = 1; o < LP; o <<= 1) s = __dadd_rn(s, __shfl_xor(s, o, 64));
     return s;
@@ -195,11 +197,11 @@ __device__ void reduce_records(const double* part, int first, int nblk, int pw, 
 // ---------------------------------------------------------------------------
 // passes
 
-__global__ __launch_bounds__(KT) void km_pack(const float* __restrict__ guide, int rho, long long N,
+__global__ __launch_bounds__(KT) void km_pack(const float* __restrict__ guide, int rho, int ps, long long N,
                                               float* __restrict__ pts, int* __restrict__ idx) {
     const long long i = (long long)blockIdx.x * KT + threadIdx.x;
     if (i >= N) return;
-    for (int d = 0; d < rho; ++d) pts[i * rho + d] = guide[(long long)d * N + i];
+    for (int d = 0; d < ps; ++d) pts[i * ps + d] = d < rho ? guide[(long long)d * N + i] : 0.0f;
     idx[i] = (int)i;
 }
 
@@ -223,7 +225,7 @@ __global__ __launch_bounds__(KT) void km_stats(KmArgs a) {
         const int p = base + L.wave * L.PPW + L.pw;
         if (p >= cnt) continue;
         double x[D];
-        load_dims(pts, s + p, rho, L.d0, x);
+        load_dims<LP, D>(pts, s + p, L.d0, x);
 #pragma unroll
         for (int k = 0; k < D; ++k)
             if (L.d0 + k < rho) {
@@ -254,7 +256,7 @@ __global__ __launch_bounds__(KT) void km_sse1(KmArgs a) {
         const int p = base + L.wave * L.PPW + L.pw;
         if (p >= cnt) continue;
         double x[D];
-        load_dims(pts, s + p, rho, L.d0, x);
+        load_dims<LP, D>(pts, s + p, L.d0, x);
 #pragma unroll
         for (int k = 0; k < D; ++k)
             if (L.d0 + k < rho) {
@@ -289,7 +291,7 @@ __global__ __launch_bounds__(KT) void km_far(KmArgs a, int which) {
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
             pp[u] = base + (u * KWAVES + L.wave) * L.PPW + L.pw;
-            load_dims(pts, pp[u] < cnt ? s + pp[u] : s, rho, L.d0, x[u]);
+            load_dims<LP, D>(pts, pp[u] < cnt ? s + pp[u] : s, L.d0, x[u]);
         }
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
@@ -361,7 +363,7 @@ __global__ __launch_bounds__(KT) void km_lloyd(KmArgs a) {
         for (int u = 0; u < UNR; ++u) {
             const int p = base + (u * KWAVES + L.wave) * L.PPW + L.pw;
             valid[u] = p < cnt;
-            load_dims(pts, valid[u] ? s + p : s, rho, L.d0, x[u]);
+            load_dims<LP, D>(pts, valid[u] ? s + p : s, L.d0, x[u]);
         }
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
@@ -420,7 +422,7 @@ __global__ __launch_bounds__(KT) void km_split(KmArgs a) {
         for (int u = 0; u < UNR; ++u) {
             const int p = base + (u * KWAVES + L.wave) * L.PPW + L.pw;
             valid[u] = p < cnt;
-            load_dims(pts, valid[u] ? s + p : s, rho, L.d0, x[u]);
+            load_dims<LP, D>(pts, valid[u] ? s + p : s, L.d0, x[u]);
         }
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
@@ -506,7 +508,7 @@ __global__ __launch_bounds__(KT) void km_scatter(KmArgs a) {
         const int p = base + L.wave * L.PPW + L.pw;
         const bool valid = p < cnt;
         double x[D];
-        load_dims(src, valid ? s + p : s, rho, L.d0, x);
+        load_dims<LP, D>(src, valid ? s + p : s, L.d0, x);
         const bool A = to_first<LP, D>(x, fa, fb, rho, L.d0);
         const bool lead = valid && L.sub == 0;
         const unsigned long long ma = __ballot(lead && A);
@@ -530,9 +532,9 @@ __global__ __launch_bounds__(KT) void km_scatter(KmArgs a) {
         }
         if (valid) {
             const int to = A ? offA + pa + ra : offB + pb + rb;
+            constexpr int PS = LP * D;
 #pragma unroll
-            for (int k = 0; k < D; ++k)
-                if (L.d0 + k < rho) dst[(long long)to * rho + L.d0 + k] = src[(long long)(s + p) * rho + L.d0 + k];
+            for (int k = 0; k < D; ++k) dst[(long long)to * PS + L.d0 + k] = src[(long long)(s + p) * PS + L.d0 + k];
             if (L.sub == 0) idst[to] = isrc[s + p];
         }
         offA += ta;
@@ -624,7 +626,7 @@ __global__ __launch_bounds__(KT) void fin_far(KmArgs a, int which) {
     __syncthreads();
     const float* pts = a.pts[ji[JI_BUF]];
     if (threadIdx.x < rho)
-        (which == 0 ? a.ca : a.cb)[job * rho + threadIdx.x] = pts[(long long)s_pos * rho + threadIdx.x];
+        (which == 0 ? a.ca : a.cb)[job * rho + threadIdx.x] = pts[(long long)s_pos * a.ps + threadIdx.x];
 }
 
 // The 2-means state machine after one assignment step (m = means of the new
@@ -747,6 +749,13 @@ int lanes_per_point(int rho) {
     return lp;
 }
 
+// floats per packed point: LP * D of the layout launch_pass picks
+int point_stride(int rho) {
+    if (rho <= 3) return 3;
+    if (rho <= 4) return 4;
+    return lanes_per_point(rho) * DPL;
+}
+
 long long chunk_points(int rho) { return (long long)KITERS * KWAVES * (64 / lanes_per_point(rho)); }
 
 long long max_blocks(long long N, int rho, int K) { return N / chunk_points(rho) + 2LL * K + 4; }
@@ -770,7 +779,7 @@ KmBuffers carve(Arena& ws, long long N, int rho, int K) {
     b.maxJobs = std::max(2 * K, 4);
     b.maxBlocks = max_blocks(N, rho, K);
     for (int q = 0; q < 2; ++q) {
-        b.pts[q] = ws.take<float>((size_t)N * rho + 64);
+        b.pts[q] = ws.take<float>((size_t)N * point_stride(rho) + 64);
         b.idx[q] = ws.take<int>((size_t)N);
     }
     b.btab = ws.take<int4>((size_t)b.maxBlocks);
@@ -797,10 +806,11 @@ void launch_lp(int which, dim3 g, hipStream_t s, const KmArgs& a, int arg) {
     }
 }
 
-// lane layout by guide dimension: one lane per point with four or eight
-// dimensions, or LP lanes of eight dimensions each
+// lane layout by guide dimension: one lane per point with three, four or
+// eight dimensions, or LP lanes of eight dimensions each (point_stride agrees)
 void launch_pass(int rho, int which, dim3 g, hipStream_t s, const KmArgs& a, int arg = 0) {
-    if (rho <= 4) launch_lp<1, 4>(which, g, s, a, arg);
+    if (rho <= 3) launch_lp<1, 3>(which, g, s, a, arg);
+    else if (rho <= 4) launch_lp<1, 4>(which, g, s, a, arg);
     else if (rho <= 8) launch_lp<1, 8>(which, g, s, a, arg);
     else if (rho <= 16) launch_lp<2, 8>(which, g, s, a, arg);
     else if (rho <= 32) launch_lp<4, 8>(which, g, s, a, arg);
@@ -874,9 +884,11 @@ void kmeans_run(Ctx& c, Arena& ws, const float* guide, int rho, long long N, int
     a.jd = B.jd;
     a.rho = rho;
     a.pw = record_width(rho);
+    a.ps = point_stride(rho);
 
     hipEvent_t t_begin = c.stage_begin();
-    hipLaunchKernelGGL(km_pack, dim3((unsigned)((N + KT - 1) / KT)), dim3(KT), 0, st, guide, rho, N, B.pts[0], B.idx[0]);
+    hipLaunchKernelGGL(km_pack, dim3((unsigned)((N + KT - 1) / KT)), dim3(KT), 0, st, guide, rho, a.ps, N, B.pts[0],
+                       B.idx[0]);
     FHD_HIP(hipGetLastError());
 
     // Upload jobs (ranges of leaves) and their block table; returns #blocks.
