@@ -175,6 +175,25 @@ fhd_status fhd_filter(fhd_ctx* ctx, const float* f, int n, const float* guide, i
                       int H, int W, const fhd_params* p, float* out, float* centers_out,
                       float* den, fhd_info* info);
 
+/* Ragged batch: Algorithm 1 on B independent images of one shape family
+ * (n channels, rho guide dimensions, sizes H[b] x W[b]), one clustering tree
+ * per image with every clustering pass launched once for all images.
+ *   H, W, px_offset host arrays of B; image b holds H[b] * W[b] pixels from
+ *           pixel px_offset[b] on; the images are packed back to back
+ *           (px_offset[0] = 0, px_offset[b + 1] = px_offset[b] + H[b] W[b]),
+ *           otherwise FHD_EINVAL.
+ *   f       device: image b is n x H[b] x W[b] planar at element n * px_offset[b].
+ *   guide   device: rho x H[b] x W[b] at element rho * px_offset[b] (may equal f).
+ *   out     device, laid out like f.  den device, one plane per image at
+ *           element px_offset[b], or NULL.
+ *   centers_out host B x K x rho (rows K_eff[b]..K-1 of image b untouched) or
+ *           NULL;  K_eff host B or NULL;  info host B or NULL.
+ * Synchronises once per clustering round. */
+fhd_status fhd_filter_batch(fhd_ctx* ctx, int B, const int* H, const int* W,
+                            const long long* px_offset, const float* f, int n,
+                            const float* guide, int rho, const fhd_params* p, float* out,
+                            float* centers_out, int* K_eff, float* den, fhd_info* info);
+
 /* Adjoint of fhd_filter_centers for least-squares coefficients (the paper
  * does not differentiate its filter; this is the exact gradient of the
  * computation of Algorithm 1 steps 2-5 with the centers held fixed).  Given
@@ -198,6 +217,19 @@ fhd_status fhd_filter_backward(fhd_ctx* ctx, const float* f, int n, const float*
                                int H, int W, const float* centers, int K, const fhd_params* p,
                                const float* out, const float* den, const float* grad_out,
                                float* grad_f, float* grad_guide, double* grad_sigma_r);
+
+/* Adjoint of fhd_filter_batch (least-squares coefficients), laid out like
+ * it: centers host B x K x rho and K_eff host B as returned by the forward
+ * call; out, den its outputs (den required); grad_out, grad_f, grad_guide
+ * device in the layouts of f and guide (gradient outputs may be NULL);
+ * grad_sigma_r host, the sum over the images, or NULL (synchronises when
+ * non-NULL).  Same limits as fhd_filter_backward. */
+fhd_status fhd_filter_batch_backward(fhd_ctx* ctx, int B, const int* H, const int* W,
+                                     const long long* px_offset, const float* f, int n,
+                                     const float* guide, int rho, const float* centers,
+                                     const int* K_eff, const fhd_params* p, const float* out,
+                                     const float* den, const float* grad_out, float* grad_f,
+                                     float* grad_guide, double* grad_sigma_r);
 
 /* The brute-force filter of eqs. (1)-(2) on the GPU (FP32), the reference
  * the approximation is measured against.  out device n x H x W; den device

@@ -18,6 +18,7 @@ import torch
 __all__ = [
     "FHDError", "Params", "Info", "load", "lib_path", "symbols",
     "filter", "filter_centers", "filter_backward", "FilterFunction", "filter_autograd",
+    "pack_batch", "filter_batch", "filter_batch_backward",
     "cluster", "pinv", "bruteforce", "nlm_guide",
 ]
 
@@ -35,7 +36,8 @@ COEF = {"lsq": 0, "hard": 1}
 symbols = [
     "fhd_default_params", "fhd_create", "fhd_destroy", "fhd_set_stream", "fhd_last_error",
     "fhd_workspace_size", "fhd_set_workspace", "fhd_cluster", "fhd_pinv",
-    "fhd_filter_centers", "fhd_filter", "fhd_filter_backward", "fhd_bruteforce", "fhd_nlm_guide",
+    "fhd_filter_centers", "fhd_filter", "fhd_filter_backward", "fhd_filter_batch",
+    "fhd_filter_batch_backward", "fhd_bruteforce", "fhd_nlm_guide",
     "fhd_timing_enable", "fhd_timing_read",
 ]
 STAGES = ("cluster", "weights", "row", "col", "brute")
@@ -101,6 +103,9 @@ def load():
             "fhd_filter_centers": (I, [V, V, I, V, I, I, I, V, I, V, pp, V, V, pi]),
             "fhd_filter": (I, [V, V, I, V, I, I, I, pp, V, V, V, pi]),
             "fhd_filter_backward": (I, [V, V, I, V, I, I, I, V, I, pp, V, V, V, V, V, P(D)]),
+            "fhd_filter_batch": (I, [V, I, V, V, V, V, I, V, I, pp, V, V, V, V, pi]),
+            "fhd_filter_batch_backward": (I, [V, I, V, V, V, V, I, V, I, V, V, pp, V, V, V, V, V,
+                                              P(D)]),
             "fhd_bruteforce": (I, [V, V, I, V, I, I, I, pp, V, V]),
             "fhd_nlm_guide": (I, [V, V, I, I, I, I, I, V, V]),
             "fhd_timing_enable": (I, [V, I]),
@@ -290,6 +295,86 @@ def filter_autograd(f, guide=None, sigma_s=3.0, sigma_r=0.1, K=16, spatial="gaus
     if centers is None:
         centers, _ = cluster(g.detach(), K, max_iter=kmeans_max_iter)
     return FilterFunction.apply(f, g, sigma_r, centers, sigma_s, spatial, radius, contract)
+
+
+def pack_batch(images):
+    """Concatenate (C, H_b, W_b) device tensors into the flat ragged layout of
+    fhd_filter_batch; returns (flat tensor, [(H_b, W_b)])."""
+    if not images:
+        raise FHDError(FHD_EINVAL, "empty batch")
+    C = images[0].shape[0]
+    for t in images:
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dim() != 3 or t.shape[0] != C:
+            raise FHDError(FHD_EINVAL, "batch images must be (C, H, W) CUDA tensors with one C")
+    flat = torch.cat([t.reshape(-1) for t in images])
+    return flat, [(int(t.shape[1]), int(t.shape[2])) for t in images]
+
+
+def _batch_arrays(sizes):
+    B = len(sizes)
+    Ha = (ctypes.c_int * B)(*[h for h, _ in sizes])
+    Wa = (ctypes.c_int * B)(*[w for _, w in sizes])
+    offs, o = [], 0
+    for h, w in sizes:
+        offs.append(o)
+        o += h * w
+    Oa = (ctypes.c_longlong * B)(*offs)
+    return B, Ha, Wa, Oa, o
+
+
+def filter_batch(flat_f, sizes, n, flat_guide=None, rho=None, sigma_s=3.0, sigma_r=0.1, K=16,
+                 spatial="gaussian", radius=None, contract="fp32", coef="lsq", kmeans_max_iter=20,
+                 return_den=False, info=False):
+    """Algorithm 1 on a ragged batch in the flat layout of :func:`pack_batch`.
+    Returns (out flat, [den flat], centers (B, K, rho) host, K_eff list [, info list])."""
+    B, Ha, Wa, Oa, N = _batch_arrays(sizes)
+    g = flat_f if flat_guide is None else flat_guide
+    rho = n if rho is None else rho
+    if flat_f.numel() != n * N or g.numel() != rho * N:
+        raise FHDError(FHD_EINVAL, "flat buffers do not match the sizes")
+    ctx = _ctx(flat_f.device.index)
+    p = make_params(sigma_s, sigma_r, K, spatial, radius, contract, coef, kmeans_max_iter)
+    out = torch.empty_like(flat_f)
+    den = torch.empty(N, device=flat_f.device, dtype=torch.float32) if return_den else None
+    cen = torch.zeros((B, K, rho), dtype=torch.float32)
+    keff = (ctypes.c_int * B)()
+    infos = (Info * B)()
+    _check(load().fhd_filter_batch(ctx, B, Ha, Wa, Oa, _dev(flat_f, "f"), n, _dev(g, "guide"), rho,
+                                   ctypes.byref(p), _dev(out, "out"), ctypes.c_void_p(cen.data_ptr()),
+                                   keff, _dev(den, "den") if den is not None else None,
+                                   infos if info else None), ctx)
+    res = [out]
+    if return_den:
+        res.append(den)
+    res += [cen, list(keff)]
+    if info:
+        res.append([i.as_dict() for i in infos])
+    return tuple(res)
+
+
+def filter_batch_backward(flat_f, sizes, n, centers, K_eff, out, den, grad_out, flat_guide=None,
+                          rho=None, sigma_s=3.0, sigma_r=0.1, spatial="gaussian", radius=None,
+                          need_f=True, need_guide=True, need_sigma_r=True):
+    """Adjoint of :func:`filter_batch`: (dL/df flat or None, dL/dguide flat or
+    None, dL/dsigma_r summed over the images or None)."""
+    B, Ha, Wa, Oa, N = _batch_arrays(sizes)
+    g = flat_f if flat_guide is None else flat_guide
+    rho = n if rho is None else rho
+    ctx = _ctx(flat_f.device.index)
+    c = torch.as_tensor(centers, dtype=torch.float32).detach().cpu().contiguous()
+    K = c.shape[1]
+    p = make_params(sigma_s, sigma_r, K, spatial, radius)
+    keff = (ctypes.c_int * B)(*K_eff)
+    gf = torch.empty_like(flat_f) if need_f else None
+    gg = torch.empty_like(g) if need_guide else None
+    gs = ctypes.c_double(0.0)
+    _check(load().fhd_filter_batch_backward(
+        ctx, B, Ha, Wa, Oa, _dev(flat_f, "f"), n, _dev(g, "guide"), rho, ctypes.c_void_p(c.data_ptr()),
+        keff, ctypes.byref(p), _dev(out, "out"), _dev(den, "den"), _dev(grad_out, "grad_out"),
+        _dev(gf, "grad_f") if gf is not None else None,
+        _dev(gg, "grad_guide") if gg is not None else None,
+        ctypes.byref(gs) if need_sigma_r else None), ctx)
+    return gf, gg, (gs.value if need_sigma_r else None)
 
 
 def cluster(guide, K, max_iter=20, labels=False):

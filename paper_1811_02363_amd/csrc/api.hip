@@ -253,6 +253,24 @@ void fill_info(fhd_info* info, int K_eff, const PinvResult& pr, double E_K, int 
     info->ms_filter = (float)ms_filter;
 }
 
+// Validates a ragged batch and returns the pixel count of every image; the
+// images must be packed back to back (px_offset[0] = 0, each image right after
+// the previous one).
+std::vector<long long> batch_counts(int B, const int* H, const int* W, const long long* px_offset) {
+    FHD_REQUIRE(B >= 1 && H != nullptr && W != nullptr && px_offset != nullptr, FHD_EINVAL,
+                "batch needs B >= 1 and the H, W, px_offset arrays");
+    std::vector<long long> cnt(B);
+    long long next = 0;
+    for (int b = 0; b < B; ++b) {
+        FHD_REQUIRE(H[b] >= 1 && W[b] >= 1, FHD_EINVAL, "every image needs H, W >= 1");
+        FHD_REQUIRE(px_offset[b] == next, FHD_EINVAL, "images must be packed back to back from offset 0");
+        cnt[b] = (long long)H[b] * W[b];
+        next += cnt[b];
+    }
+    FHD_REQUIRE(next < (1LL << 31), FHD_EUNSUPPORTED, "batch has 2^31 pixels or more");
+    return cnt;
+}
+
 }  // namespace
 }  // namespace fhd
 
@@ -505,6 +523,144 @@ fhd_status fhd_filter_backward(fhd_ctx* ctx, const float* f, int n, const float*
         for (size_t q = 0; q < M.size(); ++q) M32[q] = (float)M[q];
         adjoint_run(c, ws, fp, f, guide, centers, P32.data(), M32.data(), out, den, grad_out, grad_f, grad_guide,
                     grad_sigma_r);
+    });
+}
+
+fhd_status fhd_filter_batch(fhd_ctx* ctx, int B, const int* H, const int* W, const long long* px_offset,
+                            const float* f, int n, const float* guide, int rho, const fhd_params* p, float* out,
+                            float* centers_out, int* K_eff, float* den, fhd_info* info) {
+    return guarded(ctx, [&](Ctx& c) {
+        const std::vector<long long> cnt = batch_counts(B, H, W, px_offset);
+        for (int b = 0; b < B; ++b) check_params(p, n, rho, H[b], W[b]);
+        FHD_REQUIRE(f && guide && out, FHD_EINVAL, "NULL pointer");
+        long long N = 0;
+        for (long long q : cnt) N += q;
+        FHD_REQUIRE(!ranges_overlap(out, sizeof(float) * N * n, f, sizeof(float) * N * n) &&
+                        !ranges_overlap(out, sizeof(float) * N * n, guide, sizeof(float) * N * rho) &&
+                        !ranges_overlap(den, sizeof(float) * N, f, sizeof(float) * N * n) &&
+                        !ranges_overlap(den, sizeof(float) * N, guide, sizeof(float) * N * rho) &&
+                        !ranges_overlap(den, sizeof(float) * N, out, sizeof(float) * N * n),
+                    FHD_EINVAL, "outputs alias inputs");
+        const int K = p->K;
+        size_t passes = 0;
+        for (int b = 0; b < B; ++b) passes = std::max(passes, filter_passes_workspace(make_plan(*p, n, rho, H[b], W[b], K)));
+        const size_t cb = filter_consts_bytes(K, rho);
+        const size_t need = std::max(kmeans_workspace(N, rho, K, B), (size_t)B * cb + passes + 512) +
+                            align_up(sizeof(int) * (size_t)N, 256) + 4096;
+        Arena ws = c.arena(need);
+        const bool hard = p->coef == FHD_COEF_HARD;
+        int* labels = hard ? ws.take<int>((size_t)N) : nullptr;
+        const auto t0 = clk::now();
+        std::vector<KmResult> km;
+        {
+            Arena kws = ws;  // the clustering scratch is dead once the centers are known
+            kmeans_run_batch(c, kws, guide, rho, B, px_offset, cnt.data(), K, p->kmeans_max_iter, labels, km);
+        }
+        const double ms_cluster = ms_since(t0);
+        // all images' constants in one pinned block and one copy
+        char* dev = ws.take<char>((size_t)B * cb);
+        char* hs = static_cast<char*>(c.host_stage(1, (size_t)B * cb));
+        std::vector<PinvResult> pr(B);
+        std::vector<float> c32;
+        const auto t1 = clk::now();
+        for (int b = 0; b < B; ++b) {
+            const int Kb = km[b].K_eff;
+            c32.assign((size_t)Kb * rho, 0.0f);
+            for (size_t q = 0; q < c32.size(); ++q) c32[q] = (float)km[b].centers[q];
+            if (centers_out) std::memcpy(centers_out + (size_t)b * K * rho, c32.data(), sizeof(float) * c32.size());
+            if (K_eff) K_eff[b] = Kb;
+            std::vector<float> P32;
+            pr[b] = solve(c32.data(), Kb, rho, p->sigma_r, p->pinv_rtol, P32);
+            filter_consts_fill(c32.data(), P32.data(), Kb, rho, hs + (size_t)b * cb);
+        }
+        const double ms_solve = ms_since(t1);
+        FHD_HIP(hipMemcpyAsync(dev, hs, (size_t)B * cb, hipMemcpyHostToDevice, c.stream));
+        c.stage_done(1);
+        const auto t2 = clk::now();
+        for (int b = 0; b < B; ++b) {
+            const FilterPlan fp = make_plan(*p, n, rho, H[b], W[b], km[b].K_eff);
+            Arena pws = ws;  // stream order makes the scratch reusable image after image
+            const long long o = px_offset[b];
+            filter_passes(c, pws, fp, f + (size_t)n * o, guide + (size_t)rho * o,
+                          filter_consts_at(dev + (size_t)b * cb, km[b].K_eff, rho), hard ? labels + o : nullptr,
+                          out + (size_t)n * o, den ? den + o : nullptr);
+        }
+        if (p->strict) strict_check(c, ws, out, N * n, den, N);
+        double ms_filter = 0.0;
+        if (info) {
+            FHD_HIP(hipStreamSynchronize(c.stream));
+            ms_filter = ms_since(t2);
+            for (int b = 0; b < B; ++b)
+                fill_info(info + b, km[b].K_eff, pr[b], km[b].E_K, km[b].rounds, km[b].splits, ms_cluster, ms_solve,
+                          ms_filter);
+        }
+    });
+}
+
+fhd_status fhd_filter_batch_backward(fhd_ctx* ctx, int B, const int* H, const int* W, const long long* px_offset,
+                                     const float* f, int n, const float* guide, int rho, const float* centers,
+                                     const int* K_eff, const fhd_params* p, const float* out, const float* den,
+                                     const float* grad_out, float* grad_f, float* grad_guide, double* grad_sigma_r) {
+    return guarded(ctx, [&](Ctx& c) {
+        const std::vector<long long> cnt = batch_counts(B, H, W, px_offset);
+        for (int b = 0; b < B; ++b) check_params(p, n, rho, H[b], W[b]);
+        FHD_REQUIRE(f && guide && centers && K_eff && out && den && grad_out, FHD_EINVAL, "NULL pointer");
+        FHD_REQUIRE(p->coef == FHD_COEF_LSQ, FHD_EUNSUPPORTED, "the adjoint covers least-squares coefficients");
+        const int K = p->K;
+        long long N = 0;
+        for (long long q : cnt) N += q;
+        const size_t fb = sizeof(float) * N * n, gb = sizeof(float) * N * rho, db = sizeof(float) * N;
+        auto clash = [&](const void* o, size_t ob) {
+            return ranges_overlap(o, ob, f, fb) || ranges_overlap(o, ob, guide, gb) ||
+                   ranges_overlap(o, ob, out, fb) || ranges_overlap(o, ob, den, db) ||
+                   ranges_overlap(o, ob, grad_out, fb);
+        };
+        FHD_REQUIRE(!clash(grad_f, fb) && !clash(grad_guide, gb) && !ranges_overlap(grad_f, fb, grad_guide, gb),
+                    FHD_EINVAL, "gradient outputs alias inputs or each other");
+        std::vector<FilterPlan> plans(B);
+        size_t passes = 0;
+        for (int b = 0; b < B; ++b) {
+            FHD_REQUIRE(K_eff[b] >= 1 && K_eff[b] <= std::min(K, 64), FHD_EUNSUPPORTED,
+                        "the adjoint supports K_eff in [1, min(K, 64)]");
+            plans[b] = make_plan(*p, n, rho, H[b], W[b], K_eff[b]);
+            plans[b].contract = FHD_CONTRACT_FP32;
+            plans[b].materialize = true;
+            passes = std::max(passes, adjoint_passes_workspace(plans[b]));
+        }
+        const size_t cb = adjoint_consts_bytes(K, rho);
+        Arena ws = c.arena((size_t)B * cb + align_up(sizeof(double) * (B + 1), 256) + passes + 4096);
+        char* dev = ws.take<char>((size_t)B * cb);
+        double* sig = ws.take<double>((size_t)B + 1);
+        char* hs = static_cast<char*>(c.host_stage(1, (size_t)B * cb));
+        for (int b = 0; b < B; ++b) {
+            const int Kb = K_eff[b];
+            const float* cen = centers + (size_t)b * K * rho;
+            std::vector<float> P32;
+            (void)solve(cen, Kb, rho, p->sigma_r, p->pinv_rtol, P32);
+            std::vector<double> M((size_t)Kb * Kb);
+            pinv_sigma_derivative(cen, Kb, rho, p->sigma_r, p->pinv_rtol, M.data());
+            char* h = hs + (size_t)b * cb;
+            filter_consts_fill(cen, P32.data(), Kb, rho, h);
+            float* m32 = reinterpret_cast<float*>(h + filter_consts_bytes(Kb, rho));
+            for (size_t q = 0; q < M.size(); ++q) m32[q] = (float)M[q];
+        }
+        FHD_HIP(hipMemcpyAsync(dev, hs, (size_t)B * cb, hipMemcpyHostToDevice, c.stream));
+        c.stage_done(1);
+        for (int b = 0; b < B; ++b) {
+            const int Kb = K_eff[b];
+            const long long o = px_offset[b];
+            const char* d = dev + (size_t)b * cb;
+            Arena pws = ws;
+            adjoint_passes(c, pws, plans[b], f + (size_t)n * o, guide + (size_t)rho * o, filter_consts_at(d, Kb, rho),
+                           reinterpret_cast<const float*>(d + filter_consts_bytes(Kb, rho)), out + (size_t)n * o,
+                           den + o, grad_out + (size_t)n * o, grad_f ? grad_f + (size_t)n * o : nullptr,
+                           grad_guide ? grad_guide + (size_t)rho * o : nullptr, sig + b);
+        }
+        if (grad_sigma_r != nullptr) {
+            sum_doubles(c, sig, B, sig + B);
+            FHD_HIP(hipMemcpyAsync(grad_sigma_r, sig + B, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+            FHD_HIP(hipStreamSynchronize(c.stream));
+        }
     });
 }
 

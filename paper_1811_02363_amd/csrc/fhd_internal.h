@@ -60,9 +60,15 @@ struct KmResult {
     std::vector<double> centers;   // K_eff x rho, FP64 leaf centroids in heap order
 };
 // Workspace bytes for clustering N points of dimension rho into <= K leaves.
-size_t kmeans_workspace(long long N, int rho, int K);
+size_t kmeans_workspace(long long N, int rho, int K, int images = 1);
 void kmeans_run(Ctx& c, Arena& ws, const float* guide, int rho, long long N, int K,
                 int max_iter, int* labels, KmResult& out);
+// Several images (planar rho x N_b guides at element offsets rho * px_offset[b],
+// packed back to back), one tree each, every pass launched once for all trees.
+// labels (optional) index the concatenation of the images.
+void kmeans_run_batch(Ctx& c, Arena& ws, const float* guide, int rho, int images,
+                      const long long* px_offset, const long long* px_count, int K, int max_iter,
+                      int* labels, std::vector<KmResult>& out);
 
 // ---- K x K solve (linalg.cpp) ----------------------------------------------
 struct PinvResult {
@@ -91,9 +97,31 @@ size_t filter_workspace(const FilterPlan& fp);
 void filter_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const float* guide,
                 const float* centers_host, const float* Pfp32_host, const int* labels,
                 float* out, float* den);
+// Device copies of one image's constants: centers (K x rho), A^+ (K x K) and
+// the contraction offset (rho), FP32, in one block of filter_consts_bytes.
+struct FilterConsts {
+    const float* mu;
+    const float* P;
+    const float* offs;
+};
+size_t filter_consts_bytes(int K, int rho);
+void filter_consts_fill(const float* centers, const float* P32, int K, int rho, char* host_dst);
+FilterConsts filter_consts_at(const char* dev, int K, int rho);
+size_t filter_passes_workspace(const FilterPlan& fp);
+void filter_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const float* guide,
+                   const FilterConsts& kc, const int* labels, float* out, float* den);
 void bruteforce_run(Ctx& c, const FilterPlan& fp, const float* f, const float* guide,
                     float* out, float* den);
 size_t adjoint_workspace(const FilterPlan& fp);
+// constants of the adjoint: filter constants, then M = dA^+/dsigma_r (K x K)
+size_t adjoint_consts_bytes(int K, int rho);
+size_t adjoint_passes_workspace(const FilterPlan& fp);
+// writes the sigma_r gradient (one double) to sig_dev on the device
+void adjoint_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const float* guide,
+                    const FilterConsts& kc, const float* Md, const float* out, const float* den,
+                    const float* gout, float* gradf, float* gradp, double* sig_dev);
+// out_dev[0] = v[0] + ... + v[count-1] (fixed order), on the ctx stream
+void sum_doubles(Ctx& c, const double* v, int count, double* out_dev);
 void adjoint_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const float* guide,
                  const float* centers_host, const float* Pfp32_host, const float* M_host, const float* out,
                  const float* den, const float* gout, float* gradf, float* gradp, double* gsig);

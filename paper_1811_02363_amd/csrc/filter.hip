@@ -1175,7 +1175,35 @@ size_t row_lds_bytes(const FilterPlan& fp, int tx) {
 
 }  // namespace
 
-size_t filter_workspace(const FilterPlan& fp) {
+size_t filter_consts_bytes(int K, int rho) {
+    return align_up(sizeof(float) * K * rho, 256) + align_up(sizeof(float) * K * K, 256) +
+           align_up(sizeof(float) * rho, 256);
+}
+
+// centers, A^+ and the contraction offset (mean of the centers), FP32, laid
+// out as filter_consts_bytes says, at `dst` (host)
+void filter_consts_fill(const float* centers, const float* P32, int K, int rho, char* dst) {
+    std::memcpy(dst, centers, sizeof(float) * K * rho);
+    std::memcpy(dst + align_up(sizeof(float) * K * rho, 256), P32, sizeof(float) * K * K);
+    float* ho = reinterpret_cast<float*>(dst + align_up(sizeof(float) * K * rho, 256) +
+                                         align_up(sizeof(float) * K * K, 256));
+    for (int d = 0; d < rho; ++d) {
+        double s = 0.0;
+        for (int k = 0; k < K; ++k) s += centers[(size_t)k * rho + d];
+        ho[d] = (float)(s / K);
+    }
+}
+
+FilterConsts filter_consts_at(const char* dev, int K, int rho) {
+    FilterConsts k;
+    k.mu = reinterpret_cast<const float*>(dev);
+    k.P = reinterpret_cast<const float*>(dev + align_up(sizeof(float) * K * rho, 256));
+    k.offs = reinterpret_cast<const float*>(dev + align_up(sizeof(float) * K * rho, 256) +
+                                            align_up(sizeof(float) * K * K, 256));
+    return k;
+}
+
+size_t filter_passes_workspace(const FilterPlan& fp) {
     Arena probe;
     const long long Np = (long long)fp.H * fp.Wp;
     probe.take<float>(plane_floats(fp));
@@ -1183,15 +1211,28 @@ size_t filter_workspace(const FilterPlan& fp) {
         probe.take<float>((size_t)fp.K * Np);
         probe.take<float>((size_t)fp.K * Np);
     }
-    probe.take<float>((size_t)fp.K * fp.rho);
-    probe.take<float>((size_t)fp.K * fp.K);
-    probe.take<float>((size_t)fp.rho);
     return probe.used;
+}
+
+size_t filter_workspace(const FilterPlan& fp) {
+    return filter_passes_workspace(fp) + filter_consts_bytes(fp.K, fp.rho) + 256;
 }
 
 void filter_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const float* guide,
                 const float* centers_host, const float* Pfp32_host, const int* labels, float* out,
                 float* den) {
+    // stage the constants through pinned memory (async, stream ordered)
+    const size_t cb = filter_consts_bytes(fp.K, fp.rho);
+    char* dev = ws.take<char>(cb);
+    char* hs = static_cast<char*>(c.host_stage(1, cb));
+    filter_consts_fill(centers_host, Pfp32_host, fp.K, fp.rho, hs);
+    FHD_HIP(hipMemcpyAsync(dev, hs, cb, hipMemcpyHostToDevice, c.stream));
+    c.stage_done(1);
+    filter_passes(c, ws, fp, f, guide, filter_consts_at(dev, fp.K, fp.rho), labels, out, den);
+}
+
+void filter_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const float* guide,
+                   const FilterConsts& kc, const int* labels, float* out, float* den) {
     const long long Np = (long long)fp.H * fp.Wp;
     float* planes = ws.take<float>(plane_floats(fp));
     float* Bpl = nullptr;
@@ -1200,27 +1241,10 @@ void filter_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const f
         Bpl = ws.take<float>((size_t)fp.K * Np);
         Cpl = ws.take<float>((size_t)fp.K * Np);
     }
-    float* mu = ws.take<float>((size_t)fp.K * fp.rho);
-    float* P = ws.take<float>((size_t)fp.K * fp.K);
-    float* offs = ws.take<float>((size_t)fp.rho);
+    const float* mu = kc.mu;
+    const float* P = kc.P;
+    const float* offs = kc.offs;
     hipStream_t st = c.stream;
-    // stage centers, A^+ and the contraction offset (mean of the centers)
-    // through pinned memory (async, stream ordered)
-    const size_t kb = sizeof(float) * fp.K * fp.rho, pb = sizeof(float) * fp.K * fp.K;
-    const size_t ob = sizeof(float) * fp.rho;
-    char* hs = static_cast<char*>(c.host_stage(1, align_up(kb, 256) + align_up(pb, 256) + ob));
-    std::memcpy(hs, centers_host, kb);
-    std::memcpy(hs + align_up(kb, 256), Pfp32_host, pb);
-    float* ho = reinterpret_cast<float*>(hs + align_up(kb, 256) + align_up(pb, 256));
-    for (int d = 0; d < fp.rho; ++d) {
-        double s = 0.0;
-        for (int k = 0; k < fp.K; ++k) s += centers_host[(size_t)k * fp.rho + d];
-        ho[d] = (float)(s / fp.K);
-    }
-    FHD_HIP(hipMemcpyAsync(mu, hs, kb, hipMemcpyHostToDevice, st));
-    FHD_HIP(hipMemcpyAsync(P, hs + align_up(kb, 256), pb, hipMemcpyHostToDevice, st));
-    FHD_HIP(hipMemcpyAsync(offs, ho, ob, hipMemcpyHostToDevice, st));
-    c.stage_done(1);
 
     FA a = make_args(fp);
     a.f = f;
@@ -1313,21 +1337,46 @@ void filter_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const f
     FHD_HIP(hipGetLastError());
 }
 
-size_t adjoint_workspace(const FilterPlan& fp) {
+size_t adjoint_consts_bytes(int K, int rho) {
+    return filter_consts_bytes(K, rho) + align_up(sizeof(float) * K * K, 256);
+}
+
+size_t adjoint_passes_workspace(const FilterPlan& fp) {
     Arena probe;
     const long long Np = (long long)fp.H * fp.Wp;
     probe.take<float>(plane_floats(fp));
     for (int q = 0; q < 4; ++q) probe.take<float>((size_t)fp.K * Np);
-    probe.take<float>((size_t)fp.K * fp.rho);
-    probe.take<float>((size_t)fp.K * fp.K);
-    probe.take<float>((size_t)fp.K * fp.K);
     probe.take<double>(2 * ((size_t)(fp.N + RT - 1) / RT) + 1);
     return probe.used;
+}
+
+size_t adjoint_workspace(const FilterPlan& fp) {
+    return adjoint_passes_workspace(fp) + adjoint_consts_bytes(fp.K, fp.rho) + 256;
 }
 
 void adjoint_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const float* guide,
                  const float* centers_host, const float* Pfp32_host, const float* M_host, const float* out,
                  const float* den, const float* gout, float* gradf, float* gradp, double* gsig) {
+    const size_t cb = adjoint_consts_bytes(fp.K, fp.rho);
+    char* dev = ws.take<char>(cb);
+    char* hs = static_cast<char*>(c.host_stage(1, cb));
+    filter_consts_fill(centers_host, Pfp32_host, fp.K, fp.rho, hs);
+    std::memcpy(hs + filter_consts_bytes(fp.K, fp.rho), M_host, sizeof(float) * fp.K * fp.K);
+    FHD_HIP(hipMemcpyAsync(dev, hs, cb, hipMemcpyHostToDevice, c.stream));
+    c.stage_done(1);
+    double* sig = ws.take<double>(1);
+    adjoint_passes(c, ws, fp, f, guide, filter_consts_at(dev, fp.K, fp.rho),
+                   reinterpret_cast<const float*>(dev + filter_consts_bytes(fp.K, fp.rho)), out, den, gout, gradf,
+                   gradp, sig);
+    if (gsig != nullptr) {
+        FHD_HIP(hipMemcpyAsync(gsig, sig, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+        FHD_HIP(hipStreamSynchronize(c.stream));
+    }
+}
+
+void adjoint_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const float* guide,
+                    const FilterConsts& kc, const float* Md, const float* out, const float* den, const float* gout,
+                    float* gradf, float* gradp, double* sig_dev) {
     FHD_REQUIRE(fp.S >= 1 && fp.S <= MAXS_T, FHD_EUNSUPPORTED, "the adjoint supports radii 1..32");
     FHD_REQUIRE(fp.K <= 64, FHD_EUNSUPPORTED, "the adjoint supports K <= 64");
     FHD_REQUIRE(fp.coef == FHD_COEF_LSQ, FHD_EUNSUPPORTED, "the adjoint covers least-squares coefficients");
@@ -1338,27 +1387,15 @@ void adjoint_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const 
     float* Cpl = ws.take<float>((size_t)fp.K * Np);
     float* beta = ws.take<float>((size_t)fp.K * Np);
     float* gamma = ws.take<float>((size_t)fp.K * Np);
-    float* mu = ws.take<float>((size_t)fp.K * fp.rho);
-    float* P = ws.take<float>((size_t)fp.K * fp.K);
-    float* Md = ws.take<float>((size_t)fp.K * fp.K);
     const int nb = (int)((fp.N + RT - 1) / RT);
     double* part = ws.take<double>(2 * (size_t)nb + 1);
     hipStream_t st = c.stream;
-    const size_t kb = sizeof(float) * fp.K * fp.rho, pb = sizeof(float) * fp.K * fp.K;
-    char* hs = static_cast<char*>(c.host_stage(1, align_up(kb, 256) + 2 * align_up(pb, 256)));
-    std::memcpy(hs, centers_host, kb);
-    std::memcpy(hs + align_up(kb, 256), Pfp32_host, pb);
-    std::memcpy(hs + align_up(kb, 256) + align_up(pb, 256), M_host, pb);
-    FHD_HIP(hipMemcpyAsync(mu, hs, kb, hipMemcpyHostToDevice, st));
-    FHD_HIP(hipMemcpyAsync(P, hs + align_up(kb, 256), pb, hipMemcpyHostToDevice, st));
-    FHD_HIP(hipMemcpyAsync(Md, hs + align_up(kb, 256) + align_up(pb, 256), pb, hipMemcpyHostToDevice, st));
-    c.stage_done(1);
 
     FA a = make_args(fp);
     a.f = f;
     a.p = guide;
-    a.mu = mu;
-    a.P = P;
+    a.mu = kc.mu;
+    a.P = kc.P;
     a.planes = planes;
     a.gout = gout;
     a.gimg = out;
@@ -1422,17 +1459,19 @@ void adjoint_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const 
     hipLaunchKernelGGL(dispatch().adj[fp.S][AM_GAMMA], cg, dim3(RT), 0, st, a);
     c.stage_end(FHD_STAGE_COL, t0);
     FHD_HIP(hipGetLastError());
-    const float sig3inv = std::isinf(fp.sigma_r) ? 0.0f : (float)(1.0 / ((double)fp.sigma_r * fp.sigma_r * fp.sigma_r));
+    const float sig3inv =
+        std::isinf(fp.sigma_r) ? 0.0f : (float)(1.0 / ((double)fp.sigma_r * fp.sigma_r * fp.sigma_r));
     const int halves = (fp.K + KF - 1) / KF;
     for (int h = 0; h < halves; ++h)
         hipLaunchKernelGGL(adj_final, dim3(nb), dim3(RT), 0, st, a, Md, sig3inv, h * KF, h, gradp,
                            part + (size_t)h * nb);
-    hipLaunchKernelGGL(sum_blocks, dim3(1), dim3(RT), 0, st, part, halves * nb, part + (size_t)halves * nb);
+    hipLaunchKernelGGL(sum_blocks, dim3(1), dim3(RT), 0, st, part, halves * nb, sig_dev);
     FHD_HIP(hipGetLastError());
-    if (gsig != nullptr) {
-        FHD_HIP(hipMemcpyAsync(gsig, part + (size_t)halves * nb, sizeof(double), hipMemcpyDeviceToHost, st));
-        FHD_HIP(hipStreamSynchronize(st));
-    }
+}
+
+void sum_doubles(Ctx& c, const double* v, int count, double* out_dev) {
+    hipLaunchKernelGGL(sum_blocks, dim3(1), dim3(RT), 0, c.stream, v, count, out_dev);
+    FHD_HIP(hipGetLastError());
 }
 
 void bruteforce_run(Ctx& c, const FilterPlan& fp, const float* f, const float* guide, float* out,

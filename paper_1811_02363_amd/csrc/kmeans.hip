@@ -197,12 +197,14 @@ __device__ void reduce_records(const double* part, int first, int nblk, int pw, 
 // ---------------------------------------------------------------------------
 // passes
 
+// Points of one image (planar rho x N guide) into the packed array from
+// position `base` on; idx holds the position in the concatenation of images.
 __global__ __launch_bounds__(KT) void km_pack(const float* __restrict__ guide, int rho, int ps, long long N,
-                                              float* __restrict__ pts, int* __restrict__ idx) {
+                                              long long base, float* __restrict__ pts, int* __restrict__ idx) {
     const long long i = (long long)blockIdx.x * KT + threadIdx.x;
     if (i >= N) return;
-    for (int d = 0; d < ps; ++d) pts[i * ps + d] = d < rho ? guide[(long long)d * N + i] : 0.0f;
-    idx[i] = (int)i;
+    for (int d = 0; d < ps; ++d) pts[(base + i) * ps + d] = d < rho ? guide[(long long)d * N + i] : 0.0f;
+    idx[base + i] = (int)(base + i);
 }
 
 // Member sums and per-dimension min/max.  Record: sum[rho], min[rho], max[rho].
@@ -726,6 +728,7 @@ __global__ __launch_bounds__(KT) void fin_split(KmArgs a) {
 
 struct Leaf {
     std::string heap;  // path from the root: "1", then '0' (first child) / '1'
+    int img = 0;       // image (tree) of the batch
     int start = 0, count = 0, buf = 0;
     std::vector<double> mean;
     double sse = 0.0;
@@ -758,7 +761,11 @@ int point_stride(int rho) {
 
 long long chunk_points(int rho) { return (long long)KITERS * KWAVES * (64 / lanes_per_point(rho)); }
 
-long long max_blocks(long long N, int rho, int K) { return N / chunk_points(rho) + 2LL * K + 4; }
+int max_jobs(int K, int images) { return images * std::max(2 * K, 4); }
+
+long long max_blocks(long long N, int rho, int K, int images) {
+    return N / chunk_points(rho) + 2LL * max_jobs(K, images) + 4;
+}
 
 int record_width(int rho) { return 4 * rho + 8; }
 
@@ -774,10 +781,10 @@ struct KmBuffers {
     int maxJobs;
 };
 
-KmBuffers carve(Arena& ws, long long N, int rho, int K) {
+KmBuffers carve(Arena& ws, long long N, int rho, int K, int images) {
     KmBuffers b{};
-    b.maxJobs = std::max(2 * K, 4);
-    b.maxBlocks = max_blocks(N, rho, K);
+    b.maxJobs = max_jobs(K, images);
+    b.maxBlocks = max_blocks(N, rho, K, images);
     for (int q = 0; q < 2; ++q) {
         b.pts[q] = ws.take<float>((size_t)N * point_stride(rho) + 64);
         b.idx[q] = ws.take<int>((size_t)N);
@@ -829,19 +836,34 @@ struct Stage {
 
 }  // namespace
 
-size_t kmeans_workspace(long long N, int rho, int K) {
+size_t kmeans_workspace(long long N, int rho, int K, int images) {
     Arena probe;  // counts only
-    carve(probe, N, rho, K);
+    carve(probe, N, rho, K, images);
     return probe.used;
 }
 
 void kmeans_run(Ctx& c, Arena& ws, const float* guide, int rho, long long N, int K, int max_iter, int* labels,
                 KmResult& out) {
-    FHD_REQUIRE(N >= 1 && N < (1LL << 31), FHD_EINVAL, "image too large for clustering");
+    std::vector<KmResult> res;
+    const long long off = 0;
+    kmeans_run_batch(c, ws, guide, rho, 1, &off, &N, K, max_iter, labels, res);
+    out = res[0];
+}
+
+void kmeans_run_batch(Ctx& c, Arena& ws, const float* guide, int rho, int images, const long long* px_offset,
+                      const long long* px_count, int K, int max_iter, int* labels, std::vector<KmResult>& out) {
+    FHD_REQUIRE(images >= 1, FHD_EINVAL, "no images");
+    long long N = 0;
+    for (int b = 0; b < images; ++b) {
+        FHD_REQUIRE(px_count[b] >= 1 && px_offset[b] == N, FHD_EINVAL,
+                    "internal: images must be packed back to back");
+        N += px_count[b];
+    }
+    FHD_REQUIRE(N < (1LL << 31), FHD_EINVAL, "too many pixels for clustering");
     FHD_REQUIRE(rho >= 1 && rho <= FHD_MAX_RHO, FHD_EUNSUPPORTED, "guide dimension out of range");
     FHD_REQUIRE(K >= 1 && K <= FHD_MAX_K, FHD_EINVAL, "K out of range");
     FHD_REQUIRE(max_iter >= 1, FHD_EINVAL, "kmeans_max_iter must be >= 1");
-    KmBuffers B = carve(ws, N, rho, K);
+    KmBuffers B = carve(ws, N, rho, K, images);
     const long long CH = chunk_points(rho);
     hipStream_t st = c.stream;
 
@@ -887,12 +909,16 @@ void kmeans_run(Ctx& c, Arena& ws, const float* guide, int rho, long long N, int
     a.ps = point_stride(rho);
 
     hipEvent_t t_begin = c.stage_begin();
-    hipLaunchKernelGGL(km_pack, dim3((unsigned)((N + KT - 1) / KT)), dim3(KT), 0, st, guide, rho, a.ps, N, B.pts[0],
-                       B.idx[0]);
+    for (int b = 0; b < images; ++b)
+        hipLaunchKernelGGL(km_pack, dim3((unsigned)((px_count[b] + KT - 1) / KT)), dim3(KT), 0, st,
+                           guide + (size_t)rho * px_offset[b], rho, a.ps, px_count[b], px_offset[b], B.pts[0],
+                           B.idx[0]);
     FHD_HIP(hipGetLastError());
 
     // Upload jobs (ranges of leaves) and their block table; returns #blocks.
-    auto upload = [&](const std::vector<Leaf*>& jobs, bool with_mean, bool label_rank) -> int {
+    // The block table's last field is the block's rank within its job, or
+    // the job's label when `label` is given.
+    auto upload = [&](const std::vector<Leaf*>& jobs, bool with_mean, const std::vector<int>* label) -> int {
         int nb = 0;
         for (size_t j = 0; j < jobs.size(); ++j) {
             const Leaf& L = *jobs[j];
@@ -907,7 +933,7 @@ void kmeans_run(Ctx& c, Arena& ws, const float* guide, int rho, long long N, int
             for (int q = 0; q < nblk; ++q) {
                 const int s0 = L.start + (int)(q * CH);
                 const int cnt = (int)std::min<long long>(CH, L.count - q * CH);
-                H.btab[nb++] = make_int4((int)j, s0, cnt, label_rank ? (int)j : q);
+                H.btab[nb++] = make_int4((int)j, s0, cnt, label ? (*label)[j] : q);
             }
             if (with_mean)
                 for (int t = 0; t < rho; ++t) H.jm[j * rho + t] = L.mean[t];
@@ -920,52 +946,74 @@ void kmeans_run(Ctx& c, Arena& ws, const float* guide, int rho, long long N, int
         return nb;
     };
 
-    // ---- root: centroid, SSE, splittable
+    // ---- roots: centroid, SSE, splittable (all images in one pass)
     std::vector<Leaf> store;
-    store.reserve(4 * (size_t)K + 4);
-    store.emplace_back();
-    Leaf* root = &store.back();
-    root->heap = "1";
-    root->start = 0;
-    root->count = (int)N;
-    root->buf = 0;
+    store.reserve((size_t)images * (4 * (size_t)K + 4));
+    std::vector<std::vector<Leaf*>> leaves(images);
     {
-        std::vector<Leaf*> jobs{root};
-        const int nb = upload(jobs, false, false);
+        std::vector<Leaf*> roots;
+        for (int b = 0; b < images; ++b) {
+            store.emplace_back();
+            Leaf* r = &store.back();
+            r->heap = "1";
+            r->img = b;
+            r->start = (int)px_offset[b];
+            r->count = (int)px_count[b];
+            r->buf = 0;
+            roots.push_back(r);
+            leaves[b].push_back(r);
+        }
+        const int nb = upload(roots, false, nullptr);
+        const dim3 gj((unsigned)images);
         launch_pass(rho, P_STATS, dim3(nb), st, a);
-        hipLaunchKernelGGL(fin_stats, dim3(1), dim3(KT), 0, st, a);
+        hipLaunchKernelGGL(fin_stats, gj, dim3(KT), 0, st, a);
         launch_pass(rho, P_SSE1, dim3(nb), st, a);
-        hipLaunchKernelGGL(fin_sse1, dim3(1), dim3(KT), 0, st, a);
+        hipLaunchKernelGGL(fin_sse1, gj, dim3(KT), 0, st, a);
         FHD_HIP(hipGetLastError());
-        FHD_HIP(hipMemcpyAsync(H.jm, B.jm, sizeof(double) * rho, hipMemcpyDeviceToHost, st));
-        FHD_HIP(hipMemcpyAsync(H.jd, B.jd, sizeof(double) * JD_W, hipMemcpyDeviceToHost, st));
+        FHD_HIP(hipMemcpyAsync(H.jm, B.jm, sizeof(double) * rho * images, hipMemcpyDeviceToHost, st));
+        FHD_HIP(hipMemcpyAsync(H.jd, B.jd, sizeof(double) * JD_W * images, hipMemcpyDeviceToHost, st));
         FHD_HIP(hipStreamSynchronize(st));
-        root->mean.assign(H.jm, H.jm + rho);
-        root->splittable = H.jd[JD_SPLA] != 0.0;
-        root->sse = root->splittable ? H.jd[JD_SSEA] : 0.0;
+        for (int b = 0; b < images; ++b) {
+            Leaf* r = roots[b];
+            r->mean.assign(H.jm + (size_t)b * rho, H.jm + (size_t)(b + 1) * rho);
+            r->splittable = H.jd[(size_t)b * JD_W + JD_SPLA] != 0.0;
+            r->sse = r->splittable ? H.jd[(size_t)b * JD_W + JD_SSEA] : 0.0;
+        }
     }
 
-    std::vector<Leaf*> leaves{root};
-    int rounds = 0, splits = 0;
+    std::vector<int> rounds(images, 0), splits(images, 0);
     auto rank_less = [](const Leaf* x, const Leaf* y) {
         if (x->sse != y->sse) return x->sse > y->sse;
         return heap_less(x->heap, y->heap);
     };
-    while ((int)leaves.size() < K) {
-        // leaves the greedy rule can still pick: the top (K - #leaves) splittable ones
-        std::vector<Leaf*> cand;
-        for (Leaf* L : leaves)
-            if (L->splittable && L->sse > 0.0) cand.push_back(L);
-        if (cand.empty()) break;
-        std::sort(cand.begin(), cand.end(), rank_less);
-        const size_t budget = (size_t)K - leaves.size();
-        if (cand.size() > budget) cand.resize(budget);
+    auto open_leaf = [](const Leaf* L) { return L->splittable && L->sse > 0.0; };
+    for (;;) {
+        // per image: the leaves its greedy rule can still pick, the top
+        // (K - #leaves) open ones; their missing splits are this round's jobs
         std::vector<Leaf*> jobs;
-        for (Leaf* L : cand)
-            if (!L->has_split) jobs.push_back(L);
+        bool active = false;
+        for (int b = 0; b < images; ++b) {
+            if ((int)leaves[b].size() >= K) continue;
+            std::vector<Leaf*> cand;
+            for (Leaf* L : leaves[b])
+                if (open_leaf(L)) cand.push_back(L);
+            if (cand.empty()) continue;
+            active = true;
+            std::sort(cand.begin(), cand.end(), rank_less);
+            const size_t budget = (size_t)K - leaves[b].size();
+            if (cand.size() > budget) cand.resize(budget);
+            bool mine = false;
+            for (Leaf* L : cand)
+                if (!L->has_split) {
+                    jobs.push_back(L);
+                    mine = true;
+                }
+            if (mine) ++rounds[b];
+        }
+        if (!active) break;
         if (!jobs.empty()) {
             FHD_REQUIRE((int)jobs.size() <= B.maxJobs, FHD_EINVAL, "internal: too many jobs");
-            const int nb = upload(jobs, true, false);
+            const int nb = upload(jobs, true, nullptr);
             const dim3 g(nb), gj((unsigned)jobs.size());
             launch_pass(rho, P_FAR, g, st, a, 0);
             hipLaunchKernelGGL(fin_far, gj, dim3(KT), 0, st, a, 0);
@@ -998,56 +1046,66 @@ void kmeans_run(Ctx& c, Arena& ws, const float* guide, int rho, long long N, int
                 L.splB = jd[JD_SPLB] != 0.0;
                 FHD_REQUIRE(L.nA > 0 && L.nB > 0 && L.nA + L.nB == L.count, FHD_ENUMERIC,
                             "internal: degenerate 2-means split");
+                ++splits[L.img];
             }
-            ++rounds;
-            splits += (int)J;
         }
-        // commit greedily while the best leaf's split is known
-        while ((int)leaves.size() < K) {
-            Leaf* best = nullptr;
-            for (Leaf* L : leaves)
-                if (L->splittable && L->sse > 0.0 && (best == nullptr || rank_less(L, best))) best = L;
-            if (best == nullptr || !best->has_split) break;
-            store.emplace_back();
-            Leaf* A = &store.back();
-            store.emplace_back();
-            Leaf* Bc = &store.back();
-            A->heap = best->heap + "0";
-            A->start = best->start;
-            A->count = best->nA;
-            A->buf = 1 - best->buf;
-            A->mean = best->meanA;
-            A->sse = best->sseA;
-            A->splittable = best->splA;
-            Bc->heap = best->heap + "1";
-            Bc->start = best->start + best->nA;
-            Bc->count = best->nB;
-            Bc->buf = 1 - best->buf;
-            Bc->mean = best->meanB;
-            Bc->sse = best->sseB;
-            Bc->splittable = best->splB;
-            leaves.erase(std::find(leaves.begin(), leaves.end(), best));
-            leaves.push_back(A);
-            leaves.push_back(Bc);
+        // commit greedily, per image, while its best leaf's split is known
+        for (int b = 0; b < images; ++b) {
+            std::vector<Leaf*>& lv = leaves[b];
+            while ((int)lv.size() < K) {
+                Leaf* best = nullptr;
+                for (Leaf* L : lv)
+                    if (open_leaf(L) && (best == nullptr || rank_less(L, best))) best = L;
+                if (best == nullptr || !best->has_split) break;
+                store.emplace_back();
+                Leaf* A = &store.back();
+                store.emplace_back();
+                Leaf* Bc = &store.back();
+                A->heap = best->heap + "0";
+                A->img = b;
+                A->start = best->start;
+                A->count = best->nA;
+                A->buf = 1 - best->buf;
+                A->mean = best->meanA;
+                A->sse = best->sseA;
+                A->splittable = best->splA;
+                Bc->heap = best->heap + "1";
+                Bc->img = b;
+                Bc->start = best->start + best->nA;
+                Bc->count = best->nB;
+                Bc->buf = 1 - best->buf;
+                Bc->mean = best->meanB;
+                Bc->sse = best->sseB;
+                Bc->splittable = best->splB;
+                lv.erase(std::find(lv.begin(), lv.end(), best));
+                lv.push_back(A);
+                lv.push_back(Bc);
+            }
         }
-        bool any = false;
-        for (Leaf* L : leaves) any = any || (L->splittable && L->sse > 0.0);
-        if (!any) break;
     }
 
-    std::sort(leaves.begin(), leaves.end(), [](const Leaf* x, const Leaf* y) { return heap_less(x->heap, y->heap); });
-    out.K_eff = (int)leaves.size();
-    out.rounds = rounds;
-    out.splits = splits;
-    out.E_K = 0.0;
-    out.centers.assign((size_t)out.K_eff * rho, 0.0);
-    for (int k = 0; k < out.K_eff; ++k) {
-        out.E_K += leaves[k]->sse;
-        for (int t = 0; t < rho; ++t) out.centers[(size_t)k * rho + t] = leaves[k]->mean[t];
+    out.assign(images, KmResult{});
+    std::vector<Leaf*> all;
+    std::vector<int> lab;
+    for (int b = 0; b < images; ++b) {
+        std::vector<Leaf*>& lv = leaves[b];
+        std::sort(lv.begin(), lv.end(), [](const Leaf* x, const Leaf* y) { return heap_less(x->heap, y->heap); });
+        KmResult& r = out[b];
+        r.K_eff = (int)lv.size();
+        r.rounds = rounds[b];
+        r.splits = splits[b];
+        r.E_K = 0.0;
+        r.centers.assign((size_t)r.K_eff * rho, 0.0);
+        for (int k = 0; k < r.K_eff; ++k) {
+            r.E_K += lv[k]->sse;
+            for (int t = 0; t < rho; ++t) r.centers[(size_t)k * rho + t] = lv[k]->mean[t];
+            all.push_back(lv[k]);
+            lab.push_back(k);
+        }
     }
     if (labels != nullptr) {
-        std::vector<Leaf*> jobs(leaves.begin(), leaves.end());
-        const int nb = upload(jobs, false, true);
+        FHD_REQUIRE((int)all.size() <= B.maxJobs, FHD_EINVAL, "internal: too many leaves");
+        const int nb = upload(all, false, &lab);
         hipLaunchKernelGGL(km_labels, dim3(nb), dim3(KT), 0, st, a, labels);
         FHD_HIP(hipGetLastError());
     }
