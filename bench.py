@@ -11,9 +11,11 @@ approximation quality (PSNR of eq. (21) against the GPU brute-force filter of
 eqs. (1)-(2)) and the brute force's own throughput; forward + adjoint
 throughput on the same workload; the FP32 and BF16 forms of the distance
 contraction on the 512x512x32 hyperspectral workload (Mpix/s and PSNR each);
-the roofline of the dominant kernel (algorithmic bytes and FLOPs per launch /
+nonlocal means on the 1024x1024 workload (FP32 and FP16 forms); the ragged
+batch of 16 images, forward and forward + adjoint, with its HBM fraction; the
+roofline of the dominant kernel (algorithmic bytes and FLOPs per launch /
 HIP-event duration on the library's stream); and the FP64 CPU oracle timed on
-a bounded crop of the same workload.
+the same workload (whole image by default).
 
 `--copy-calibration` instead runs a plain device copy of known size (the
 reference for scaling rocprofv3's FETCH_SIZE / WRITE_SIZE counters).
@@ -34,11 +36,12 @@ METRIC = "Mpix/s (fwd; fwd+bwd) at stated PSNR vs brute force, BF16 vs FP32 form
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
 FP32_VECTOR_PEAK = 157.3     # TFLOP/s, MI355X published FP32 vector (packed FMA)
 
-# HBM bytes per launch of the row pass at the 2048x2048 workload from
-# rocprofv3 --pmc (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel
-# calibration) for the row kernel as it is in this tree; None when the counters
-# have not been taken for this version of the kernel.
-MEASURED_TRAFFIC = None
+# HBM bytes per launch of the two convolution passes at the 2048x2048 workload
+# from rocprofv3 --pmc: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB per dispatch,
+# scaled by what the counters read for a 1 GiB device copy: 524,302 KiB
+# fetched, 1,048,576 KiB written), for the kernels as they are in this tree;
+# an entry is None when the counters have not been taken for that version.
+MEASURED_TRAFFIC = {"row": 2212312576, "col": 2334632704}
 
 
 def parse():
@@ -49,7 +52,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--quick", action="store_true",
                     help="forward timing only (no quality, adjoint or precision legs)")
-    ap.add_argument("--cpu-crop", type=int, default=512)
+    ap.add_argument("--cpu-crop", type=int, default=2048,
+                    help="side of the top-left crop the CPU oracle filters (2048 = whole image)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run a device copy of MIB MiB three times and exit")
     return ap.parse_args()
@@ -72,9 +76,12 @@ def cpu_baseline(f, cfg, crop):
     oracle.fhd_filter(sub, sub, cfg["sigma_s"], cfg["sigma_r"], cfg["K"], S=cfg["S"],
                       conv_method="separable")
     dt = time.perf_counter() - t0
-    return {"value": round(crop * crop / dt / 1e6, 4), "unit": "Mpix/s", "cores": threads,
+    h, w = sub.shape[1:]
+    what = "the whole image" if (h, w) == f.shape[1:] else f"the {h}x{w} top-left crop"
+    return {"value": round(h * w / dt / 1e6, 4), "unit": "Mpix/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"FP64 oracle, whole Algorithm 1 on the {crop}x{crop} top-left crop "
+            "sample": f"FP64 oracle, whole Algorithm 1 (bisecting K-means in NumPy, one thread; "
+                      f"K x K solve; convolutions in C with OpenMP on {threads} threads) on {what} "
                       f"of the same input and parameters ({dt:.1f} s)"}
 
 
@@ -112,6 +119,82 @@ def row_col_models(n, rho, K, S):
     row_bytes = 4 * (n + rho + K * (n + 1))
     col_bytes = 4 * (K * (n + 1) + rho + n)
     return {"row": (row_bytes, row_flops), "col": (col_bytes, col_flops)}
+
+
+def error_stats(out, den, ref):
+    """PSNR of eq. (21) against the reference, the median and maximum absolute
+    error, and the normaliser statistics (the least-squares coefficients can
+    drive r_hat to or through zero, where the unguarded ratio blows up)."""
+    e = (out - ref).abs().amax(0)
+    return {"psnr_vs_brute_db": round(psnr(out, ref), 2),
+            "median_abs_err": float(e.median()), "max_abs_err": float(e.max()),
+            "den_min": float(den.min()), "den_nonpos": int((den <= 0).sum()),
+            "den_below_1e-2": int((den < 1e-2).sum())}
+
+
+def nlm_leg(torch, fhd, synth):
+    """Nonlocal means on the 1024x1024 workload: the patch-PCA guide, then the
+    filter with FP32 and FP16 distance contractions; PSNR against the GPU
+    brute force on the same guide and, for denoising, against the clean image."""
+    c3 = synth.CONFIGS[3]
+    noisy, clean = synth.config_input(3)
+    x = torch.from_numpy(noisy).cuda()
+    cl = torch.from_numpy(clean).cuda()
+    N = c3["H"] * c3["W"]
+    g = fhd.nlm_guide(x, patch=c3["patch"], dims=c3["dims"])
+    ms_guide = timed(torch, lambda: fhd.nlm_guide(x, patch=c3["patch"], dims=c3["dims"]), 3)
+    kw = dict(sigma_r=c3["sigma_r"], spatial="box", radius=c3["S"])
+    ref = fhd.bruteforce(x, g, **kw)
+    ms_b = timed(torch, lambda: fhd.bruteforce(x, g, **kw), 3)
+    leg = {"workload": "nlm_rgb_1024: 1024x1024 RGB, noise 0.1, 5x5x3 patches -> 16-d PCA guide, "
+                       "box 21x21, sigma_r 0.1 sqrt(75), K 32",
+           "guide_ms": round(ms_guide, 3), "brute_force_mpix_s": round(N / ms_b / 1e3, 1),
+           "noisy_psnr_vs_clean_db": round(psnr(x, cl), 2)}
+    for form, coef in (("fp32", "lsq"), ("fp16", "lsq"), ("fp32", "hard")):
+        run = lambda: fhd.filter(x, g, K=c3["K"], contract=form, coef=coef, **kw)
+        o, d = fhd.filter(x, g, K=c3["K"], contract=form, coef=coef, return_den=True, **kw)
+        ms = timed(torch, run, 5)
+        leg[form if coef == "lsq" else "hard_fp32"] = dict(
+            error_stats(o, d, ref), mpix_s=round(N / ms / 1e3, 2),
+            mpix_s_with_guide=round(N / (ms + ms_guide) / 1e3, 2),
+            denoised_psnr_vs_clean_db=round(psnr(o, cl), 2))
+    return leg
+
+
+def batch_leg(torch, np, fhd, synth):
+    """The ragged batch of 16 RGB images (384x384 .. 768x1024): one batched
+    forward call, then forward plus the batched adjoint (image, guide and
+    sigma_r gradients).  HBM fraction from the algorithmic bytes per pixel of
+    the two-pass design (forward 4 [2n + 2 rho + 2K(n+1)], adjoint
+    4 [4K(n+1) + 2K + 7n + 5 rho + 2])."""
+    c4 = synth.CONFIGS[4]
+    imgs = [torch.from_numpy(a).cuda() for a in synth.config_input(4)]
+    flat, sizes = fhd.pack_batch(imgs)
+    n, K, S = c4["n"], c4["K"], c4["S"]
+    N = sum(h * w for h, w in sizes)
+    kw = dict(sigma_s=c4["sigma_s"], sigma_r=c4["sigma_r"], radius=S)
+    G = torch.from_numpy(np.random.default_rng(11).standard_normal(flat.numel()).astype(np.float32)).cuda()
+
+    def fwd():
+        return fhd.filter_batch(flat, sizes, n, K=K, return_den=True, **kw)
+
+    def fb():
+        out, den, cen, keff = fwd()
+        fhd.filter_batch_backward(flat, sizes, n, cen, keff, out, den, G, **kw)
+
+    fb()
+    ms_f = timed(torch, fwd, 5)
+    ms_fb = timed(torch, fb, 5)
+    rho = n
+    bf = 4 * (2 * n + 2 * rho + 2 * K * (n + 1))
+    bb = 4 * (4 * K * (n + 1) + 2 * K + 7 * n + 5 * rho + 2)
+    gbs = (bf + bb) * N / (ms_fb * 1e-3) / 1e9
+    return {"workload": "bf_rgb_batch16: 16 RGB images 384x384 .. 768x1024, sigma_s 3 (S 9), "
+                        "sigma_r 0.1, K 32",
+            "pixels": N, "fwd_mpix_s": round(N / ms_f / 1e3, 2), "fwd_ms": round(ms_f, 3),
+            "fwd_bwd_mpix_s": round(N / ms_fb / 1e3, 2), "fwd_bwd_ms": round(ms_fb, 3),
+            "fwd_bwd_model_bytes_per_px": bf + bb, "fwd_bwd_hbm_gbs": round(gbs, 1),
+            "fwd_bwd_hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def main():
@@ -172,7 +255,7 @@ def main():
     else:
         roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
-    roofline.update({"traffic": MEASURED_TRAFFIC, "kernel": f"{dom} pass",
+    roofline.update({"traffic": MEASURED_TRAFFIC.get(dom), "kernel": f"{dom} pass",
                      "flops_per_launch": fpx * N, "bytes_per_launch": bpx * N,
                      "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
                      "avg_ms": round(avg[dom], 4), "launches": stages[dom][1]})
@@ -203,9 +286,10 @@ def main():
         # quality: eq. (21) against the GPU brute force of eqs. (1)-(2)
         brute = fhd.bruteforce(x, sigma_s=ss, sigma_r=sr, radius=S)
         ms_brute = timed(torch, lambda: fhd.bruteforce(x, sigma_s=ss, sigma_r=sr, radius=S), 5)
-        res["quality"] = {"psnr_vs_brute_db": round(psnr(out, brute), 2),
-                          "brute_force_mpix_s": round(N / ms_brute / 1e3, 1),
-                          "brute_force_ms": round(ms_brute, 3)}
+        o, d = fhd.filter(x, sigma_s=ss, sigma_r=sr, K=K, radius=S, return_den=True)
+        res["quality"] = dict(error_stats(o, d, brute),
+                              brute_force_mpix_s=round(N / ms_brute / 1e3, 1),
+                              brute_force_ms=round(ms_brute, 3))
 
         # forward + hand-written adjoint (image and guide gradients, sigma_r)
         G = torch.from_numpy(np.random.default_rng(7).standard_normal(f.shape).astype(np.float32)).cuda()
@@ -241,6 +325,8 @@ def main():
                            "psnr_vs_brute_db": round(psnr(outs[form], ref2), 2)}
         forms["bf16_vs_fp32_max_abs"] = float((outs["bf16"] - outs["fp32"]).abs().max())
         res["forms"] = forms
+        res["nlm"] = nlm_leg(torch, fhd, synth)
+        res["batch"] = batch_leg(torch, np, fhd, synth)
 
     if not args.no_cpu and not args.quick:
         res["cpu_baseline"] = cpu_baseline(f, cfg, args.cpu_crop)
