@@ -38,7 +38,10 @@ constexpr int KT = 256;          // threads per block
 constexpr int KWAVES = KT / 64;  // waves per block
 constexpr int KITERS = 16;       // point groups per block and pass
 constexpr int DPL = 8;           // dimensions per lane (at most)
-constexpr int UNR = 4;           // points per lane group in flight per step
+// points per lane group in flight per step: eight for one lane of up to four
+// dimensions per point, else four (register budget)
+template <int D>
+constexpr int unr() { return D <= 4 ? 8 : 4; }
 
 // per-job integer state
 enum { JI_START, JI_COUNT, JI_BUF, JI_STOP, JI_STEPS, JI_FIRST, JI_NBLK, JI_NA, JI_W = 8 };
@@ -159,37 +162,46 @@ __device__ __forceinline__ double block_sum(double v, double (*red)[64]) {
 }
 
 // Finalize helper: res[e] = reduction over the job's blocks of record entry
-// e0 + e, for e < E, with the operation opof(e) (0 sum, 1 min, 2 max).  The
-// work is spread over the block in a fixed order (a group of threads per
-// entry, blocks strided over the group, then the group's results in order).
+// e0 + e, for e < E, with the operation opof(e) (0 sum, 1 min, 2 max).  A
+// fixed order: a power-of-two group of G threads per entry; thread `sub` of a
+// group folds records sub, sub + G, sub + 2G, ... into four partials (loads
+// issued four at a time), combined as (p0 op p1) op (p2 op p3); then a
+// pairwise tree over the group in LDS.
 template <class OpOf>
 __device__ void reduce_records(const double* part, int first, int nblk, int pw, int e0, int E, OpOf opof,
                                double* tmp, double* res) {
+    auto ident = [](int op) { return op == 0 ? 0.0 : (op == 1 ? INFINITY : -INFINITY); };
+    auto fold = [](int op, double u, double v) { return op == 0 ? u + v : (op == 1 ? fmin(u, v) : fmax(u, v)); };
     for (int base = 0; base < E; base += KT) {
         const int Ec = min(KT, E - base);
-        const int G = KT / Ec;  // threads per entry
+        const int G = 1 << (31 - __clz(KT / Ec));  // threads per entry, a power of two
         const int t = threadIdx.x;
-        if (t < Ec * G) {
-            const int e = base + t / G, sub = t % G;
-            const int op = opof(e);
-            double acc = op == 0 ? 0.0 : (op == 1 ? INFINITY : -INFINITY);
-            for (int b = sub; b < nblk; b += G) {
-                const double w = part[(long long)(first + b) * pw + e0 + e];
-                acc = op == 0 ? acc + w : (op == 1 ? fmin(acc, w) : fmax(acc, w));
+        const bool act = t < Ec * G;
+        const int e = base + t / G, sub = t & (G - 1);
+        const int op = act ? opof(e) : 0;
+        double acc = ident(op);
+        if (act) {
+            double p0 = acc, p1 = acc, p2 = acc, p3 = acc;
+            const long long stride = (long long)G * pw;
+            const double* r = part + (long long)(first + sub) * pw + e0 + e;
+            int b = sub;
+            for (; b + 3 * G < nblk; b += 4 * G, r += 4 * stride) {
+                const double w0 = r[0], w1 = r[stride], w2 = r[2 * stride], w3 = r[3 * stride];
+                p0 = fold(op, p0, w0);
+                p1 = fold(op, p1, w1);
+                p2 = fold(op, p2, w2);
+                p3 = fold(op, p3, w3);
             }
-            tmp[t] = acc;
+            for (; b < nblk; b += G, r += stride) p0 = fold(op, p0, r[0]);
+            acc = fold(op, fold(op, p0, p1), fold(op, p2, p3));
         }
+        tmp[t] = acc;
         __syncthreads();
-        if (t < Ec) {
-            const int e = base + t;
-            const int op = opof(e);
-            double r = tmp[t * G];
-            for (int s = 1; s < G; ++s) {
-                const double w = tmp[t * G + s];
-                r = op == 0 ? r + w : (op == 1 ? fmin(r, w) : fmax(r, w));
-            }
-            res[e] = r;
+        for (int h = G >> 1; h >= 1; h >>= 1) {
+            if (act && sub < h) tmp[t] = fold(op, tmp[t], tmp[t + h]);
+            __syncthreads();
         }
+        if (t < Ec) res[base + t] = tmp[t * G];
         __syncthreads();
     }
 }
@@ -287,7 +299,8 @@ __global__ __launch_bounds__(KT) void km_far(KmArgs a, int which) {
     load_center((which == 0 ? a.jm : a.ca) + job * rho, rho, L.d0, r);
     double best = -1.0;
     int bidx = INT_MAX, bpos = -1;
-    for (int base = 0; base < cnt; base += UNR * KWAVES * L.PPW) {
+    for (int base = 0; base < cnt; base += unr<D>() * KWAVES * L.PPW) {
+        constexpr int UNR = unr<D>();
         double x[UNR][D];
         int pp[UNR];
 #pragma unroll
@@ -358,7 +371,8 @@ __global__ __launch_bounds__(KT) void km_lloyd(KmArgs a) {
     for (int k = 0; k < D; ++k) sa[k] = sb[k] = 0.0;
     double na = 0.0, nb = 0.0;
     // UNR points per lane group per step, all loads issued before use
-    for (int base = 0; base < cnt; base += UNR * KWAVES * L.PPW) {
+    for (int base = 0; base < cnt; base += unr<D>() * KWAVES * L.PPW) {
+        constexpr int UNR = unr<D>();
         double x[UNR][D];
         bool valid[UNR];
 #pragma unroll
@@ -417,7 +431,8 @@ __global__ __launch_bounds__(KT) void km_split(KmArgs a) {
         hi_a[k] = hi_b[k] = -INFINITY;
     }
     double ea = 0.0, eb = 0.0, na = 0.0, nb = 0.0;
-    for (int base = 0; base < cnt; base += UNR * KWAVES * L.PPW) {
+    for (int base = 0; base < cnt; base += unr<D>() * KWAVES * L.PPW) {
+        constexpr int UNR = unr<D>();
         double x[UNR][D];
         bool valid[UNR];
 #pragma unroll
