@@ -4,7 +4,11 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <atomic>
+#include <exception>
+#include <mutex>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "fhd_internal.h"
@@ -90,8 +94,35 @@ void Ctx::stage_end(int stage, hipEvent_t begin) {
     ev_rec[stage].emplace_back(begin, e);
 }
 
+void Ctx::fork(int n) {
+    for (int k = 0; k <= NAUX; ++k)
+        if (aux_ev[k] == nullptr) FHD_HIP(hipEventCreateWithFlags(&aux_ev[k], hipEventDisableTiming));
+    for (int k = 0; k < n; ++k)
+        if (aux[k] == nullptr) FHD_HIP(hipStreamCreateWithFlags(&aux[k], hipStreamNonBlocking));
+    FHD_HIP(hipEventRecord(aux_ev[NAUX], stream));
+    for (int k = 0; k < n; ++k) FHD_HIP(hipStreamWaitEvent(aux[k], aux_ev[NAUX], 0));
+}
+
+void Ctx::join(int n) {
+    for (int k = 0; k < n; ++k) {
+        FHD_HIP(hipEventRecord(aux_ev[k], aux[k]));
+        FHD_HIP(hipStreamWaitEvent(stream, aux_ev[k], 0));
+    }
+}
+
 void Ctx::release() {
-    if (stream != nullptr || true) (void)hipStreamSynchronize(stream);
+    for (int k = 0; k < NAUX; ++k)
+        if (aux[k] != nullptr) {
+            (void)hipStreamSynchronize(aux[k]);
+            (void)hipStreamDestroy(aux[k]);
+            aux[k] = nullptr;
+        }
+    for (int k = 0; k <= NAUX; ++k)
+        if (aux_ev[k] != nullptr) {
+            (void)hipEventDestroy(aux_ev[k]);
+            aux_ev[k] = nullptr;
+        }
+    (void)hipStreamSynchronize(stream);
     if (own_ws != nullptr) (void)hipFree(own_ws);
     own_ws = nullptr;
     for (auto& v : ev_rec)
@@ -251,6 +282,67 @@ void fill_info(fhd_info* info, int K_eff, const PinvResult& pr, double E_K, int 
     info->ms_cluster = (float)ms_cluster;
     info->ms_solve = (float)ms_solve;
     info->ms_filter = (float)ms_filter;
+}
+
+// body(i) for i in [0, n) on up to eight host threads (the per-image K x K
+// solves of a batch); the first exception is rethrown after all have ended.
+template <class F>
+void parallel_for(int n, F&& body) {
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int nt = std::min<int>(n, (int)std::min(8u, hw));
+    if (nt <= 1) {
+        for (int i = 0; i < n; ++i) body(i);
+        return;
+    }
+    std::atomic<int> next{0};
+    std::exception_ptr err;
+    std::mutex m;
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back([&] {
+            for (;;) {
+                const int i = next.fetch_add(1);
+                if (i >= n) break;
+                try {
+                    body(i);
+                } catch (...) {
+                    std::lock_guard<std::mutex> g(m);
+                    if (!err) err = std::current_exception();
+                }
+            }
+        });
+    for (auto& x : th) x.join();
+    if (err) std::rethrow_exception(err);
+}
+
+// Per-image work of a batch spread over the auxiliary streams: while alive,
+// `on(i)` points the context at stream i % n; the destructor joins the
+// auxiliary streams back into the context's stream (also on errors).
+struct Spread {
+    Ctx& c;
+    hipStream_t main;
+    int n;
+    Spread(Ctx& cx, int images) : c(cx), main(cx.stream), n(std::min(images, Ctx::NAUX)) { c.fork(n); }
+    int on(int i) {
+        c.stream = c.aux[i % n];
+        return i % n;
+    }
+    ~Spread() {
+        c.stream = main;
+        try {
+            c.join(n);
+        } catch (...) {
+        }
+    }
+};
+
+// images by decreasing pixel count (ties by index): the order in which
+// they are dealt to the streams
+std::vector<int> by_size(const std::vector<long long>& cnt) {
+    std::vector<int> o(cnt.size());
+    for (size_t i = 0; i < o.size(); ++i) o[i] = (int)i;
+    std::stable_sort(o.begin(), o.end(), [&](int x, int y) { return cnt[x] > cnt[y]; });
+    return o;
 }
 
 // Validates a ragged batch and returns the pixel count of every image; the
@@ -545,7 +637,9 @@ fhd_status fhd_filter_batch(fhd_ctx* ctx, int B, const int* H, const int* W, con
         size_t passes = 0;
         for (int b = 0; b < B; ++b) passes = std::max(passes, filter_passes_workspace(make_plan(*p, n, rho, H[b], W[b], K)));
         const size_t cb = filter_consts_bytes(K, rho);
-        const size_t need = std::max(kmeans_workspace(N, rho, K, B), (size_t)B * cb + passes + 512) +
+        const int ns = std::min(B, Ctx::NAUX);
+        passes = align_up(passes, 256);
+        const size_t need = std::max(kmeans_workspace(N, rho, K, B), (size_t)B * cb + ns * passes + 512) +
                             align_up(sizeof(int) * (size_t)N, 256) + 4096;
         Arena ws = c.arena(need);
         const bool hard = p->coef == FHD_COEF_HARD;
@@ -561,29 +655,36 @@ fhd_status fhd_filter_batch(fhd_ctx* ctx, int B, const int* H, const int* W, con
         char* dev = ws.take<char>((size_t)B * cb);
         char* hs = static_cast<char*>(c.host_stage(1, (size_t)B * cb));
         std::vector<PinvResult> pr(B);
-        std::vector<float> c32;
         const auto t1 = clk::now();
-        for (int b = 0; b < B; ++b) {
+        parallel_for(B, [&](int b) {
             const int Kb = km[b].K_eff;
-            c32.assign((size_t)Kb * rho, 0.0f);
+            std::vector<float> c32((size_t)Kb * rho);
             for (size_t q = 0; q < c32.size(); ++q) c32[q] = (float)km[b].centers[q];
             if (centers_out) std::memcpy(centers_out + (size_t)b * K * rho, c32.data(), sizeof(float) * c32.size());
             if (K_eff) K_eff[b] = Kb;
             std::vector<float> P32;
             pr[b] = solve(c32.data(), Kb, rho, p->sigma_r, p->pinv_rtol, P32);
             filter_consts_fill(c32.data(), P32.data(), Kb, rho, hs + (size_t)b * cb);
-        }
+        });
         const double ms_solve = ms_since(t1);
         FHD_HIP(hipMemcpyAsync(dev, hs, (size_t)B * cb, hipMemcpyHostToDevice, c.stream));
         c.stage_done(1);
         const auto t2 = clk::now();
-        for (int b = 0; b < B; ++b) {
-            const FilterPlan fp = make_plan(*p, n, rho, H[b], W[b], km[b].K_eff);
-            Arena pws = ws;  // stream order makes the scratch reusable image after image
-            const long long o = px_offset[b];
-            filter_passes(c, pws, fp, f + (size_t)n * o, guide + (size_t)rho * o,
-                          filter_consts_at(dev + (size_t)b * cb, km[b].K_eff, rho), hard ? labels + o : nullptr,
-                          out + (size_t)n * o, den ? den + o : nullptr);
+        {
+            // one scratch region per stream; stream order makes it reusable image after image
+            char* region = ws.take<char>((size_t)ns * passes);
+            Spread sp(c, B);
+            const std::vector<int> order = by_size(cnt);
+            for (int i = 0; i < B; ++i) {
+                const int b = order[i];
+                const int k = sp.on(i);
+                const FilterPlan fp = make_plan(*p, n, rho, H[b], W[b], km[b].K_eff);
+                Arena pws{region + (size_t)k * passes, passes};
+                const long long o = px_offset[b];
+                filter_passes(c, pws, fp, f + (size_t)n * o, guide + (size_t)rho * o,
+                              filter_consts_at(dev + (size_t)b * cb, km[b].K_eff, rho),
+                              hard ? labels + o : nullptr, out + (size_t)n * o, den ? den + o : nullptr);
+            }
         }
         if (p->strict) strict_check(c, ws, out, N * n, den, N);
         double ms_filter = 0.0;
@@ -628,11 +729,13 @@ fhd_status fhd_filter_batch_backward(fhd_ctx* ctx, int B, const int* H, const in
             passes = std::max(passes, adjoint_passes_workspace(plans[b]));
         }
         const size_t cb = adjoint_consts_bytes(K, rho);
-        Arena ws = c.arena((size_t)B * cb + align_up(sizeof(double) * (B + 1), 256) + passes + 4096);
+        const int ns = std::min(B, Ctx::NAUX);
+        passes = align_up(passes, 256);
+        Arena ws = c.arena((size_t)B * cb + align_up(sizeof(double) * (B + 1), 256) + ns * passes + 4096);
         char* dev = ws.take<char>((size_t)B * cb);
         double* sig = ws.take<double>((size_t)B + 1);
         char* hs = static_cast<char*>(c.host_stage(1, (size_t)B * cb));
-        for (int b = 0; b < B; ++b) {
+        parallel_for(B, [&](int b) {
             const int Kb = K_eff[b];
             const float* cen = centers + (size_t)b * K * rho;
             std::vector<float> P32;
@@ -643,18 +746,26 @@ fhd_status fhd_filter_batch_backward(fhd_ctx* ctx, int B, const int* H, const in
             filter_consts_fill(cen, P32.data(), Kb, rho, h);
             float* m32 = reinterpret_cast<float*>(h + filter_consts_bytes(Kb, rho));
             for (size_t q = 0; q < M.size(); ++q) m32[q] = (float)M[q];
-        }
+        });
         FHD_HIP(hipMemcpyAsync(dev, hs, (size_t)B * cb, hipMemcpyHostToDevice, c.stream));
         c.stage_done(1);
-        for (int b = 0; b < B; ++b) {
-            const int Kb = K_eff[b];
-            const long long o = px_offset[b];
-            const char* d = dev + (size_t)b * cb;
-            Arena pws = ws;
-            adjoint_passes(c, pws, plans[b], f + (size_t)n * o, guide + (size_t)rho * o, filter_consts_at(d, Kb, rho),
-                           reinterpret_cast<const float*>(d + filter_consts_bytes(Kb, rho)), out + (size_t)n * o,
-                           den + o, grad_out + (size_t)n * o, grad_f ? grad_f + (size_t)n * o : nullptr,
-                           grad_guide ? grad_guide + (size_t)rho * o : nullptr, sig + b);
+        {
+            char* region = ws.take<char>((size_t)ns * passes);
+            Spread sp(c, B);
+            const std::vector<int> order = by_size(cnt);
+            for (int i = 0; i < B; ++i) {
+                const int b = order[i];
+                const int k = sp.on(i);
+                const int Kb = K_eff[b];
+                const long long o = px_offset[b];
+                const char* d = dev + (size_t)b * cb;
+                Arena pws{region + (size_t)k * passes, passes};
+                adjoint_passes(c, pws, plans[b], f + (size_t)n * o, guide + (size_t)rho * o,
+                               filter_consts_at(d, Kb, rho),
+                               reinterpret_cast<const float*>(d + filter_consts_bytes(Kb, rho)), out + (size_t)n * o,
+                               den + o, grad_out + (size_t)n * o, grad_f ? grad_f + (size_t)n * o : nullptr,
+                               grad_guide ? grad_guide + (size_t)rho * o : nullptr, sig + b);
+            }
         }
         if (grad_sigma_r != nullptr) {
             sum_doubles(c, sig, B, sig + B);

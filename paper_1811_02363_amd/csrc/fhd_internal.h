@@ -158,6 +158,15 @@ struct Ctx {
     hipEvent_t stage_begin();
     void stage_end(int stage, hipEvent_t begin);
 
+    // auxiliary streams (default priority) for the independent per-image
+    // work of a batch: fork(n) makes aux[0..n) wait for what `stream` has
+    // enqueued so far, join(n) makes `stream` wait for aux[0..n)
+    static constexpr int NAUX = 4;
+    hipStream_t aux[NAUX] = {};
+    hipEvent_t aux_ev[NAUX + 1] = {};
+    void fork(int n);
+    void join(int n);
+
     Arena arena(size_t need);
     // A pinned buffer of at least `bytes`, safe to overwrite (waits for the
     // copies enqueued from it before the last stage_done(slot)).

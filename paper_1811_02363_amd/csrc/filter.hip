@@ -173,6 +173,22 @@ __device__ __forceinline__ void store_row(const FA& a, float* dst, int x, const 
     }
 }
 
+// The S zero rows above and below every intermediate plane are written by
+// the row pass itself: its grid has H + 2S rows, and a block of an outside
+// row stores zeros over its column run in all K(n+1) planes.
+__device__ __forceinline__ bool row_halo(const FA& a, int S, int& y, int x0) {
+    y = (int)blockIdx.y - S;
+    if (y >= 0 && y < a.H) return false;
+    const int w = min(a.tx, a.W - x0);
+    const int planes = a.K * (a.n + 1);
+    float* row = a.planes + (long long)(y + S) * a.Wp + x0;
+    for (int t = threadIdx.x; t < planes * w; t += RT) {
+        const int pl = t / w, x = t - pl * w;
+        row[(long long)pl * a.Pp + x] = 0.0f;
+    }
+    return true;
+}
+
 // Gaussian row pass, radius S known at compile time: each task filters R
 // outputs of one cluster from a register window of R + 2S inputs.
 template <int S>
@@ -180,8 +196,9 @@ __global__ __launch_bounds__(RT) void row_gauss(FA a) {
     extern __shared__ float lds[];
     constexpr int R = R_ROW;
     constexpr int WIN = R + 2 * S;
-    const int y = blockIdx.y;
     const int x0 = blockIdx.x * a.tx;
+    int y;
+    if (row_halo(a, S, y, x0)) return;
     const int hw = a.tx + 2 * S;
     const int csp = pidx(hw - 1) + 1;
     float* cs = lds;
@@ -246,8 +263,9 @@ __global__ __launch_bounds__(RT) void row_generic(FA a) {
     extern __shared__ float lds[];
     constexpr int R = 16;
     const int S = a.S;
-    const int y = blockIdx.y;
     const int x0 = blockIdx.x * a.tx;
+    int y;
+    if (row_halo(a, S, y, x0)) return;
     const int hw = a.tx + 2 * S;
     const int csp = pidx(hw - 1) + 1;
     float* cs = lds;
@@ -1284,15 +1302,7 @@ void filter_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, cons
         a.Cpl = Cpl;
     }
 
-    // the S zero rows above and below every intermediate plane
-    if (fp.S > 0) {
-        const size_t pitch = sizeof(float) * (size_t)(fp.H + 2 * fp.S) * fp.Wp;
-        const size_t width = sizeof(float) * (size_t)fp.S * fp.Wp;
-        const size_t planes_n = (size_t)fp.K * (fp.n + 1);
-        FHD_HIP(hipMemset2DAsync(planes, pitch, 0, width, planes_n, st));
-        FHD_HIP(hipMemset2DAsync(planes + (size_t)(fp.H + fp.S) * fp.Wp, pitch, 0, width, planes_n, st));
-    }
-
+    // (the S zero rows above and below every plane come from the row pass)
     // row pass
     const bool box = fp.spatial == FHD_SPATIAL_BOX;
     const bool unrolled = !box && fp.S >= 1 && fp.S <= MAXS_T;
@@ -1305,7 +1315,8 @@ void filter_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, cons
     }
     FHD_REQUIRE(lds <= 160 * 1024, FHD_EUNSUPPORTED, "row pass does not fit in LDS");
     a.tx = tx;
-    const dim3 rg((fp.W + tx - 1) / tx, fp.H);
+    FHD_REQUIRE(fp.H + 2 * fp.S <= 65535, FHD_EUNSUPPORTED, "image height plus 2 radius exceeds 65535");
+    const dim3 rg((fp.W + tx - 1) / tx, fp.H + 2 * fp.S);
     KernFn rowk = unrolled ? dispatch().row[fp.S] : (box ? row_generic<true> : row_generic<false>);
     FHD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(rowk),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -1417,13 +1428,6 @@ void adjoint_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, con
     }
     a.Bpl = Bpl;
     a.Cpl = Cpl;
-    {
-        const size_t pitch = sizeof(float) * (size_t)(fp.H + 2 * fp.S) * fp.Wp;
-        const size_t width = sizeof(float) * (size_t)fp.S * fp.Wp;
-        const size_t planes_n = (size_t)fp.K * (fp.n + 1);
-        FHD_HIP(hipMemset2DAsync(planes, pitch, 0, width, planes_n, st));
-        FHD_HIP(hipMemset2DAsync(planes + (size_t)(fp.H + fp.S) * fp.Wp, pitch, 0, width, planes_n, st));
-    }
     int tx = row_tx(fp.K, fp.S, R_ROW);
     size_t lds = row_lds_bytes(fp, tx);
     while (lds > 150 * 1024 && tx > 4 * R_ROW) {
@@ -1432,7 +1436,8 @@ void adjoint_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, con
     }
     FHD_REQUIRE(lds <= 160 * 1024, FHD_EUNSUPPORTED, "row pass does not fit in LDS");
     a.tx = tx;
-    const dim3 rg((fp.W + tx - 1) / tx, fp.H);
+    FHD_REQUIRE(fp.H + 2 * fp.S <= 65535, FHD_EUNSUPPORTED, "image height plus 2 radius exceeds 65535");
+    const dim3 rg((fp.W + tx - 1) / tx, fp.H + 2 * fp.S);
     KernFn rowk = dispatch().row[fp.S];
     FHD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(rowk), hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds));
