@@ -55,6 +55,7 @@ struct FA {
     float* gamma;       // K planes
     float* gradf;       // n planes or null
     int n, rho, K, H, W, Wp, S, coef, tx, xcd_groups;
+    int gsplit;         // column pass: blocks sharing one tile's channel groups
     long long N, Np;    // pixels; stride of the B / C planes
     long long Pp;       // stride of the intermediate planes: H + 2S rows of Wp, row y at y + S
     float inv2s2;       // 1 / (2 sigma_r^2), 0 for sigma_r = inf
@@ -319,11 +320,12 @@ struct ColTile {
 
 __device__ __forceinline__ ColTile col_tile(const FA& a, int ty) {
     // XCD-aware order: consecutive blocks on one XCD take vertically adjacent
-    // tiles, so the S-row halos they share stay in that XCD's L2.
+    // tiles, so the S-row halos they share stay in that XCD's L2.  With a
+    // split of the channel groups the grid repeats this order gsplit times.
     const int gx = (a.W + TXC - 1) / TXC, gy = (a.H + ty - 1) / ty;
     const int total = gx * gy;
     const int per = a.xcd_groups;  // blocks per XCD
-    const int b = blockIdx.x;
+    const int b = (int)blockIdx.x % (per * 8);
     const int t = (b & 7) * per + (b >> 3);
     ColTile c;
     c.block_active = t < total;
@@ -439,6 +441,38 @@ __device__ __forceinline__ bool plane_next(int n, int K, int& g, int& l, int& c)
     return ++g < groups;
 }
 
+// Order in which a block of the column pass visits its planes (g, l, c):
+// part p of a tile split gsplit ways takes the channel groups p, p + gsplit,
+// ...; a part other than 0 first visits the normaliser plane (group 0,
+// channel 0) of every cluster, so it can divide its own channels.
+struct PlaneSeq {
+    int n, K, groups, gsplit, part;
+    __device__ void start(int& ph, int& g, int& l, int& c) const {
+        ph = part == 0 ? 1 : 0;
+        g = 0;
+        l = 0;
+        c = 0;
+    }
+    // successor of (ph, g, l, c); false at the end
+    __device__ bool next(int& ph, int& g, int& l, int& c) const {
+        if (ph == 0) {
+            if (++l < K) return true;
+            ph = 1;
+            g = part;
+            l = 0;
+            c = 0;
+            return g < groups;
+        }
+        ++c;
+        if (c < CG && g * CG + c <= n) return true;
+        c = 0;
+        if (++l < K) return true;
+        l = 0;
+        g += gsplit;
+        return g < groups;
+    }
+};
+
 template <int S, int MODE>
 __global__ __launch_bounds__(RT) void col_gauss(FA a) {
     constexpr int R = R_COL;
@@ -455,6 +489,9 @@ __global__ __launch_bounds__(RT) void col_gauss(FA a) {
     const int lx = threadIdx.x & (TXC - 1), tr = threadIdx.x / TXC;
     const int x = tile.x, y0 = tile.y0;
     const int ly0 = tr * R;
+    const int groups = (n + 1 + CG - 1) / CG;
+    const PlaneSeq seq{n, K, groups, a.gsplit, (int)blockIdx.x / (a.xcd_groups * 8)};
+    if (seq.part >= groups) return;
     // staging: thread loads rows tr, tr+4, ... of the tile at column lx
     const long long tile_off = (long long)tile.by0 * a.Wp + tile.bx0 + tr * (long long)a.Wp + lx;
     const long long step = (long long)(RT / TXC) * a.Wp;
@@ -473,13 +510,51 @@ __global__ __launch_bounds__(RT) void col_gauss(FA a) {
     int lab[R];
     col_load_labels<R, MODE>(a, x, y0, lab);
     float pre[PER];
-    fetch(plane_index(n, 0, 0, 0), pre);
+    int ph, sg, sl, sc;  // the plane staged next
+    seq.start(ph, sg, sl, sc);
+    fetch(plane_index(n, sg, sl, sc), pre);
     stash(tbuf[0], pre);
     __syncthreads();
     int buf = 0;
-    const int groups = (n + 1 + CG - 1) / CG;
+    // filter the staged plane (tile row ly0 + q holds image row y0 - S + q),
+    // queue the following one, and add h_l times the result to acc
+    auto consume = [&](const float (&hl)[R], float (&acc)[R]) {
+        int nph = ph, ng = sg, nl = sl, nc = sc;
+        const bool more = seq.next(nph, ng, nl, nc);
+        if (more) fetch(plane_index(n, ng, nl, nc), pre);
+        const float* col = tbuf[buf] + ly0 * TXC + lx;
+        float win[WIN];
+#pragma unroll
+        for (int q = 0; q < WIN; ++q) win[q] = col[q * TXC];
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            float s = a.w[0] * win[t + S];
+#pragma unroll
+            for (int j = 1; j <= S; ++j) s = fmaf(a.w[j], win[t + S - j] + win[t + S + j], s);
+            acc[t] = fmaf(hl[t], s, acc[t]);
+        }
+        if (more) stash(tbuf[buf ^ 1], pre);
+        __syncthreads();
+        buf ^= 1;
+        ph = nph;
+        sg = ng;
+        sl = nl;
+        sc = nc;
+    };
     float dv[R];
-    for (int g = 0; g < groups; ++g) {
+    if (seq.part != 0) {  // the normaliser, for this part's own division
+        float ad[R];
+#pragma unroll
+        for (int t = 0; t < R; ++t) ad[t] = 0.0f;
+        for (int l = 0; l < K; ++l) {
+            float hl[R];
+            recomb_weights<R, MODE>(a, l, x, y0, ly0, lx, TY, sp, lab, hl);
+            consume(hl, ad);
+        }
+#pragma unroll
+        for (int t = 0; t < R; ++t) dv[t] = 1.0f / ad[t];
+    }
+    for (int g = seq.part; g < groups; g += seq.gsplit) {
         float acc[CG][R];
 #pragma unroll
         for (int c = 0; c < CG; ++c)
@@ -491,24 +566,7 @@ __global__ __launch_bounds__(RT) void col_gauss(FA a) {
 #pragma unroll
             for (int c = 0; c < CG; ++c) {
                 if (g * CG + c > n) break;
-                int ng = g, nl = l, nc = c;
-                const bool more = plane_next(n, K, ng, nl, nc);
-                if (more) fetch(plane_index(n, ng, nl, nc), pre);
-                // filter the staged plane: tile row ly0 + q holds image row y0 - S + q
-                const float* col = tbuf[buf] + ly0 * TXC + lx;
-                float win[WIN];
-#pragma unroll
-                for (int q = 0; q < WIN; ++q) win[q] = col[q * TXC];
-#pragma unroll
-                for (int t = 0; t < R; ++t) {
-                    float s = a.w[0] * win[t + S];
-#pragma unroll
-                    for (int j = 1; j <= S; ++j) s = fmaf(a.w[j], win[t + S - j] + win[t + S + j], s);
-                    acc[c][t] = fmaf(hl[t], s, acc[c][t]);
-                }
-                if (more) stash(tbuf[buf ^ 1], pre);
-                __syncthreads();
-                buf ^= 1;
+                consume(hl, acc[c]);
             }
         }
         if (tile.active) col_finish<R>(a, x, y0, g, acc, dv);
@@ -727,16 +785,23 @@ constexpr int KF = 32;
 __global__ __launch_bounds__(RT) void adj_final(FA a, const float* __restrict__ Md, float sig3inv, int l0,
                                                 int accumulate, float* __restrict__ gradp,
                                                 double* __restrict__ part) {
-    __shared__ float sP[KF * 64], sA[KF * 64];
+    // column m of the block's rows of A^+ and M, zero-padded to KF rows, so
+    // the unrolled loops below carry no bounds branches
+    __shared__ float sP[64 * KF], sA[64 * KF];
     __shared__ float smu[KF * FHD_MAX_RHO];
     __shared__ double red[RT / 64];
     const int K = a.K, rho = a.rho;
     const int kl = min(KF, K - l0);
-    for (int t = threadIdx.x; t < kl * K; t += RT) {
-        sP[t] = a.P[(long long)l0 * K + t];
-        sA[t] = Md[(long long)l0 * K + t];
+    const int rp = rho <= 8 ? 8 : rho;  // center row pitch, zero-padded to 8 for short guides
+    for (int t = threadIdx.x; t < K * KF; t += RT) {
+        const int m = t / KF, l = t - m * KF;
+        sP[t] = l < kl ? a.P[(long long)(l0 + l) * K + m] : 0.0f;
+        sA[t] = l < kl ? Md[(long long)(l0 + l) * K + m] : 0.0f;
     }
-    for (int t = threadIdx.x; t < kl * rho; t += RT) smu[t] = a.mu[(long long)l0 * rho + t];
+    for (int t = threadIdx.x; t < KF * rp; t += RT) {
+        const int l = t / rp, r = t - l * rp;
+        smu[t] = (l < kl && r < rho) ? a.mu[(long long)(l0 + l) * rho + r] : 0.0f;
+    }
     __syncthreads();
     const long long i = (long long)blockIdx.x * RT + threadIdx.x;
     const bool valid = i < a.N;
@@ -748,14 +813,18 @@ __global__ __launch_bounds__(RT) void adj_final(FA a, const float* __restrict__ 
     for (int m = 0; m < K; ++m) {
         const float gm = valid ? a.gamma[(long long)m * a.Np + po] : 0.0f;
         const float bm = valid ? a.Bpl[(long long)m * a.Np + po] : 0.0f;
+        const float* cp = sP + m * KF;
+        const float* ca = sA + m * KF;
 #pragma unroll
-        for (int l = 0; l < KF; ++l)
-            if (l < kl) {
-                pg[l] = fmaf(sP[l * K + m], gm, pg[l]);
-                ac[l] = fmaf(sA[l * K + m], bm, ac[l]);
-            }
+        for (int l = 0; l < KF; ++l) {
+            pg[l] = fmaf(cp[l], gm, pg[l]);
+            ac[l] = fmaf(ca[l], bm, ac[l]);
+        }
     }
-    // weights w_l = dL/db_l * b_l
+    float pr8[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) pr8[r] = (valid && r < rho) ? a.p[(long long)r * a.N + i] : 0.0f;
+    // weights w_l = dL/db_l * b_l (rows l >= kl of A^+ are zero, so pg[l] = 0 there)
     double sig = 0.0;
     float wsum = 0.0f;
 #pragma unroll
@@ -763,13 +832,21 @@ __global__ __launch_bounds__(RT) void adj_final(FA a, const float* __restrict__ 
         if (l >= kl) break;
         const long long pl = (long long)(l0 + l) * a.Np + po;
         const float bl = valid ? a.Bpl[pl] : 0.0f;
+        const float gl = valid ? a.gamma[pl] : 0.0f;
         const float bb = (valid ? a.beta[pl] : 0.0f) + pg[l];
         const float w = bb * bl;
-        const float gl = valid ? a.gamma[pl] : 0.0f;
         float d2 = 0.0f;
-        for (int r = 0; r < rho; ++r) {
-            const float d = (valid ? a.p[(long long)r * a.N + i] : 0.0f) - smu[l * rho + r];
-            d2 = fmaf(d, d, d2);
+        if (rho <= 8) {
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {  // padded entries: (0 - 0)^2
+                const float d = pr8[r] - smu[l * rp + r];
+                d2 = fmaf(d, d, d2);
+            }
+        } else {
+            for (int r = 0; r < rho; ++r) {
+                const float d = (valid ? a.p[(long long)r * a.N + i] : 0.0f) - smu[l * rp + r];
+                d2 = fmaf(d, d, d2);
+            }
         }
         sig += (double)w * d2 * sig3inv + (double)gl * ac[l];
         pg[l] = w;  // reuse: w_l
@@ -780,8 +857,7 @@ __global__ __launch_bounds__(RT) void adj_final(FA a, const float* __restrict__ 
         for (int r = 0; r < rho; ++r) {
             float s = 0.0f;
 #pragma unroll
-            for (int l = 0; l < KF; ++l)
-                if (l < kl) s = fmaf(pg[l], smu[l * rho + r], s);
+            for (int l = 0; l < KF; ++l) s = fmaf(pg[l], smu[l * rp + r], s);
             const float pr = a.p[(long long)r * a.N + i];
             float* gp = gradp + (long long)r * a.N + i;
             const float v = m2s * (pr * wsum - s);
@@ -815,65 +891,75 @@ __global__ __launch_bounds__(RT) void sum_blocks(const double* __restrict__ part
 }
 
 // ---------------------------------------------------------------------------
-// Weights pass (guides with more than RHO_INLINE dimensions): B and C planes.
-// One block per run of `tx` pixels of a row; distances accumulated over
-// eight-dimension chunks of the guide.
+// Weights pass (guides with more than RHO_INLINE dimensions, more than
+// KMAX_INLINE clusters, or the adjoint): B and C planes.  One thread per pixel
+// of a row run of blockDim.x pixels.  Centers (rho padded to a multiple of 8)
+// and A^+ (columns padded to a multiple of 8) sit in LDS with zero padding, so
+// the loops carry no bounds branches: padded dimensions add (0 - 0)^2 and
+// padded columns produce coefficients that are never stored.
+__host__ __device__ constexpr int pad8(int v) { return (v + 7) & ~7; }
+
+size_t weights_fp32_lds(int K, int rho, int npx) {
+    return sizeof(float) * ((size_t)K * pad8(K) + (size_t)K * pad8(rho) + (size_t)K * npx);
+}
+
+int weights_fp32_npx(int K) { return K <= 64 ? RT : 64; }
+
 __global__ __launch_bounds__(RT) void weights_fp32(FA a, float* Bpl, float* Cpl) {
     extern __shared__ float lds[];
-    const int K = a.K, rho = a.rho;
-    const int y = blockIdx.y, x0 = blockIdx.x * a.tx;
-    const int hw = a.tx;
-    float* bs = lds;  // hw x (K+1)
-    const long long rowoff = (long long)y * a.W;
-    for (int h = threadIdx.x; h < hw; h += RT)
-        for (int m = 0; m < K; ++m) bs[h * (K + 1) + m] = 0.0f;
-    for (int r0 = 0; r0 < rho; r0 += 8) {
-        for (int h = threadIdx.x; h < hw; h += RT) {
-            const int x = x0 + h;
-            const bool in = x < a.W;
-            float pr[8];
+    const int K = a.K, rho = a.rho, KP = pad8(K), RP = pad8(rho);
+    const int npx = blockDim.x;
+    float* sP = lds;              // K x KP
+    float* smu = sP + K * KP;     // K x RP
+    float* bs = smu + K * RP;     // K x npx (center-major)
+    for (int t = threadIdx.x; t < K * KP; t += npx) {
+        const int m = t / KP, l = t - m * KP;
+        sP[t] = l < K ? a.P[m * K + l] : 0.0f;
+    }
+    for (int t = threadIdx.x; t < K * RP; t += npx) {
+        const int m = t / RP, r = t - m * RP;
+        smu[t] = r < rho ? a.mu[m * rho + r] : 0.0f;
+    }
+    __syncthreads();
+    const int y = blockIdx.y, x = blockIdx.x * npx + threadIdx.x;
+    if (x >= a.W) return;
+    const long long pix = (long long)y * a.W + x;
+    const long long ppl = (long long)y * a.Wp + x;
+    for (int m = 0; m < K; ++m) bs[m * npx + threadIdx.x] = 0.0f;
+    for (int r0 = 0; r0 < RP; r0 += 8) {
+        float pr[8];
 #pragma unroll
-            for (int r = 0; r < 8; ++r)
-                pr[r] = (in && r0 + r < rho) ? a.p[(long long)(r0 + r) * a.N + rowoff + x] : 0.0f;
-            for (int m = 0; m < K; ++m) {
-                float d2 = bs[h * (K + 1) + m];
+        for (int r = 0; r < 8; ++r) pr[r] = r0 + r < rho ? a.p[(long long)(r0 + r) * a.N + pix] : 0.0f;
+        for (int m = 0; m < K; ++m) {
+            const float* mu = smu + m * RP + r0;
+            float d2 = bs[m * npx + threadIdx.x];
 #pragma unroll
-                for (int r = 0; r < 8; ++r)
-                    if (r0 + r < rho) {
-                        const float d = pr[r] - a.mu[m * rho + r0 + r];
-                        d2 = fmaf(d, d, d2);
-                    }
-                bs[h * (K + 1) + m] = d2;
+            for (int r = 0; r < 8; ++r) {
+                const float d = pr[r] - mu[r];
+                d2 = fmaf(d, d, d2);
             }
+            bs[m * npx + threadIdx.x] = d2;
         }
     }
-    for (int h = threadIdx.x; h < hw; h += RT)
-        for (int m = 0; m < K; ++m) bs[h * (K + 1) + m] = __expf(-bs[h * (K + 1) + m] * a.inv2s2);
-    __syncthreads();
-    const long long prow = (long long)y * a.Wp;
-    for (int t = threadIdx.x; t < hw * K; t += RT) {
-        const int l = t / hw, h = t - l * hw;
-        if (x0 + h < a.W) Bpl[(long long)l * a.Np + prow + x0 + h] = bs[h * (K + 1) + l];
+    for (int m = 0; m < K; ++m) {
+        const float b = __expf(-bs[m * npx + threadIdx.x] * a.inv2s2);
+        bs[m * npx + threadIdx.x] = b;
+        Bpl[(long long)m * a.Np + ppl] = b;
     }
     if (Cpl == nullptr) return;
-    const int groups = (K + 7) >> 3;
-    for (int t = threadIdx.x; t < hw * groups; t += RT) {
-        const int g = t / hw, h = t - g * hw;
-        if (x0 + h >= a.W) continue;
+    for (int l0 = 0; l0 < K; l0 += 8) {
         float acc[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) acc[q] = 0.0f;
-        const float* brow = bs + h * (K + 1);
         for (int m = 0; m < K; ++m) {
-            const float bv = brow[m];
-            const float* prow2 = a.P + (long long)m * K + g * 8;
+            const float bv = bs[m * npx + threadIdx.x];
+            const float* prow = sP + m * KP + l0;  // A^+ symmetric: row m = column m
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
-                if (g * 8 + q < K) acc[q] = fmaf(prow2[q], bv, acc[q]);
+            for (int q = 0; q < 8; ++q) acc[q] = fmaf(prow[q], bv, acc[q]);
         }
 #pragma unroll
         for (int q = 0; q < 8; ++q)
-            if (g * 8 + q < K) Cpl[(long long)(g * 8 + q) * a.Np + prow + x0 + h] = acc[q];
+            if (l0 + q < K) Cpl[(long long)(l0 + q) * a.Np + ppl] = acc[q];
     }
 }
 
@@ -1157,6 +1243,7 @@ FA make_args(const FilterPlan& fp) {
     a.Wp = fp.Wp;
     a.S = fp.S;
     a.coef = fp.coef;
+    a.gsplit = 1;
     a.N = fp.N;
     a.Np = (long long)fp.H * fp.Wp;
     a.Pp = (long long)(fp.H + 2 * fp.S) * fp.Wp;
@@ -1288,13 +1375,12 @@ void filter_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, cons
         a.Bpl = Bpl;
         a.Cpl = Cpl;
     } else if (fp.materialize) {
-        const int tx = 128;
-        a.tx = tx;
-        const size_t lds = sizeof(float) * (size_t)tx * (fp.K + 1);
+        const int npx = weights_fp32_npx(fp.K);
+        const size_t lds = weights_fp32_lds(fp.K, fp.rho, npx);
         FHD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(weights_fp32),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         hipEvent_t tw = c.stage_begin();
-        hipLaunchKernelGGL(weights_fp32, dim3((fp.W + tx - 1) / tx, fp.H), dim3(RT), lds, st, a, Bpl,
+        hipLaunchKernelGGL(weights_fp32, dim3((fp.W + npx - 1) / npx, fp.H), dim3(npx), lds, st, a, Bpl,
                            fp.coef == FHD_COEF_HARD ? nullptr : Cpl);
         c.stage_end(FHD_STAGE_WEIGHTS, tw);
         FHD_HIP(hipGetLastError());
@@ -1331,7 +1417,11 @@ void filter_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, cons
     const int total = gx * gy;
     const int per = (total + 7) / 8;
     a.xcd_groups = per;
-    const dim3 cg(per * 8);
+    // too few tiles to fill the chip: split each tile's channel groups over
+    // several blocks (each extra part also filters the normaliser planes)
+    const int groups = (fp.n + 1 + CG - 1) / CG;
+    a.gsplit = unrolled ? std::max(1, std::min(groups, 1024 / (per * 8))) : 1;
+    const dim3 cg(per * 8 * a.gsplit);
     size_t clds = (fp.materialize || fp.coef == FHD_COEF_HARD) ? 0 : sizeof(float) * fp.rho * ty * TXC;
     if (!unrolled) clds += sizeof(float) * (size_t)(ty + 2 * fp.S) * TXC;
     const int mode = fp.coef == FHD_COEF_HARD ? WM_HARD : (fp.materialize ? WM_PLANES : WM_INLINE);
@@ -1416,13 +1506,12 @@ void adjoint_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, con
     a.gradf = gradf;
     // weights recomputed from the guide (never stored by the forward call)
     {
-        const int tx = 128;
-        a.tx = tx;
-        const size_t lds = sizeof(float) * (size_t)tx * (fp.K + 1);
+        const int npx = weights_fp32_npx(fp.K);
+        const size_t lds = weights_fp32_lds(fp.K, fp.rho, npx);
         FHD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(weights_fp32),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         hipEvent_t tw = c.stage_begin();
-        hipLaunchKernelGGL(weights_fp32, dim3((fp.W + tx - 1) / tx, fp.H), dim3(RT), lds, st, a, Bpl, Cpl);
+        hipLaunchKernelGGL(weights_fp32, dim3((fp.W + npx - 1) / npx, fp.H), dim3(npx), lds, st, a, Bpl, Cpl);
         c.stage_end(FHD_STAGE_WEIGHTS, tw);
         FHD_HIP(hipGetLastError());
     }
