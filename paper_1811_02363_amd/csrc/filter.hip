@@ -1007,13 +1007,19 @@ __global__ __launch_bounds__(RT) void weights_mfma(FA a, float* Bpl, float* Cpl,
     __shared__ float smn[MW_K];                    // |mu~|^2
     __shared__ float spn[MW_PIX];                  // |p~|^2
     __shared__ float sb[MW_PIX * (MW_K + 1)];      // b for the block's pixels
-    const int K = a.K, rho = a.rho;
+    extern __shared__ float sPp[];                 // A^+, K x pad8(K), zero-padded columns
+    const int K = a.K, rho = a.rho, KP = pad8(K);
     const int rp = (rho + 15) & ~15;               // dims rounded up to whole chunks
     const int y = blockIdx.y, x0 = blockIdx.x * MW_PIX;
     for (int t = threadIdx.x; t < K * rp; t += RT) {
         const int k = t / rp, d = t - k * rp;
         smu[k * MW_RHO + d] = d < rho ? round16<BF16>(a.mu[k * rho + d] - offs[d]) : (unsigned short)0;
     }
+    if (Cpl != nullptr)
+        for (int t = threadIdx.x; t < K * KP; t += RT) {
+            const int m = t / KP, l = t - m * KP;
+            sPp[t] = l < K ? a.P[m * K + l] : 0.0f;
+        }
     __syncthreads();
     for (int k = threadIdx.x; k < K; k += RT) {
         float s = 0.0f;
@@ -1092,10 +1098,9 @@ __global__ __launch_bounds__(RT) void weights_mfma(FA a, float* Bpl, float* Cpl,
         for (int q = 0; q < 8; ++q) acc2[q] = 0.0f;
         for (int m = 0; m < K; ++m) {
             const float bv = sb[h * (MW_K + 1) + m];
-            const float* prow2 = a.P + (long long)m * K + g * 8;
+            const float* prow2 = sPp + m * KP + g * 8;  // A^+ symmetric: row m = column m
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
-                if (g * 8 + q < K) acc2[q] = fmaf(prow2[q], bv, acc2[q]);
+            for (int q = 0; q < 8; ++q) acc2[q] = fmaf(prow2[q], bv, acc2[q]);
         }
 #pragma unroll
         for (int q = 0; q < 8; ++q)
@@ -1362,13 +1367,17 @@ void filter_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, cons
     a.den = den;
 
     if (fp.materialize && fp.contract != FHD_CONTRACT_FP32) {
+        const size_t plds = sizeof(float) * (size_t)fp.K * pad8(fp.K);
+        const void* wk = fp.contract == FHD_CONTRACT_BF16 ? reinterpret_cast<const void*>(weights_mfma<true>)
+                                                          : reinterpret_cast<const void*>(weights_mfma<false>);
+        FHD_HIP(hipFuncSetAttribute(wk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)plds));
         hipEvent_t tw = c.stage_begin();
         const dim3 g((fp.W + MW_PIX - 1) / MW_PIX, fp.H);
         if (fp.contract == FHD_CONTRACT_BF16)
-            hipLaunchKernelGGL(weights_mfma<true>, g, dim3(RT), 0, st, a, Bpl,
+            hipLaunchKernelGGL(weights_mfma<true>, g, dim3(RT), plds, st, a, Bpl,
                                fp.coef == FHD_COEF_HARD ? nullptr : Cpl, offs);
         else
-            hipLaunchKernelGGL(weights_mfma<false>, g, dim3(RT), 0, st, a, Bpl,
+            hipLaunchKernelGGL(weights_mfma<false>, g, dim3(RT), plds, st, a, Bpl,
                                fp.coef == FHD_COEF_HARD ? nullptr : Cpl, offs);
         FHD_HIP(hipGetLastError());
         c.stage_end(FHD_STAGE_WEIGHTS, tw);
