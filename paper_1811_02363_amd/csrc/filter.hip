@@ -122,7 +122,7 @@ __device__ void row_factors(const FA& a, int y, int x0, int hw, int csp, float* 
         sP[t] = l < K ? a.P[m * K + l] : 0.0f;
     }
     __syncthreads();
-    const bool hard = a.coef == FHD_COEF_HARD;
+    const bool hard = a.coef == FHD_COEF_HARD || a.factor_b;  // the factor is b itself
     for (int h = threadIdx.x; h < hw; h += RT) {
         const int x = x0 - a.S + h;
         const bool in = x >= 0 && x < a.W;
@@ -789,8 +789,12 @@ __global__ __launch_bounds__(RT) void adj_final(FA a, const float* __restrict__ 
     // the unrolled loops below carry no bounds branches
     __shared__ float sP[64 * KF], sA[64 * KF];
     __shared__ float smu[KF * FHD_MAX_RHO];
+    __shared__ float sall[64 * 8];  // every center, dims padded to 8 (weights inline)
     __shared__ double red[RT / 64];
     const int K = a.K, rho = a.rho;
+    // without B planes (guides of at most 8 dimensions) b_m is recomputed
+    // here exactly as the weights pass and the inline row pass form it
+    const bool inl = a.Bpl == nullptr;
     const int kl = min(KF, K - l0);
     const int rp = rho <= 8 ? 8 : rho;  // center row pitch, zero-padded to 8 for short guides
     for (int t = threadIdx.x; t < K * KF; t += RT) {
@@ -802,17 +806,34 @@ __global__ __launch_bounds__(RT) void adj_final(FA a, const float* __restrict__ 
         const int l = t / rp, r = t - l * rp;
         smu[t] = (l < kl && r < rho) ? a.mu[(long long)(l0 + l) * rho + r] : 0.0f;
     }
+    if (inl)
+        for (int t = threadIdx.x; t < K * 8; t += RT) {
+            const int m = t / 8, r = t - m * 8;
+            sall[t] = r < rho ? a.mu[(long long)m * rho + r] : 0.0f;
+        }
     __syncthreads();
     const long long i = (long long)blockIdx.x * RT + threadIdx.x;
     const bool valid = i < a.N;
     const int y = valid ? (int)(i / a.W) : 0, x = valid ? (int)(i % a.W) : 0;
     const long long po = (long long)y * a.Wp + x;
+    float pr8[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) pr8[r] = (valid && r < rho) ? a.p[(long long)r * a.N + i] : 0.0f;
+    auto b_inline = [&](const float* mu8) {
+        float d2 = 0.0f;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {  // padded entries: (0 - 0)^2
+            const float d = pr8[r] - mu8[r];
+            d2 = fmaf(d, d, d2);
+        }
+        return __expf(-d2 * a.inv2s2);
+    };
     float pg[KF], ac[KF];
 #pragma unroll
     for (int l = 0; l < KF; ++l) pg[l] = ac[l] = 0.0f;
     for (int m = 0; m < K; ++m) {
         const float gm = valid ? a.gamma[(long long)m * a.Np + po] : 0.0f;
-        const float bm = valid ? a.Bpl[(long long)m * a.Np + po] : 0.0f;
+        const float bm = !valid ? 0.0f : (inl ? b_inline(sall + m * 8) : a.Bpl[(long long)m * a.Np + po]);
         const float* cp = sP + m * KF;
         const float* ca = sA + m * KF;
 #pragma unroll
@@ -821,9 +842,6 @@ __global__ __launch_bounds__(RT) void adj_final(FA a, const float* __restrict__ 
             ac[l] = fmaf(ca[l], bm, ac[l]);
         }
     }
-    float pr8[8];
-#pragma unroll
-    for (int r = 0; r < 8; ++r) pr8[r] = (valid && r < rho) ? a.p[(long long)r * a.N + i] : 0.0f;
     // weights w_l = dL/db_l * b_l (rows l >= kl of A^+ are zero, so pg[l] = 0 there)
     double sig = 0.0;
     float wsum = 0.0f;
@@ -831,7 +849,7 @@ __global__ __launch_bounds__(RT) void adj_final(FA a, const float* __restrict__ 
     for (int l = 0; l < KF; ++l) {
         if (l >= kl) break;
         const long long pl = (long long)(l0 + l) * a.Np + po;
-        const float bl = valid ? a.Bpl[pl] : 0.0f;
+        const float bl = !valid ? 0.0f : (inl ? b_inline(sall + (l0 + l) * 8) : a.Bpl[pl]);
         const float gl = valid ? a.gamma[pl] : 0.0f;
         const float bb = (valid ? a.beta[pl] : 0.0f) + pg[l];
         const float w = bb * bl;
@@ -944,7 +962,7 @@ __global__ __launch_bounds__(RT) void weights_fp32(FA a, float* Bpl, float* Cpl)
     for (int m = 0; m < K; ++m) {
         const float b = __expf(-bs[m * npx + threadIdx.x] * a.inv2s2);
         bs[m * npx + threadIdx.x] = b;
-        Bpl[(long long)m * a.Np + ppl] = b;
+        if (Bpl != nullptr) Bpl[(long long)m * a.Np + ppl] = b;
     }
     if (Cpl == nullptr) return;
     for (int l0 = 0; l0 < K; l0 += 8) {
@@ -1513,24 +1531,31 @@ void adjoint_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, con
     a.beta = beta;
     a.gamma = gamma;
     a.gradf = gradf;
-    // weights recomputed from the guide (never stored by the forward call)
+    // Weights recomputed from the guide (never stored by the forward call).
+    // Short guides (the inline case of the forward pass) keep only the C
+    // planes: the row passes form c and b per halo pixel as the forward row
+    // pass does, and the final kernel recomputes b.
+    const bool inl = fp.rho <= RHO_INLINE && fp.K <= KMAX_INLINE;
     {
         const int npx = weights_fp32_npx(fp.K);
         const size_t lds = weights_fp32_lds(fp.K, fp.rho, npx);
         FHD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(weights_fp32),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         hipEvent_t tw = c.stage_begin();
-        hipLaunchKernelGGL(weights_fp32, dim3((fp.W + npx - 1) / npx, fp.H), dim3(npx), lds, st, a, Bpl, Cpl);
+        hipLaunchKernelGGL(weights_fp32, dim3((fp.W + npx - 1) / npx, fp.H), dim3(npx), lds, st, a,
+                           inl ? nullptr : Bpl, Cpl);
         c.stage_end(FHD_STAGE_WEIGHTS, tw);
         FHD_HIP(hipGetLastError());
     }
-    a.Bpl = Bpl;
-    a.Cpl = Cpl;
+    a.Bpl = inl ? nullptr : Bpl;
+    a.Cpl = inl ? nullptr : Cpl;   // row passes: null = factors formed inline
+    FilterPlan rp = fp;
+    rp.materialize = !inl;
     int tx = row_tx(fp.K, fp.S, R_ROW);
-    size_t lds = row_lds_bytes(fp, tx);
+    size_t lds = row_lds_bytes(rp, tx);
     while (lds > 150 * 1024 && tx > 4 * R_ROW) {
         tx = std::max(4 * R_ROW, tx / 2 / R_ROW * R_ROW);
-        lds = row_lds_bytes(fp, tx);
+        lds = row_lds_bytes(rp, tx);
     }
     FHD_REQUIRE(lds <= 160 * 1024, FHD_EUNSUPPORTED, "row pass does not fit in LDS");
     a.tx = tx;
@@ -1558,6 +1583,7 @@ void adjoint_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, con
     t0 = c.stage_begin();
     hipLaunchKernelGGL(rowk, rg, dim3(RT), lds, st, a);
     c.stage_end(FHD_STAGE_ROW, t0);
+    a.Cpl = Cpl;  // the GAMMA epilogue multiplies by c_l(i)
     t0 = c.stage_begin();
     hipLaunchKernelGGL(dispatch().adj[fp.S][AM_GAMMA], cg, dim3(RT), 0, st, a);
     c.stage_end(FHD_STAGE_COL, t0);
