@@ -1418,7 +1418,9 @@ void filter_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, cons
     // (the S zero rows above and below every plane come from the row pass)
     // row pass
     const bool box = fp.spatial == FHD_SPATIAL_BOX;
-    const bool unrolled = !box && fp.S >= 1 && fp.S <= MAXS_T;
+    // radii 1..32 take the unrolled register-window kernels (a box is the
+    // window with every tap 1); the generic kernels cover the rest
+    const bool unrolled = fp.S >= 1 && fp.S <= MAXS_T;
     const int rR = unrolled ? R_ROW : 16;
     int tx = row_tx(fp.K, fp.S, rR);
     size_t lds = row_lds_bytes(fp, tx);
