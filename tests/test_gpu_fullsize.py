@@ -1,0 +1,165 @@
+"""Parity at the workloads' full sizes, in the configuration the benchmark
+times, through the C ABI.
+
+* Sampled outputs against the oracle's eqs. (13)-(16) evaluated pixel by
+  pixel (direct window sums) with the GPU's centers: max-abs <= 1e-4 for the
+  FP32 path, <= 2e-3 for the BF16/FP16 contraction.
+* The clustering trees against the oracle's bisecting K-means at full size
+  (2048x2048 RGB, hyperspectral, nonlocal-means guide, two images of the
+  batch), and the clustering invariants at 2048x2048 (labels partition the
+  image, centers are the FP64 means of their members, E_K is the sum of the
+  leaves' SSE).
+* The adjoint's transpose property at full size (linear in f for a fixed
+  guide), GPU against GPU.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL32, TOL16 = 1e-4, 2e-3
+
+
+@pytest.fixture(scope="module")
+def fhd():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1811_02363_amd as m
+    m.load()
+    return m
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _samples(H, W, n, seed):
+    rng = np.random.default_rng(seed)
+    ys = np.concatenate([rng.integers(0, H, n), [0, 0, H - 1, H - 1, H // 2]])
+    xs = np.concatenate([rng.integers(0, W, n), [0, W - 1, 0, W - 1, 3]])
+    return ys, xs
+
+
+def _sampled_err(out, f, g, cen, ss, sr, S, spatial, ys, xs):
+    c = np.asarray(cen, np.float64)
+    P, _, _ = oracle.pinv(oracle.kernel_matrix(c, sr))
+    ref, _ = oracle.fast_filter_at(f, g, c, P, ss, sr, ys, xs, S=S, spatial=spatial)
+    return float(np.abs(out[:, ys, xs].T - ref).max())
+
+
+def test_hyperspectral_full_size(fhd):
+    """512x512x32, guide = image, K 64, S 12: FP32 and BF16 forms, and the
+    tree against the oracle's."""
+    cfg = synth.CONFIGS[2]
+    f = synth.config_input(2)
+    fd = _dev(f)
+    ys, xs = _samples(512, 512, 120, 21)
+    kw = dict(sigma_s=cfg["sigma_s"], sigma_r=cfg["sigma_r"], K=cfg["K"], radius=cfg["S"])
+    for form, tol in (("fp32", TOL32), ("bf16", TOL16)):
+        out, cen = fhd.filter(fd, contract=form, return_centers=True, **kw)
+        err = _sampled_err(out.cpu().numpy(), f, f, cen.numpy(), cfg["sigma_s"], cfg["sigma_r"], cfg["S"],
+                           "gaussian", ys, xs)
+        print(f"hyperspectral {form}: sampled max-abs {err:.3e}")
+        assert err < tol
+    cl = oracle.bisecting_kmeans(f, cfg["K"])
+    assert np.array_equal(cl.centers.astype(np.float32), cen.numpy())
+
+
+def test_nlm_full_size(fhd):
+    """1024x1024 nonlocal means: the GPU's PCA guide against the oracle's,
+    the tree of the GPU guide against the oracle's tree of the same guide,
+    FP32 and FP16 sampled outputs."""
+    cfg = synth.CONFIGS[3]
+    noisy, clean = synth.config_input(3)
+    xd = _dev(noisy)
+    g, ev = fhd.nlm_guide(xd, patch=cfg["patch"], dims=cfg["dims"], eigvals=True)
+    gr, lam, basis, mean = oracle.nlm_guide(noisy, cfg["patch"], cfg["dims"])
+    assert np.abs(ev.numpy() - lam).max() < 1e-6 * lam[0]
+    gh = g.cpu().numpy()
+    G = gh.reshape(cfg["dims"], -1)
+    C = (G.astype(np.float64) @ G.T.astype(np.float64)) / G.shape[1] - np.outer(G.mean(1), G.mean(1))
+    assert np.abs(C - np.diag(lam[:cfg["dims"]])).max() < 1e-5 * lam[0]
+    ys, xs = _samples(1024, 1024, 120, 22)
+    kw = dict(sigma_r=cfg["sigma_r"], K=cfg["K"], spatial="box", radius=cfg["S"])
+    cens = {}
+    for form, tol in (("fp32", TOL32), ("fp16", TOL16)):
+        out, cen = fhd.filter(xd, g, contract=form, return_centers=True, **kw)
+        cens[form] = cen.numpy()
+        err = _sampled_err(out.cpu().numpy(), noisy, gh, cen.numpy(), None, cfg["sigma_r"], cfg["S"], "box",
+                           ys, xs)
+        print(f"nlm {form}: sampled max-abs {err:.3e}")
+        assert err < tol
+    cl = oracle.bisecting_kmeans(gh, cfg["K"])
+    assert np.array_equal(cl.centers.astype(np.float32), cens["fp32"])
+
+
+def test_batch_full_size(fhd):
+    """The 16-image ragged batch (384x384 .. 768x1024) in one batched call:
+    sampled outputs of every image, and the trees of the smallest and the
+    largest image against the oracle's."""
+    cfg = synth.CONFIGS[4]
+    imgs = synth.config_input(4)
+    flat, sizes = fhd.pack_batch([_dev(x) for x in imgs])
+    out, cen, keff = fhd.filter_batch(flat, sizes, 3, sigma_s=cfg["sigma_s"], sigma_r=cfg["sigma_r"],
+                                      K=cfg["K"], radius=cfg["S"])
+    o, worst = 0, 0.0
+    for b, (h, w) in enumerate(sizes):
+        ob = out[o * 3:(o + h * w) * 3].reshape(3, h, w).cpu().numpy()
+        o += h * w
+        ys, xs = _samples(h, w, 16, 100 + b)
+        worst = max(worst, _sampled_err(ob, imgs[b], imgs[b], cen[b, :keff[b]].numpy(), cfg["sigma_s"],
+                                        cfg["sigma_r"], cfg["S"], "gaussian", ys, xs))
+    print(f"batch: sampled max-abs over 16 images {worst:.3e}")
+    assert worst < TOL32
+    for b in (0, len(imgs) - 1):
+        cl = oracle.bisecting_kmeans(imgs[b], cfg["K"])
+        assert np.array_equal(cl.centers.astype(np.float32), cen[b, :keff[b]].numpy()), f"image {b}"
+
+
+def test_c1_clustering_invariants_full_size(fhd):
+    """2048x2048 RGB, K 32: labels cover the image, every center is the FP64
+    mean of its members, E_K equals the sum of the leaves' SSE, and the tree
+    equals the oracle's."""
+    cfg = synth.CONFIGS[1]
+    f = synth.config_input(1)
+    cen, lab, info = fhd.cluster(_dev(f), cfg["K"], labels=True)
+    lab = lab.cpu().numpy().ravel()
+    K = cen.shape[0]
+    assert K == cfg["K"] and lab.min() >= 0 and lab.max() < K
+    X = f.reshape(3, -1).astype(np.float64)
+    cnt = np.bincount(lab, minlength=K)
+    assert cnt.min() > 0 and cnt.sum() == X.shape[1]
+    mu = np.stack([np.bincount(lab, weights=X[d], minlength=K) for d in range(3)], 1) / cnt[:, None]
+    assert np.abs(mu.astype(np.float32) - cen.numpy()).max() <= 2e-7
+    sse = sum(((X[:, lab == k] - mu[k][:, None]) ** 2).sum() for k in range(K))
+    print(f"c1 clustering: K {K}, E_K {info['E_K']:.6f} vs {sse:.6f}, rounds {info['kmeans_rounds']}")
+    assert abs(info["E_K"] - sse) <= 1e-9 * sse
+    # and the tree itself is the oracle's (A5, 4,194,304 points)
+    cl = oracle.bisecting_kmeans(f, cfg["K"])
+    assert np.array_equal(cl.centers.astype(np.float32), cen.numpy())
+
+
+def test_adjoint_transpose_full_size(fhd):
+    """<G, F(d)> = <F^T G, d> at 2048x2048 with a separate guide (the filter
+    is linear in f), both sides from the GPU."""
+    cfg = synth.CONFIGS[1]
+    g = synth.config_input(1)
+    rng = np.random.default_rng(31)
+    f = rng.random(g.shape, dtype=np.float32)
+    d = rng.standard_normal(g.shape).astype(np.float32)
+    G = rng.standard_normal(g.shape).astype(np.float32)
+    fd, gd = _dev(f), _dev(g)
+    cen, _ = fhd.cluster(gd, cfg["K"])
+    kw = dict(sigma_s=cfg["sigma_s"], sigma_r=cfg["sigma_r"], radius=cfg["S"])
+    out, den = fhd.filter_centers(fd, gd, cen, return_den=True, **kw)
+    gf, _, _ = fhd.filter_backward(fd, gd, cen, out, den, _dev(G), need_guide=False, need_sigma_r=False, **kw)
+    Fd = fhd.filter_centers(_dev(d), gd, cen, **kw)
+    lhs = float(torch.sum(_dev(G).double() * Fd.double()))
+    rhs = float(torch.sum(gf.double() * _dev(d).double()))
+    scale = float(torch.sum((_dev(G) * Fd).abs().double()))
+    print(f"full-size transpose: <G, F d> {lhs:.8e}  <F^T G, d> {rhs:.8e}")
+    assert abs(lhs - rhs) <= 1e-5 * scale
