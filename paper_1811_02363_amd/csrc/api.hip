@@ -635,11 +635,18 @@ fhd_status fhd_filter_batch(fhd_ctx* ctx, int B, const int* H, const int* W, con
                     FHD_EINVAL, "outputs alias inputs");
         const int K = p->K;
         size_t passes = 0;
-        for (int b = 0; b < B; ++b) passes = std::max(passes, filter_passes_workspace(make_plan(*p, n, rho, H[b], W[b], K)));
+        std::vector<FilterPlan> kplans(B);  // plans at the requested K (an upper bound for K_eff)
+        bool batched = true;                // one launch per pass for all images
+        for (int b = 0; b < B; ++b) {
+            kplans[b] = make_plan(*p, n, rho, H[b], W[b], K);
+            passes = std::max(passes, filter_passes_workspace(kplans[b]));
+            batched = batched && filter_batch_supported(kplans[b]);
+        }
         const size_t cb = filter_consts_bytes(K, rho);
         const int ns = std::min(B, Ctx::NAUX);
         passes = align_up(passes, 256);
-        const size_t need = std::max(kmeans_workspace(N, rho, K, B), (size_t)B * cb + ns * passes + 512) +
+        const size_t fws = batched ? filter_batch_workspace(B, kplans.data()) : ns * passes;
+        const size_t need = std::max(kmeans_workspace(N, rho, K, B), (size_t)B * cb + fws + 512) +
                             align_up(sizeof(int) * (size_t)N, 256) + 4096;
         Arena ws = c.arena(need);
         const bool hard = p->coef == FHD_COEF_HARD;
@@ -670,7 +677,25 @@ fhd_status fhd_filter_batch(fhd_ctx* ctx, int B, const int* H, const int* W, con
         FHD_HIP(hipMemcpyAsync(dev, hs, (size_t)B * cb, hipMemcpyHostToDevice, c.stream));
         c.stage_done(1);
         const auto t2 = clk::now();
-        {
+        if (batched) {
+            std::vector<FilterPlan> plans(B);
+            std::vector<const float*> fb(B), gb(B);
+            std::vector<const int*> lb(B);
+            std::vector<float*> ob(B), db(B);
+            std::vector<FilterConsts> kc(B);
+            for (int b = 0; b < B; ++b) {
+                const long long o = px_offset[b];
+                plans[b] = make_plan(*p, n, rho, H[b], W[b], km[b].K_eff);
+                fb[b] = f + (size_t)n * o;
+                gb[b] = guide + (size_t)rho * o;
+                lb[b] = hard ? labels + o : nullptr;
+                ob[b] = out + (size_t)n * o;
+                db[b] = den ? den + o : nullptr;
+                kc[b] = filter_consts_at(dev + (size_t)b * cb, km[b].K_eff, rho);
+            }
+            filter_passes_batch(c, ws, B, plans.data(), fb.data(), gb.data(), kc.data(), hard ? lb.data() : nullptr,
+                                ob.data(), den ? db.data() : nullptr);
+        } else {
             // one scratch region per stream; stream order makes it reusable image after image
             char* region = ws.take<char>((size_t)ns * passes);
             Spread sp(c, B);

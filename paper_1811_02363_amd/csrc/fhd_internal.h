@@ -108,6 +108,12 @@ size_t filter_consts_bytes(int K, int rho);
 void filter_consts_fill(const float* centers, const float* P32, int K, int rho, char* host_dst);
 FilterConsts filter_consts_at(const char* dev, int K, int rho);
 size_t filter_passes_workspace(const FilterPlan& fp);
+// One launch per pass for all images of a batch (weights inline, radius 1..32).
+bool filter_batch_supported(const FilterPlan& fp);
+size_t filter_batch_workspace(int B, const FilterPlan* plans);
+void filter_passes_batch(Ctx& c, Arena& ws, int B, const FilterPlan* plans, const float* const* f,
+                         const float* const* guide, const FilterConsts* kc, const int* const* labels,
+                         float* const* out, float* const* den);
 void filter_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const float* guide,
                    const FilterConsts& kc, const int* labels, float* out, float* den);
 void bruteforce_run(Ctx& c, const FilterPlan& fp, const float* f, const float* guide,

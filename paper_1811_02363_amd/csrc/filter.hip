@@ -177,8 +177,8 @@ __device__ __forceinline__ void store_row(const FA& a, float* dst, int x, const 
 // The S zero rows above and below every intermediate plane are written by
 // the row pass itself: its grid has H + 2S rows, and a block of an outside
 // row stores zeros over its column run in all K(n+1) planes.
-__device__ __forceinline__ bool row_halo(const FA& a, int S, int& y, int x0) {
-    y = (int)blockIdx.y - S;
+__device__ __forceinline__ bool row_halo(const FA& a, int S, int by, int& y, int x0) {
+    y = by - S;
     if (y >= 0 && y < a.H) return false;
     const int w = min(a.tx, a.W - x0);
     const int planes = a.K * (a.n + 1);
@@ -193,13 +193,13 @@ __device__ __forceinline__ bool row_halo(const FA& a, int S, int& y, int x0) {
 // Gaussian row pass, radius S known at compile time: each task filters R
 // outputs of one cluster from a register window of R + 2S inputs.
 template <int S>
-__global__ __launch_bounds__(RT) void row_gauss(FA a) {
+__device__ __forceinline__ void row_gauss_body(const FA& a, int bx, int by) {
     extern __shared__ float lds[];
     constexpr int R = R_ROW;
     constexpr int WIN = R + 2 * S;
-    const int x0 = blockIdx.x * a.tx;
+    const int x0 = bx * a.tx;
     int y;
-    if (row_halo(a, S, y, x0)) return;
+    if (row_halo(a, S, by, y, x0)) return;
     const int hw = a.tx + 2 * S;
     const int csp = pidx(hw - 1) + 1;
     float* cs = lds;
@@ -258,6 +258,31 @@ __global__ __launch_bounds__(RT) void row_gauss(FA a) {
     }
 }
 
+// Batched launches: the blocks of image b of a ragged batch are
+// [pre[b], pre[b + 1]) of one 1-D grid; the image's parameters are fas[b].
+__device__ __forceinline__ int batch_block(const int* __restrict__ pre, int B, int& b) {
+    const int blk = (int)blockIdx.x;
+    int i = 0;
+    while (i + 1 < B && blk >= pre[i + 1]) ++i;  // uniform per block, B small
+    b = i;
+    return blk - pre[i];
+}
+
+template <int S>
+__global__ __launch_bounds__(RT) void row_gauss(FA a) {
+    row_gauss_body<S>(a, (int)blockIdx.x, (int)blockIdx.y);
+}
+
+template <int S>
+__global__ __launch_bounds__(RT) void row_gauss_batch(const FA* __restrict__ fas, const int* __restrict__ pre,
+                                                      int B) {
+    int b;
+    const int t = batch_block(pre, B, b);
+    const FA& a = fas[b];
+    const int gx = (a.W + a.tx - 1) / a.tx;
+    row_gauss_body<S>(a, t % gx, t / gx);
+}
+
 // Row pass for any radius: box kernel as a running sum, Gaussian tap by tap.
 template <bool BOX>
 __global__ __launch_bounds__(RT) void row_generic(FA a) {
@@ -266,7 +291,7 @@ __global__ __launch_bounds__(RT) void row_generic(FA a) {
     const int S = a.S;
     const int x0 = blockIdx.x * a.tx;
     int y;
-    if (row_halo(a, S, y, x0)) return;
+    if (row_halo(a, S, (int)blockIdx.y, y, x0)) return;
     const int hw = a.tx + 2 * S;
     const int csp = pidx(hw - 1) + 1;
     float* cs = lds;
@@ -318,14 +343,14 @@ struct ColTile {
     bool active;        // this thread's column is inside the image
 };
 
-__device__ __forceinline__ ColTile col_tile(const FA& a, int ty) {
+__device__ __forceinline__ ColTile col_tile(const FA& a, int ty, int blk) {
     // XCD-aware order: consecutive blocks on one XCD take vertically adjacent
     // tiles, so the S-row halos they share stay in that XCD's L2.  With a
     // split of the channel groups the grid repeats this order gsplit times.
     const int gx = (a.W + TXC - 1) / TXC, gy = (a.H + ty - 1) / ty;
     const int total = gx * gy;
     const int per = a.xcd_groups;  // blocks per XCD
-    const int b = (int)blockIdx.x % (per * 8);
+    const int b = blk % (per * 8);
     const int t = (b & 7) * per + (b >> 3);
     ColTile c;
     c.block_active = t < total;
@@ -474,7 +499,7 @@ struct PlaneSeq {
 };
 
 template <int S, int MODE>
-__global__ __launch_bounds__(RT) void col_gauss(FA a) {
+__device__ __forceinline__ void col_gauss_body(const FA& a, int blk) {
     constexpr int R = R_COL;
     constexpr int TY = TYC;
     constexpr int ROWS = TY + 2 * S;
@@ -482,7 +507,7 @@ __global__ __launch_bounds__(RT) void col_gauss(FA a) {
     constexpr int WIN = R + 2 * S;
     __shared__ float tbuf[2][PER * RT];
     extern __shared__ float sp[];
-    const ColTile tile = col_tile(a, TY);
+    const ColTile tile = col_tile(a, TY, blk);
     if (!tile.block_active) return;
     if (MODE == WM_INLINE) col_stage_guide(a, tile.bx0, tile.by0, TY, sp);
     const int n = a.n, K = a.K;
@@ -490,7 +515,7 @@ __global__ __launch_bounds__(RT) void col_gauss(FA a) {
     const int x = tile.x, y0 = tile.y0;
     const int ly0 = tr * R;
     const int groups = (n + 1 + CG - 1) / CG;
-    const PlaneSeq seq{n, K, groups, a.gsplit, (int)blockIdx.x / (a.xcd_groups * 8)};
+    const PlaneSeq seq{n, K, groups, a.gsplit, blk / (a.xcd_groups * 8)};
     if (seq.part >= groups) return;
     // staging: thread loads rows tr, tr+4, ... of the tile at column lx
     const long long tile_off = (long long)tile.by0 * a.Wp + tile.bx0 + tr * (long long)a.Wp + lx;
@@ -573,6 +598,19 @@ __global__ __launch_bounds__(RT) void col_gauss(FA a) {
     }
 }
 
+template <int S, int MODE>
+__global__ __launch_bounds__(RT) void col_gauss(FA a) {
+    col_gauss_body<S, MODE>(a, (int)blockIdx.x);
+}
+
+template <int S, int MODE>
+__global__ __launch_bounds__(RT) void col_gauss_batch(const FA* __restrict__ fas, const int* __restrict__ pre,
+                                                      int B) {
+    int b;
+    const int t = batch_block(pre, B, b);
+    col_gauss_body<S, MODE>(fas[b], t);
+}
+
 // Column pass for any radius (box as a running sum, Gaussian tap by tap),
 // single-buffered tile in dynamic LDS after the guide tile.
 template <bool BOX, int MODE>
@@ -580,7 +618,7 @@ __global__ __launch_bounds__(RT) void col_generic(FA a) {
     constexpr int R = 16;
     constexpr int TY = R * (RT / TXC);
     extern __shared__ float sp[];
-    const ColTile tile = col_tile(a, TY);
+    const ColTile tile = col_tile(a, TY, (int)blockIdx.x);
     if (!tile.block_active) return;
     if (MODE == WM_INLINE) col_stage_guide(a, tile.bx0, tile.by0, TY, sp);
     float* tb = sp + (MODE == WM_INLINE ? a.rho * TY * TXC : 0);
@@ -655,7 +693,7 @@ __global__ __launch_bounds__(RT) void col_adj(FA a) {
     constexpr int PER = (ROWS * TXC + RT - 1) / RT;
     constexpr int WIN = R + 2 * S;
     __shared__ float tbuf[2][PER * RT];
-    const ColTile tile = col_tile(a, TY);
+    const ColTile tile = col_tile(a, TY, (int)blockIdx.x);
     if (!tile.block_active) return;
     const int n = a.n, K = a.K;
     const int lx = threadIdx.x & (TXC - 1), tr = threadIdx.x / TXC;
@@ -1224,6 +1262,22 @@ struct Tables<0> {
     static void fill(KernFn*, KernFn (*)[3]) {}
 };
 
+typedef void (*BatchFn)(const FA*, const int*, int);
+template <int S>
+struct BatchTables {
+    static void fill(BatchFn* row, BatchFn (*col)[3]) {
+        row[S] = row_gauss_batch<S>;
+        col[S][WM_INLINE] = col_gauss_batch<S, WM_INLINE>;
+        col[S][WM_PLANES] = col_gauss_batch<S, WM_PLANES>;
+        col[S][WM_HARD] = col_gauss_batch<S, WM_HARD>;
+        BatchTables<S - 1>::fill(row, col);
+    }
+};
+template <>
+struct BatchTables<0> {
+    static void fill(BatchFn*, BatchFn (*)[3]) {}
+};
+
 template <int S>
 struct AdjTables {
     static void fill(KernFn (*adj)[2]) {
@@ -1241,12 +1295,17 @@ struct Dispatch {
     KernFn row[MAXS_T + 1];
     KernFn col[MAXS_T + 1][3];
     KernFn adj[MAXS_T + 1][2];
+    BatchFn rowb[MAXS_T + 1];
+    BatchFn colb[MAXS_T + 1][3];
     Dispatch() {
         row[0] = nullptr;
         col[0][0] = col[0][1] = col[0][2] = nullptr;
         adj[0][0] = adj[0][1] = nullptr;
+        rowb[0] = nullptr;
+        colb[0][0] = colb[0][1] = colb[0][2] = nullptr;
         Tables<MAXS_T>::fill(row, col);
         AdjTables<MAXS_T>::fill(adj);
+        BatchTables<MAXS_T>::fill(rowb, colb);
     }
 };
 
@@ -1464,6 +1523,88 @@ void filter_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, cons
     hipEvent_t tc = c.stage_begin();
     hipLaunchKernelGGL(colk, cg, dim3(RT), clds, st, a);
     c.stage_end(FHD_STAGE_COL, tc);
+    FHD_HIP(hipGetLastError());
+}
+
+bool filter_batch_supported(const FilterPlan& fp) {
+    return !fp.materialize && fp.S >= 1 && fp.S <= MAXS_T;
+}
+
+size_t filter_batch_workspace(int B, const FilterPlan* plans) {
+    Arena probe;
+    for (int b = 0; b < B; ++b) probe.take<float>(plane_floats(plans[b]));
+    probe.take<FA>((size_t)B);
+    probe.take<int>(2 * (size_t)(B + 1));
+    return probe.used;
+}
+
+// The row and column passes of every image of a batch, one launch each for
+// all images (images of at most 8 guide dimensions and 32 clusters, radius
+// 1..32: weights inline).
+void filter_passes_batch(Ctx& c, Arena& ws, int B, const FilterPlan* plans, const float* const* f,
+                         const float* const* guide, const FilterConsts* kc, const int* const* labels,
+                         float* const* out, float* const* den) {
+    const int S = plans[0].S;
+    const bool hard = plans[0].coef == FHD_COEF_HARD;
+    std::vector<FA> fas(B);
+    std::vector<int> pre_row(B + 1, 0), pre_col(B + 1, 0);
+    size_t lds = 0;
+    for (int b = 0; b < B; ++b) {
+        const FilterPlan& fp = plans[b];
+        FHD_REQUIRE(filter_batch_supported(fp) && fp.S == S && (fp.coef == FHD_COEF_HARD) == hard, FHD_EINVAL,
+                    "internal: batch plans differ");
+        FHD_REQUIRE(fp.H + 2 * fp.S <= 65535, FHD_EUNSUPPORTED, "image height plus 2 radius exceeds 65535");
+        FA& a = fas[b];
+        a = make_args(fp);
+        a.f = f[b];
+        a.p = guide[b];
+        a.mu = kc[b].mu;
+        a.P = kc[b].P;
+        a.labels = labels ? labels[b] : nullptr;
+        a.planes = ws.take<float>(plane_floats(fp));
+        a.out = out[b];
+        a.den = den ? den[b] : nullptr;
+        int tx = row_tx(fp.K, fp.S, R_ROW);
+        size_t l = row_lds_bytes(fp, tx);
+        while (l > 150 * 1024 && tx > 4 * R_ROW) {
+            tx = std::max(4 * R_ROW, tx / 2 / R_ROW * R_ROW);
+            l = row_lds_bytes(fp, tx);
+        }
+        FHD_REQUIRE(l <= 160 * 1024, FHD_EUNSUPPORTED, "row pass does not fit in LDS");
+        lds = std::max(lds, l);
+        a.tx = tx;
+        pre_row[b + 1] = pre_row[b] + ((fp.W + tx - 1) / tx) * (fp.H + 2 * fp.S);
+        const int gx = (fp.W + TXC - 1) / TXC, gy = (fp.H + TYC - 1) / TYC;
+        a.xcd_groups = (gx * gy + 7) / 8;
+        a.gsplit = 1;
+        pre_col[b + 1] = pre_col[b] + a.xcd_groups * 8;
+    }
+    FA* dfa = ws.take<FA>((size_t)B);
+    int* dpre = ws.take<int>(2 * (size_t)(B + 1));
+    const size_t fab = sizeof(FA) * B, prb = sizeof(int) * (B + 1);
+    char* hs = static_cast<char*>(c.host_stage(2, align_up(fab, 256) + 2 * prb));
+    std::memcpy(hs, fas.data(), fab);
+    std::memcpy(hs + align_up(fab, 256), pre_row.data(), prb);
+    std::memcpy(hs + align_up(fab, 256) + prb, pre_col.data(), prb);
+    hipStream_t st = c.stream;
+    FHD_HIP(hipMemcpyAsync(dfa, hs, fab, hipMemcpyHostToDevice, st));
+    FHD_HIP(hipMemcpyAsync(dpre, hs + align_up(fab, 256), 2 * prb, hipMemcpyHostToDevice, st));
+    c.stage_done(2);
+    BatchFn rowk = dispatch().rowb[S];
+    FHD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(rowk), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds));
+    hipEvent_t t0 = c.stage_begin();
+    hipLaunchKernelGGL(rowk, dim3(pre_row[B]), dim3(RT), lds, st, (const FA*)dfa, (const int*)dpre, B);
+    c.stage_end(FHD_STAGE_ROW, t0);
+    FHD_HIP(hipGetLastError());
+    const int mode = hard ? WM_HARD : WM_INLINE;
+    const size_t clds = hard ? 0 : sizeof(float) * plans[0].rho * TYC * TXC;
+    BatchFn colk = dispatch().colb[S][mode];
+    FHD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(colk), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)clds));
+    t0 = c.stage_begin();
+    hipLaunchKernelGGL(colk, dim3(pre_col[B]), dim3(RT), clds, st, (const FA*)dfa, (const int*)(dpre + B + 1), B);
+    c.stage_end(FHD_STAGE_COL, t0);
     FHD_HIP(hipGetLastError());
 }
 
