@@ -745,6 +745,7 @@ fhd_status fhd_filter_batch_backward(fhd_ctx* ctx, int B, const int* H, const in
                     FHD_EINVAL, "gradient outputs alias inputs or each other");
         std::vector<FilterPlan> plans(B);
         size_t passes = 0;
+        bool batched = true;
         for (int b = 0; b < B; ++b) {
             FHD_REQUIRE(K_eff[b] >= 1 && K_eff[b] <= std::min(K, 64), FHD_EUNSUPPORTED,
                         "the adjoint supports K_eff in [1, min(K, 64)]");
@@ -752,11 +753,13 @@ fhd_status fhd_filter_batch_backward(fhd_ctx* ctx, int B, const int* H, const in
             plans[b].contract = FHD_CONTRACT_FP32;
             plans[b].materialize = true;
             passes = std::max(passes, adjoint_passes_workspace(plans[b]));
+            batched = batched && adjoint_batch_supported(plans[b]);
         }
         const size_t cb = adjoint_consts_bytes(K, rho);
         const int ns = std::min(B, Ctx::NAUX);
         passes = align_up(passes, 256);
-        Arena ws = c.arena((size_t)B * cb + align_up(sizeof(double) * (B + 1), 256) + ns * passes + 4096);
+        const size_t region = batched ? adjoint_batch_workspace(B, plans.data()) : ns * passes;
+        Arena ws = c.arena((size_t)B * cb + align_up(sizeof(double) * (B + 1), 256) + region + 4096);
         char* dev = ws.take<char>((size_t)B * cb);
         double* sig = ws.take<double>((size_t)B + 1);
         char* hs = static_cast<char*>(c.host_stage(1, (size_t)B * cb));
@@ -774,7 +777,27 @@ fhd_status fhd_filter_batch_backward(fhd_ctx* ctx, int B, const int* H, const in
         });
         FHD_HIP(hipMemcpyAsync(dev, hs, (size_t)B * cb, hipMemcpyHostToDevice, c.stream));
         c.stage_done(1);
-        {
+        if (batched) {
+            std::vector<const float*> fb_(B), gb_(B), Mb(B), ob(B), db_(B), gob(B);
+            std::vector<float*> gfb(B), ggb(B);
+            std::vector<FilterConsts> kc(B);
+            for (int b = 0; b < B; ++b) {
+                const int Kb = K_eff[b];
+                const long long o = px_offset[b];
+                const char* d = dev + (size_t)b * cb;
+                kc[b] = filter_consts_at(d, Kb, rho);
+                Mb[b] = reinterpret_cast<const float*>(d + filter_consts_bytes(Kb, rho));
+                fb_[b] = f + (size_t)n * o;
+                gb_[b] = guide + (size_t)rho * o;
+                ob[b] = out + (size_t)n * o;
+                db_[b] = den + o;
+                gob[b] = grad_out + (size_t)n * o;
+                gfb[b] = grad_f ? grad_f + (size_t)n * o : nullptr;
+                ggb[b] = grad_guide ? grad_guide + (size_t)rho * o : nullptr;
+            }
+            adjoint_passes_batch(c, ws, B, plans.data(), fb_.data(), gb_.data(), kc.data(), Mb.data(), ob.data(),
+                                 db_.data(), gob.data(), gfb.data(), ggb.data(), sig + B);
+        } else {
             char* region = ws.take<char>((size_t)ns * passes);
             Spread sp(c, B);
             const std::vector<int> order = by_size(cnt);
@@ -793,7 +816,7 @@ fhd_status fhd_filter_batch_backward(fhd_ctx* ctx, int B, const int* H, const in
             }
         }
         if (grad_sigma_r != nullptr) {
-            sum_doubles(c, sig, B, sig + B);
+            if (!batched) sum_doubles(c, sig, B, sig + B);
             FHD_HIP(hipMemcpyAsync(grad_sigma_r, sig + B, sizeof(double), hipMemcpyDeviceToHost, c.stream));
             FHD_HIP(hipStreamSynchronize(c.stream));
         }

@@ -126,6 +126,15 @@ size_t adjoint_passes_workspace(const FilterPlan& fp);
 void adjoint_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const float* guide,
                     const FilterConsts& kc, const float* Md, const float* out, const float* den,
                     const float* gout, float* gradf, float* gradp, double* sig_dev);
+// One launch per pass for the adjoint of all images of a batch (guides of at
+// most 8 dimensions, at most 32 clusters, radius 1..32); per-image pointers;
+// the sigma_r gradient summed over all images goes to sig_dev.
+bool adjoint_batch_supported(const FilterPlan& fp);
+size_t adjoint_batch_workspace(int B, const FilterPlan* plans);
+void adjoint_passes_batch(Ctx& c, Arena& ws, int B, const FilterPlan* plans, const float* const* f,
+                          const float* const* guide, const FilterConsts* kc, const float* const* Md,
+                          const float* const* out, const float* const* den, const float* const* gout,
+                          float* const* gradf, float* const* gradp, double* sig_dev);
 // out_dev[0] = v[0] + ... + v[count-1] (fixed order), on the ctx stream
 void sum_doubles(Ctx& c, const double* v, int count, double* out_dev);
 void adjoint_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const float* guide,

@@ -54,6 +54,8 @@ struct FA {
     float* beta;        // K planes
     float* gamma;       // K planes
     float* gradf;       // n planes or null
+    const float* Md;    // dA^+/dsigma_r (K x K), batched adjoint
+    float* gradp;       // rho planes or null, batched adjoint
     int n, rho, K, H, W, Wp, S, coef, tx, xcd_groups;
     int gsplit;         // column pass: blocks sharing one tile's channel groups
     long long N, Np;    // pixels; stride of the B / C planes
@@ -686,14 +688,14 @@ __global__ __launch_bounds__(RT) void col_generic(FA a) {
 enum { AM_BETA = 0, AM_GAMMA = 1 };
 
 template <int S, int MODE>
-__global__ __launch_bounds__(RT) void col_adj(FA a) {
+__device__ __forceinline__ void col_adj_body(const FA& a, int blk) {
     constexpr int R = R_COL;
     constexpr int TY = TYC;
     constexpr int ROWS = TY + 2 * S;
     constexpr int PER = (ROWS * TXC + RT - 1) / RT;
     constexpr int WIN = R + 2 * S;
     __shared__ float tbuf[2][PER * RT];
-    const ColTile tile = col_tile(a, TY, (int)blockIdx.x);
+    const ColTile tile = col_tile(a, TY, blk);
     if (!tile.block_active) return;
     const int n = a.n, K = a.K;
     const int lx = threadIdx.x & (TXC - 1), tr = threadIdx.x / TXC;
@@ -810,6 +812,19 @@ __global__ __launch_bounds__(RT) void col_adj(FA a) {
     }
 }
 
+template <int S, int MODE>
+__global__ __launch_bounds__(RT) void col_adj(FA a) {
+    col_adj_body<S, MODE>(a, (int)blockIdx.x);
+}
+
+template <int S, int MODE>
+__global__ __launch_bounds__(RT) void col_adj_batch(const FA* __restrict__ fas, const int* __restrict__ pre,
+                                                    int B) {
+    int b;
+    const int t = batch_block(pre, B, b);
+    col_adj_body<S, MODE>(fas[b], t);
+}
+
 // Per-pixel end of the adjoint: dL/db = beta + A^+ gamma (A^+ symmetric),
 // dL/dp = sum_l dL/db_l b_l (-2 s)(p - mu_l) with s = 1 / (2 sigma_r^2), and
 // this pixel's share of dL/dsigma_r:
@@ -820,9 +835,9 @@ __global__ __launch_bounds__(RT) void col_adj(FA a) {
 // fixed order.
 constexpr int KF = 32;
 
-__global__ __launch_bounds__(RT) void adj_final(FA a, const float* __restrict__ Md, float sig3inv, int l0,
-                                                int accumulate, float* __restrict__ gradp,
-                                                double* __restrict__ part) {
+__device__ __forceinline__ void adj_final_body(const FA& a, const float* __restrict__ Md, float sig3inv, int l0,
+                                               int accumulate, float* __restrict__ gradp, double* part_slot,
+                                               int blk) {
     // column m of the block's rows of A^+ and M, zero-padded to KF rows, so
     // the unrolled loops below carry no bounds branches
     __shared__ float sP[64 * KF], sA[64 * KF];
@@ -850,7 +865,7 @@ __global__ __launch_bounds__(RT) void adj_final(FA a, const float* __restrict__ 
             sall[t] = r < rho ? a.mu[(long long)m * rho + r] : 0.0f;
         }
     __syncthreads();
-    const long long i = (long long)blockIdx.x * RT + threadIdx.x;
+    const long long i = (long long)blk * RT + threadIdx.x;
     const bool valid = i < a.N;
     const int y = valid ? (int)(i / a.W) : 0, x = valid ? (int)(i % a.W) : 0;
     const long long po = (long long)y * a.Wp + x;
@@ -927,8 +942,24 @@ __global__ __launch_bounds__(RT) void adj_final(FA a, const float* __restrict__ 
     if (threadIdx.x == 0) {
         double t = 0.0;
         for (int q = 0; q < RT / 64; ++q) t += red[q];
-        part[blockIdx.x] = t;
+        *part_slot = t;
     }
+}
+
+__global__ __launch_bounds__(RT) void adj_final(FA a, const float* __restrict__ Md, float sig3inv, int l0,
+                                                int accumulate, float* __restrict__ gradp,
+                                                double* __restrict__ part) {
+    adj_final_body(a, Md, sig3inv, l0, accumulate, gradp, part + blockIdx.x, (int)blockIdx.x);
+}
+
+// one launch for every image (at most 32 clusters: a single cluster range);
+// the block partials of all images follow one another in `part`
+__global__ __launch_bounds__(RT) void adj_final_batch(const FA* __restrict__ fas, const int* __restrict__ pre, int B,
+                                                      float sig3inv, double* __restrict__ part) {
+    int b;
+    const int t = batch_block(pre, B, b);
+    const FA& a = fas[b];
+    adj_final_body(a, a.Md, sig3inv, 0, 0, a.gradp, part + blockIdx.x, t);
 }
 
 __global__ __launch_bounds__(RT) void sum_blocks(const double* __restrict__ part, int nb, double* __restrict__ out) {
@@ -961,7 +992,7 @@ size_t weights_fp32_lds(int K, int rho, int npx) {
 
 int weights_fp32_npx(int K) { return K <= 64 ? RT : 64; }
 
-__global__ __launch_bounds__(RT) void weights_fp32(FA a, float* Bpl, float* Cpl) {
+__device__ __forceinline__ void weights_fp32_body(const FA& a, float* Bpl, float* Cpl, int bx, int by) {
     extern __shared__ float lds[];
     const int K = a.K, rho = a.rho, KP = pad8(K), RP = pad8(rho);
     const int npx = blockDim.x;
@@ -977,7 +1008,7 @@ __global__ __launch_bounds__(RT) void weights_fp32(FA a, float* Bpl, float* Cpl)
         smu[t] = r < rho ? a.mu[m * rho + r] : 0.0f;
     }
     __syncthreads();
-    const int y = blockIdx.y, x = blockIdx.x * npx + threadIdx.x;
+    const int y = by, x = bx * npx + threadIdx.x;
     if (x >= a.W) return;
     const long long pix = (long long)y * a.W + x;
     const long long ppl = (long long)y * a.Wp + x;
@@ -1017,6 +1048,20 @@ __global__ __launch_bounds__(RT) void weights_fp32(FA a, float* Bpl, float* Cpl)
         for (int q = 0; q < 8; ++q)
             if (l0 + q < K) Cpl[(long long)(l0 + q) * a.Np + ppl] = acc[q];
     }
+}
+
+__global__ __launch_bounds__(RT) void weights_fp32(FA a, float* Bpl, float* Cpl) {
+    weights_fp32_body(a, Bpl, Cpl, (int)blockIdx.x, (int)blockIdx.y);
+}
+
+// batched adjoint (weights inline elsewhere): the C planes of every image
+__global__ __launch_bounds__(RT) void weights_fp32_batch(const FA* __restrict__ fas, const int* __restrict__ pre,
+                                                         int B) {
+    int b;
+    const int t = batch_block(pre, B, b);
+    const FA& a = fas[b];
+    const int gx = (a.W + (int)blockDim.x - 1) / (int)blockDim.x;
+    weights_fp32_body(a, nullptr, const_cast<float*>(a.Cpl), t % gx, t / gx);
 }
 
 // ---------------------------------------------------------------------------
@@ -1291,12 +1336,26 @@ struct AdjTables<0> {
     static void fill(KernFn (*)[2]) {}
 };
 
+template <int S>
+struct AdjBatchTables {
+    static void fill(void (*(*adj)[2])(const FA*, const int*, int)) {
+        adj[S][AM_BETA] = col_adj_batch<S, AM_BETA>;
+        adj[S][AM_GAMMA] = col_adj_batch<S, AM_GAMMA>;
+        AdjBatchTables<S - 1>::fill(adj);
+    }
+};
+template <>
+struct AdjBatchTables<0> {
+    static void fill(void (*(*)[2])(const FA*, const int*, int)) {}
+};
+
 struct Dispatch {
     KernFn row[MAXS_T + 1];
     KernFn col[MAXS_T + 1][3];
     KernFn adj[MAXS_T + 1][2];
     BatchFn rowb[MAXS_T + 1];
     BatchFn colb[MAXS_T + 1][3];
+    BatchFn adjb[MAXS_T + 1][2];
     Dispatch() {
         row[0] = nullptr;
         col[0][0] = col[0][1] = col[0][2] = nullptr;
@@ -1306,6 +1365,8 @@ struct Dispatch {
         Tables<MAXS_T>::fill(row, col);
         AdjTables<MAXS_T>::fill(adj);
         BatchTables<MAXS_T>::fill(rowb, colb);
+        adjb[0][0] = adjb[0][1] = nullptr;
+        AdjBatchTables<MAXS_T>::fill(adjb);
     }
 };
 
@@ -1738,6 +1799,147 @@ void adjoint_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, con
         hipLaunchKernelGGL(adj_final, dim3(nb), dim3(RT), 0, st, a, Md, sig3inv, h * KF, h, gradp,
                            part + (size_t)h * nb);
     hipLaunchKernelGGL(sum_blocks, dim3(1), dim3(RT), 0, st, part, halves * nb, sig_dev);
+    FHD_HIP(hipGetLastError());
+}
+
+bool adjoint_batch_supported(const FilterPlan& fp) {
+    return fp.S >= 1 && fp.S <= MAXS_T && fp.rho <= RHO_INLINE && fp.K <= KMAX_INLINE &&
+           fp.coef == FHD_COEF_LSQ && fp.H + 2 * fp.S <= 65535;
+}
+
+size_t adjoint_batch_workspace(int B, const FilterPlan* plans) {
+    Arena probe;
+    long long nb = 0;
+    for (int b = 0; b < B; ++b) {
+        const long long Np = (long long)plans[b].H * plans[b].Wp;
+        probe.take<float>(plane_floats(plans[b]));
+        for (int q = 0; q < 3; ++q) probe.take<float>((size_t)plans[b].K * Np);
+        nb += (plans[b].N + RT - 1) / RT;
+    }
+    probe.take<double>((size_t)nb + 1);
+    probe.take<FA>(3 * (size_t)B);
+    probe.take<int>(4 * (size_t)(B + 1));
+    return probe.used;
+}
+
+// The adjoint of every image of a batch with one launch per pass for all
+// images (guides of at most 8 dimensions, at most 32 clusters, radius 1..32:
+// the weights b are formed inline, only the C planes are stored).  Three
+// tables of per-image arguments: the first row pass (c_l [f, 1]), the second
+// row pass (b_l Y), and the weights / GAMMA / final passes, which read the
+// C planes.  The block partials of dL/dsigma_r of all images are summed into
+// sig_dev.
+void adjoint_passes_batch(Ctx& c, Arena& ws, int B, const FilterPlan* plans, const float* const* f,
+                          const float* const* guide, const FilterConsts* kc, const float* const* Md,
+                          const float* const* out, const float* const* den, const float* const* gout,
+                          float* const* gradf, float* const* gradp, double* sig_dev) {
+    const int S = plans[0].S;
+    std::vector<FA> fas(3 * (size_t)B);
+    std::vector<int> pre(4 * (size_t)(B + 1), 0);
+    int* pre_w = pre.data();
+    int* pre_r = pre_w + (B + 1);
+    int* pre_c = pre_r + (B + 1);
+    int* pre_f = pre_c + (B + 1);
+    size_t rlds = 0, wlds = 0;
+    const int npx = RT;
+    for (int b = 0; b < B; ++b) {
+        const FilterPlan& fp = plans[b];
+        FHD_REQUIRE(adjoint_batch_supported(fp) && fp.S == S && fp.sigma_r == plans[0].sigma_r, FHD_EINVAL,
+                    "internal: batch adjoint plans differ");
+        FHD_REQUIRE(weights_fp32_npx(fp.K) == npx, FHD_EINVAL, "internal: weights block size");
+        const long long Np = (long long)fp.H * fp.Wp;
+        FA a = make_args(fp);
+        a.f = f[b];
+        a.p = guide[b];
+        a.mu = kc[b].mu;
+        a.P = kc[b].P;
+        a.planes = ws.take<float>(plane_floats(fp));
+        float* Cpl = ws.take<float>((size_t)fp.K * Np);
+        a.beta = ws.take<float>((size_t)fp.K * Np);
+        a.gamma = ws.take<float>((size_t)fp.K * Np);
+        a.gout = gout[b];
+        a.gimg = out[b];
+        a.gden = den[b];
+        a.gradf = gradf[b];
+        a.Md = Md[b];
+        a.gradp = gradp[b];
+        a.Bpl = nullptr;
+        a.Cpl = nullptr;
+        FilterPlan rp = fp;
+        rp.materialize = false;
+        int tx = row_tx(fp.K, fp.S, R_ROW);
+        size_t l = row_lds_bytes(rp, tx);
+        while (l > 150 * 1024 && tx > 4 * R_ROW) {
+            tx = std::max(4 * R_ROW, tx / 2 / R_ROW * R_ROW);
+            l = row_lds_bytes(rp, tx);
+        }
+        FHD_REQUIRE(l <= 160 * 1024, FHD_EUNSUPPORTED, "row pass does not fit in LDS");
+        rlds = std::max(rlds, l);
+        wlds = std::max(wlds, weights_fp32_lds(fp.K, fp.rho, npx));
+        a.tx = tx;
+        const int gx = (fp.W + TXC - 1) / TXC, gy = (fp.H + TYC - 1) / TYC;
+        a.xcd_groups = (gx * gy + 7) / 8;
+        a.gsplit = 1;
+        a.fmode = 0;
+        a.factor_b = 0;
+        fas[b] = a;                 // first row pass, BETA column pass
+        a.fmode = 1;
+        a.factor_b = 1;
+        fas[B + b] = a;             // second row pass
+        a.Cpl = Cpl;
+        fas[2 * (size_t)B + b] = a; // weights (C planes), GAMMA column pass, final pass
+        pre_w[b + 1] = pre_w[b] + ((fp.W + npx - 1) / npx) * fp.H;
+        pre_r[b + 1] = pre_r[b] + ((fp.W + tx - 1) / tx) * (fp.H + 2 * fp.S);
+        pre_c[b + 1] = pre_c[b] + a.xcd_groups * 8;
+        pre_f[b + 1] = pre_f[b] + (int)((fp.N + RT - 1) / RT);
+    }
+    double* part = ws.take<double>((size_t)pre_f[B] + 1);
+    FA* dfa = ws.take<FA>(3 * (size_t)B);
+    int* dpre = ws.take<int>(4 * (size_t)(B + 1));
+    const size_t fab = sizeof(FA) * 3 * B, prb = sizeof(int) * 4 * (B + 1);
+    char* hs = static_cast<char*>(c.host_stage(2, align_up(fab, 256) + prb));
+    std::memcpy(hs, fas.data(), fab);
+    std::memcpy(hs + align_up(fab, 256), pre.data(), prb);
+    hipStream_t st = c.stream;
+    FHD_HIP(hipMemcpyAsync(dfa, hs, fab, hipMemcpyHostToDevice, st));
+    FHD_HIP(hipMemcpyAsync(dpre, hs + align_up(fab, 256), prb, hipMemcpyHostToDevice, st));
+    c.stage_done(2);
+    const FA* fa0 = dfa;
+    const FA* fa1 = dfa + B;
+    const FA* fa2 = dfa + 2 * B;
+    const int* dw = dpre;
+    const int* dr = dpre + (B + 1);
+    const int* dc = dpre + 2 * (B + 1);
+    const int* df = dpre + 3 * (B + 1);
+    FHD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(weights_fp32_batch),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)wlds));
+    hipEvent_t t0 = c.stage_begin();
+    hipLaunchKernelGGL(weights_fp32_batch, dim3(pre_w[B]), dim3(npx), wlds, st, fa2, dw, B);
+    c.stage_end(FHD_STAGE_WEIGHTS, t0);
+    FHD_HIP(hipGetLastError());
+    BatchFn rowk = dispatch().rowb[S];
+    FHD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(rowk), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)rlds));
+    // dL/db_l from the recombination: recompute Q_l = w * (c_l [f, 1])
+    t0 = c.stage_begin();
+    hipLaunchKernelGGL(rowk, dim3(pre_r[B]), dim3(RT), rlds, st, fa0, dr, B);
+    c.stage_end(FHD_STAGE_ROW, t0);
+    t0 = c.stage_begin();
+    hipLaunchKernelGGL(dispatch().adjb[S][AM_BETA], dim3(pre_c[B]), dim3(RT), 0, st, fa0, dc, B);
+    c.stage_end(FHD_STAGE_COL, t0);
+    // the adjoint convolution of dL/dQ_l = b_l Y
+    t0 = c.stage_begin();
+    hipLaunchKernelGGL(rowk, dim3(pre_r[B]), dim3(RT), rlds, st, fa1, dr, B);
+    c.stage_end(FHD_STAGE_ROW, t0);
+    t0 = c.stage_begin();
+    hipLaunchKernelGGL(dispatch().adjb[S][AM_GAMMA], dim3(pre_c[B]), dim3(RT), 0, st, fa2, dc, B);
+    c.stage_end(FHD_STAGE_COL, t0);
+    FHD_HIP(hipGetLastError());
+    const float sig3inv = std::isinf(plans[0].sigma_r)
+                              ? 0.0f
+                              : (float)(1.0 / ((double)plans[0].sigma_r * plans[0].sigma_r * plans[0].sigma_r));
+    hipLaunchKernelGGL(adj_final_batch, dim3(pre_f[B]), dim3(RT), 0, st, fa2, df, B, sig3inv, part);
+    hipLaunchKernelGGL(sum_blocks, dim3(1), dim3(RT), 0, st, part, pre_f[B], sig_dev);
     FHD_HIP(hipGetLastError());
 }
 

@@ -7,7 +7,7 @@ the same as when the image is clustered alone, so centers and outputs must be
 bit-identical to the single-image calls; each image is also checked against
 the FP64 oracle (max-abs 1e-4).  The batch adjoint must equal the per-image
 adjoint (bit-identical image and guide gradients; sigma_r summed over images,
-1e-12 relative).
+1e-12 relative), on both of its paths.
 """
 import numpy as np
 import pytest
@@ -79,11 +79,14 @@ def test_batch_against_oracle(fhd):
     assert worst < 1e-4
 
 
-def test_batch_backward_equals_per_image(fhd):
+@pytest.mark.parametrize("K", [32, 48])
+def test_batch_backward_equals_per_image(fhd, K):
+    """K 32: one launch per pass for all images; K 48: the images spread over
+    streams, one adjoint each."""
     imgs = _images(1600)
     dev = [torch.from_numpy(x).cuda() for x in imgs]
     flat, sizes = fhd.pack_batch(dev)
-    out, den, cen, keff = fhd.filter_batch(flat, sizes, 3, sigma_s=3.0, sigma_r=0.1, K=32, radius=9,
+    out, den, cen, keff = fhd.filter_batch(flat, sizes, 3, sigma_s=3.0, sigma_r=0.1, K=K, radius=9,
                                            return_den=True)
     G = torch.from_numpy(np.random.default_rng(3).standard_normal(flat.numel()).astype(np.float32)).cuda()
     gf, gg, gs = fhd.filter_batch_backward(flat, sizes, 3, cen, keff, out, den, G, sigma_s=3.0, sigma_r=0.1,
