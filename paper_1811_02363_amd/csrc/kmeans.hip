@@ -36,35 +36,45 @@ namespace {
 
 constexpr int KT = 256;          // threads per block
 constexpr int KWAVES = KT / 64;  // waves per block
+constexpr int FT = 256;          // threads per finalize block
+static_assert(FT == KT, "the assignment step runs the finalize reduction with its own threads");
 constexpr int KITERS = 16;       // point groups per block and pass
 constexpr int DPL = 8;           // dimensions per lane (at most)
 // points per lane group in flight per step: eight for one lane of up to four
 // dimensions per point, else four (register budget)
 template <int D>
 constexpr int unr() { return D <= 4 ? 8 : 4; }
+// the assignment step stages its points as FP32 (converted at use): sixteen
+// points per lane group in flight for up to four dimensions, else eight
+template <int D>
+constexpr int unr_lloyd() { return D <= 4 ? 16 : 8; }
 
 // per-job integer state
-enum { JI_START, JI_COUNT, JI_BUF, JI_STOP, JI_STEPS, JI_FIRST, JI_NBLK, JI_NA, JI_W = 8 };
+enum { JI_START, JI_COUNT, JI_BUF, JI_FIRST, JI_NBLK, JI_NA, JI_W = 8 };
 // per-job FP64 results
 enum { JD_SSEA, JD_SSEB, JD_NA, JD_NB, JD_SPLA, JD_SPLB, JD_W = 6 };
 
 struct KmArgs {
     float* pts[2];
     int* idx[2];
-    const int4* btab;  // per block: job, first point, point count, rank within job (or label)
+    const int4* btab;  // per block: job (bit 30: its point buffer), first point, point count,
+                       // rank within job (or label)
     int* blkA;         // per block: members of the first child (split pass)
-    double* part;      // per block records, pw doubles each
+    double* part;      // per block records, entry-major: entry e of block b at part[e * pst + b]
+    double* part2;     // the same for the odd assignment steps
     int* ji;           // per job ints, JI_W each
     double* jm;        // per job centroid (rho)
     double* ca;        // per job current centers (first / second child), rho each
     double* cb;
-    double* la;        // per job centers of the latest accepted assignment
-    double* lb;
+    double* cst;       // assignment-step centers, three generations: (ca, cb) of job j for step t
+                       // at cst[((t % 3) * mj + j) * 2 rho]
+    int* jstop;        // per job, two generations: stopped before step t at jstop[(t & 1) * mj + j]
+    int mj;            // job capacity
     double* fa;        // per job centers whose assignment gives the final labels
     double* fb;
     double* jd;        // per job results, JD_W each
     int rho;
-    int pw;
+    long long pst;     // record entry stride (the block capacity)
     int ps;            // point stride in floats (LP * D of the launched layout)
 };
 
@@ -91,6 +101,17 @@ __device__ __forceinline__ void load_dims(const float* pts, long long pos, int d
 #pragma unroll
     for (int k = 0; k < D; ++k) x[k] = (double)p[k];
 }
+
+template <int LP, int D>
+__device__ __forceinline__ void load_dims_f(const float* pts, long long pos, int d0, float (&x)[D]) {
+    const float* p = pts + pos * (LP * D) + d0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) x[k] = p[k];
+}
+
+constexpr int JOB_BITS = 0x3fffffff;
+__device__ __forceinline__ int bjob(int4 bt) { return bt.x & JOB_BITS; }
+__device__ __forceinline__ int bbuf(int4 bt) { return bt.x >> 30; }
 
 template <int D>
 __device__ __forceinline__ void load_center(const double* c, int rho, int d0, double (&v)[D]) {
@@ -120,6 +141,14 @@ __device__ __forceinline__ bool to_first(const double (&x)[D], const double (&a)
     return dist2<LP, D>(x, a, rho, d0) <= dist2<LP, D>(x, b, rho, d0);
 }
 
+// One block's record: entry e at p[e * st].
+struct RecRef {
+    double* p;
+    long long st;
+    __device__ double& operator[](int e) const { return p[(long long)e * st]; }
+    __device__ RecRef operator+(int o) const { return RecRef{p + (long long)o * st, st}; }
+};
+
 template <int OP>
 __device__ __forceinline__ double op2(double u, double v) {
     return OP == 0 ? u + v : (OP == 1 ? fmin(u, v) : fmax(u, v));
@@ -128,7 +157,7 @@ __device__ __forceinline__ double op2(double u, double v) {
 // Block reduction of per-lane dimension values (lanes with equal `sub` hold
 // the same dimensions); thread t < rho writes the total of dimension t to out[t].
 template <int LP, int D, int OP>
-__device__ __forceinline__ void block_dims(double (&v)[D], double (*red)[64], int rho, double* out) {
+__device__ __forceinline__ void block_dims(double (&v)[D], double (*red)[64], int rho, RecRef out) {
 #pragma unroll
     for (int k = 0; k < D; ++k)
 #pragma unroll
@@ -164,36 +193,35 @@ __device__ __forceinline__ double block_sum(double v, double (*red)[64]) {
 // Finalize helper: res[e] = reduction over the job's blocks of record entry
 // e0 + e, for e < E, with the operation opof(e) (0 sum, 1 min, 2 max).  A
 // fixed order: a power-of-two group of G threads per entry; thread `sub` of a
-// group folds records sub, sub + G, sub + 2G, ... into four partials (loads
-// issued four at a time), combined as (p0 op p1) op (p2 op p3); then a
-// pairwise tree over the group in LDS.
+// group folds records sub, sub + G, sub + 2G, ... (adjacent threads read
+// adjacent blocks' entries; sixteen loads in flight)
+// into four partials by slot (q mod 4), combined as (p0 op p1) op (p2 op p3);
+// then a pairwise tree over the group in LDS.  Called by all FT threads.
 template <class OpOf>
-__device__ void reduce_records(const double* part, int first, int nblk, int pw, int e0, int E, OpOf opof,
+__device__ void reduce_records(const double* part, int first, int nblk, long long pst, int e0, int E, OpOf opof,
                                double* tmp, double* res) {
     auto ident = [](int op) { return op == 0 ? 0.0 : (op == 1 ? INFINITY : -INFINITY); };
     auto fold = [](int op, double u, double v) { return op == 0 ? u + v : (op == 1 ? fmin(u, v) : fmax(u, v)); };
-    for (int base = 0; base < E; base += KT) {
-        const int Ec = min(KT, E - base);
-        const int G = 1 << (31 - __clz(KT / Ec));  // threads per entry, a power of two
+    for (int base = 0; base < E; base += FT) {
+        const int Ec = min(FT, E - base);
+        const int G = 1 << (31 - __clz(FT / Ec));  // threads per entry, a power of two
         const int t = threadIdx.x;
         const bool act = t < Ec * G;
         const int e = base + t / G, sub = t & (G - 1);
         const int op = act ? opof(e) : 0;
-        double acc = ident(op);
+        const double id = ident(op);
+        double acc = id;
         if (act) {
-            double p0 = acc, p1 = acc, p2 = acc, p3 = acc;
-            const long long stride = (long long)G * pw;
-            const double* r = part + (long long)(first + sub) * pw + e0 + e;
-            int b = sub;
-            for (; b + 3 * G < nblk; b += 4 * G, r += 4 * stride) {
-                const double w0 = r[0], w1 = r[stride], w2 = r[2 * stride], w3 = r[3 * stride];
-                p0 = fold(op, p0, w0);
-                p1 = fold(op, p1, w1);
-                p2 = fold(op, p2, w2);
-                p3 = fold(op, p3, w3);
+            double p[4] = {id, id, id, id};
+            const double* r = part + (long long)(e0 + e) * pst + first + sub;
+            for (int b = sub; b < nblk; b += 16 * G, r += 16 * G) {
+                double w[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) w[q] = b + q * G < nblk ? r[q * G] : id;
+#pragma unroll
+                for (int q = 0; q < 16; ++q) p[q & 3] = fold(op, p[q & 3], w[q]);
             }
-            for (; b < nblk; b += G, r += stride) p0 = fold(op, p0, r[0]);
-            acc = fold(op, fold(op, p0, p1), fold(op, p2, p3));
+            acc = fold(op, fold(op, p[0], p[1]), fold(op, p[2], p[3]));
         }
         tmp[t] = acc;
         __syncthreads();
@@ -224,7 +252,7 @@ template <int LP, int D>
 __global__ __launch_bounds__(KT) void km_stats(KmArgs a) {
     __shared__ double red[KWAVES][64];
     const int4 bt = a.btab[blockIdx.x];
-    const int job = bt.x, s = bt.y, cnt = bt.z;
+    const int job = bjob(bt), s = bt.y, cnt = bt.z;
     const float* pts = a.pts[a.ji[job * JI_W + JI_BUF]];
     const int rho = a.rho;
     const Lanes<LP, D> L;
@@ -248,7 +276,7 @@ __global__ __launch_bounds__(KT) void km_stats(KmArgs a) {
                 mx[k] = fmax(mx[k], x[k]);
             }
     }
-    double* rec = a.part + (long long)blockIdx.x * a.pw;
+    const RecRef rec{a.part + blockIdx.x, a.pst};
     block_dims<LP, D, 0>(sum, red, rho, rec);
     block_dims<LP, D, 1>(mn, red, rho, rec + rho);
     block_dims<LP, D, 2>(mx, red, rho, rec + 2 * rho);
@@ -259,7 +287,7 @@ template <int LP, int D>
 __global__ __launch_bounds__(KT) void km_sse1(KmArgs a) {
     __shared__ double red[KWAVES][64];
     const int4 bt = a.btab[blockIdx.x];
-    const int job = bt.x, s = bt.y, cnt = bt.z;
+    const int job = bjob(bt), s = bt.y, cnt = bt.z;
     const float* pts = a.pts[a.ji[job * JI_W + JI_BUF]];
     const int rho = a.rho;
     const Lanes<LP, D> L;
@@ -279,7 +307,7 @@ __global__ __launch_bounds__(KT) void km_sse1(KmArgs a) {
             }
     }
     const double tot = block_sum(e, red);
-    if (threadIdx.x == 0) a.part[(long long)blockIdx.x * a.pw] = tot;
+    if (threadIdx.x == 0) a.part[blockIdx.x] = tot;
 }
 
 // Seed search: the member farthest from the centroid (which == 0) or from the
@@ -289,7 +317,7 @@ __global__ __launch_bounds__(KT) void km_far(KmArgs a, int which) {
     __shared__ double rb[KWAVES];
     __shared__ int ri[KWAVES], rp[KWAVES];
     const int4 bt = a.btab[blockIdx.x];
-    const int job = bt.x, s = bt.y, cnt = bt.z;
+    const int job = bjob(bt), s = bt.y, cnt = bt.z;
     const int buf = a.ji[job * JI_W + JI_BUF];
     const float* pts = a.pts[buf];
     const int* idx = a.idx[buf];
@@ -345,50 +373,134 @@ __global__ __launch_bounds__(KT) void km_far(KmArgs a, int which) {
                 bidx = ri[q];
                 bpos = rp[q];
             }
-        double* rec = a.part + (long long)blockIdx.x * a.pw;
+        const RecRef rec{a.part + blockIdx.x, a.pst};
         rec[0] = best;
         rec[1] = (double)bidx;
         rec[2] = (double)bpos;
     }
 }
 
-// One assignment step with the current centers (ca, cb).
+// The 2-means state machine after assignment step `st` (labels L_st from the
+// centers c_st; m = means of L_st, from the step's records in `res`):
+//   a child would be empty   -> stop; final labels L_{st-1} (centers c_{st-1});
+//   m equals c_st, st >= 1   -> converged; final labels L_st (centers c_st);
+//   otherwise                -> c_{st+1} = m; after max_iter steps stop with
+//                               final labels L_st (centers c_st).
+// Equal means from a fixed summation order follow from equal labels, and
+// equal means make the next assignment repeat the current one, so this stops
+// with the labels and centers of the label-change rule.  Returns 0, 1, 2 for
+// the three cases (one thread).
+__device__ __forceinline__ int lloyd_act(const double* res, const double* c, int rho, int st) {
+    const double NA = res[2 * rho], NB = res[2 * rho + 1];
+    if (NA == 0.0 || NB == 0.0) return 0;
+    bool same = st >= 1;
+    for (int t = 0; t < rho && same; ++t) same = (res[t] / NA == c[t]) && (res[rho + t] / NB == c[rho + t]);
+    return same ? 1 : 2;
+}
+
+// The job's final state after it stops at the decision on step `st`: the
+// centers whose assignment gives the final labels (fa, fb) and the children's
+// centroids (ca, cb).  Threads < rho.
+__device__ __forceinline__ void lloyd_final(const KmArgs& a, int job, int act, int st, const double* res) {
+    const int rho = a.rho, t = threadIdx.x;
+    if (t >= rho) return;
+    const double* c = a.cst + ((long long)(st % 3) * a.mj + job) * 2 * rho;             // c_st
+    const double* l = a.cst + ((long long)((st + 2) % 3) * a.mj + job) * 2 * rho;       // c_{st-1}
+    const double* f = act == 0 && st >= 1 ? l : c;
+    a.fa[job * rho + t] = f[t];
+    a.fb[job * rho + t] = f[rho + t];
+    if (act == 2) {
+        a.ca[job * rho + t] = res[t] / res[2 * rho];
+        a.cb[job * rho + t] = res[rho + t] / res[2 * rho + 1];
+    } else {
+        a.ca[job * rho + t] = c[t];
+        a.cb[job * rho + t] = c[rho + t];
+    }
+}
+
+// Assignment step t of every running job.  From the second step on, every
+// block first reduces its job's records of step t - 1 and takes the state
+// machine's decision itself (the same fixed-order sums in every block, so the
+// same decision and centers); the job's first block records the outcome.
 // Record: sumA[rho], sumB[rho], nA, nB.
 template <int LP, int D>
-__global__ __launch_bounds__(KT) void km_lloyd(KmArgs a) {
+__global__ __launch_bounds__(KT) void km_lloyd(KmArgs a, int t) {
     __shared__ double red[KWAVES][64];
+    __shared__ double tmp[KT];
+    __shared__ double res[2 * FHD_MAX_RHO + 2];
+    __shared__ double cen[2 * FHD_MAX_RHO];
+    __shared__ int s_act;
     const int4 bt = a.btab[blockIdx.x];
-    const int job = bt.x, s = bt.y, cnt = bt.z;
-    const int* ji = a.ji + job * JI_W;
-    if (ji[JI_STOP]) return;
-    const float* pts = a.pts[ji[JI_BUF]];
+    const int job = bjob(bt), s = bt.y, cnt = bt.z, rank = bt.w;
     const int rho = a.rho;
+    const bool lead = rank == 0;
+    int* stop_now = a.jstop + (long long)(t & 1) * a.mj + job;
+    double* cnow = a.cst + ((long long)(t % 3) * a.mj + job) * 2 * rho;
+    if (t > 0) {
+        if (a.jstop[(long long)((t - 1) & 1) * a.mj + job]) {
+            if (lead && threadIdx.x == 0) *stop_now = 1;
+            return;
+        }
+        const int* ji = a.ji + job * JI_W;
+        reduce_records((t - 1) & 1 ? a.part2 : a.part, ji[JI_FIRST], ji[JI_NBLK], a.pst, 0, 2 * rho + 2,
+                       [](int) { return 0; }, tmp, res);
+        const double* cprev = a.cst + ((long long)((t - 1) % 3) * a.mj + job) * 2 * rho;
+        if (threadIdx.x == 0) s_act = lloyd_act(res, cprev, rho, t - 1);
+        __syncthreads();
+        const int act = s_act;
+        if (act != 2) {
+            if (lead) {
+                lloyd_final(a, job, act, t - 1, res);
+                if (threadIdx.x == 0) *stop_now = 1;
+            }
+            return;
+        }
+        if (threadIdx.x < 2 * rho)
+            cen[threadIdx.x] = threadIdx.x < rho ? res[threadIdx.x] / res[2 * rho]
+                                                 : res[threadIdx.x] / res[2 * rho + 1];
+        __syncthreads();
+        if (lead) {
+            if (threadIdx.x < 2 * rho) cnow[threadIdx.x] = cen[threadIdx.x];
+            if (threadIdx.x == 0) *stop_now = 0;
+        }
+    } else {
+        if (threadIdx.x < 2 * rho) cen[threadIdx.x] = cnow[threadIdx.x];
+        if (lead && threadIdx.x == 0) *stop_now = 0;
+        __syncthreads();
+    }
+    const float* pts = a.pts[bbuf(bt)];
     const Lanes<LP, D> L;
-    double ca[D], cb[D], sa[D], sb[D];
-    load_center(a.ca + job * rho, rho, L.d0, ca);
-    load_center(a.cb + job * rho, rho, L.d0, cb);
+    double ca[D], cb[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        ca[k] = L.d0 + k < rho ? cen[L.d0 + k] : 0.0;
+        cb[k] = L.d0 + k < rho ? cen[rho + L.d0 + k] : 0.0;
+    }
+    double sa[D], sb[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) sa[k] = sb[k] = 0.0;
     double na = 0.0, nb = 0.0;
-    // UNR points per lane group per step, all loads issued before use
-    for (int base = 0; base < cnt; base += unr<D>() * KWAVES * L.PPW) {
-        constexpr int UNR = unr<D>();
-        double x[UNR][D];
+    constexpr int UNR = unr_lloyd<D>();
+    for (int base = 0; base < cnt; base += UNR * KWAVES * L.PPW) {
+        float x[UNR][D];
         bool valid[UNR];
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
             const int p = base + (u * KWAVES + L.wave) * L.PPW + L.pw;
             valid[u] = p < cnt;
-            load_dims<LP, D>(pts, valid[u] ? s + p : s, L.d0, x[u]);
+            load_dims_f<LP, D>(pts, valid[u] ? s + p : s, L.d0, x[u]);
         }
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
-            const bool A = to_first<LP, D>(x[u], ca, cb, rho, L.d0);
+            double xd[D];
+#pragma unroll
+            for (int k = 0; k < D; ++k) xd[k] = (double)x[u][k];
+            const bool A = to_first<LP, D>(xd, ca, cb, rho, L.d0);
             if (valid[u]) {
 #pragma unroll
                 for (int k = 0; k < D; ++k) {
-                    if (A) sa[k] += x[u][k];
-                    else sb[k] += x[u][k];
+                    if (A) sa[k] += xd[k];
+                    else sb[k] += xd[k];
                 }
                 if (L.sub == 0) {
                     if (A) na += 1.0;
@@ -397,7 +509,7 @@ __global__ __launch_bounds__(KT) void km_lloyd(KmArgs a) {
             }
         }
     }
-    double* rec = a.part + (long long)blockIdx.x * a.pw;
+    const RecRef rec{(t & 1 ? a.part2 : a.part) + blockIdx.x, a.pst};
     block_dims<LP, D, 0>(sa, red, rho, rec);
     block_dims<LP, D, 0>(sb, red, rho, rec + rho);
     const double tna = block_sum(na, red);
@@ -415,7 +527,7 @@ template <int LP, int D>
 __global__ __launch_bounds__(KT) void km_split(KmArgs a) {
     __shared__ double red[KWAVES][64];
     const int4 bt = a.btab[blockIdx.x];
-    const int job = bt.x, s = bt.y, cnt = bt.z;
+    const int job = bjob(bt), s = bt.y, cnt = bt.z;
     const float* pts = a.pts[a.ji[job * JI_W + JI_BUF]];
     const int rho = a.rho;
     const Lanes<LP, D> L;
@@ -466,7 +578,7 @@ __global__ __launch_bounds__(KT) void km_split(KmArgs a) {
             }
         }
     }
-    double* rec = a.part + (long long)blockIdx.x * a.pw;
+    const RecRef rec{a.part + blockIdx.x, a.pst};
     const double tea = block_sum(ea, red);
     const double teb = block_sum(eb, red);
     const double tna = block_sum(na, red);
@@ -491,7 +603,7 @@ __global__ __launch_bounds__(KT) void km_scatter(KmArgs a) {
     __shared__ int red[KWAVES];
     __shared__ int s_offA, s_offB, s_wa[KWAVES], s_wb[KWAVES];
     const int4 bt = a.btab[blockIdx.x];
-    const int job = bt.x, s = bt.y, cnt = bt.z, rank = bt.w;
+    const int job = bjob(bt), s = bt.y, cnt = bt.z, rank = bt.w;
     const int* ji = a.ji + job * JI_W;
     const int buf = ji[JI_BUF];
     const float* src = a.pts[buf];
@@ -563,7 +675,7 @@ __global__ __launch_bounds__(KT) void km_scatter(KmArgs a) {
 // labels[pixel] = cluster index, for every member of every leaf.
 __global__ __launch_bounds__(KT) void km_labels(KmArgs a, int* __restrict__ labels) {
     const int4 bt = a.btab[blockIdx.x];
-    const int job = bt.x, s = bt.y, cnt = bt.z, lab = bt.w;
+    const int job = bjob(bt), s = bt.y, cnt = bt.z, lab = bt.w;
     const int* idx = a.idx[a.ji[job * JI_W + JI_BUF]];
     for (int p = threadIdx.x; p < cnt; p += KT) labels[idx[s + p]] = lab;
 }
@@ -571,12 +683,12 @@ __global__ __launch_bounds__(KT) void km_labels(KmArgs a, int* __restrict__ labe
 // ---------------------------------------------------------------------------
 // finalize kernels: one block per job
 
-__global__ __launch_bounds__(KT) void fin_stats(KmArgs a) {
-    __shared__ double tmp[KT];
+__global__ __launch_bounds__(FT) void fin_stats(KmArgs a) {
+    __shared__ double tmp[FT];
     __shared__ double res[3 * FHD_MAX_RHO];
     const int job = blockIdx.x, rho = a.rho;
     const int* ji = a.ji + job * JI_W;
-    reduce_records(a.part, ji[JI_FIRST], ji[JI_NBLK], a.pw, 0, 3 * rho,
+    reduce_records(a.part, ji[JI_FIRST], ji[JI_NBLK], a.pst, 0, 3 * rho,
                    [rho](int e) { return e < rho ? 0 : (e < 2 * rho ? 1 : 2); }, tmp, res);
     if (threadIdx.x < rho) a.jm[job * rho + threadIdx.x] = res[threadIdx.x] / (double)ji[JI_COUNT];
     if (threadIdx.x == 0) {
@@ -586,12 +698,12 @@ __global__ __launch_bounds__(KT) void fin_stats(KmArgs a) {
     }
 }
 
-__global__ __launch_bounds__(KT) void fin_sse1(KmArgs a) {
-    __shared__ double tmp[KT];
+__global__ __launch_bounds__(FT) void fin_sse1(KmArgs a) {
+    __shared__ double tmp[FT];
     __shared__ double res[1];
     const int job = blockIdx.x;
     const int* ji = a.ji + job * JI_W;
-    reduce_records(a.part, ji[JI_FIRST], ji[JI_NBLK], a.pw, 0, 1, [](int) { return 0; }, tmp, res);
+    reduce_records(a.part, ji[JI_FIRST], ji[JI_NBLK], a.pst, 0, 1, [](int) { return 0; }, tmp, res);
     if (threadIdx.x == 0) a.jd[job * JD_W + JD_SSEA] = res[0];
 }
 
@@ -605,12 +717,13 @@ __global__ __launch_bounds__(KT) void fin_far(KmArgs a, int which) {
     double B = -1.0;
     int I = INT_MAX, P = -1;
     for (int b = threadIdx.x; b < nblk; b += KT) {
-        const double* rec = a.part + (long long)(first + b) * a.pw;
-        const int bi = (int)rec[1];
-        if (rec[0] > B || (rec[0] == B && bi < I)) {
-            B = rec[0];
+        const double* rec = a.part + first + b;
+        const double rb0 = rec[0];
+        const int bi = (int)rec[a.pst];
+        if (rb0 > B || (rb0 == B && bi < I)) {
+            B = rb0;
             I = bi;
-            P = (int)rec[2];
+            P = (int)rec[2 * a.pst];
         }
     }
 #pragma unroll
@@ -644,77 +757,36 @@ __global__ __launch_bounds__(KT) void fin_far(KmArgs a, int which) {
     const float* pts = a.pts[ji[JI_BUF]];
     if (threadIdx.x < rho)
         (which == 0 ? a.ca : a.cb)[job * rho + threadIdx.x] = pts[(long long)s_pos * a.ps + threadIdx.x];
+    if (threadIdx.x < rho) {  // the seeds are the centers of assignment step 0
+        double* c0 = a.cst + (long long)job * 2 * rho;
+        c0[which * rho + threadIdx.x] = pts[(long long)s_pos * a.ps + threadIdx.x];
+    }
 }
 
-// The 2-means state machine after one assignment step (m = means of the new
-// labels):
-//   a child would be empty  -> stop; final labels = assignment with la/lb;
-//   m equals ca/cb, step>=1 -> converged; final labels = assignment with ca/cb;
-//   otherwise               -> la/lb = ca/cb, ca/cb = m; after max_iter steps
-//                              stop with final labels = assignment with la/lb.
-// Equal means from a fixed summation order follow from equal labels, and
-// equal means make the next assignment repeat the current one, so this stops
-// with the labels and centers of the label-change rule.
-__global__ __launch_bounds__(KT) void fin_lloyd(KmArgs a, int T) {
-    __shared__ double tmp[KT];
+// The decision on the last assignment step T - 1 of the jobs still running:
+// every outcome stops the job.
+__global__ __launch_bounds__(FT) void fin_lloyd(KmArgs a, int T) {
+    __shared__ double tmp[FT];
     __shared__ double res[2 * FHD_MAX_RHO + 2];
     __shared__ int s_act;
     const int job = blockIdx.x, rho = a.rho;
-    int* ji = a.ji + job * JI_W;
-    if (ji[JI_STOP]) return;
-    reduce_records(a.part, ji[JI_FIRST], ji[JI_NBLK], a.pw, 0, 2 * rho + 2, [](int) { return 0; }, tmp, res);
-    double* ca = a.ca + job * rho;
-    double* cb = a.cb + job * rho;
-    const double NA = res[2 * rho], NB = res[2 * rho + 1];
-    const int steps = ji[JI_STEPS];
-    if (threadIdx.x == 0) {
-        int act;
-        if (NA == 0.0 || NB == 0.0) {
-            act = 0;  // keep the previous step
-        } else {
-            bool same = steps >= 1;
-            for (int t = 0; t < rho && same; ++t) same = (res[t] / NA == ca[t]) && (res[rho + t] / NB == cb[t]);
-            act = same ? 1 : 2;
-        }
-        s_act = act;
-    }
+    if (a.jstop[(long long)((T - 1) & 1) * a.mj + job]) return;
+    const int* ji = a.ji + job * JI_W;
+    reduce_records((T - 1) & 1 ? a.part2 : a.part, ji[JI_FIRST], ji[JI_NBLK], a.pst, 0, 2 * rho + 2,
+                   [](int) { return 0; }, tmp, res);
+    const double* c = a.cst + ((long long)((T - 1) % 3) * a.mj + job) * 2 * rho;
+    if (threadIdx.x == 0) s_act = lloyd_act(res, c, rho, T - 1);
     __syncthreads();
-    const int act = s_act;
-    if (threadIdx.x < rho) {
-        const int t = threadIdx.x;
-        if (act == 0) {
-            a.fa[job * rho + t] = a.la[job * rho + t];
-            a.fb[job * rho + t] = a.lb[job * rho + t];
-        } else if (act == 1) {
-            a.fa[job * rho + t] = ca[t];
-            a.fb[job * rho + t] = cb[t];
-        } else {
-            const double oa = ca[t], ob = cb[t];
-            a.la[job * rho + t] = oa;
-            a.lb[job * rho + t] = ob;
-            ca[t] = res[t] / NA;
-            cb[t] = res[rho + t] / NB;
-            a.fa[job * rho + t] = oa;  // final if this was the last allowed step
-            a.fb[job * rho + t] = ob;
-        }
-    }
-    if (threadIdx.x == 0) {
-        if (act != 2) {
-            ji[JI_STOP] = 1;
-        } else {
-            ji[JI_STEPS] = steps + 1;
-            if (steps + 1 >= T) ji[JI_STOP] = 1;
-        }
-    }
+    lloyd_final(a, job, s_act, T - 1, res);
 }
 
-__global__ __launch_bounds__(KT) void fin_split(KmArgs a) {
-    __shared__ double tmp[KT];
+__global__ __launch_bounds__(FT) void fin_split(KmArgs a) {
+    __shared__ double tmp[FT];
     __shared__ double res[4 + 4 * FHD_MAX_RHO];
     const int job = blockIdx.x, rho = a.rho;
     int* ji = a.ji + job * JI_W;
     reduce_records(
-        a.part, ji[JI_FIRST], ji[JI_NBLK], a.pw, 0, 4 + 4 * rho,
+        a.part, ji[JI_FIRST], ji[JI_NBLK], a.pst, 0, 4 + 4 * rho,
         [rho](int e) {
             if (e < 4) return 0;
             const int q = (e - 4) / rho;
@@ -774,6 +846,7 @@ int point_stride(int rho) {
     return lanes_per_point(rho) * DPL;
 }
 
+// points per block: 16 lane groups of four waves
 long long chunk_points(int rho) { return (long long)KITERS * KWAVES * (64 / lanes_per_point(rho)); }
 
 int max_jobs(int K, int images) { return images * std::max(2 * K, 4); }
@@ -790,8 +863,11 @@ struct KmBuffers {
     int4* btab;
     int* blkA;
     double* part;
+    double* part2;
+    double* cst;
+    int* jstop;
     int* ji;
-    double *jm, *ca, *cb, *la, *lb, *fa, *fb, *jd;
+    double *jm, *ca, *cb, *fa, *fb, *jd;
     long long maxBlocks;
     int maxJobs;
 };
@@ -806,9 +882,12 @@ KmBuffers carve(Arena& ws, long long N, int rho, int K, int images) {
     }
     b.btab = ws.take<int4>((size_t)b.maxBlocks);
     b.blkA = ws.take<int>((size_t)b.maxBlocks);
-    b.part = ws.take<double>((size_t)b.maxBlocks * record_width(rho));
+    b.part = ws.take<double>((size_t)b.maxBlocks * record_width(rho));  // entry-major, stride maxBlocks
+    b.part2 = ws.take<double>((size_t)b.maxBlocks * record_width(rho));
+    b.cst = ws.take<double>((size_t)3 * b.maxJobs * 2 * rho);
+    b.jstop = ws.take<int>((size_t)2 * b.maxJobs);
     b.ji = ws.take<int>((size_t)b.maxJobs * JI_W);
-    double** dv[] = {&b.jm, &b.ca, &b.cb, &b.la, &b.lb, &b.fa, &b.fb};
+    double** dv[] = {&b.jm, &b.ca, &b.cb, &b.fa, &b.fb};
     for (double** p : dv) *p = ws.take<double>((size_t)b.maxJobs * rho);
     b.jd = ws.take<double>((size_t)b.maxJobs * JD_W);
     return b;
@@ -822,7 +901,7 @@ void launch_lp(int which, dim3 g, hipStream_t s, const KmArgs& a, int arg) {
         case P_STATS: hipLaunchKernelGGL((km_stats<LP, D>), g, dim3(KT), 0, s, a); break;
         case P_SSE1: hipLaunchKernelGGL((km_sse1<LP, D>), g, dim3(KT), 0, s, a); break;
         case P_FAR: hipLaunchKernelGGL((km_far<LP, D>), g, dim3(KT), 0, s, a, arg); break;
-        case P_LLOYD: hipLaunchKernelGGL((km_lloyd<LP, D>), g, dim3(KT), 0, s, a); break;
+        case P_LLOYD: hipLaunchKernelGGL((km_lloyd<LP, D>), g, dim3(KT), 0, s, a, arg); break;
         case P_SPLIT: hipLaunchKernelGGL((km_split<LP, D>), g, dim3(KT), 0, s, a); break;
         default: hipLaunchKernelGGL((km_scatter<LP, D>), g, dim3(KT), 0, s, a); break;
     }
@@ -914,13 +993,15 @@ void kmeans_run_batch(Ctx& c, Arena& ws, const float* guide, int rho, int images
     a.jm = B.jm;
     a.ca = B.ca;
     a.cb = B.cb;
-    a.la = B.la;
-    a.lb = B.lb;
+    a.part2 = B.part2;
+    a.cst = B.cst;
+    a.jstop = B.jstop;
+    a.mj = B.maxJobs;
     a.fa = B.fa;
     a.fb = B.fb;
     a.jd = B.jd;
     a.rho = rho;
-    a.pw = record_width(rho);
+    a.pst = B.maxBlocks;
     a.ps = point_stride(rho);
 
     hipEvent_t t_begin = c.stage_begin();
@@ -948,7 +1029,7 @@ void kmeans_run_batch(Ctx& c, Arena& ws, const float* guide, int rho, int images
             for (int q = 0; q < nblk; ++q) {
                 const int s0 = L.start + (int)(q * CH);
                 const int cnt = (int)std::min<long long>(CH, L.count - q * CH);
-                H.btab[nb++] = make_int4((int)j, s0, cnt, label ? (*label)[j] : q);
+                H.btab[nb++] = make_int4((int)j | (L.buf << 30), s0, cnt, label ? (*label)[j] : q);
             }
             if (with_mean)
                 for (int t = 0; t < rho; ++t) H.jm[j * rho + t] = L.mean[t];
@@ -981,9 +1062,9 @@ void kmeans_run_batch(Ctx& c, Arena& ws, const float* guide, int rho, int images
         const int nb = upload(roots, false, nullptr);
         const dim3 gj((unsigned)images);
         launch_pass(rho, P_STATS, dim3(nb), st, a);
-        hipLaunchKernelGGL(fin_stats, gj, dim3(KT), 0, st, a);
+        hipLaunchKernelGGL(fin_stats, gj, dim3(FT), 0, st, a);
         launch_pass(rho, P_SSE1, dim3(nb), st, a);
-        hipLaunchKernelGGL(fin_sse1, gj, dim3(KT), 0, st, a);
+        hipLaunchKernelGGL(fin_sse1, gj, dim3(FT), 0, st, a);
         FHD_HIP(hipGetLastError());
         FHD_HIP(hipMemcpyAsync(H.jm, B.jm, sizeof(double) * rho * images, hipMemcpyDeviceToHost, st));
         FHD_HIP(hipMemcpyAsync(H.jd, B.jd, sizeof(double) * JD_W * images, hipMemcpyDeviceToHost, st));
@@ -1034,12 +1115,10 @@ void kmeans_run_batch(Ctx& c, Arena& ws, const float* guide, int rho, int images
             hipLaunchKernelGGL(fin_far, gj, dim3(KT), 0, st, a, 0);
             launch_pass(rho, P_FAR, g, st, a, 1);
             hipLaunchKernelGGL(fin_far, gj, dim3(KT), 0, st, a, 1);
-            for (int it = 0; it < max_iter; ++it) {
-                launch_pass(rho, P_LLOYD, g, st, a);
-                hipLaunchKernelGGL(fin_lloyd, gj, dim3(KT), 0, st, a, max_iter);
-            }
+            for (int it = 0; it < max_iter; ++it) launch_pass(rho, P_LLOYD, g, st, a, it);
+            hipLaunchKernelGGL(fin_lloyd, gj, dim3(FT), 0, st, a, max_iter);
             launch_pass(rho, P_SPLIT, g, st, a);
-            hipLaunchKernelGGL(fin_split, gj, dim3(KT), 0, st, a);
+            hipLaunchKernelGGL(fin_split, gj, dim3(FT), 0, st, a);
             launch_pass(rho, P_SCATTER, g, st, a);
             FHD_HIP(hipGetLastError());
             const size_t J = jobs.size();
