@@ -449,9 +449,9 @@ __device__ __forceinline__ void col_finish(const FA& a, int x, int y0, int g, co
 
 // Column pass.  A block owns a tile of TXC columns x ty rows; for every
 // plane (cluster l, channel) in turn it stages the tile's rows plus the 2S
-// halo rows in LDS (double-buffered: the next plane's rows are in flight from
-// global memory while the current one is filtered), and every thread filters
-// R consecutive rows of one column from a register window.
+// halo rows in LDS (the next plane's rows are in flight from global memory
+// into registers while the current one is filtered), and every thread
+// filters R consecutive rows of one column from a register window.
 __device__ __forceinline__ int plane_index(int n, int g, int l, int c) {
     const int gi = g * CG + c;
     return l * (n + 1) + (gi == 0 ? n : gi - 1);
@@ -507,7 +507,7 @@ __device__ __forceinline__ void col_gauss_body(const FA& a, int blk) {
     constexpr int ROWS = TY + 2 * S;
     constexpr int PER = (ROWS * TXC + RT - 1) / RT;  // staged values per thread and plane
     constexpr int WIN = R + 2 * S;
-    __shared__ float tbuf[2][PER * RT];
+    __shared__ float tbuf[PER * RT];
     extern __shared__ float sp[];
     const ColTile tile = col_tile(a, TY, blk);
     if (!tile.block_active) return;
@@ -540,33 +540,40 @@ __device__ __forceinline__ void col_gauss_body(const FA& a, int blk) {
     int ph, sg, sl, sc;  // the plane staged next
     seq.start(ph, sg, sl, sc);
     fetch(plane_index(n, sg, sl, sc), pre);
-    stash(tbuf[0], pre);
+    stash(tbuf, pre);
     __syncthreads();
-    int buf = 0;
-    // filter the staged plane (tile row ly0 + q holds image row y0 - S + q),
-    // queue the following one, and add h_l times the result to acc
-    auto consume = [&](const float (&hl)[R], float (&acc)[R]) {
+    // filter the staged plane (tile row ly0 + q holds image row y0 - S + q)
+    // into s and queue the following one
+    auto filter_plane = [&](float (&s)[R]) {
         int nph = ph, ng = sg, nl = sl, nc = sc;
         const bool more = seq.next(nph, ng, nl, nc);
         if (more) fetch(plane_index(n, ng, nl, nc), pre);
-        const float* col = tbuf[buf] + ly0 * TXC + lx;
+        const float* col = tbuf + ly0 * TXC + lx;
         float win[WIN];
 #pragma unroll
         for (int q = 0; q < WIN; ++q) win[q] = col[q * TXC];
 #pragma unroll
         for (int t = 0; t < R; ++t) {
-            float s = a.w[0] * win[t + S];
+            float v = a.w[0] * win[t + S];
 #pragma unroll
-            for (int j = 1; j <= S; ++j) s = fmaf(a.w[j], win[t + S - j] + win[t + S + j], s);
-            acc[t] = fmaf(hl[t], s, acc[t]);
+            for (int j = 1; j <= S; ++j) v = fmaf(a.w[j], win[t + S - j] + win[t + S + j], v);
+            s[t] = v;
         }
-        if (more) stash(tbuf[buf ^ 1], pre);
+        // one LDS copy of a plane: the next plane waits in registers while
+        // this one is filtered
         __syncthreads();
-        buf ^= 1;
+        if (more) stash(tbuf, pre);
+        __syncthreads();
         ph = nph;
         sg = ng;
         sl = nl;
         sc = nc;
+    };
+    auto consume = [&](const float (&hl)[R], float (&acc)[R]) {
+        float s[R];
+        filter_plane(s);
+#pragma unroll
+        for (int t = 0; t < R; ++t) acc[t] = fmaf(hl[t], s[t], acc[t]);
     };
     float dv[R];
     if (seq.part != 0) {  // the normaliser, for this part's own division
@@ -587,13 +594,34 @@ __device__ __forceinline__ void col_gauss_body(const FA& a, int blk) {
         for (int c = 0; c < CG; ++c)
 #pragma unroll
             for (int t = 0; t < R; ++t) acc[c][t] = 0.0f;
+        const int nc = min(CG, n + 1 - g * CG);  // channels of this group
         for (int l = 0; l < K; ++l) {
             float hl[R];
             recomb_weights<R, MODE>(a, l, x, y0, ly0, lx, TY, sp, lab, hl);
+            // one copy of the plane loop (a uniform switch picks the
+            // accumulator), so only one window is ever live
+#pragma unroll 1
+            for (int c = 0; c < nc; ++c) {
+                float s[R];
+                filter_plane(s);
+                switch (c) {
+                    case 0:
 #pragma unroll
-            for (int c = 0; c < CG; ++c) {
-                if (g * CG + c > n) break;
-                consume(hl, acc[c]);
+                        for (int t = 0; t < R; ++t) acc[0][t] = fmaf(hl[t], s[t], acc[0][t]);
+                        break;
+                    case 1:
+#pragma unroll
+                        for (int t = 0; t < R; ++t) acc[1][t] = fmaf(hl[t], s[t], acc[1][t]);
+                        break;
+                    case 2:
+#pragma unroll
+                        for (int t = 0; t < R; ++t) acc[2][t] = fmaf(hl[t], s[t], acc[2][t]);
+                        break;
+                    default:
+#pragma unroll
+                        for (int t = 0; t < R; ++t) acc[3][t] = fmaf(hl[t], s[t], acc[3][t]);
+                        break;
+                }
             }
         }
         if (tile.active) col_finish<R>(a, x, y0, g, acc, dv);
