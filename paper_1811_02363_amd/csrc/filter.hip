@@ -722,7 +722,7 @@ __device__ __forceinline__ void col_adj_body(const FA& a, int blk) {
     constexpr int ROWS = TY + 2 * S;
     constexpr int PER = (ROWS * TXC + RT - 1) / RT;
     constexpr int WIN = R + 2 * S;
-    __shared__ float tbuf[2][PER * RT];
+    __shared__ float tbuf[PER * RT];
     const ColTile tile = col_tile(a, TY, blk);
     if (!tile.block_active) return;
     const int n = a.n, K = a.K;
@@ -745,9 +745,8 @@ __device__ __forceinline__ void col_adj_body(const FA& a, int blk) {
     };
     float pre[PER];
     fetch(plane_index(n, 0, 0, 0), pre);
-    stash(tbuf[0], pre);
+    stash(tbuf, pre);
     __syncthreads();
-    int buf = 0;
     const int groups = (n + 1 + CG - 1) / CG;
     const bool act = tile.active;
     for (int g = 0; g < groups; ++g) {
@@ -793,28 +792,42 @@ __device__ __forceinline__ void col_adj_body(const FA& a, int blk) {
                             ? a.Cpl[(long long)l * a.Np + (long long)(y0 + t) * a.Wp + x]
                             : 0.0f;
             }
+            // one copy of the plane loop (a uniform switch picks the
+            // channel's registers), one LDS copy of a plane
+            auto upd = [&](const float (&v)[R], float (&fb)[R], int gi, const float (&sv)[R]) {
 #pragma unroll
-            for (int c = 0; c < CG; ++c) {
-                const int gi = g * CG + c;
-                if (gi > n) break;
+                for (int t = 0; t < R; ++t) {
+                    acc[t] = fmaf(v[t], sv[t], acc[t]);
+                    if (MODE == AM_GAMMA && gi > 0) fb[t] = fmaf(cl[t], sv[t], fb[t]);
+                }
+            };
+            const int nch = min(CG, n + 1 - g * CG);
+#pragma unroll 1
+            for (int c = 0; c < nch; ++c) {
                 int ng = g, nl = l, nc = c;
                 const bool more = plane_next(n, K, ng, nl, nc);
                 if (more) fetch(plane_index(n, ng, nl, nc), pre);
-                const float* col = tbuf[buf] + ly0 * TXC + lx;
+                const float* col = tbuf + ly0 * TXC + lx;
                 float win[WIN];
 #pragma unroll
                 for (int q = 0; q < WIN; ++q) win[q] = col[q * TXC];
+                float sv[R];
 #pragma unroll
                 for (int t = 0; t < R; ++t) {
-                    float s = a.w[0] * win[t + S];
+                    float v = a.w[0] * win[t + S];
 #pragma unroll
-                    for (int j = 1; j <= S; ++j) s = fmaf(a.w[j], win[t + S - j] + win[t + S + j], s);
-                    acc[t] = fmaf(vec[c][t], s, acc[t]);
-                    if (MODE == AM_GAMMA && gi > 0) fbar[c][t] = fmaf(cl[t], s, fbar[c][t]);
+                    for (int j = 1; j <= S; ++j) v = fmaf(a.w[j], win[t + S - j] + win[t + S + j], v);
+                    sv[t] = v;
                 }
-                if (more) stash(tbuf[buf ^ 1], pre);
+                switch (c) {
+                    case 0: upd(vec[0], fbar[0], g * CG, sv); break;
+                    case 1: upd(vec[1], fbar[1], g * CG + 1, sv); break;
+                    case 2: upd(vec[2], fbar[2], g * CG + 2, sv); break;
+                    default: upd(vec[3], fbar[3], g * CG + 3, sv); break;
+                }
                 __syncthreads();
-                buf ^= 1;
+                if (more) stash(tbuf, pre);
+                __syncthreads();
             }
             if (act) {
                 float* dst = (MODE == AM_BETA ? a.beta : a.gamma) + (long long)l * a.Np + (long long)y0 * a.Wp + x;
