@@ -73,10 +73,40 @@ __device__ __forceinline__ int pidx(int i) { return i + (i >> 3); }
 // Row pass, phase 1: the convolved factor g_l (c_l or b_l) and f on the halo
 // run [x0 - S, x0 + tx + S) of row y, zero outside the image, into LDS:
 //   cs[l * csp + pidx(h)], fs[ch * csp + pidx(h)].
-// Inline weights (rho <= RHO_INLINE, K <= KMAX_INLINE): one thread per halo
-// pixel computes b_m = phi(mu_m - p) for every center and accumulates
-// c = A^+ b in registers (A^+ read from LDS as broadcasts).
+// Inline weights (rho <= RHO_INLINE, K <= KMAX_INLINE): b_m = phi(mu_m - p)
+// for every halo pixel and center, and c = A^+ b on the matrix cores.
 constexpr int KMAX_INLINE = 32;
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// c = A^+ b for 32 consecutive pixels of a run on the matrix cores, one wave:
+// C[i][l] = sum_m b_m(pixel i) A^+[m][l] as 16 steps of a 32 x 32 x 2 FP32
+// product.  Lane j supplies b for pixel j % 32 and center 2s + j / 32 (the
+// A operand of step s) and A^+[2s + j / 32][j % 32] (the B operand, from
+// the zero-padded copy sP); it receives C[i][j % 32] for the 16 rows
+// i = 8 (r / 4) + 4 (j / 32) + r % 4, r < 16.
+__device__ __forceinline__ f32x16 inline_coef_mfma(const FA& a, const float (&pr)[RHO_INLINE], bool in,
+                                                   const float* smu, const float* sP) {
+    const int kh = (threadIdx.x & 63) >> 5, pl = threadIdx.x & 31;
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+#pragma unroll 4
+    for (int s = 0; s < KMAX_INLINE / 2; ++s) {
+        const int m = 2 * s + kh;
+        if (2 * s >= a.K) break;  // uniform
+        float d2 = 0.0f;
+#pragma unroll
+        for (int r = 0; r < RHO_INLINE; ++r) {  // padded entries are 0 - 0
+            const float d = pr[r] - smu[m * RHO_INLINE + r];
+            d2 = fmaf(d, d, d2);
+        }
+        const float b = (in && m < a.K) ? __expf(-d2 * a.inv2s2) : 0.0f;
+        const float pm = m < a.K ? sP[m * KMAX_INLINE + pl] : 0.0f;  // columns >= K are zero in sP
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b, pm, acc, 0, 0, 0);
+    }
+    return acc;
+}
 
 __device__ void row_factors(const FA& a, int y, int x0, int hw, int csp, float* cs, float* fs,
                             float* smu, float* sP) {
@@ -125,40 +155,44 @@ __device__ void row_factors(const FA& a, int y, int x0, int hw, int csp, float* 
     }
     __syncthreads();
     const bool hard = a.coef == FHD_COEF_HARD || a.factor_b;  // the factor is b itself
-    for (int h = threadIdx.x; h < hw; h += RT) {
+    if (hard) {
+        for (int h = threadIdx.x; h < hw; h += RT) {
+            const int x = x0 - a.S + h;
+            const bool in = x >= 0 && x < a.W;
+            float pr[RHO_INLINE];
+#pragma unroll
+            for (int r = 0; r < RHO_INLINE; ++r)
+                pr[r] = (in && r < rho) ? a.p[(long long)r * a.N + rowoff + x] : 0.0f;
+            for (int m = 0; m < K; ++m) {
+                float d2 = 0.0f;
+#pragma unroll
+                for (int r = 0; r < RHO_INLINE; ++r) {  // padded entries are 0 - 0
+                    const float d = pr[r] - smu[m * RHO_INLINE + r];
+                    d2 = fmaf(d, d, d2);
+                }
+                cs[m * csp + pidx(h)] = in ? __expf(-d2 * a.inv2s2) : 0.0f;
+            }
+        }
+        __syncthreads();
+        return;
+    }
+    // c = A^+ b: each wave takes runs of 32 halo pixels
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int pl = lane & 31, kh = lane >> 5;
+    for (int g0 = wave * 32; g0 < hw; g0 += (RT / 64) * 32) {
+        const int h = g0 + pl;
         const int x = x0 - a.S + h;
-        const bool in = x >= 0 && x < a.W;
+        const bool in = h < hw && x >= 0 && x < a.W;
         float pr[RHO_INLINE];
 #pragma unroll
         for (int r = 0; r < RHO_INLINE; ++r)
             pr[r] = (in && r < rho) ? a.p[(long long)r * a.N + rowoff + x] : 0.0f;
-        float c[KMAX_INLINE];
+        const f32x16 acc = inline_coef_mfma(a, pr, in, smu, sP);
+        if (pl < K) {
 #pragma unroll
-        for (int l = 0; l < KMAX_INLINE; ++l) c[l] = 0.0f;
-        for (int m = 0; m < K; ++m) {
-            float d2 = 0.0f;
-#pragma unroll
-            for (int r = 0; r < RHO_INLINE; ++r) {  // padded entries are 0 - 0
-                const float d = pr[r] - smu[m * RHO_INLINE + r];
-                d2 = fmaf(d, d, d2);
-            }
-            const float b = in ? __expf(-d2 * a.inv2s2) : 0.0f;
-            if (hard) {
-                cs[m * csp + pidx(h)] = b;
-            } else {
-                const float* prow = sP + m * KMAX_INLINE;  // P symmetric: column m = row m
-#pragma unroll
-                for (int l = 0; l < KMAX_INLINE; ++l) c[l] = fmaf(prow[l], b, c[l]);
-            }
-        }
-        if (!hard) {
-            if (K == KMAX_INLINE) {
-#pragma unroll
-                for (int l = 0; l < KMAX_INLINE; ++l) cs[l * csp + pidx(h)] = c[l];
-            } else {
-#pragma unroll
-                for (int l = 0; l < KMAX_INLINE; ++l)
-                    if (l < K) cs[l * csp + pidx(h)] = c[l];
+            for (int r = 0; r < 16; ++r) {
+                const int hh = g0 + 8 * (r >> 2) + 4 * kh + (r & 3);
+                if (hh < hw) cs[pl * csp + pidx(hh)] = acc[r];
             }
         }
     }
