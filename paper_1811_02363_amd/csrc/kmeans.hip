@@ -857,6 +857,28 @@ long long max_blocks(long long N, int rho, int K, int images) {
 
 int record_width(int rho) { return 4 * rho + 8; }
 
+// The job tables exchanged with the host every round, in one layout shared
+// by the pinned host staging and its device mirror, so that each direction
+// is one copy: [btab | ji | jm | ca | cb | jd], each part 256-byte aligned.
+struct TableLayout {
+    size_t btab, ji, jm, ca, cb, jd, end;
+    TableLayout(long long maxBlocks, int maxJobs, int rho) {
+        size_t off = 0;
+        auto take = [&](size_t bytes) {
+            const size_t o = off;
+            off += align_up(bytes, 256);
+            return o;
+        };
+        btab = take(sizeof(int4) * maxBlocks);
+        ji = take(sizeof(int) * maxJobs * JI_W);
+        jm = take(sizeof(double) * maxJobs * rho);
+        ca = take(sizeof(double) * maxJobs * rho);
+        cb = take(sizeof(double) * maxJobs * rho);
+        jd = take(sizeof(double) * maxJobs * JD_W);
+        end = off;
+    }
+};
+
 struct KmBuffers {
     float* pts[2];
     int* idx[2];
@@ -868,6 +890,7 @@ struct KmBuffers {
     int* jstop;
     int* ji;
     double *jm, *ca, *cb, *fa, *fb, *jd;
+    char* tables;  // device mirror of the host staging (TableLayout)
     long long maxBlocks;
     int maxJobs;
 };
@@ -880,16 +903,22 @@ KmBuffers carve(Arena& ws, long long N, int rho, int K, int images) {
         b.pts[q] = ws.take<float>((size_t)N * point_stride(rho) + 64);
         b.idx[q] = ws.take<int>((size_t)N);
     }
-    b.btab = ws.take<int4>((size_t)b.maxBlocks);
+    const TableLayout L(b.maxBlocks, b.maxJobs, rho);
+    b.tables = ws.take<char>(L.end);
+    char* t = b.tables;
+    b.btab = t ? reinterpret_cast<int4*>(t + L.btab) : nullptr;
+    b.ji = t ? reinterpret_cast<int*>(t + L.ji) : nullptr;
+    b.jm = t ? reinterpret_cast<double*>(t + L.jm) : nullptr;
+    b.ca = t ? reinterpret_cast<double*>(t + L.ca) : nullptr;
+    b.cb = t ? reinterpret_cast<double*>(t + L.cb) : nullptr;
+    b.jd = t ? reinterpret_cast<double*>(t + L.jd) : nullptr;
     b.blkA = ws.take<int>((size_t)b.maxBlocks);
     b.part = ws.take<double>((size_t)b.maxBlocks * record_width(rho));  // entry-major, stride maxBlocks
     b.part2 = ws.take<double>((size_t)b.maxBlocks * record_width(rho));
     b.cst = ws.take<double>((size_t)3 * b.maxJobs * 2 * rho);
     b.jstop = ws.take<int>((size_t)2 * b.maxJobs);
-    b.ji = ws.take<int>((size_t)b.maxJobs * JI_W);
-    double** dv[] = {&b.jm, &b.ca, &b.cb, &b.fa, &b.fb};
-    for (double** p : dv) *p = ws.take<double>((size_t)b.maxJobs * rho);
-    b.jd = ws.take<double>((size_t)b.maxJobs * JD_W);
+    b.fa = ws.take<double>((size_t)b.maxJobs * rho);
+    b.fb = ws.take<double>((size_t)b.maxJobs * rho);
     return b;
 }
 
@@ -961,25 +990,23 @@ void kmeans_run_batch(Ctx& c, Arena& ws, const float* guide, int rho, int images
     const long long CH = chunk_points(rho);
     hipStream_t st = c.stream;
 
-    const size_t stage_bytes = align_up(sizeof(int4) * B.maxBlocks, 256) + align_up(sizeof(int) * B.maxJobs * JI_W, 256) +
-                               3 * align_up(sizeof(double) * B.maxJobs * rho, 256) +
-                               align_up(sizeof(double) * B.maxJobs * JD_W, 256);
-    char* hs = static_cast<char*>(c.host_stage(0, stage_bytes));
+    const TableLayout TL(B.maxBlocks, B.maxJobs, rho);
+    char* hs = static_cast<char*>(c.host_stage(0, TL.end));
     Stage H;
-    {
-        size_t off = 0;
-        auto take = [&](size_t bytes) {
-            char* p = hs + off;
-            off += align_up(bytes, 256);
-            return p;
-        };
-        H.btab = reinterpret_cast<int4*>(take(sizeof(int4) * B.maxBlocks));
-        H.ji = reinterpret_cast<int*>(take(sizeof(int) * B.maxJobs * JI_W));
-        H.jm = reinterpret_cast<double*>(take(sizeof(double) * B.maxJobs * rho));
-        H.ca = reinterpret_cast<double*>(take(sizeof(double) * B.maxJobs * rho));
-        H.cb = reinterpret_cast<double*>(take(sizeof(double) * B.maxJobs * rho));
-        H.jd = reinterpret_cast<double*>(take(sizeof(double) * B.maxJobs * JD_W));
-    }
+    H.btab = reinterpret_cast<int4*>(hs + TL.btab);
+    H.ji = reinterpret_cast<int*>(hs + TL.ji);
+    H.jm = reinterpret_cast<double*>(hs + TL.jm);
+    H.ca = reinterpret_cast<double*>(hs + TL.ca);
+    H.cb = reinterpret_cast<double*>(hs + TL.cb);
+    H.jd = reinterpret_cast<double*>(hs + TL.jd);
+    // one copy per direction: host -> device covers btab and ji (and jm),
+    // device -> host covers jm, ca, cb and jd
+    auto to_device = [&](size_t upto) {
+        FHD_HIP(hipMemcpyAsync(B.tables, hs, upto, hipMemcpyHostToDevice, st));
+    };
+    auto to_host = [&](size_t from, size_t upto) {
+        FHD_HIP(hipMemcpyAsync(hs + from, B.tables + from, upto - from, hipMemcpyDeviceToHost, st));
+    };
 
     KmArgs a{};
     for (int q = 0; q < 2; ++q) {
@@ -1035,10 +1062,7 @@ void kmeans_run_batch(Ctx& c, Arena& ws, const float* guide, int rho, int images
                 for (int t = 0; t < rho; ++t) H.jm[j * rho + t] = L.mean[t];
         }
         FHD_REQUIRE(nb <= B.maxBlocks, FHD_EINVAL, "internal: block table overflow");
-        FHD_HIP(hipMemcpyAsync(B.btab, H.btab, sizeof(int4) * nb, hipMemcpyHostToDevice, st));
-        FHD_HIP(hipMemcpyAsync(B.ji, H.ji, sizeof(int) * JI_W * jobs.size(), hipMemcpyHostToDevice, st));
-        if (with_mean)
-            FHD_HIP(hipMemcpyAsync(B.jm, H.jm, sizeof(double) * rho * jobs.size(), hipMemcpyHostToDevice, st));
+        to_device(with_mean ? TL.jm + sizeof(double) * rho * jobs.size() : TL.ji + sizeof(int) * JI_W * jobs.size());
         return nb;
     };
 
@@ -1066,8 +1090,7 @@ void kmeans_run_batch(Ctx& c, Arena& ws, const float* guide, int rho, int images
         launch_pass(rho, P_SSE1, dim3(nb), st, a);
         hipLaunchKernelGGL(fin_sse1, gj, dim3(FT), 0, st, a);
         FHD_HIP(hipGetLastError());
-        FHD_HIP(hipMemcpyAsync(H.jm, B.jm, sizeof(double) * rho * images, hipMemcpyDeviceToHost, st));
-        FHD_HIP(hipMemcpyAsync(H.jd, B.jd, sizeof(double) * JD_W * images, hipMemcpyDeviceToHost, st));
+        to_host(TL.jm, TL.jd + sizeof(double) * JD_W * images);
         FHD_HIP(hipStreamSynchronize(st));
         for (int b = 0; b < images; ++b) {
             Leaf* r = roots[b];
@@ -1122,9 +1145,7 @@ void kmeans_run_batch(Ctx& c, Arena& ws, const float* guide, int rho, int images
             launch_pass(rho, P_SCATTER, g, st, a);
             FHD_HIP(hipGetLastError());
             const size_t J = jobs.size();
-            FHD_HIP(hipMemcpyAsync(H.ca, B.ca, sizeof(double) * rho * J, hipMemcpyDeviceToHost, st));
-            FHD_HIP(hipMemcpyAsync(H.cb, B.cb, sizeof(double) * rho * J, hipMemcpyDeviceToHost, st));
-            FHD_HIP(hipMemcpyAsync(H.jd, B.jd, sizeof(double) * JD_W * J, hipMemcpyDeviceToHost, st));
+            to_host(TL.ca, TL.jd + sizeof(double) * JD_W * J);
             FHD_HIP(hipStreamSynchronize(st));
             for (size_t j = 0; j < J; ++j) {
                 Leaf& L = *jobs[j];
