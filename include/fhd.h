@@ -197,7 +197,9 @@ fhd_status fhd_filter_batch(fhd_ctx* ctx, int B, const int* H, const int* W,
 /* Adjoint of fhd_filter_centers for least-squares coefficients (the paper
  * does not differentiate its filter; this is the exact gradient of the
  * computation of Algorithm 1 steps 2-5 with the centers held fixed).  Given
- * G = dL/dg_hat it returns dL/df, dL/dguide and dL/dsigma_r; the weights are
+ * G = dL/dg_hat it returns dL/df, dL/dguide, dL/dsigma_r and dL/dsigma_s
+ * (the spatial scale enters only through the window omega of eqs. (13)-(14):
+ * d omega / d sigma_s = omega |j|^2 / sigma_s^3, radius held fixed); the weights are
  * recomputed from the guide in FP32 (never stored by the forward call), so the
  * gradient is that of the FP32 contraction whatever `p->contract` says.  The
  * sigma_r term through A^+ holds the rank decision of the pseudo-inverse fixed
@@ -211,25 +213,30 @@ fhd_status fhd_filter_batch(fhd_ctx* ctx, int B, const int* H, const int* W,
  *            image (joint filtering of f by itself), dL/df is the sum of the
  *            two outputs.
  *   grad_sigma_r host, one double, or NULL.  Synchronises when non-NULL.
+ *   grad_sigma_s host, one double, or NULL (Gaussian window only, else
+ *            FHD_EUNSUPPORTED).  Synchronises when non-NULL; costs one more
+ *            row pass and column pass and one more K-plane set.
  * Gradient outputs must not alias inputs.  Workspace: five K-plane sets plus
  * the intermediate planes of the forward call. */
 fhd_status fhd_filter_backward(fhd_ctx* ctx, const float* f, int n, const float* guide, int rho,
                                int H, int W, const float* centers, int K, const fhd_params* p,
                                const float* out, const float* den, const float* grad_out,
-                               float* grad_f, float* grad_guide, double* grad_sigma_r);
+                               float* grad_f, float* grad_guide, double* grad_sigma_r,
+                               double* grad_sigma_s);
 
 /* Adjoint of fhd_filter_batch (least-squares coefficients), laid out like
  * it: centers host B x K x rho and K_eff host B as returned by the forward
  * call; out, den its outputs (den required); grad_out, grad_f, grad_guide
  * device in the layouts of f and guide (gradient outputs may be NULL);
- * grad_sigma_r host, the sum over the images, or NULL (synchronises when
- * non-NULL).  Same limits as fhd_filter_backward. */
+ * grad_sigma_r and grad_sigma_s host, the sums over the images, or NULL
+ * (synchronise when non-NULL; with grad_sigma_s the images' adjoints run one
+ * by one on the auxiliary streams).  Same limits as fhd_filter_backward. */
 fhd_status fhd_filter_batch_backward(fhd_ctx* ctx, int B, const int* H, const int* W,
                                      const long long* px_offset, const float* f, int n,
                                      const float* guide, int rho, const float* centers,
                                      const int* K_eff, const fhd_params* p, const float* out,
                                      const float* den, const float* grad_out, float* grad_f,
-                                     float* grad_guide, double* grad_sigma_r);
+                                     float* grad_guide, double* grad_sigma_r, double* grad_sigma_s);
 
 /* The brute-force filter of eqs. (1)-(2) on the GPU (FP32), the reference
  * the approximation is measured against.  out device n x H x W; den device

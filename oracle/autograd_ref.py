@@ -6,6 +6,7 @@ The paper does not differentiate its filter.  These plain PyTorch (CPU,
 float64) transcriptions of eqs. (1)-(2) and of Algorithm 1 with fixed
 centers let autograd provide reference gradients with respect to the image
 f, the guide p, sigma_r and sigma_s.  Centers are constants (stop-gradient).
+The window radius S is held fixed when sigma_s varies.
 """
 from __future__ import annotations
 
@@ -109,3 +110,20 @@ def sigma_r_shares(f, p, centers, sigma_s, sigma_r, S, G, spatial="gaussian", fu
     M = torch.autograd.functional.jacobian(pinv_of, s0)
     share_A = (C.grad * (B.detach() @ M.T)).sum(1)
     return share_b.numpy(), share_A.numpy()
+
+
+def sigma_s_shares(f, p, centers, sigma_s, sigma_r, S, G, spatial="gaussian", full_rank=True):
+    """Per-pixel split of dL/dsigma_s for L = <G, g>, in FP64: share(i) =
+    G(i) . dg(i)/dsigma_s, the derivative image taken in forward mode through
+    Algorithm 1 (the window's taps are the only dependence on sigma_s).  Their
+    sum is the total gradient; the sum of their magnitudes sizes the rounding
+    error of any evaluation of that total."""
+    f = torch.as_tensor(f, dtype=torch.float64)
+    p = torch.as_tensor(p, dtype=torch.float64)
+    s0 = torch.tensor(float(sigma_s), dtype=torch.float64)
+
+    def g_of(s):
+        return fast_filter_torch(f, p, centers, s, sigma_r, S, spatial, full_rank)[0]
+
+    _, dg = torch.autograd.functional.jvp(g_of, (s0,), (torch.ones((), dtype=torch.float64),))
+    return (torch.as_tensor(G, dtype=torch.float64) * dg).sum(0).numpy()

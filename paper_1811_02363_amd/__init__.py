@@ -102,10 +102,10 @@ def load():
             "fhd_pinv": (I, [V, I, I, D, D, V, V, P(I), P(D)]),
             "fhd_filter_centers": (I, [V, V, I, V, I, I, I, V, I, V, pp, V, V, pi]),
             "fhd_filter": (I, [V, V, I, V, I, I, I, pp, V, V, V, pi]),
-            "fhd_filter_backward": (I, [V, V, I, V, I, I, I, V, I, pp, V, V, V, V, V, P(D)]),
+            "fhd_filter_backward": (I, [V, V, I, V, I, I, I, V, I, pp, V, V, V, V, V, P(D), P(D)]),
             "fhd_filter_batch": (I, [V, I, V, V, V, V, I, V, I, pp, V, V, V, V, pi]),
             "fhd_filter_batch_backward": (I, [V, I, V, V, V, V, I, V, I, V, V, pp, V, V, V, V, V,
-                                              P(D)]),
+                                              P(D), P(D)]),
             "fhd_bruteforce": (I, [V, V, I, V, I, I, I, pp, V, V]),
             "fhd_nlm_guide": (I, [V, V, I, I, I, I, I, V, V]),
             "fhd_timing_enable": (I, [V, I]),
@@ -232,10 +232,12 @@ def filter_centers(f, guide, centers, sigma_s=3.0, sigma_r=0.1, spatial="gaussia
 
 
 def filter_backward(f, guide, centers, out, den, grad_out, sigma_s=3.0, sigma_r=0.1,
-                    spatial="gaussian", radius=None, need_f=True, need_guide=True, need_sigma_r=True):
+                    spatial="gaussian", radius=None, need_f=True, need_guide=True, need_sigma_r=True,
+                    need_sigma_s=False):
     """Adjoint of :func:`filter_centers` (least-squares coefficients): given
     G = dL/dg_hat and the forward call's (g_hat, r_hat), returns
-    (dL/df or None, dL/dguide or None, dL/dsigma_r as float or None)."""
+    (dL/df or None, dL/dguide or None, dL/dsigma_r as float or None), and
+    dL/dsigma_s as a fourth entry when ``need_sigma_s`` (Gaussian window)."""
     n, rho, H, W, g = _shape(f, guide)
     ctx = _ctx(f.device.index)
     c = torch.as_tensor(centers, dtype=torch.float32).detach().cpu().contiguous()
@@ -246,29 +248,33 @@ def filter_backward(f, guide, centers, out, den, grad_out, sigma_s=3.0, sigma_r=
     gf = torch.empty_like(f) if need_f else None
     gg = torch.empty_like(g) if need_guide else None
     gs = ctypes.c_double(0.0)
+    gss = ctypes.c_double(0.0)
     _check(load().fhd_filter_backward(
         ctx, _dev(f, "f"), n, _dev(g, "guide"), rho, H, W, ctypes.c_void_p(c.data_ptr()), K,
         ctypes.byref(p), _dev(out, "out"), _dev(den, "den"), _dev(grad_out, "grad_out"),
         _dev(gf, "grad_f") if gf is not None else None,
         _dev(gg, "grad_guide") if gg is not None else None,
-        ctypes.byref(gs) if need_sigma_r else None), ctx)
-    return gf, gg, (gs.value if need_sigma_r else None)
+        ctypes.byref(gs) if need_sigma_r else None,
+        ctypes.byref(gss) if need_sigma_s else None), ctx)
+    res = (gf, gg, (gs.value if need_sigma_r else None))
+    return res + (gss.value,) if need_sigma_s else res
 
 
 class FilterFunction(torch.autograd.Function):
     """g_hat = filter_centers(f, guide, centers) with gradients with respect to
-    f, guide and sigma_r (a 0-d tensor) from the library's adjoint; the
-    centers are constants.  Pass the same tensor as f and guide for joint
+    f, guide, sigma_r and sigma_s (0-d tensors; sigma_s with the Gaussian
+    window) from the library's adjoint; the centers are constants.  Pass the same tensor as f and guide for joint
     filtering of an image by itself: autograd adds the two contributions."""
 
     @staticmethod
     def forward(ctx, f, guide, sigma_r, centers, sigma_s, spatial, radius, contract):
-        sr = float(sigma_r)
-        out, den = filter_centers(f.detach(), guide.detach(), centers, sigma_s=sigma_s, sigma_r=sr,
+        sr, ss = float(sigma_r), float(sigma_s)
+        out, den = filter_centers(f.detach(), guide.detach(), centers, sigma_s=ss, sigma_r=sr,
                                   spatial=spatial, radius=radius, contract=contract, return_den=True)
         ctx.save_for_backward(f, guide, out, den)
-        ctx.conf = (centers, sigma_s, sr, spatial, radius)
+        ctx.conf = (centers, ss, sr, spatial, radius)
         ctx.sr_tensor = isinstance(sigma_r, torch.Tensor)
+        ctx.ss_tensor = isinstance(sigma_s, torch.Tensor)
         return out
 
     @staticmethod
@@ -276,21 +282,22 @@ class FilterFunction(torch.autograd.Function):
         f, guide, out, den = ctx.saved_tensors
         centers, sigma_s, sr, spatial, radius = ctx.conf
         need_f, need_g, need_s = ctx.needs_input_grad[0], ctx.needs_input_grad[1], ctx.needs_input_grad[2]
-        gf, gg, gs = filter_backward(f.detach(), guide.detach(), centers, out, den,
-                                     grad_out.contiguous(), sigma_s=sigma_s, sigma_r=sr,
-                                     spatial=spatial, radius=radius, need_f=need_f, need_guide=need_g,
-                                     need_sigma_r=need_s and ctx.sr_tensor)
-        gsr = None
-        if need_s and ctx.sr_tensor:
-            gsr = torch.tensor(gs, dtype=torch.float32)
-        return gf, gg, gsr, None, None, None, None, None
+        need_ss = ctx.needs_input_grad[4] and ctx.ss_tensor
+        res = filter_backward(f.detach(), guide.detach(), centers, out, den,
+                              grad_out.contiguous(), sigma_s=sigma_s, sigma_r=sr,
+                              spatial=spatial, radius=radius, need_f=need_f, need_guide=need_g,
+                              need_sigma_r=need_s and ctx.sr_tensor, need_sigma_s=need_ss)
+        gf, gg, gs = res[:3]
+        gsr = torch.tensor(gs, dtype=torch.float32) if need_s and ctx.sr_tensor else None
+        gss = torch.tensor(res[3], dtype=torch.float32) if need_ss else None
+        return gf, gg, gsr, None, gss, None, None, None
 
 
 def filter_autograd(f, guide=None, sigma_s=3.0, sigma_r=0.1, K=16, spatial="gaussian",
                     radius=None, contract="fp32", centers=None, kmeans_max_iter=20):
     """Differentiable Algorithm 1: the centers come from the bisecting K-means
     of the (detached) guide unless given, then :class:`FilterFunction`.
-    ``sigma_r`` may be a 0-d tensor that requires grad."""
+    ``sigma_r`` and ``sigma_s`` may be 0-d tensors that require grad."""
     g = f if guide is None else guide
     if centers is None:
         centers, _ = cluster(g.detach(), K, max_iter=kmeans_max_iter)
@@ -354,9 +361,10 @@ def filter_batch(flat_f, sizes, n, flat_guide=None, rho=None, sigma_s=3.0, sigma
 
 def filter_batch_backward(flat_f, sizes, n, centers, K_eff, out, den, grad_out, flat_guide=None,
                           rho=None, sigma_s=3.0, sigma_r=0.1, spatial="gaussian", radius=None,
-                          need_f=True, need_guide=True, need_sigma_r=True):
+                          need_f=True, need_guide=True, need_sigma_r=True, need_sigma_s=False):
     """Adjoint of :func:`filter_batch`: (dL/df flat or None, dL/dguide flat or
-    None, dL/dsigma_r summed over the images or None)."""
+    None, dL/dsigma_r summed over the images or None), and dL/dsigma_s summed
+    over the images as a fourth entry when ``need_sigma_s``."""
     B, Ha, Wa, Oa, N = _batch_arrays(sizes)
     g = flat_f if flat_guide is None else flat_guide
     rho = n if rho is None else rho
@@ -368,13 +376,16 @@ def filter_batch_backward(flat_f, sizes, n, centers, K_eff, out, den, grad_out, 
     gf = torch.empty_like(flat_f) if need_f else None
     gg = torch.empty_like(g) if need_guide else None
     gs = ctypes.c_double(0.0)
+    gss = ctypes.c_double(0.0)
     _check(load().fhd_filter_batch_backward(
         ctx, B, Ha, Wa, Oa, _dev(flat_f, "f"), n, _dev(g, "guide"), rho, ctypes.c_void_p(c.data_ptr()),
         keff, ctypes.byref(p), _dev(out, "out"), _dev(den, "den"), _dev(grad_out, "grad_out"),
         _dev(gf, "grad_f") if gf is not None else None,
         _dev(gg, "grad_guide") if gg is not None else None,
-        ctypes.byref(gs) if need_sigma_r else None), ctx)
-    return gf, gg, (gs.value if need_sigma_r else None)
+        ctypes.byref(gs) if need_sigma_r else None,
+        ctypes.byref(gss) if need_sigma_s else None), ctx)
+    res = (gf, gg, (gs.value if need_sigma_r else None))
+    return res + (gss.value,) if need_sigma_s else res
 
 
 def cluster(guide, K, max_iter=20, labels=False):

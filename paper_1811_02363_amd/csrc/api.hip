@@ -588,9 +588,11 @@ fhd_status fhd_filter(fhd_ctx* ctx, const float* f, int n, const float* guide, i
 fhd_status fhd_filter_backward(fhd_ctx* ctx, const float* f, int n, const float* guide, int rho, int H, int W,
                                const float* centers, int K, const fhd_params* p, const float* out,
                                const float* den, const float* grad_out, float* grad_f, float* grad_guide,
-                               double* grad_sigma_r) {
+                               double* grad_sigma_r, double* grad_sigma_s) {
     return guarded(ctx, [&](Ctx& c) {
         check_params(p, n, rho, H, W);
+        FHD_REQUIRE(grad_sigma_s == nullptr || p->spatial == FHD_SPATIAL_GAUSSIAN, FHD_EUNSUPPORTED,
+                    "dL/dsigma_s needs the Gaussian spatial kernel");
         FHD_REQUIRE(f && guide && centers && out && den && grad_out, FHD_EINVAL, "NULL pointer");
         FHD_REQUIRE(K >= 1 && K <= 64, FHD_EUNSUPPORTED, "the adjoint supports K in [1, 64]");
         FHD_REQUIRE(p->coef == FHD_COEF_LSQ, FHD_EUNSUPPORTED, "the adjoint covers least-squares coefficients");
@@ -606,7 +608,7 @@ fhd_status fhd_filter_backward(fhd_ctx* ctx, const float* f, int n, const float*
         FilterPlan fp = make_plan(*p, n, rho, H, W, K);
         fp.contract = FHD_CONTRACT_FP32;
         fp.materialize = true;
-        Arena ws = c.arena(adjoint_workspace(fp) + 4096);
+        Arena ws = c.arena(adjoint_workspace(fp, grad_sigma_s != nullptr) + 4096);
         std::vector<float> P32;
         (void)solve(centers, K, rho, p->sigma_r, p->pinv_rtol, P32);
         std::vector<double> M((size_t)K * K);
@@ -614,7 +616,7 @@ fhd_status fhd_filter_backward(fhd_ctx* ctx, const float* f, int n, const float*
         std::vector<float> M32(M.size());
         for (size_t q = 0; q < M.size(); ++q) M32[q] = (float)M[q];
         adjoint_run(c, ws, fp, f, guide, centers, P32.data(), M32.data(), out, den, grad_out, grad_f, grad_guide,
-                    grad_sigma_r);
+                    grad_sigma_r, grad_sigma_s);
     });
 }
 
@@ -726,10 +728,14 @@ fhd_status fhd_filter_batch(fhd_ctx* ctx, int B, const int* H, const int* W, con
 fhd_status fhd_filter_batch_backward(fhd_ctx* ctx, int B, const int* H, const int* W, const long long* px_offset,
                                      const float* f, int n, const float* guide, int rho, const float* centers,
                                      const int* K_eff, const fhd_params* p, const float* out, const float* den,
-                                     const float* grad_out, float* grad_f, float* grad_guide, double* grad_sigma_r) {
+                                     const float* grad_out, float* grad_f, float* grad_guide, double* grad_sigma_r,
+                                     double* grad_sigma_s) {
     return guarded(ctx, [&](Ctx& c) {
         const std::vector<long long> cnt = batch_counts(B, H, W, px_offset);
         for (int b = 0; b < B; ++b) check_params(p, n, rho, H[b], W[b]);
+        FHD_REQUIRE(grad_sigma_s == nullptr || p->spatial == FHD_SPATIAL_GAUSSIAN, FHD_EUNSUPPORTED,
+                    "dL/dsigma_s needs the Gaussian spatial kernel");
+        const bool with_s = grad_sigma_s != nullptr;
         FHD_REQUIRE(f && guide && centers && K_eff && out && den && grad_out, FHD_EINVAL, "NULL pointer");
         FHD_REQUIRE(p->coef == FHD_COEF_LSQ, FHD_EUNSUPPORTED, "the adjoint covers least-squares coefficients");
         const int K = p->K;
@@ -745,23 +751,24 @@ fhd_status fhd_filter_batch_backward(fhd_ctx* ctx, int B, const int* H, const in
                     FHD_EINVAL, "gradient outputs alias inputs or each other");
         std::vector<FilterPlan> plans(B);
         size_t passes = 0;
-        bool batched = true;
+        bool batched = !with_s;  // dL/dsigma_s: the per-image adjoints
         for (int b = 0; b < B; ++b) {
             FHD_REQUIRE(K_eff[b] >= 1 && K_eff[b] <= std::min(K, 64), FHD_EUNSUPPORTED,
                         "the adjoint supports K_eff in [1, min(K, 64)]");
             plans[b] = make_plan(*p, n, rho, H[b], W[b], K_eff[b]);
             plans[b].contract = FHD_CONTRACT_FP32;
             plans[b].materialize = true;
-            passes = std::max(passes, adjoint_passes_workspace(plans[b]));
+            passes = std::max(passes, adjoint_passes_workspace(plans[b], with_s));
             batched = batched && adjoint_batch_supported(plans[b]);
         }
         const size_t cb = adjoint_consts_bytes(K, rho);
         const int ns = std::min(B, Ctx::NAUX);
         passes = align_up(passes, 256);
         const size_t region = batched ? adjoint_batch_workspace(B, plans.data()) : ns * passes;
-        Arena ws = c.arena((size_t)B * cb + align_up(sizeof(double) * (B + 1), 256) + region + 4096);
+        Arena ws = c.arena((size_t)B * cb + 2 * align_up(sizeof(double) * (B + 1), 256) + region + 4096);
         char* dev = ws.take<char>((size_t)B * cb);
         double* sig = ws.take<double>((size_t)B + 1);
+        double* sigs = ws.take<double>((size_t)B + 1);
         char* hs = static_cast<char*>(c.host_stage(1, (size_t)B * cb));
         parallel_for(B, [&](int b) {
             const int Kb = K_eff[b];
@@ -812,14 +819,19 @@ fhd_status fhd_filter_batch_backward(fhd_ctx* ctx, int B, const int* H, const in
                                filter_consts_at(d, Kb, rho),
                                reinterpret_cast<const float*>(d + filter_consts_bytes(Kb, rho)), out + (size_t)n * o,
                                den + o, grad_out + (size_t)n * o, grad_f ? grad_f + (size_t)n * o : nullptr,
-                               grad_guide ? grad_guide + (size_t)rho * o : nullptr, sig + b);
+                               grad_guide ? grad_guide + (size_t)rho * o : nullptr, sig + b,
+                               with_s ? sigs + b : nullptr);
             }
         }
         if (grad_sigma_r != nullptr) {
             if (!batched) sum_doubles(c, sig, B, sig + B);
             FHD_HIP(hipMemcpyAsync(grad_sigma_r, sig + B, sizeof(double), hipMemcpyDeviceToHost, c.stream));
-            FHD_HIP(hipStreamSynchronize(c.stream));
         }
+        if (with_s) {
+            sum_doubles(c, sigs, B, sigs + B);
+            FHD_HIP(hipMemcpyAsync(grad_sigma_s, sigs + B, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+        }
+        if (grad_sigma_r != nullptr || with_s) FHD_HIP(hipStreamSynchronize(c.stream));
     });
 }
 

@@ -118,14 +118,16 @@ void filter_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, cons
                    const FilterConsts& kc, const int* labels, float* out, float* den);
 void bruteforce_run(Ctx& c, const FilterPlan& fp, const float* f, const float* guide,
                     float* out, float* den);
-size_t adjoint_workspace(const FilterPlan& fp);
+// with_s: also the dL/dsigma_s passes (one more K-plane set)
+size_t adjoint_workspace(const FilterPlan& fp, bool with_s);
 // constants of the adjoint: filter constants, then M = dA^+/dsigma_r (K x K)
 size_t adjoint_consts_bytes(int K, int rho);
-size_t adjoint_passes_workspace(const FilterPlan& fp);
-// writes the sigma_r gradient (one double) to sig_dev on the device
+size_t adjoint_passes_workspace(const FilterPlan& fp, bool with_s);
+// writes the sigma_r gradient (one double) to sig_dev on the device, and the
+// sigma_s gradient to sigs_dev when it is not null (Gaussian kernel only)
 void adjoint_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const float* guide,
                     const FilterConsts& kc, const float* Md, const float* out, const float* den,
-                    const float* gout, float* gradf, float* gradp, double* sig_dev);
+                    const float* gout, float* gradf, float* gradp, double* sig_dev, double* sigs_dev);
 // One launch per pass for the adjoint of all images of a batch (guides of at
 // most 8 dimensions, at most 32 clusters, radius 1..32); per-image pointers;
 // the sigma_r gradient summed over all images goes to sig_dev.
@@ -139,7 +141,8 @@ void adjoint_passes_batch(Ctx& c, Arena& ws, int B, const FilterPlan* plans, con
 void sum_doubles(Ctx& c, const double* v, int count, double* out_dev);
 void adjoint_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const float* guide,
                  const float* centers_host, const float* Pfp32_host, const float* M_host, const float* out,
-                 const float* den, const float* gout, float* gradf, float* gradp, double* gsig);
+                 const float* den, const float* gout, float* gradf, float* gradp, double* gsig,
+                 double* gsigs);
 
 // ---- nonlocal-means guide (nlm.hip) ----------------------------------------
 size_t nlm_workspace(int n, int H, int W, int m, int dims);

@@ -61,7 +61,10 @@ struct FA {
     long long N, Np;    // pixels; stride of the B / C planes
     long long Pp;       // stride of the intermediate planes: H + 2S rows of Wp, row y at y + S
     float inv2s2;       // 1 / (2 sigma_r^2), 0 for sigma_r = inf
-    float w[FHD_MAX_RADIUS + 1];  // 1-D spatial taps w[|j|]
+    float* betas;       // adjoint, dL/dsigma_s: K planes of Y . (d omega / d sigma_s) * (c_l [f, 1]), or null
+    int bacc;           // adjoint column pass: add to the output planes instead of overwriting
+    float w[FHD_MAX_RADIUS + 1];   // 1-D spatial taps w[|j|]
+    float wd[FHD_MAX_RADIUS + 1];  // their derivative d w[|j|] / d sigma_s = w j^2 / sigma_s^3
 };
 
 // LDS skew: one pad word after every R_ROW = 8 entries.  A thread's window
@@ -747,7 +750,9 @@ __global__ __launch_bounds__(RT) void col_generic(FA a) {
 //          (Z_l = w * (b_l Y): the adjoint of the convolution applied to
 //          dL/dQ_l = b_l Y; w is symmetric and zero-extended, so its adjoint is
 //          itself)
-enum { AM_BETA = 0, AM_GAMMA = 1 };
+// AM_BETAS: AM_BETA plus, for dL/dsigma_s, the same planes filtered with the
+// derivative taps (the column factor of d omega / d sigma_s) into a.betas
+enum { AM_BETA = 0, AM_GAMMA = 1, AM_BETAS = 2 };
 
 template <int S, int MODE>
 __device__ __forceinline__ void col_adj_body(const FA& a, int blk) {
@@ -795,7 +800,7 @@ __device__ __forceinline__ void col_adj_body(const FA& a, int blk) {
                 float v = 0.0f;
                 if (act && gi <= n && y0 + t < a.H) {
                     const long long off = (long long)(y0 + t) * a.W + x;
-                    if (MODE == AM_BETA) {
+                    if (MODE != AM_GAMMA) {
                         const float inv = 1.0f / a.gden[off];
                         if (ch < n) {
                             v = a.gout[(long long)ch * a.N + off] * inv;
@@ -818,20 +823,23 @@ __device__ __forceinline__ void col_adj_body(const FA& a, int blk) {
 #pragma unroll
             for (int t = 0; t < R; ++t) fbar[c][t] = 0.0f;
         for (int l = 0; l < K; ++l) {
-            float acc[R], cl[R];
+            float acc[R], cl[R], accd[R];
 #pragma unroll
             for (int t = 0; t < R; ++t) {
                 acc[t] = 0.0f;
+                accd[t] = 0.0f;
                 cl[t] = (MODE == AM_GAMMA && act && y0 + t < a.H)
                             ? a.Cpl[(long long)l * a.Np + (long long)(y0 + t) * a.Wp + x]
                             : 0.0f;
             }
             // one copy of the plane loop (a uniform switch picks the
             // channel's registers), one LDS copy of a plane
-            auto upd = [&](const float (&v)[R], float (&fb)[R], int gi, const float (&sv)[R]) {
+            auto upd = [&](const float (&v)[R], float (&fb)[R], int gi, const float (&sv)[R],
+                           const float (&sd)[R]) {
 #pragma unroll
                 for (int t = 0; t < R; ++t) {
                     acc[t] = fmaf(v[t], sv[t], acc[t]);
+                    if (MODE == AM_BETAS) accd[t] = fmaf(v[t], sd[t], accd[t]);
                     if (MODE == AM_GAMMA && gi > 0) fb[t] = fmaf(cl[t], sv[t], fb[t]);
                 }
             };
@@ -845,29 +853,43 @@ __device__ __forceinline__ void col_adj_body(const FA& a, int blk) {
                 float win[WIN];
 #pragma unroll
                 for (int q = 0; q < WIN; ++q) win[q] = col[q * TXC];
-                float sv[R];
+                float sv[R], sd[R];
 #pragma unroll
                 for (int t = 0; t < R; ++t) {
                     float v = a.w[0] * win[t + S];
 #pragma unroll
                     for (int j = 1; j <= S; ++j) v = fmaf(a.w[j], win[t + S - j] + win[t + S + j], v);
                     sv[t] = v;
+                    float vd = 0.0f;  // wd[0] = 0
+                    if (MODE == AM_BETAS) {
+#pragma unroll
+                        for (int j = 1; j <= S; ++j) vd = fmaf(a.wd[j], win[t + S - j] + win[t + S + j], vd);
+                    }
+                    sd[t] = vd;
                 }
                 switch (c) {
-                    case 0: upd(vec[0], fbar[0], g * CG, sv); break;
-                    case 1: upd(vec[1], fbar[1], g * CG + 1, sv); break;
-                    case 2: upd(vec[2], fbar[2], g * CG + 2, sv); break;
-                    default: upd(vec[3], fbar[3], g * CG + 3, sv); break;
+                    case 0: upd(vec[0], fbar[0], g * CG, sv, sd); break;
+                    case 1: upd(vec[1], fbar[1], g * CG + 1, sv, sd); break;
+                    case 2: upd(vec[2], fbar[2], g * CG + 2, sv, sd); break;
+                    default: upd(vec[3], fbar[3], g * CG + 3, sv, sd); break;
                 }
                 __syncthreads();
                 if (more) stash(tbuf, pre);
                 __syncthreads();
             }
             if (act) {
-                float* dst = (MODE == AM_BETA ? a.beta : a.gamma) + (long long)l * a.Np + (long long)y0 * a.Wp + x;
+                const long long off = (long long)l * a.Np + (long long)y0 * a.Wp + x;
+                float* dst = (MODE == AM_GAMMA ? a.gamma : a.beta) + off;
                 for (int t = 0; t < R && y0 + t < a.H; ++t) {
-                    *dst = (g == 0 ? 0.0f : *dst) + acc[t];
+                    *dst = ((g == 0 && !a.bacc) ? 0.0f : *dst) + acc[t];
                     dst += a.Wp;
+                }
+                if (MODE == AM_BETAS) {
+                    float* dd = a.betas + off;
+                    for (int t = 0; t < R && y0 + t < a.H; ++t) {
+                        *dd = (g == 0 ? 0.0f : *dd) + accd[t];
+                        dd += a.Wp;
+                    }
                 }
             }
         }
@@ -912,13 +934,13 @@ constexpr int KF = 32;
 
 __device__ __forceinline__ void adj_final_body(const FA& a, const float* __restrict__ Md, float sig3inv, int l0,
                                                int accumulate, float* __restrict__ gradp, double* part_slot,
-                                               int blk) {
+                                               double* parts_slot, int blk) {
     // column m of the block's rows of A^+ and M, zero-padded to KF rows, so
     // the unrolled loops below carry no bounds branches
     __shared__ float sP[64 * KF], sA[64 * KF];
     __shared__ float smu[KF * FHD_MAX_RHO];
     __shared__ float sall[64 * 8];  // every center, dims padded to 8 (weights inline)
-    __shared__ double red[RT / 64];
+    __shared__ double red[RT / 64], reds[RT / 64];
     const int K = a.K, rho = a.rho;
     // without B planes (guides of at most 8 dimensions) b_m is recomputed
     // here exactly as the weights pass and the inline row pass form it
@@ -971,7 +993,7 @@ __device__ __forceinline__ void adj_final_body(const FA& a, const float* __restr
         }
     }
     // weights w_l = dL/db_l * b_l (rows l >= kl of A^+ are zero, so pg[l] = 0 there)
-    double sig = 0.0;
+    double sig = 0.0, sigs = 0.0;
     float wsum = 0.0f;
 #pragma unroll
     for (int l = 0; l < KF; ++l) {
@@ -995,6 +1017,8 @@ __device__ __forceinline__ void adj_final_body(const FA& a, const float* __restr
             }
         }
         sig += (double)w * d2 * sig3inv + (double)gl * ac[l];
+        // dL/dsigma_s: b_l(i) Y(i) . ((d omega / d sigma_s) * (c_l [f, 1]))(i)
+        if (a.betas != nullptr && valid) sigs += (double)bl * a.betas[pl];
         pg[l] = w;  // reuse: w_l
         wsum += w;
     }
@@ -1011,20 +1035,31 @@ __device__ __forceinline__ void adj_final_body(const FA& a, const float* __restr
         }
     }
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) sig += __shfl_xor(sig, o, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sig;
+    for (int o = 1; o < 64; o <<= 1) {
+        sig += __shfl_xor(sig, o, 64);
+        sigs += __shfl_xor(sigs, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6] = sig;
+        reds[threadIdx.x >> 6] = sigs;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int q = 0; q < RT / 64; ++q) t += red[q];
+        double t = 0.0, ts = 0.0;
+        for (int q = 0; q < RT / 64; ++q) {
+            t += red[q];
+            ts += reds[q];
+        }
         *part_slot = t;
+        if (parts_slot != nullptr) *parts_slot = ts;
     }
 }
 
 __global__ __launch_bounds__(RT) void adj_final(FA a, const float* __restrict__ Md, float sig3inv, int l0,
                                                 int accumulate, float* __restrict__ gradp,
-                                                double* __restrict__ part) {
-    adj_final_body(a, Md, sig3inv, l0, accumulate, gradp, part + blockIdx.x, (int)blockIdx.x);
+                                                double* __restrict__ part, double* __restrict__ parts) {
+    adj_final_body(a, Md, sig3inv, l0, accumulate, gradp, part + blockIdx.x,
+                   parts != nullptr ? parts + blockIdx.x : nullptr, (int)blockIdx.x);
 }
 
 // one launch for every image (at most 32 clusters: a single cluster range);
@@ -1034,7 +1069,7 @@ __global__ __launch_bounds__(RT) void adj_final_batch(const FA* __restrict__ fas
     int b;
     const int t = batch_block(pre, B, b);
     const FA& a = fas[b];
-    adj_final_body(a, a.Md, sig3inv, 0, 0, a.gradp, part + blockIdx.x, t);
+    adj_final_body(a, a.Md, sig3inv, 0, 0, a.gradp, part + blockIdx.x, nullptr, t);
 }
 
 __global__ __launch_bounds__(RT) void sum_blocks(const double* __restrict__ part, int nb, double* __restrict__ out) {
@@ -1400,15 +1435,16 @@ struct BatchTables<0> {
 
 template <int S>
 struct AdjTables {
-    static void fill(KernFn (*adj)[2]) {
+    static void fill(KernFn (*adj)[3]) {
         adj[S][AM_BETA] = col_adj<S, AM_BETA>;
         adj[S][AM_GAMMA] = col_adj<S, AM_GAMMA>;
+        adj[S][AM_BETAS] = col_adj<S, AM_BETAS>;
         AdjTables<S - 1>::fill(adj);
     }
 };
 template <>
 struct AdjTables<0> {
-    static void fill(KernFn (*)[2]) {}
+    static void fill(KernFn (*)[3]) {}
 };
 
 template <int S>
@@ -1427,14 +1463,14 @@ struct AdjBatchTables<0> {
 struct Dispatch {
     KernFn row[MAXS_T + 1];
     KernFn col[MAXS_T + 1][3];
-    KernFn adj[MAXS_T + 1][2];
+    KernFn adj[MAXS_T + 1][3];
     BatchFn rowb[MAXS_T + 1];
     BatchFn colb[MAXS_T + 1][3];
     BatchFn adjb[MAXS_T + 1][2];
     Dispatch() {
         row[0] = nullptr;
         col[0][0] = col[0][1] = col[0][2] = nullptr;
-        adj[0][0] = adj[0][1] = nullptr;
+        adj[0][0] = adj[0][1] = adj[0][2] = nullptr;
         rowb[0] = nullptr;
         colb[0][0] = colb[0][1] = colb[0][2] = nullptr;
         Tables<MAXS_T>::fill(row, col);
@@ -1466,10 +1502,12 @@ FA make_args(const FilterPlan& fp) {
     a.Np = (long long)fp.H * fp.Wp;
     a.Pp = (long long)(fp.H + 2 * fp.S) * fp.Wp;
     a.inv2s2 = std::isinf(fp.sigma_r) ? 0.0f : (float)(1.0 / (2.0 * (double)fp.sigma_r * fp.sigma_r));
-    for (int j = 0; j <= fp.S; ++j)
-        a.w[j] = fp.spatial == FHD_SPATIAL_BOX
-                     ? 1.0f
-                     : (float)std::exp(-(double)j * j / (2.0 * (double)fp.sigma_s * fp.sigma_s));
+    for (int j = 0; j <= fp.S; ++j) {
+        const bool box = fp.spatial == FHD_SPATIAL_BOX;
+        const double s = fp.sigma_s, wj = box ? 1.0 : std::exp(-(double)j * j / (2.0 * s * s));
+        a.w[j] = (float)wj;
+        a.wd[j] = box ? 0.0f : (float)(wj * j * j / (s * s * s));
+    }
     return a;
 }
 
@@ -1748,22 +1786,23 @@ size_t adjoint_consts_bytes(int K, int rho) {
     return filter_consts_bytes(K, rho) + align_up(sizeof(float) * K * K, 256);
 }
 
-size_t adjoint_passes_workspace(const FilterPlan& fp) {
+size_t adjoint_passes_workspace(const FilterPlan& fp, bool with_s) {
     Arena probe;
     const long long Np = (long long)fp.H * fp.Wp;
     probe.take<float>(plane_floats(fp));
-    for (int q = 0; q < 4; ++q) probe.take<float>((size_t)fp.K * Np);
+    for (int q = 0; q < (with_s ? 5 : 4); ++q) probe.take<float>((size_t)fp.K * Np);
     probe.take<double>(2 * ((size_t)(fp.N + RT - 1) / RT) + 1);
+    if (with_s) probe.take<double>(2 * ((size_t)(fp.N + RT - 1) / RT) + 1);
     return probe.used;
 }
 
-size_t adjoint_workspace(const FilterPlan& fp) {
-    return adjoint_passes_workspace(fp) + adjoint_consts_bytes(fp.K, fp.rho) + 256;
+size_t adjoint_workspace(const FilterPlan& fp, bool with_s) {
+    return adjoint_passes_workspace(fp, with_s) + adjoint_consts_bytes(fp.K, fp.rho) + 512;
 }
 
 void adjoint_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const float* guide,
                  const float* centers_host, const float* Pfp32_host, const float* M_host, const float* out,
-                 const float* den, const float* gout, float* gradf, float* gradp, double* gsig) {
+                 const float* den, const float* gout, float* gradf, float* gradp, double* gsig, double* gsigs) {
     const size_t cb = adjoint_consts_bytes(fp.K, fp.rho);
     char* dev = ws.take<char>(cb);
     char* hs = static_cast<char*>(c.host_stage(1, cb));
@@ -1771,19 +1810,21 @@ void adjoint_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const 
     std::memcpy(hs + filter_consts_bytes(fp.K, fp.rho), M_host, sizeof(float) * fp.K * fp.K);
     FHD_HIP(hipMemcpyAsync(dev, hs, cb, hipMemcpyHostToDevice, c.stream));
     c.stage_done(1);
-    double* sig = ws.take<double>(1);
+    double* sig = ws.take<double>(2);
     adjoint_passes(c, ws, fp, f, guide, filter_consts_at(dev, fp.K, fp.rho),
                    reinterpret_cast<const float*>(dev + filter_consts_bytes(fp.K, fp.rho)), out, den, gout, gradf,
-                   gradp, sig);
-    if (gsig != nullptr) {
-        FHD_HIP(hipMemcpyAsync(gsig, sig, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+                   gradp, sig, gsigs != nullptr ? sig + 1 : nullptr);
+    if (gsig != nullptr || gsigs != nullptr) {
+        if (gsig != nullptr) FHD_HIP(hipMemcpyAsync(gsig, sig, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+        if (gsigs != nullptr)
+            FHD_HIP(hipMemcpyAsync(gsigs, sig + 1, sizeof(double), hipMemcpyDeviceToHost, c.stream));
         FHD_HIP(hipStreamSynchronize(c.stream));
     }
 }
 
 void adjoint_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const float* guide,
                     const FilterConsts& kc, const float* Md, const float* out, const float* den, const float* gout,
-                    float* gradf, float* gradp, double* sig_dev) {
+                    float* gradf, float* gradp, double* sig_dev, double* sigs_dev) {
     FHD_REQUIRE(fp.S >= 1 && fp.S <= MAXS_T, FHD_EUNSUPPORTED, "the adjoint supports radii 1..32");
     FHD_REQUIRE(fp.K <= 64, FHD_EUNSUPPORTED, "the adjoint supports K <= 64");
     FHD_REQUIRE(fp.coef == FHD_COEF_LSQ, FHD_EUNSUPPORTED, "the adjoint covers least-squares coefficients");
@@ -1796,6 +1837,11 @@ void adjoint_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, con
     float* gamma = ws.take<float>((size_t)fp.K * Np);
     const int nb = (int)((fp.N + RT - 1) / RT);
     double* part = ws.take<double>(2 * (size_t)nb + 1);
+    const bool with_s = sigs_dev != nullptr;
+    FHD_REQUIRE(!with_s || fp.spatial == FHD_SPATIAL_GAUSSIAN, FHD_EUNSUPPORTED,
+                "dL/dsigma_s needs the Gaussian spatial kernel");
+    float* betas = with_s ? ws.take<float>((size_t)fp.K * Np) : nullptr;
+    double* parts = with_s ? ws.take<double>(2 * (size_t)nb + 1) : nullptr;
     hipStream_t st = c.stream;
 
     FA a = make_args(fp);
@@ -1854,7 +1900,27 @@ void adjoint_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, con
     hipLaunchKernelGGL(rowk, rg, dim3(RT), lds, st, a);
     c.stage_end(FHD_STAGE_ROW, t0);
     t0 = c.stage_begin();
-    hipLaunchKernelGGL(dispatch().adj[fp.S][AM_BETA], cg, dim3(RT), 0, st, a);
+    if (with_s) {
+        // beta_l, and the first half of (d omega / d sigma_s) = w' (x) w + w (x) w':
+        // the column derivative taps on the same row-filtered planes
+        a.betas = betas;
+        hipLaunchKernelGGL(dispatch().adj[fp.S][AM_BETAS], cg, dim3(RT), 0, st, a);
+        c.stage_end(FHD_STAGE_COL, t0);
+        // the second half: row derivative taps, then the column taps, added
+        FA ad = a;
+        for (int j = 0; j <= fp.S; ++j) ad.w[j] = a.wd[j];
+        t0 = c.stage_begin();
+        hipLaunchKernelGGL(rowk, rg, dim3(RT), lds, st, ad);
+        c.stage_end(FHD_STAGE_ROW, t0);
+        FA ab = a;
+        ab.beta = betas;
+        ab.betas = nullptr;
+        ab.bacc = 1;
+        t0 = c.stage_begin();
+        hipLaunchKernelGGL(dispatch().adj[fp.S][AM_BETA], cg, dim3(RT), 0, st, ab);
+    } else {
+        hipLaunchKernelGGL(dispatch().adj[fp.S][AM_BETA], cg, dim3(RT), 0, st, a);
+    }
     c.stage_end(FHD_STAGE_COL, t0);
     // the adjoint convolution of dL/dQ_l = b_l Y
     a.fmode = 1;
@@ -1872,8 +1938,9 @@ void adjoint_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, con
     const int halves = (fp.K + KF - 1) / KF;
     for (int h = 0; h < halves; ++h)
         hipLaunchKernelGGL(adj_final, dim3(nb), dim3(RT), 0, st, a, Md, sig3inv, h * KF, h, gradp,
-                           part + (size_t)h * nb);
+                           part + (size_t)h * nb, with_s ? parts + (size_t)h * nb : nullptr);
     hipLaunchKernelGGL(sum_blocks, dim3(1), dim3(RT), 0, st, part, halves * nb, sig_dev);
+    if (with_s) hipLaunchKernelGGL(sum_blocks, dim3(1), dim3(RT), 0, st, parts, halves * nb, sigs_dev);
     FHD_HIP(hipGetLastError());
 }
 

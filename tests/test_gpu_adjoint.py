@@ -7,10 +7,10 @@ runs in FP32: each gradient entry sums (2S+1)^2 K products whose terms carry
 A^+ (cond(A) <= 2e4 in these cases, checked), so the FP32 rounding (6e-8 per
 operation) grows to about 1e-5..1e-4 relative; 1e-4 holds with a margin in
 these cases while still catching any dropped term (those change the gradient at the 1e-2..1
-level).  dL/dsigma_r is a sum over all pixels of per-pixel shares that largely
-cancel, so its error is bounded by the same 1e-4 times the sum of the shares'
-magnitudes (from the FP64 per-pixel split of the reference), not times the
-total.  (1e-4 relative L2 is also the gradient bar of the method's
+level).  dL/dsigma_r and dL/dsigma_s are sums over all pixels of per-pixel
+shares that largely cancel, so their errors are bounded by the same 1e-4
+times the sum of the shares' magnitudes (from the FP64 per-pixel split of
+the reference), not times the total.  (1e-4 relative L2 is also the gradient bar of the method's
 parity targets.)
 """
 import numpy as np
@@ -179,3 +179,60 @@ def test_adjoint_rejects_unsupported(fhd):
     cen70 = np.random.default_rng(0).random((70, 3)).astype(np.float32)
     with pytest.raises(fhd.FHDError, match="FHD_EUNSUPPORTED"):
         fhd.filter_backward(f, f, cen70, out, den, out.clone(), sigma_s=2.0, sigma_r=0.3, radius=4)
+    # dL/dsigma_s: the box window has no sigma_s
+    ob, db = fhd.filter_centers(f, f, cen, sigma_r=0.3, radius=4, spatial="box", return_den=True)
+    with pytest.raises(fhd.FHDError, match="FHD_EUNSUPPORTED"):
+        fhd.filter_backward(f, f, cen, ob, db, ob.clone(), sigma_r=0.3, radius=4, spatial="box",
+                            need_sigma_s=True)
+
+
+SIGMA_S_CASES = [
+    # (H, W, rho of a separate guide, K, sigma_s, S, sigma_r)
+    (37, 53, 3, 16, 2.0, 6, 0.3),
+    (29, 70, 5, 48, 1.5, 4, 0.15),  # K > 32: two final-kernel launches
+    (45, 38, 3, 8, 3.0, 9, 0.25),
+]
+
+
+@pytest.mark.parametrize("case", SIGMA_S_CASES, ids=lambda c: f"{c[0]}x{c[1]}-rho{c[2]}-K{c[3]}-S{c[5]}")
+def test_sigma_s_gradient_against_fp64_autograd(fhd, case):
+    """dL/dsigma_s (window taps differentiated, radius fixed) against FP64
+    autograd; the other gradients of the same call are unchanged by asking
+    for it."""
+    H, W, rho, K, ss, S, sr = case
+    f = synth.voronoi_rgb(H, W, 9, 0.05, 10 + K)
+    g = synth.hyperspectral(H, W, rho, 4, 0.5, 0.02, 20 + K)
+    cen = oracle.bisecting_kmeans(g, K).centers.astype(np.float32)
+    G = np.random.default_rng(K).standard_normal(f.shape).astype(np.float32)
+    ft = torch.tensor(f, dtype=torch.float64)
+    gt = torch.tensor(g, dtype=torch.float64)
+    st = torch.tensor(float(ss), dtype=torch.float64, requires_grad=True)
+    out64, _ = ar.fast_filter_torch(ft, gt, np.asarray(cen, np.float64), st, sr, S)
+    (out64 * torch.tensor(G, dtype=torch.float64)).sum().backward()
+    rss = float(st.grad)
+    scale = float(np.abs(ar.sigma_s_shares(f, g, np.asarray(cen, np.float64), ss, sr, S, G)).sum())
+    fd, gd = _dev(f), _dev(g)
+    out, den = fhd.filter_centers(fd, gd, cen, sigma_s=ss, sigma_r=sr, radius=S, return_den=True)
+    gf, gg, gs, gss = fhd.filter_backward(fd, gd, cen, out, den, _dev(G), sigma_s=ss, sigma_r=sr, radius=S,
+                                          need_sigma_s=True)
+    gf0, gg0, gs0 = fhd.filter_backward(fd, gd, cen, out, den, _dev(G), sigma_s=ss, sigma_r=sr, radius=S)
+    es = abs(gss - rss) / scale
+    print(f"{case}: dsigma_s {gss:.6e} vs {rss:.6e} (err / sum|shares| {es:.2e}, "
+          f"cancellation {scale / abs(rss):.1f}x)")
+    assert es < TOL
+    assert torch.equal(gf, gf0) and torch.equal(gg, gg0) and gs == gs0
+
+
+def test_sigma_s_autograd_function(fhd):
+    """FilterFunction: a 0-d sigma_s tensor receives the adjoint's value."""
+    f = synth.voronoi_rgb(40, 48, 8, 0.05, 3)
+    cen = oracle.bisecting_kmeans(f, 12).centers.astype(np.float32)
+    fd = _dev(f)
+    ss = torch.tensor(2.5, requires_grad=True)
+    out = fhd.FilterFunction.apply(fd, fd, 0.2, cen, ss, "gaussian", 7, "fp32")
+    G = torch.randn_like(out)
+    (out * G).sum().backward()
+    o2, d2 = fhd.filter_centers(fd, fd, cen, sigma_s=2.5, sigma_r=0.2, radius=7, return_den=True)
+    ref = fhd.filter_backward(fd, fd, cen, o2, d2, G, sigma_s=2.5, sigma_r=0.2, radius=7,
+                              need_f=False, need_guide=False, need_sigma_r=False, need_sigma_s=True)[3]
+    assert abs(float(ss.grad) - ref) <= 1e-6 * abs(ref)

@@ -104,6 +104,31 @@ def test_batch_backward_equals_per_image(fhd, K):
     assert abs(gs - total) <= 1e-12 * max(1.0, abs(total))
 
 
+def test_batch_backward_sigma_s(fhd):
+    """dL/dsigma_s of the batch is the sum of the per-image values (the other
+    gradients are unchanged by asking for it)."""
+    imgs = _images(1700)
+    dev = [torch.from_numpy(x).cuda() for x in imgs]
+    flat, sizes = fhd.pack_batch(dev)
+    out, den, cen, keff = fhd.filter_batch(flat, sizes, 3, sigma_s=3.0, sigma_r=0.1, K=16, radius=9,
+                                           return_den=True)
+    G = torch.from_numpy(np.random.default_rng(5).standard_normal(flat.numel()).astype(np.float32)).cuda()
+    kw = dict(sigma_s=3.0, sigma_r=0.1, radius=9)
+    gf, gg, gs, gss = fhd.filter_batch_backward(flat, sizes, 3, cen, keff, out, den, G, need_sigma_s=True, **kw)
+    gf0, gg0, gs0 = fhd.filter_batch_backward(flat, sizes, 3, cen, keff, out, den, G, **kw)
+    assert torch.equal(gf, gf0) and torch.equal(gg, gg0)
+    assert abs(gs - gs0) <= 1e-12 * max(1.0, abs(gs0))
+    outs, dens, Gs = _split(out, sizes, 3), _split(den, sizes, 1), _split(G, sizes, 3)
+    total = 0.0
+    for b, x in enumerate(dev):
+        r = fhd.filter_backward(x, x, cen[b, :keff[b]], outs[b].contiguous(), dens[b][0].contiguous(),
+                                Gs[b].contiguous(), need_f=False, need_guide=False, need_sigma_r=False,
+                                need_sigma_s=True, **kw)
+        total += r[3]
+    print(f"batch dsigma_s {gss:.10e} vs per-image sum {total:.10e}")
+    assert abs(gss - total) <= 1e-12 * max(1.0, abs(total))
+
+
 def test_batch_rejects_gaps(fhd):
     import ctypes
     lib = fhd.load()

@@ -93,3 +93,22 @@ def test_sigma_r_shares_sum_to_gradient():
         _, _, gs = _grads_ref(f, g, c, G, 2.0, 0.3, 4, full_rank=full)
         sb, sa = ar.sigma_r_shares(f, g, c, 2.0, 0.3, 4, G, full_rank=full)
         assert abs(sb.sum() + sa.sum() - gs) <= 1e-10 * (np.abs(sb).sum() + np.abs(sa).sum())
+
+
+def test_sigma_s_gradient_matches_finite_difference():
+    """dL/dsigma_s through the window's taps (radius fixed) against central
+    differences of the oracle in sigma_s, and its per-pixel split against the
+    total."""
+    f, g, cen, G = _setup(rho_guide=4, K=8)
+    ss, sr, S = 2.0, 0.3, 5
+    ft = torch.tensor(f)
+    gt = torch.tensor(g)
+    st = torch.tensor(ss, dtype=torch.float64, requires_grad=True)
+    out, _ = ar.fast_filter_torch(ft, gt, cen, st, sr, S)
+    (out * torch.tensor(G)).sum().backward()
+    gss = float(st.grad)
+    h = 1e-5 * ss
+    fd = (_loss_oracle(f, g, cen, G, ss + h, sr, S) - _loss_oracle(f, g, cen, G, ss - h, sr, S)) / (2 * h)
+    assert abs(gss - fd) <= 1e-6 * max(1.0, abs(fd)), (gss, fd)
+    sh = ar.sigma_s_shares(f, g, cen, ss, sr, S, G)
+    assert abs(sh.sum() - gss) <= 1e-10 * np.abs(sh).sum()
