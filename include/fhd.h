@@ -196,8 +196,9 @@ fhd_status fhd_filter_batch(fhd_ctx* ctx, int B, const int* H, const int* W,
 
 /* Adjoint of fhd_filter_centers for least-squares coefficients (the paper
  * does not differentiate its filter; this is the exact gradient of the
- * computation of Algorithm 1 steps 2-5 with the centers held fixed).  Given
- * G = dL/dg_hat it returns dL/df, dL/dguide, dL/dsigma_r and dL/dsigma_s
+ * computation of Algorithm 1 steps 2-5 for given centers; the clustering
+ * that produced them is not differentiated).  Given
+ * G = dL/dg_hat it returns dL/df, dL/dguide, dL/dsigma_r, dL/dsigma_s and dL/dmu
  * (the spatial scale enters only through the window omega of eqs. (13)-(14):
  * d omega / d sigma_s = omega |j|^2 / sigma_s^3, radius held fixed); the weights are
  * recomputed from the guide in FP32 (never stored by the forward call), so the
@@ -216,13 +217,19 @@ fhd_status fhd_filter_batch(fhd_ctx* ctx, int B, const int* H, const int* W,
  *   grad_sigma_s host, one double, or NULL (Gaussian window only, else
  *            FHD_EUNSUPPORTED).  Synchronises when non-NULL; costs one more
  *            row pass and column pass and one more K-plane set.
+ *   grad_centers host K x rho (FP64), or NULL: dL/dmu with every pixel's
+ *            weights b_m(i) = phi(mu_m - p(i)) and A = [phi(mu_k - mu_l)]
+ *            differentiated (eq. (12)), the clustering that produced the
+ *            centers held fixed.  Synchronises when non-NULL; one more pass
+ *            over beta and gamma; FHD_EUNSUPPORTED when its K x K + K(rho+1)
+ *            sums exceed the LDS of a block (K = 64 with rho near 64).
  * Gradient outputs must not alias inputs.  Workspace: five K-plane sets plus
  * the intermediate planes of the forward call. */
 fhd_status fhd_filter_backward(fhd_ctx* ctx, const float* f, int n, const float* guide, int rho,
                                int H, int W, const float* centers, int K, const fhd_params* p,
                                const float* out, const float* den, const float* grad_out,
                                float* grad_f, float* grad_guide, double* grad_sigma_r,
-                               double* grad_sigma_s);
+                               double* grad_sigma_s, double* grad_centers);
 
 /* Adjoint of fhd_filter_batch (least-squares coefficients), laid out like
  * it: centers host B x K x rho and K_eff host B as returned by the forward

@@ -127,3 +127,48 @@ def sigma_s_shares(f, p, centers, sigma_s, sigma_r, S, G, spatial="gaussian", fu
 
     _, dg = torch.autograd.functional.jvp(g_of, (s0,), (torch.ones((), dtype=torch.float64),))
     return (torch.as_tensor(G, dtype=torch.float64) * dg).sum(0).numpy()
+
+
+def centers_abs_scale(f, p, centers, sigma_s, sigma_r, S, G, spatial="gaussian", full_rank=True):
+    """Magnitude scale of the pixel terms behind dL/dmu, in FP64, per center
+    coordinate (k, t): sum_i |w_k(i) (p_t(i) - mu_kt)| / sigma_r^2 (through
+    the weights, w_k = dL/db_k b_k) plus sum_i |gamma(i)^T (dA^+/dmu_kt) b(i)|
+    (through A^+, gamma = dL/dc).  The total is the sum of these terms with
+    their signs; the sum of magnitudes sizes the rounding error of any
+    evaluation of it."""
+    n, H, W = f.shape
+    rho = p.shape[0]
+    f = torch.as_tensor(f, dtype=torch.float64)
+    p = torch.as_tensor(p, dtype=torch.float64)
+    mu = torch.as_tensor(centers, dtype=torch.float64)
+    K = mu.shape[0]
+    X = p.reshape(rho, -1).T
+    d2 = ((X[:, None, :] - mu[None, :, :]) ** 2).sum(-1)
+    B = torch.exp(-d2 / (2.0 * float(sigma_r) ** 2)).requires_grad_(True)
+
+    def pinv_of(m):
+        dm = ((m[:, None, :] - m[None, :, :]) ** 2).sum(-1)
+        A = torch.exp(-dm / (2.0 * float(sigma_r) ** 2))
+        return torch.linalg.inv(A) if full_rank else torch.linalg.pinv(A, hermitian=True)
+
+    P = pinv_of(mu)
+    C = B @ P.T
+    C.retain_grad()
+    Fl = f.reshape(n, -1)
+    U = torch.cat([B.T[:, None, :] * Fl[None, :, :], B.T[:, None, :]], dim=1)
+    w = _omega2(S, sigma_s, spatial)
+    V = F.conv2d(U.reshape(K * (n + 1), 1, H, W), w[None, None], padding=S).reshape(K, n + 1, H * W)
+    v = (C.T[:, None, :] * V).sum(0)
+    g = v[:n] / v[n]
+    (g * torch.as_tensor(G, dtype=torch.float64).reshape(n, -1)).sum().backward()
+    wl = (B.grad * B.detach()).abs()                       # N x K
+    diff = (X[:, None, :] - mu[None, :, :]).abs()           # N x K x rho
+    sb = (wl[:, :, None] * diff).sum(0) / float(sigma_r) ** 2
+    D = torch.autograd.functional.jacobian(pinv_of, mu)     # K x K x K x rho: d(A^+)_lm / dmu_kt
+    gam, bb = C.grad, B.detach()
+    sA = torch.zeros(K, rho, dtype=torch.float64)
+    for k in range(K):
+        for t in range(rho):
+            # d(c_l)/dmu_kt = sum_m D[l, m, k, t] b_m  (c = A^+ b, A^+ symmetric up to rounding)
+            sA[k, t] = (gam * (bb @ D[:, :, k, t].T)).sum(1).abs().sum()
+    return sb.numpy(), sA.numpy()

@@ -102,7 +102,7 @@ def load():
             "fhd_pinv": (I, [V, I, I, D, D, V, V, P(I), P(D)]),
             "fhd_filter_centers": (I, [V, V, I, V, I, I, I, V, I, V, pp, V, V, pi]),
             "fhd_filter": (I, [V, V, I, V, I, I, I, pp, V, V, V, pi]),
-            "fhd_filter_backward": (I, [V, V, I, V, I, I, I, V, I, pp, V, V, V, V, V, P(D), P(D)]),
+            "fhd_filter_backward": (I, [V, V, I, V, I, I, I, V, I, pp, V, V, V, V, V, P(D), P(D), V]),
             "fhd_filter_batch": (I, [V, I, V, V, V, V, I, V, I, pp, V, V, V, V, pi]),
             "fhd_filter_batch_backward": (I, [V, I, V, V, V, V, I, V, I, V, V, pp, V, V, V, V, V,
                                               P(D), P(D)]),
@@ -233,11 +233,13 @@ def filter_centers(f, guide, centers, sigma_s=3.0, sigma_r=0.1, spatial="gaussia
 
 def filter_backward(f, guide, centers, out, den, grad_out, sigma_s=3.0, sigma_r=0.1,
                     spatial="gaussian", radius=None, need_f=True, need_guide=True, need_sigma_r=True,
-                    need_sigma_s=False):
+                    need_sigma_s=False, need_centers=False):
     """Adjoint of :func:`filter_centers` (least-squares coefficients): given
     G = dL/dg_hat and the forward call's (g_hat, r_hat), returns
-    (dL/df or None, dL/dguide or None, dL/dsigma_r as float or None), and
-    dL/dsigma_s as a fourth entry when ``need_sigma_s`` (Gaussian window)."""
+    (dL/df or None, dL/dguide or None, dL/dsigma_r as float or None),
+    followed by dL/dsigma_s (float) when ``need_sigma_s`` (Gaussian window)
+    and dL/dcenters ((K, rho) float64 host tensor, clustering held fixed)
+    when ``need_centers``."""
     n, rho, H, W, g = _shape(f, guide)
     ctx = _ctx(f.device.index)
     c = torch.as_tensor(centers, dtype=torch.float32).detach().cpu().contiguous()
@@ -249,21 +251,27 @@ def filter_backward(f, guide, centers, out, den, grad_out, sigma_s=3.0, sigma_r=
     gg = torch.empty_like(g) if need_guide else None
     gs = ctypes.c_double(0.0)
     gss = ctypes.c_double(0.0)
+    gmu = torch.zeros((K, rho), dtype=torch.float64) if need_centers else None
     _check(load().fhd_filter_backward(
         ctx, _dev(f, "f"), n, _dev(g, "guide"), rho, H, W, ctypes.c_void_p(c.data_ptr()), K,
         ctypes.byref(p), _dev(out, "out"), _dev(den, "den"), _dev(grad_out, "grad_out"),
         _dev(gf, "grad_f") if gf is not None else None,
         _dev(gg, "grad_guide") if gg is not None else None,
         ctypes.byref(gs) if need_sigma_r else None,
-        ctypes.byref(gss) if need_sigma_s else None), ctx)
+        ctypes.byref(gss) if need_sigma_s else None,
+        ctypes.c_void_p(gmu.data_ptr()) if need_centers else None), ctx)
     res = (gf, gg, (gs.value if need_sigma_r else None))
-    return res + (gss.value,) if need_sigma_s else res
+    if need_sigma_s:
+        res += (gss.value,)
+    if need_centers:
+        res += (gmu,)
+    return res
 
 
 class FilterFunction(torch.autograd.Function):
     """g_hat = filter_centers(f, guide, centers) with gradients with respect to
     f, guide, sigma_r and sigma_s (0-d tensors; sigma_s with the Gaussian
-    window) from the library's adjoint; the centers are constants.  Pass the same tensor as f and guide for joint
+    window) and the centers (a (K, rho) tensor) from the library's adjoint.  Pass the same tensor as f and guide for joint
     filtering of an image by itself: autograd adds the two contributions."""
 
     @staticmethod
@@ -283,14 +291,20 @@ class FilterFunction(torch.autograd.Function):
         centers, sigma_s, sr, spatial, radius = ctx.conf
         need_f, need_g, need_s = ctx.needs_input_grad[0], ctx.needs_input_grad[1], ctx.needs_input_grad[2]
         need_ss = ctx.needs_input_grad[4] and ctx.ss_tensor
-        res = filter_backward(f.detach(), guide.detach(), centers, out, den,
+        need_mu = ctx.needs_input_grad[3]
+        cen = centers.detach() if isinstance(centers, torch.Tensor) else centers
+        res = filter_backward(f.detach(), guide.detach(), cen, out, den,
                               grad_out.contiguous(), sigma_s=sigma_s, sigma_r=sr,
                               spatial=spatial, radius=radius, need_f=need_f, need_guide=need_g,
-                              need_sigma_r=need_s and ctx.sr_tensor, need_sigma_s=need_ss)
+                              need_sigma_r=need_s and ctx.sr_tensor, need_sigma_s=need_ss,
+                              need_centers=need_mu)
         gf, gg, gs = res[:3]
         gsr = torch.tensor(gs, dtype=torch.float32) if need_s and ctx.sr_tensor else None
         gss = torch.tensor(res[3], dtype=torch.float32) if need_ss else None
-        return gf, gg, gsr, None, gss, None, None, None
+        gmu = None
+        if need_mu:
+            gmu = res[-1].to(dtype=centers.dtype, device=centers.device)
+        return gf, gg, gsr, gmu, gss, None, None, None
 
 
 def filter_autograd(f, guide=None, sigma_s=3.0, sigma_r=0.1, K=16, spatial="gaussian",

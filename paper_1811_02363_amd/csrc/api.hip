@@ -588,7 +588,7 @@ fhd_status fhd_filter(fhd_ctx* ctx, const float* f, int n, const float* guide, i
 fhd_status fhd_filter_backward(fhd_ctx* ctx, const float* f, int n, const float* guide, int rho, int H, int W,
                                const float* centers, int K, const fhd_params* p, const float* out,
                                const float* den, const float* grad_out, float* grad_f, float* grad_guide,
-                               double* grad_sigma_r, double* grad_sigma_s) {
+                               double* grad_sigma_r, double* grad_sigma_s, double* grad_centers) {
     return guarded(ctx, [&](Ctx& c) {
         check_params(p, n, rho, H, W);
         FHD_REQUIRE(grad_sigma_s == nullptr || p->spatial == FHD_SPATIAL_GAUSSIAN, FHD_EUNSUPPORTED,
@@ -608,7 +608,7 @@ fhd_status fhd_filter_backward(fhd_ctx* ctx, const float* f, int n, const float*
         FilterPlan fp = make_plan(*p, n, rho, H, W, K);
         fp.contract = FHD_CONTRACT_FP32;
         fp.materialize = true;
-        Arena ws = c.arena(adjoint_workspace(fp, grad_sigma_s != nullptr) + 4096);
+        Arena ws = c.arena(adjoint_workspace(fp, grad_sigma_s != nullptr, grad_centers != nullptr) + 4096);
         std::vector<float> P32;
         (void)solve(centers, K, rho, p->sigma_r, p->pinv_rtol, P32);
         std::vector<double> M((size_t)K * K);
@@ -616,7 +616,7 @@ fhd_status fhd_filter_backward(fhd_ctx* ctx, const float* f, int n, const float*
         std::vector<float> M32(M.size());
         for (size_t q = 0; q < M.size(); ++q) M32[q] = (float)M[q];
         adjoint_run(c, ws, fp, f, guide, centers, P32.data(), M32.data(), out, den, grad_out, grad_f, grad_guide,
-                    grad_sigma_r, grad_sigma_s);
+                    grad_sigma_r, grad_sigma_s, p->pinv_rtol, grad_centers);
     });
 }
 
@@ -758,7 +758,7 @@ fhd_status fhd_filter_batch_backward(fhd_ctx* ctx, int B, const int* H, const in
             plans[b] = make_plan(*p, n, rho, H[b], W[b], K_eff[b]);
             plans[b].contract = FHD_CONTRACT_FP32;
             plans[b].materialize = true;
-            passes = std::max(passes, adjoint_passes_workspace(plans[b], with_s));
+            passes = std::max(passes, adjoint_passes_workspace(plans[b], with_s, false));
             batched = batched && adjoint_batch_supported(plans[b]);
         }
         const size_t cb = adjoint_consts_bytes(K, rho);
@@ -820,7 +820,7 @@ fhd_status fhd_filter_batch_backward(fhd_ctx* ctx, int B, const int* H, const in
                                reinterpret_cast<const float*>(d + filter_consts_bytes(Kb, rho)), out + (size_t)n * o,
                                den + o, grad_out + (size_t)n * o, grad_f ? grad_f + (size_t)n * o : nullptr,
                                grad_guide ? grad_guide + (size_t)rho * o : nullptr, sig + b,
-                               with_s ? sigs + b : nullptr);
+                               with_s ? sigs + b : nullptr, nullptr);
             }
         }
         if (grad_sigma_r != nullptr) {

@@ -81,6 +81,11 @@ void kernel_matrix(const float* centers, int K, int rho, double sigma_r, double*
 // Pseudo-inverse of the symmetric A; rtol <= 0: K * 2^-52 relative to s_max.
 PinvResult pinv_symmetric(const double* A, int K, double rtol, double* P);
 void pinv_sigma_derivative(const float* centers, int K, int rho, double sigma_r, double rtol, double* M);
+// dL/dmu (K x rho) from the adjoint's pixel sums: Gm = sum_i gamma(i) b(i)^T
+// (K x K, = dL/dA^+), S1_l = sum_i w_l(i), S2_l = sum_i w_l(i) p(i) (K x rho),
+// w_l = dL/db_l b_l; the pseudo-inverse's rank held fixed.
+void centers_gradient(const float* centers, int K, int rho, double sigma_r, double rtol, const double* Gm,
+                      const double* S1, const double* S2, double* grad);
 // Symmetric eigen-decomposition (t destroyed): eigenvalues lam (unsorted),
 // column i of v (row-major n x n) the i-th unit eigenvector.
 void sym_eigen(std::vector<double>& t, int n, std::vector<double>& lam, std::vector<double>& v);
@@ -119,15 +124,19 @@ void filter_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, cons
 void bruteforce_run(Ctx& c, const FilterPlan& fp, const float* f, const float* guide,
                     float* out, float* den);
 // with_s: also the dL/dsigma_s passes (one more K-plane set)
-size_t adjoint_workspace(const FilterPlan& fp, bool with_s);
+// with_mu: also the pixel sums of the centers gradient
+size_t adjoint_workspace(const FilterPlan& fp, bool with_s, bool with_mu);
 // constants of the adjoint: filter constants, then M = dA^+/dsigma_r (K x K)
 size_t adjoint_consts_bytes(int K, int rho);
-size_t adjoint_passes_workspace(const FilterPlan& fp, bool with_s);
+size_t adjoint_passes_workspace(const FilterPlan& fp, bool with_s, bool with_mu);
 // writes the sigma_r gradient (one double) to sig_dev on the device, and the
-// sigma_s gradient to sigs_dev when it is not null (Gaussian kernel only)
+// sigma_s gradient to sigs_dev when it is not null (Gaussian kernel only),
+// and the centers gradient's pixel sums [Gm (K x K), S1 (K), S2 (K x rho)]
+// to mu_dev when it is not null
 void adjoint_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const float* guide,
                     const FilterConsts& kc, const float* Md, const float* out, const float* den,
-                    const float* gout, float* gradf, float* gradp, double* sig_dev, double* sigs_dev);
+                    const float* gout, float* gradf, float* gradp, double* sig_dev, double* sigs_dev,
+                    double* mu_dev);
 // One launch per pass for the adjoint of all images of a batch (guides of at
 // most 8 dimensions, at most 32 clusters, radius 1..32); per-image pointers;
 // the sigma_r gradient summed over all images goes to sig_dev.
@@ -142,7 +151,7 @@ void sum_doubles(Ctx& c, const double* v, int count, double* out_dev);
 void adjoint_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const float* guide,
                  const float* centers_host, const float* Pfp32_host, const float* M_host, const float* out,
                  const float* den, const float* gout, float* gradf, float* gradp, double* gsig,
-                 double* gsigs);
+                 double* gsigs, double rtol, double* gmu);
 
 // ---- nonlocal-means guide (nlm.hip) ----------------------------------------
 size_t nlm_workspace(int n, int H, int W, int m, int dims);

@@ -1088,6 +1088,97 @@ __global__ __launch_bounds__(RT) void sum_blocks(const double* __restrict__ part
 }
 
 // ---------------------------------------------------------------------------
+// Pixel sums for dL/dmu (centers gradient, assignment frozen):
+//   Gm[l][m] = sum_i gamma_l(i) b_m(i)       (= dL/dA^+, since c = A^+ b)
+//   S1[l]    = sum_i w_l(i),  S2[l][r] = sum_i w_l(i) p_r(i),
+// w_l = dL/db_l b_l = (beta_l + (A^+ gamma)_l) b_l.  A fixed grid of blocks
+// of one wave; each takes chunks of CMU pixels in turn: one thread per pixel
+// forms b, gamma and w into LDS (row pitch CMU + 1, conflict-free), then one
+// thread per sum entry adds the chunk's terms (FP64).  Each block writes its FP64 totals; sum_entries adds the
+// blocks in order.
+constexpr int CMU = 64;
+constexpr int CMP = CMU + 1;
+constexpr int MU_GRID = 1024;
+
+size_t adj_centers_lds(int K, int rho) {
+    const size_t E = (size_t)K * K + K + (size_t)K * rho;
+    return sizeof(double) * E + sizeof(float) * ((size_t)K * K + (size_t)K * rho + 3 * (size_t)K * CMP +
+                                                 (size_t)rho * CMP);
+}
+
+__global__ __launch_bounds__(CMU) void adj_centers(FA a, double* __restrict__ part) {
+    extern __shared__ double smem[];
+    const int K = a.K, rho = a.rho;
+    const int E = K * K + K + K * rho;
+    double* sacc = smem;
+    float* sP = reinterpret_cast<float*>(sacc + E);  // A^+ (K x K)
+    float* smu = sP + K * K;                          // centers (K x rho)
+    float* sb = smu + K * rho;                        // b_m of the chunk's pixels
+    float* sg = sb + K * CMP;                         // gamma_m
+    float* sw = sg + K * CMP;                         // w_l
+    float* spp = sw + K * CMP;                        // p_r
+    const int t = threadIdx.x;
+    for (int e = t; e < E; e += CMU) sacc[e] = 0.0;
+    for (int e = t; e < K * K; e += CMU) sP[e] = a.P[e];
+    for (int e = t; e < K * rho; e += CMU) smu[e] = a.mu[e];
+    __syncthreads();
+    const long long nch = (a.N + CMU - 1) / CMU;
+    for (long long ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+        const long long i = ch * CMU + t;
+        const bool valid = i < a.N;
+        const long long po = valid ? (i / a.W) * a.Wp + i % a.W : 0;
+        for (int r = 0; r < rho; ++r) spp[r * CMP + t] = valid ? a.p[(long long)r * a.N + i] : 0.0f;
+        for (int m = 0; m < K; ++m) {
+            float d2 = 0.0f;
+            for (int r = 0; r < rho; ++r) {
+                const float d = spp[r * CMP + t] - smu[m * rho + r];
+                d2 = fmaf(d, d, d2);
+            }
+            sb[m * CMP + t] = valid ? __expf(-d2 * a.inv2s2) : 0.0f;
+            sg[m * CMP + t] = valid ? a.gamma[(long long)m * a.Np + po] : 0.0f;
+        }
+        for (int l = 0; l < K; ++l) {
+            float pg = 0.0f;
+            for (int m = 0; m < K; ++m) pg = fmaf(sP[l * K + m], sg[m * CMP + t], pg);
+            const float bt = valid ? a.beta[(long long)l * a.Np + po] : 0.0f;
+            sw[l * CMP + t] = (bt + pg) * sb[l * CMP + t];
+        }
+        __syncthreads();
+        // FP64 sums of the (exact) products of FP32 values: the pseudo-inverse
+        // derivative amplifies rounding in these sums by up to 1 / lambda_min^2
+        for (int e = t; e < E; e += CMU) {
+            double s = 0.0;
+            if (e < K * K) {
+                const float* gl = sg + (e / K) * CMP;
+                const float* bm = sb + (e % K) * CMP;
+                for (int q = 0; q < CMU; ++q) s = fma((double)gl[q], (double)bm[q], s);
+            } else if (e < K * K + K) {
+                const float* wl = sw + (e - K * K) * CMP;
+                for (int q = 0; q < CMU; ++q) s += (double)wl[q];
+            } else {
+                const int f = e - K * K - K;
+                const float* wl = sw + (f / rho) * CMP;
+                const float* pr = spp + (f % rho) * CMP;
+                for (int q = 0; q < CMU; ++q) s = fma((double)wl[q], (double)pr[q], s);
+            }
+            sacc[e] += s;
+        }
+        __syncthreads();
+    }
+    for (int e = t; e < E; e += CMU) part[(long long)blockIdx.x * E + e] = sacc[e];
+}
+
+// out[e] = sum over b < nb of part[b * E + e], in order
+__global__ __launch_bounds__(RT) void sum_entries(const double* __restrict__ part, int nb, int E,
+                                                  double* __restrict__ out) {
+    const int e = blockIdx.x * RT + threadIdx.x;
+    if (e >= E) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[(long long)b * E + e];
+    out[e] = s;
+}
+
+// ---------------------------------------------------------------------------
 // Weights pass (guides with more than RHO_INLINE dimensions, more than
 // KMAX_INLINE clusters, or the adjoint): B and C planes.  One thread per pixel
 // of a row run of blockDim.x pixels.  Centers (rho padded to a multiple of 8)
@@ -1786,23 +1877,28 @@ size_t adjoint_consts_bytes(int K, int rho) {
     return filter_consts_bytes(K, rho) + align_up(sizeof(float) * K * K, 256);
 }
 
-size_t adjoint_passes_workspace(const FilterPlan& fp, bool with_s) {
+int centers_sum_entries(int K, int rho) { return K * K + K + K * rho; }
+
+size_t adjoint_passes_workspace(const FilterPlan& fp, bool with_s, bool with_mu) {
     Arena probe;
     const long long Np = (long long)fp.H * fp.Wp;
     probe.take<float>(plane_floats(fp));
     for (int q = 0; q < (with_s ? 5 : 4); ++q) probe.take<float>((size_t)fp.K * Np);
     probe.take<double>(2 * ((size_t)(fp.N + RT - 1) / RT) + 1);
     if (with_s) probe.take<double>(2 * ((size_t)(fp.N + RT - 1) / RT) + 1);
+    if (with_mu) probe.take<double>((size_t)MU_GRID * centers_sum_entries(fp.K, fp.rho));
     return probe.used;
 }
 
-size_t adjoint_workspace(const FilterPlan& fp, bool with_s) {
-    return adjoint_passes_workspace(fp, with_s) + adjoint_consts_bytes(fp.K, fp.rho) + 512;
+size_t adjoint_workspace(const FilterPlan& fp, bool with_s, bool with_mu) {
+    return adjoint_passes_workspace(fp, with_s, with_mu) + adjoint_consts_bytes(fp.K, fp.rho) +
+           align_up(sizeof(double) * (2 + (size_t)centers_sum_entries(fp.K, fp.rho)), 256) + 512;
 }
 
 void adjoint_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const float* guide,
                  const float* centers_host, const float* Pfp32_host, const float* M_host, const float* out,
-                 const float* den, const float* gout, float* gradf, float* gradp, double* gsig, double* gsigs) {
+                 const float* den, const float* gout, float* gradf, float* gradp, double* gsig, double* gsigs,
+                 double rtol, double* gmu) {
     const size_t cb = adjoint_consts_bytes(fp.K, fp.rho);
     char* dev = ws.take<char>(cb);
     char* hs = static_cast<char*>(c.host_stage(1, cb));
@@ -1810,21 +1906,30 @@ void adjoint_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const 
     std::memcpy(hs + filter_consts_bytes(fp.K, fp.rho), M_host, sizeof(float) * fp.K * fp.K);
     FHD_HIP(hipMemcpyAsync(dev, hs, cb, hipMemcpyHostToDevice, c.stream));
     c.stage_done(1);
-    double* sig = ws.take<double>(2);
+    const int E = centers_sum_entries(fp.K, fp.rho);
+    double* sig = ws.take<double>(2 + (size_t)E);
     adjoint_passes(c, ws, fp, f, guide, filter_consts_at(dev, fp.K, fp.rho),
                    reinterpret_cast<const float*>(dev + filter_consts_bytes(fp.K, fp.rho)), out, den, gout, gradf,
-                   gradp, sig, gsigs != nullptr ? sig + 1 : nullptr);
-    if (gsig != nullptr || gsigs != nullptr) {
-        if (gsig != nullptr) FHD_HIP(hipMemcpyAsync(gsig, sig, sizeof(double), hipMemcpyDeviceToHost, c.stream));
-        if (gsigs != nullptr)
-            FHD_HIP(hipMemcpyAsync(gsigs, sig + 1, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+                   gradp, sig, gsigs != nullptr ? sig + 1 : nullptr, gmu != nullptr ? sig + 2 : nullptr);
+    if (gsig != nullptr || gsigs != nullptr || gmu != nullptr) {
+        std::vector<double> h(2 + (size_t)E);
+        FHD_HIP(hipMemcpyAsync(h.data(), sig, sizeof(double) * (gmu != nullptr ? 2 + E : 2), hipMemcpyDeviceToHost,
+                               c.stream));
         FHD_HIP(hipStreamSynchronize(c.stream));
+        if (gsig != nullptr) *gsig = h[0];
+        if (gsigs != nullptr) *gsigs = h[1];
+        if (gmu != nullptr) {
+            const int K = fp.K, rho = fp.rho;
+            const double* Gm = h.data() + 2;
+            centers_gradient(centers_host, K, rho, fp.sigma_r, rtol, Gm, Gm + (size_t)K * K,
+                             Gm + (size_t)K * K + K, gmu);
+        }
     }
 }
 
 void adjoint_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const float* guide,
                     const FilterConsts& kc, const float* Md, const float* out, const float* den, const float* gout,
-                    float* gradf, float* gradp, double* sig_dev, double* sigs_dev) {
+                    float* gradf, float* gradp, double* sig_dev, double* sigs_dev, double* mu_dev) {
     FHD_REQUIRE(fp.S >= 1 && fp.S <= MAXS_T, FHD_EUNSUPPORTED, "the adjoint supports radii 1..32");
     FHD_REQUIRE(fp.K <= 64, FHD_EUNSUPPORTED, "the adjoint supports K <= 64");
     FHD_REQUIRE(fp.coef == FHD_COEF_LSQ, FHD_EUNSUPPORTED, "the adjoint covers least-squares coefficients");
@@ -1842,6 +1947,11 @@ void adjoint_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, con
                 "dL/dsigma_s needs the Gaussian spatial kernel");
     float* betas = with_s ? ws.take<float>((size_t)fp.K * Np) : nullptr;
     double* parts = with_s ? ws.take<double>(2 * (size_t)nb + 1) : nullptr;
+    const int Emu = centers_sum_entries(fp.K, fp.rho);
+    const size_t mulds = adj_centers_lds(fp.K, fp.rho);
+    FHD_REQUIRE(mu_dev == nullptr || mulds <= 160 * 1024, FHD_EUNSUPPORTED,
+                "dL/dcenters: K x K plus K x rho sums do not fit in LDS");
+    double* mupart = mu_dev != nullptr ? ws.take<double>((size_t)MU_GRID * Emu) : nullptr;
     hipStream_t st = c.stream;
 
     FA a = make_args(fp);
@@ -1941,6 +2051,13 @@ void adjoint_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, con
                            part + (size_t)h * nb, with_s ? parts + (size_t)h * nb : nullptr);
     hipLaunchKernelGGL(sum_blocks, dim3(1), dim3(RT), 0, st, part, halves * nb, sig_dev);
     if (with_s) hipLaunchKernelGGL(sum_blocks, dim3(1), dim3(RT), 0, st, parts, halves * nb, sigs_dev);
+    if (mu_dev != nullptr) {
+        // the pixel sums of the centers gradient (beta and gamma are complete)
+        FHD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(adj_centers),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)mulds));
+        hipLaunchKernelGGL(adj_centers, dim3(MU_GRID), dim3(CMU), mulds, st, a, mupart);
+        hipLaunchKernelGGL(sum_entries, dim3((Emu + RT - 1) / RT), dim3(RT), 0, st, mupart, MU_GRID, Emu, mu_dev);
+    }
     FHD_HIP(hipGetLastError());
 }
 

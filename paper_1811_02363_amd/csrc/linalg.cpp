@@ -160,34 +160,19 @@ PinvResult pinv_symmetric(const double* A, int K, double rtol, double* P) {
 // differences D_ij = (g(lam_i) - g(lam_j)) / (lam_i - lam_j) (g' on equal
 // pairs): -1/(lam_i lam_j) for two kept, 1/(lam_i (lam_i - lam_j)) for kept i
 // and dropped j, 0 for two dropped.  dA/dsigma_r = A o |mu_k - mu_l|^2 / sigma_r^3.
-void pinv_sigma_derivative(const float* centers, int K, int rho, double sigma_r, double rtol, double* M) {
-    std::fill(M, M + (size_t)K * K, 0.0);
-    if (std::isinf(sigma_r)) return;
-    std::vector<double> A((size_t)K * K), dA((size_t)K * K);
-    kernel_matrix(centers, K, rho, sigma_r, A.data());
-    const double s3 = sigma_r * sigma_r * sigma_r;
-    for (int k = 0; k < K; ++k)
-        for (int l = 0; l < K; ++l) {
-            double d2 = 0.0;
-            for (int t = 0; t < rho; ++t) {
-                const double d = (double)centers[(size_t)k * rho + t] - (double)centers[(size_t)l * rho + t];
-                d2 += d * d;
-            }
-            dA[(size_t)k * K + l] = A[(size_t)k * K + l] * d2 / s3;
-        }
-    std::vector<double> lam, V;
-    sym_eigen(A, K, lam, V);
-    double smax = 0.0;
-    for (double x : lam) smax = std::max(smax, std::fabs(x));
-    const double tol = (rtol > 0.0 ? rtol : (double)K * 0x1p-52) * smax;
-    std::vector<char> kept(K);
-    for (int i = 0; i < K; ++i) kept[i] = std::fabs(lam[i]) > tol;
-    // E = V^T dA V, then E_ij *= D_ij, then M = V E V^T
+// The derivative of A^+ (symmetric A, the pseudo-inverse's rank held fixed)
+// along a symmetric direction X: V (D o (V^T X V)) V^T with the divided
+// differences D_ij of f(lambda) = 1/lambda on kept eigenvalues, 0 on dropped
+// ones (kept-kept -1/(l_i l_j), kept-dropped 1/(l_i (l_i - l_j)), dropped-
+// dropped 0).  D is symmetric, so the same map applied to dL/dA^+ gives
+// dL/dA (the map is its own adjoint).
+static void pinv_directional(const std::vector<double>& lam, const std::vector<double>& V,
+                             const std::vector<char>& kept, int K, const double* X, double* Y) {
     std::vector<double> T((size_t)K * K, 0.0), E((size_t)K * K, 0.0);
     for (int k = 0; k < K; ++k)
         for (int j = 0; j < K; ++j) {
             double s = 0.0;
-            for (int l = 0; l < K; ++l) s += dA[(size_t)k * K + l] * V[(size_t)l * K + j];
+            for (int l = 0; l < K; ++l) s += X[(size_t)k * K + l] * V[(size_t)l * K + j];
             T[(size_t)k * K + j] = s;
         }
     for (int i = 0; i < K; ++i)
@@ -215,7 +200,70 @@ void pinv_sigma_derivative(const float* centers, int K, int rho, double sigma_r,
         for (int l = 0; l < K; ++l) {
             double s = 0.0;
             for (int j = 0; j < K; ++j) s += T[(size_t)k * K + j] * V[(size_t)l * K + j];
-            M[(size_t)k * K + l] = s;
+            Y[(size_t)k * K + l] = s;
+        }
+}
+
+// eigen-decomposition of A and the kept set of its pseudo-inverse
+static void pinv_spectrum(const std::vector<double>& A, int K, double rtol, std::vector<double>& lam,
+                          std::vector<double>& V, std::vector<char>& kept) {
+    std::vector<double> t = A;
+    sym_eigen(t, K, lam, V);
+    double smax = 0.0;
+    for (double x : lam) smax = std::max(smax, std::fabs(x));
+    const double tol = (rtol > 0.0 ? rtol : (double)K * 0x1p-52) * smax;
+    kept.assign(K, 0);
+    for (int i = 0; i < K; ++i) kept[i] = std::fabs(lam[i]) > tol;
+}
+
+void pinv_sigma_derivative(const float* centers, int K, int rho, double sigma_r, double rtol, double* M) {
+    std::fill(M, M + (size_t)K * K, 0.0);
+    if (std::isinf(sigma_r)) return;
+    std::vector<double> A((size_t)K * K), dA((size_t)K * K);
+    kernel_matrix(centers, K, rho, sigma_r, A.data());
+    const double s3 = sigma_r * sigma_r * sigma_r;
+    for (int k = 0; k < K; ++k)
+        for (int l = 0; l < K; ++l) {
+            double d2 = 0.0;
+            for (int t = 0; t < rho; ++t) {
+                const double d = (double)centers[(size_t)k * rho + t] - (double)centers[(size_t)l * rho + t];
+                d2 += d * d;
+            }
+            dA[(size_t)k * K + l] = A[(size_t)k * K + l] * d2 / s3;
+        }
+    std::vector<double> lam, V;
+    std::vector<char> kept;
+    pinv_spectrum(A, K, rtol, lam, V, kept);
+    pinv_directional(lam, V, kept, K, dA.data(), M);
+}
+
+void centers_gradient(const float* centers, int K, int rho, double sigma_r, double rtol, const double* Gm,
+                      const double* S1, const double* S2, double* grad) {
+    std::fill(grad, grad + (size_t)K * rho, 0.0);
+    if (std::isinf(sigma_r)) return;  // b = 1 and A = 1: nothing depends on the centers
+    const double is2 = 1.0 / (sigma_r * sigma_r);
+    // through b_l(i): sum_i w_l(i) (p(i) - mu_l) / sigma_r^2
+    for (int k = 0; k < K; ++k)
+        for (int t = 0; t < rho; ++t)
+            grad[(size_t)k * rho + t] = (S2[(size_t)k * rho + t] - S1[k] * (double)centers[(size_t)k * rho + t]) * is2;
+    // through A: dL/dA = the pseudo-inverse derivative map applied to
+    // dL/dA^+ = Gm (symmetrised: A is symmetric), then
+    // dA_kl / dmu_k = A_kl (mu_l - mu_k) / sigma_r^2 for l != k
+    std::vector<double> A((size_t)K * K), Gs((size_t)K * K), GA((size_t)K * K);
+    kernel_matrix(centers, K, rho, sigma_r, A.data());
+    for (int k = 0; k < K; ++k)
+        for (int l = 0; l < K; ++l) Gs[(size_t)k * K + l] = 0.5 * (Gm[(size_t)k * K + l] + Gm[(size_t)l * K + k]);
+    std::vector<double> lam, V;
+    std::vector<char> kept;
+    pinv_spectrum(A, K, rtol, lam, V, kept);
+    pinv_directional(lam, V, kept, K, Gs.data(), GA.data());
+    for (int k = 0; k < K; ++k)
+        for (int l = 0; l < K; ++l) {
+            if (l == k) continue;
+            const double c = 2.0 * GA[(size_t)k * K + l] * A[(size_t)k * K + l] * is2;  // A_kl and A_lk
+            for (int t = 0; t < rho; ++t)
+                grad[(size_t)k * rho + t] +=
+                    c * ((double)centers[(size_t)l * rho + t] - (double)centers[(size_t)k * rho + t]);
         }
 }
 

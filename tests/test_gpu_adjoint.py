@@ -236,3 +236,47 @@ def test_sigma_s_autograd_function(fhd):
     ref = fhd.filter_backward(fd, fd, cen, o2, d2, G, sigma_s=2.5, sigma_r=0.2, radius=7,
                               need_f=False, need_guide=False, need_sigma_r=False, need_sigma_s=True)[3]
     assert abs(float(ss.grad) - ref) <= 1e-6 * abs(ref)
+
+
+@pytest.mark.parametrize("case", SIGMA_S_CASES, ids=lambda c: f"{c[0]}x{c[1]}-rho{c[2]}-K{c[3]}-S{c[5]}")
+def test_centers_gradient_against_fp64_autograd(fhd, case):
+    """dL/dmu (the clustering held fixed) against FP64 autograd through the
+    oracle's transcription; error per entry within 1e-4 of the sum of the
+    magnitudes of its per-pixel terms (through b and through A^+, FP64), since
+    those terms cancel."""
+    H, W, rho, K, ss, S, sr = case
+    f = synth.voronoi_rgb(H, W, 9, 0.05, 10 + K)
+    g = synth.hyperspectral(H, W, rho, 4, 0.5, 0.02, 20 + K)
+    cen = oracle.bisecting_kmeans(g, K).centers.astype(np.float32)
+    G = np.random.default_rng(K).standard_normal(f.shape).astype(np.float32)
+    ct = torch.tensor(np.asarray(cen, np.float64), requires_grad=True)
+    out64, _ = ar.fast_filter_torch(torch.tensor(f, dtype=torch.float64), torch.tensor(g, dtype=torch.float64),
+                                    ct, ss, sr, S)
+    (out64 * torch.tensor(G, dtype=torch.float64)).sum().backward()
+    ref = ct.grad.numpy()
+    sb, sA = ar.centers_abs_scale(f, g, np.asarray(cen, np.float64), ss, sr, S, G)
+    fd, gd = _dev(f), _dev(g)
+    out, den = fhd.filter_centers(fd, gd, cen, sigma_s=ss, sigma_r=sr, radius=S, return_den=True)
+    res = fhd.filter_backward(fd, gd, cen, out, den, _dev(G), sigma_s=ss, sigma_r=sr, radius=S,
+                              need_centers=True)
+    gmu = res[3].numpy()
+    scale = sb + sA
+    err = np.abs(gmu - ref) / scale
+    print(f"{case}: dmu rel L2 {_rel(gmu, ref):.2e}, max err / scale {err.max():.2e}, "
+          f"|ref| max {np.abs(ref).max():.3e}")
+    assert err.max() < TOL
+
+
+def test_centers_gradient_autograd_function(fhd):
+    """FilterFunction: a (K, rho) centers tensor receives the adjoint's value."""
+    f = synth.voronoi_rgb(40, 48, 8, 0.05, 3)
+    cen = oracle.bisecting_kmeans(f, 12).centers.astype(np.float32)
+    fd = _dev(f)
+    ct = torch.tensor(cen, requires_grad=True)
+    out = fhd.FilterFunction.apply(fd, fd, 0.2, ct, 2.5, "gaussian", 7, "fp32")
+    G = torch.randn_like(out)
+    (out * G).sum().backward()
+    o2, d2 = fhd.filter_centers(fd, fd, cen, sigma_s=2.5, sigma_r=0.2, radius=7, return_den=True)
+    ref = fhd.filter_backward(fd, fd, cen, o2, d2, G, sigma_s=2.5, sigma_r=0.2, radius=7, need_f=False,
+                              need_guide=False, need_sigma_r=False, need_centers=True)[3]
+    assert torch.allclose(ct.grad.double(), ref, rtol=1e-6, atol=0.0)
