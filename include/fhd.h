@@ -54,7 +54,14 @@ typedef enum {
     FHD_EUNSUPPORTED = -5   /* valid but outside what this build implements */
 } fhd_status;
 
-enum { FHD_SPATIAL_GAUSSIAN = 0, FHD_SPATIAL_BOX = 1 };
+/* Spatial window omega of eqs. (13)-(14): the Gaussian truncated at the
+ * radius, the box, or the recursive Gaussian of Young and van Vliet (1995),
+ * the O(1) convolution the paper uses (Sec. III): per axis a causal and an
+ * anti-causal third-order recursion, each from a zero state at its end of
+ * the image, rows then columns; no radius, cost independent of sigma_s
+ * (sigma_s >= 0.5; forward filter only: the adjoint and the brute force
+ * return FHD_EUNSUPPORTED). */
+enum { FHD_SPATIAL_GAUSSIAN = 0, FHD_SPATIAL_BOX = 1, FHD_SPATIAL_YOUNG = 2 };
 /* Precision of the point-to-center distance contraction (weights step only;
  * convolutions and normalisation stay FP32). */
 enum { FHD_CONTRACT_FP32 = 0, FHD_CONTRACT_BF16 = 1, FHD_CONTRACT_FP16 = 2 };
@@ -69,8 +76,9 @@ enum { FHD_COEF_LSQ = 0, FHD_COEF_HARD = 1 };
 #define FHD_MAX_RADIUS 128   /* window half-width S */
 
 typedef struct {
-    float sigma_s;        /* Gaussian spatial std (pixels), > 0; ignored for box */
-    int radius;           /* S; < 0 means ceil(3 sigma_s) (Sec. IV); required (>= 0) for box */
+    float sigma_s;        /* Gaussian spatial std (pixels), > 0 (>= 0.5 recursive); ignored for box */
+    int radius;           /* S; < 0 means ceil(3 sigma_s) (Sec. IV); required (>= 0) for box;
+                             ignored for the recursive Gaussian */
     float sigma_r;        /* range std, > 0; +INFINITY allowed (phi == 1) */
     int K;                /* requested clusters, 1..FHD_MAX_K; fewer are used when the
                              guide has fewer distinct vectors (reported as K_eff) */

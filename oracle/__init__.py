@@ -161,6 +161,52 @@ def bruteforce_at(f, guide, sigma_s, sigma_r, ys, xs, S=None, spatial="gaussian"
     return out, den
 
 
+def young_coefficients(sigma):
+    """Coefficients of the recursive Gaussian of Young and van Vliet (1995),
+    the O(1) convolution the paper uses for Gaussian windows (Sec. III):
+    q from sigma (two published branches), then b0..b3 and the gain
+    B = 1 - (b1 + b2 + b3) / b0.  Returns (B, b1/b0, b2/b0, b3/b0)."""
+    s = float(sigma)
+    if s >= 2.5:
+        q = 0.98711 * s - 0.96330
+    elif s >= 0.5:
+        q = 3.97156 - 4.14554 * np.sqrt(1.0 - 0.26891 * s)
+    else:
+        raise ValueError("the recursive Gaussian needs sigma >= 0.5")
+    b0 = 1.57825 + 2.44413 * q + 1.4281 * q ** 2 + 0.422205 * q ** 3
+    b1 = 2.44413 * q + 2.85619 * q ** 2 + 1.26661 * q ** 3
+    b2 = -(1.4281 * q ** 2 + 1.26661 * q ** 3)
+    b3 = 0.422205 * q ** 3
+    return 1.0 - (b1 + b2 + b3) / b0, b1 / b0, b2 / b0, b3 / b0
+
+
+def young_1d(u, sigma, axis):
+    """The recursive Gaussian along one axis of u (FP64): the causal pass
+    w[t] = B u[t] + a1 w[t-1] + a2 w[t-2] + a3 w[t-3], then the anti-causal
+    pass y[t] = B w[t] + a1 y[t+1] + a2 y[t+2] + a3 y[t+3], each from a zero
+    state at its own end of the image (reading A15 of the design notes)."""
+    B, a1, a2, a3 = young_coefficients(sigma)
+    x = np.moveaxis(_f64(u), axis, 0)
+    T = x.shape[0]
+    w = np.zeros_like(x)
+    p1 = p2 = p3 = np.zeros(x.shape[1:])
+    for t in range(T):
+        w[t] = B * x[t] + a1 * p1 + a2 * p2 + a3 * p3
+        p1, p2, p3 = w[t], p1, p2
+    y = np.zeros_like(x)
+    p1 = p2 = p3 = np.zeros(x.shape[1:])
+    for t in range(T - 1, -1, -1):
+        y[t] = B * w[t] + a1 * p1 + a2 * p2 + a3 * p3
+        p1, p2, p3 = y[t], p1, p2
+    return np.moveaxis(y, 0, axis)
+
+
+def young_conv(u, sigma):
+    """The separable recursive Gaussian of a stack of planes (C,H,W): along
+    the rows (x), then along the columns (y)."""
+    return young_1d(young_1d(u, sigma, 2), sigma, 1)
+
+
 def conv(u, S, sigma_s, spatial="gaussian", method="direct"):
     """omega * u for a stack of planes (C,H,W), zero-extended (eqs. (13)-(14))."""
     u = _f64(u)
@@ -355,13 +401,15 @@ def fast_filter(f, guide, centers, P, sigma_s, sigma_r, S=None,
     v_k = omega * (b_k f), r_k = omega * b_k (eqs. (13)-(14)) and the
     recombination g = sum_k c_k v_k / sum_k c_k r_k (eqs. (15)-(16)).
 
+    ``spatial='young'`` convolves with the recursive Gaussian of sigma_s
+    (:func:`young_conv`, no radius).
     ``coef='hard'`` uses c_k(i) = 1 iff pixel i is in cluster k (eq. (17)),
     which gives eq. (18); ``labels`` must then be given.
     Returns (g (n,H,W), r_hat (H,W)) in FP64.
     """
     f = _f64(f)
     n, H, W = f.shape
-    if S is None:
+    if S is None and spatial != "young":
         S = default_radius(sigma_s)
     mu = np.asarray(centers, dtype=np.float64)
     K = mu.shape[0]
@@ -380,7 +428,10 @@ def fast_filter(f, guide, centers, P, sigma_s, sigma_r, S=None,
         U = np.empty((n + 1, H * W))
         U[:n] = B[:, k] * F
         U[n] = B[:, k]
-        V = conv(U.reshape(n + 1, H, W), S, sigma_s, spatial, conv_method).reshape(n + 1, -1)
+        if spatial == "young":
+            V = young_conv(U.reshape(n + 1, H, W), sigma_s).reshape(n + 1, -1)
+        else:
+            V = conv(U.reshape(n + 1, H, W), S, sigma_s, spatial, conv_method).reshape(n + 1, -1)
         v += C[:, k] * V[:n]
         r += C[:, k] * V[n]
     return (v / r).reshape(n, H, W), r.reshape(H, W)

@@ -28,7 +28,7 @@ lib_path = os.path.join(_HERE, "libfhd.so")
 FHD_OK, FHD_EINVAL, FHD_ENOMEM, FHD_EHIP, FHD_ENUMERIC, FHD_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 _STATUS = {0: "FHD_OK", -1: "FHD_EINVAL", -2: "FHD_ENOMEM", -3: "FHD_EHIP",
            -4: "FHD_ENUMERIC", -5: "FHD_EUNSUPPORTED"}
-SPATIAL = {"gaussian": 0, "box": 1}
+SPATIAL = {"gaussian": 0, "box": 1, "young": 2}
 CONTRACT = {"fp32": 0, "bf16": 1, "fp16": 2}
 COEF = {"lsq": 0, "hard": 1}
 

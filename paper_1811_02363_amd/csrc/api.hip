@@ -160,6 +160,7 @@ struct DeviceGuard {
 };
 
 int resolve_radius(const fhd_params& p) {
+    if (p.spatial == FHD_SPATIAL_YOUNG) return 0;  // infinite support, no window radius
     if (p.radius >= 0) return p.radius;
     return (int)std::ceil(3.0 * (double)p.sigma_s - 1e-9);
 }
@@ -170,10 +171,14 @@ void check_params(const fhd_params* p, int n, int rho, int H, int W) {
     FHD_REQUIRE(n <= FHD_MAX_N, FHD_EUNSUPPORTED, "n exceeds FHD_MAX_N");
     FHD_REQUIRE(rho <= FHD_MAX_RHO, FHD_EUNSUPPORTED, "rho exceeds FHD_MAX_RHO");
     FHD_REQUIRE((long long)H * W < (1LL << 31), FHD_EUNSUPPORTED, "image has 2^31 pixels or more");
-    FHD_REQUIRE(p->spatial == FHD_SPATIAL_GAUSSIAN || p->spatial == FHD_SPATIAL_BOX, FHD_EINVAL,
-                "unknown spatial kernel");
+    FHD_REQUIRE(p->spatial == FHD_SPATIAL_GAUSSIAN || p->spatial == FHD_SPATIAL_BOX ||
+                    p->spatial == FHD_SPATIAL_YOUNG,
+                FHD_EINVAL, "unknown spatial kernel");
     if (p->spatial == FHD_SPATIAL_GAUSSIAN)
         FHD_REQUIRE(p->sigma_s > 0.0f && std::isfinite(p->sigma_s), FHD_EINVAL, "sigma_s must be > 0");
+    else if (p->spatial == FHD_SPATIAL_YOUNG)
+        FHD_REQUIRE(p->sigma_s >= 0.5f && std::isfinite(p->sigma_s), FHD_EINVAL,
+                    "the recursive Gaussian needs sigma_s >= 0.5");
     else
         FHD_REQUIRE(p->radius >= 0, FHD_EINVAL, "the box kernel needs radius >= 0");
     FHD_REQUIRE(p->sigma_r > 0.0f && !std::isnan(p->sigma_r), FHD_EINVAL, "sigma_r must be > 0");
@@ -203,7 +208,7 @@ FilterPlan make_plan(const fhd_params& p, int n, int rho, int H, int W, int K) {
     fp.sigma_r = p.sigma_r;
     fp.N = (long long)H * W;
     fp.Wp = (int)align_up((size_t)W, 4);
-    fp.materialize = rho > 8 || K > 32 || p.contract != FHD_CONTRACT_FP32;
+    fp.materialize = rho > 8 || K > 32 || p.contract != FHD_CONTRACT_FP32 || p.spatial == FHD_SPATIAL_YOUNG;
     return fp;
 }
 
@@ -593,6 +598,8 @@ fhd_status fhd_filter_backward(fhd_ctx* ctx, const float* f, int n, const float*
         check_params(p, n, rho, H, W);
         FHD_REQUIRE(grad_sigma_s == nullptr || p->spatial == FHD_SPATIAL_GAUSSIAN, FHD_EUNSUPPORTED,
                     "dL/dsigma_s needs the Gaussian spatial kernel");
+        FHD_REQUIRE(p->spatial != FHD_SPATIAL_YOUNG, FHD_EUNSUPPORTED,
+                    "the adjoint covers the truncated Gaussian and box windows");
         FHD_REQUIRE(f && guide && centers && out && den && grad_out, FHD_EINVAL, "NULL pointer");
         FHD_REQUIRE(K >= 1 && K <= 64, FHD_EUNSUPPORTED, "the adjoint supports K in [1, 64]");
         FHD_REQUIRE(p->coef == FHD_COEF_LSQ, FHD_EUNSUPPORTED, "the adjoint covers least-squares coefficients");
@@ -735,6 +742,8 @@ fhd_status fhd_filter_batch_backward(fhd_ctx* ctx, int B, const int* H, const in
         for (int b = 0; b < B; ++b) check_params(p, n, rho, H[b], W[b]);
         FHD_REQUIRE(grad_sigma_s == nullptr || p->spatial == FHD_SPATIAL_GAUSSIAN, FHD_EUNSUPPORTED,
                     "dL/dsigma_s needs the Gaussian spatial kernel");
+        FHD_REQUIRE(p->spatial != FHD_SPATIAL_YOUNG, FHD_EUNSUPPORTED,
+                    "the adjoint covers the truncated Gaussian and box windows");
         const bool with_s = grad_sigma_s != nullptr;
         FHD_REQUIRE(f && guide && centers && K_eff && out && den && grad_out, FHD_EINVAL, "NULL pointer");
         FHD_REQUIRE(p->coef == FHD_COEF_LSQ, FHD_EUNSUPPORTED, "the adjoint covers least-squares coefficients");
@@ -839,6 +848,8 @@ fhd_status fhd_bruteforce(fhd_ctx* ctx, const float* f, int n, const float* guid
                           const fhd_params* p, float* out, float* den) {
     return guarded(ctx, [&](Ctx& c) {
         check_params(p, n, rho, H, W);
+        FHD_REQUIRE(p->spatial != FHD_SPATIAL_YOUNG, FHD_EUNSUPPORTED,
+                    "the brute force evaluates eqs. (1)-(2) with a finite window");
         FHD_REQUIRE(f && guide && out, FHD_EINVAL, "NULL pointer");
         const long long N = (long long)H * W;
         FHD_REQUIRE(!ranges_overlap(out, sizeof(float) * N * n, f, sizeof(float) * N * n) &&

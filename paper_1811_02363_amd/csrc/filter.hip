@@ -65,6 +65,7 @@ struct FA {
     int bacc;           // adjoint column pass: add to the output planes instead of overwriting
     float w[FHD_MAX_RADIUS + 1];   // 1-D spatial taps w[|j|]
     float wd[FHD_MAX_RADIUS + 1];  // their derivative d w[|j|] / d sigma_s = w j^2 / sigma_s^3
+    float yc[4];        // recursive Gaussian: B, b1/b0, b2/b0, b3/b0
 };
 
 // LDS skew: one pad word after every R_ROW = 8 entries.  A thread's window
@@ -1088,6 +1089,93 @@ __global__ __launch_bounds__(RT) void sum_blocks(const double* __restrict__ part
 }
 
 // ---------------------------------------------------------------------------
+// Recursive Gaussian window (Young and van Vliet; the paper's O(1) choice):
+// every 1-D pass is the causal recursion w[t] = B u[t] + a1 w[t-1] +
+// a2 w[t-2] + a3 w[t-3] from a zero state at the start, then the same
+// anti-causal recursion from a zero state at the end.  Rows first (one thread
+// per plane row; the factor c_l or b_l times [f, 1] formed on the fly from
+// the materialised planes), then columns in place (one thread per plane
+// column, adjacent threads on adjacent columns), then the recombination of
+// eqs. (15)-(16) per pixel.  The planes have no halo rows (S = 0).
+__global__ __launch_bounds__(RT) void row_young(FA a, const float* __restrict__ fac) {
+    const long long t = (long long)blockIdx.x * RT + threadIdx.x;
+    const int planes = a.K * (a.n + 1);
+    if (t >= (long long)planes * a.H) return;
+    const int y = (int)(t % a.H);
+    const int pl = (int)(t / a.H);
+    const int l = pl / (a.n + 1), ch = pl - l * (a.n + 1);
+    const float* cp = fac + (long long)l * a.Np + (long long)y * a.Wp;
+    const float* fr = ch < a.n ? a.f + (long long)ch * a.N + (long long)y * a.W : nullptr;
+    float* dst = a.planes + (long long)pl * a.Pp + (long long)y * a.Wp;
+    const float B = a.yc[0], a1 = a.yc[1], a2 = a.yc[2], a3 = a.yc[3];
+    float p1 = 0.0f, p2 = 0.0f, p3 = 0.0f;
+    for (int x = 0; x < a.W; ++x) {
+        const float u = fr != nullptr ? cp[x] * fr[x] : cp[x];
+        const float w = B * u + a1 * p1 + a2 * p2 + a3 * p3;
+        dst[x] = w;
+        p3 = p2;
+        p2 = p1;
+        p1 = w;
+    }
+    p1 = p2 = p3 = 0.0f;
+    for (int x = a.W - 1; x >= 0; --x) {
+        const float v = B * dst[x] + a1 * p1 + a2 * p2 + a3 * p3;
+        dst[x] = v;
+        p3 = p2;
+        p2 = p1;
+        p1 = v;
+    }
+}
+
+__global__ __launch_bounds__(RT) void col_young(FA a) {
+    const long long t = (long long)blockIdx.x * RT + threadIdx.x;
+    const int planes = a.K * (a.n + 1);
+    if (t >= (long long)planes * a.W) return;
+    const int x = (int)(t % a.W);
+    const int pl = (int)(t / a.W);
+    float* col = a.planes + (long long)pl * a.Pp + x;
+    const float B = a.yc[0], a1 = a.yc[1], a2 = a.yc[2], a3 = a.yc[3];
+    float p1 = 0.0f, p2 = 0.0f, p3 = 0.0f;
+    for (int y = 0; y < a.H; ++y) {
+        float* e = col + (long long)y * a.Wp;
+        const float w = B * *e + a1 * p1 + a2 * p2 + a3 * p3;
+        *e = w;
+        p3 = p2;
+        p2 = p1;
+        p1 = w;
+    }
+    p1 = p2 = p3 = 0.0f;
+    for (int y = a.H - 1; y >= 0; --y) {
+        float* e = col + (long long)y * a.Wp;
+        const float v = B * *e + a1 * p1 + a2 * p2 + a3 * p3;
+        *e = v;
+        p3 = p2;
+        p2 = p1;
+        p1 = v;
+    }
+}
+
+// out = sum_l h_l V_l[0:n] / sum_l h_l V_l[n] with h_l = b_l(i) (least
+// squares, transposed form) or the cluster indicator (hard variant)
+__global__ __launch_bounds__(RT) void recomb_young(FA a, int hard) {
+    const long long i = (long long)blockIdx.x * RT + threadIdx.x;
+    if (i >= a.N) return;
+    const long long po = (i / a.W) * a.Wp + i % a.W;
+    const int n = a.n;
+    const int lab = hard ? a.labels[i] : -1;
+    auto h = [&](int l) { return hard ? (l == lab ? 1.0f : 0.0f) : a.Bpl[(long long)l * a.Np + po]; };
+    float r = 0.0f;
+    for (int l = 0; l < a.K; ++l) r = fmaf(h(l), a.planes[(long long)(l * (n + 1) + n) * a.Pp + po], r);
+    if (a.den != nullptr) a.den[i] = r;
+    const float inv = 1.0f / r;
+    for (int ch = 0; ch < n; ++ch) {
+        float v = 0.0f;
+        for (int l = 0; l < a.K; ++l) v = fmaf(h(l), a.planes[(long long)(l * (n + 1) + ch) * a.Pp + po], v);
+        a.out[(long long)ch * a.N + i] = v * inv;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Pixel sums for dL/dmu (centers gradient, assignment frozen):
 //   Gm[l][m] = sum_i gamma_l(i) b_m(i)       (= dL/dA^+, since c = A^+ b)
 //   S1[l]    = sum_i w_l(i),  S2[l][r] = sum_i w_l(i) p_r(i),
@@ -1577,6 +1665,23 @@ const Dispatch& dispatch() {
     return d;
 }
 
+// The recursive Gaussian of Young and van Vliet (1995), the O(1) Gaussian
+// convolution the paper uses (Sec. III): q from sigma (two published
+// branches, sigma >= 0.5), the polynomial coefficients b0..b3, the gain
+// B = 1 - (b1 + b2 + b3) / b0.  c = {B, b1/b0, b2/b0, b3/b0}.
+void young_coefficients(double sigma, double* c) {
+    const double q = sigma >= 2.5 ? 0.98711 * sigma - 0.96330 : 3.97156 - 4.14554 * std::sqrt(1.0 - 0.26891 * sigma);
+    const double q2 = q * q, q3 = q2 * q;
+    const double b0 = 1.57825 + 2.44413 * q + 1.4281 * q2 + 0.422205 * q3;
+    const double b1 = 2.44413 * q + 2.85619 * q2 + 1.26661 * q3;
+    const double b2 = -(1.4281 * q2 + 1.26661 * q3);
+    const double b3 = 0.422205 * q3;
+    c[0] = 1.0 - (b1 + b2 + b3) / b0;
+    c[1] = b1 / b0;
+    c[2] = b2 / b0;
+    c[3] = b3 / b0;
+}
+
 FA make_args(const FilterPlan& fp) {
     FA a;
     std::memset(&a, 0, sizeof(a));
@@ -1593,6 +1698,11 @@ FA make_args(const FilterPlan& fp) {
     a.Np = (long long)fp.H * fp.Wp;
     a.Pp = (long long)(fp.H + 2 * fp.S) * fp.Wp;
     a.inv2s2 = std::isinf(fp.sigma_r) ? 0.0f : (float)(1.0 / (2.0 * (double)fp.sigma_r * fp.sigma_r));
+    if (fp.spatial == FHD_SPATIAL_YOUNG) {
+        double yc[4];
+        young_coefficients(fp.sigma_s, yc);
+        for (int q = 0; q < 4; ++q) a.yc[q] = (float)yc[q];
+    }
     for (int j = 0; j <= fp.S; ++j) {
         const bool box = fp.spatial == FHD_SPATIAL_BOX;
         const double s = fp.sigma_s, wj = box ? 1.0 : std::exp(-(double)j * j / (2.0 * s * s));
@@ -1737,6 +1847,23 @@ void filter_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, cons
         FHD_HIP(hipGetLastError());
         a.Bpl = Bpl;
         a.Cpl = Cpl;
+    }
+
+    if (fp.spatial == FHD_SPATIAL_YOUNG) {  // recursive Gaussian (materialised weights, S = 0)
+        const bool hard = fp.coef == FHD_COEF_HARD;
+        const long long planes = (long long)fp.K * (fp.n + 1);
+        const long long nr = planes * fp.H, nc = planes * fp.W;
+        FHD_REQUIRE((nr + RT - 1) / RT < (1LL << 31) && (nc + RT - 1) / RT < (1LL << 31), FHD_EUNSUPPORTED,
+                    "too many plane rows for the recursive passes");
+        hipEvent_t ty = c.stage_begin();
+        hipLaunchKernelGGL(row_young, dim3((unsigned)((nr + RT - 1) / RT)), dim3(RT), 0, st, a, hard ? Bpl : Cpl);
+        c.stage_end(FHD_STAGE_ROW, ty);
+        ty = c.stage_begin();
+        hipLaunchKernelGGL(col_young, dim3((unsigned)((nc + RT - 1) / RT)), dim3(RT), 0, st, a);
+        hipLaunchKernelGGL(recomb_young, dim3((unsigned)((fp.N + RT - 1) / RT)), dim3(RT), 0, st, a, hard ? 1 : 0);
+        c.stage_end(FHD_STAGE_COL, ty);
+        FHD_HIP(hipGetLastError());
+        return;
     }
 
     // (the S zero rows above and below every plane come from the row pass)
