@@ -161,6 +161,28 @@ def nlm_leg(torch, fhd, synth):
     return leg
 
 
+def window_leg(torch, fhd, x, sr, K):
+    """The 2048x2048 RGB workload with the truncated-Gaussian FIR window and
+    with the recursive Gaussian (the paper's O(1) convolution), at sigma_s 5
+    and 20: Mpix/s and PSNR against the GPU brute force with the truncated
+    window of radius 3 sigma_s.  The FIR's cost grows with the radius; the
+    recursion's does not."""
+    N = x.shape[1] * x.shape[2]
+    leg = {"workload": "bf_rgb_2048, sigma_r 0.12, K 32: window forms at sigma_s 5 and 20"}
+    for ss in (5.0, 20.0):
+        S = int(round(3 * ss))
+        brute = fhd.bruteforce(x, sigma_s=ss, sigma_r=sr, radius=S)
+        ent = {}
+        for name, kw in (("fir", dict(spatial="gaussian", radius=S)), ("recursive", dict(spatial="young"))):
+            run = lambda: fhd.filter(x, sigma_s=ss, sigma_r=sr, K=K, **kw)
+            o = run()
+            ms = timed(torch, run, 5)
+            ent[name] = {"mpix_s": round(N / ms / 1e3, 2), "ms": round(ms, 3),
+                         "psnr_vs_brute_db": round(psnr(o, brute), 2)}
+        leg[f"sigma_s_{int(ss)}_S{S}"] = ent
+    return leg
+
+
 def batch_leg(torch, np, fhd, synth):
     """The ragged batch of 16 RGB images (384x384 .. 768x1024): one batched
     forward call, then forward plus the batched adjoint (image, guide and
@@ -327,6 +349,7 @@ def main():
         res["forms"] = forms
         res["nlm"] = nlm_leg(torch, fhd, synth)
         res["batch"] = batch_leg(torch, np, fhd, synth)
+        res["window"] = window_leg(torch, fhd, x, sr, K)
 
     if not args.no_cpu and not args.quick:
         res["cpu_baseline"] = cpu_baseline(f, cfg, args.cpu_crop)

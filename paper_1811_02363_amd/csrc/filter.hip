@@ -1092,38 +1092,76 @@ __global__ __launch_bounds__(RT) void sum_blocks(const double* __restrict__ part
 // Recursive Gaussian window (Young and van Vliet; the paper's O(1) choice):
 // every 1-D pass is the causal recursion w[t] = B u[t] + a1 w[t-1] +
 // a2 w[t-2] + a3 w[t-3] from a zero state at the start, then the same
-// anti-causal recursion from a zero state at the end.  Rows first (one thread
-// per plane row; the factor c_l or b_l times [f, 1] formed on the fly from
-// the materialised planes), then columns in place (one thread per plane
-// column, adjacent threads on adjacent columns), then the recombination of
-// eqs. (15)-(16) per pixel.  The planes have no halo rows (S = 0).
-__global__ __launch_bounds__(RT) void row_young(FA a, const float* __restrict__ fac) {
-    const long long t = (long long)blockIdx.x * RT + threadIdx.x;
-    const int planes = a.K * (a.n + 1);
-    if (t >= (long long)planes * a.H) return;
-    const int y = (int)(t % a.H);
-    const int pl = (int)(t / a.H);
+// anti-causal recursion from a zero state at the end.  Rows first (the
+// factor c_l or b_l times [f, 1] formed on the fly from the materialised
+// planes, rows walked in LDS tiles), then columns in place (one thread per
+// plane column, adjacent threads on adjacent columns), then the
+// recombination of eqs. (15)-(16) per pixel.  The planes have no halo rows
+// (S = 0).
+// Row recursions: a block of YT threads takes YT rows of one plane and walks
+// them in YT x YT tiles staged in LDS (loaded and stored row-contiguously,
+// so the global accesses coalesce); thread t runs the recursion of row t
+// across each tile (pitch YT + 1: conflict-free in both directions).
+constexpr int YT = 64;
+
+__global__ __launch_bounds__(YT) void row_young(FA a, const float* __restrict__ fac) {
+    __shared__ float tile[YT][YT + 1];
+    const int nyb = (a.H + YT - 1) / YT;
+    const int pl = blockIdx.x / nyb, y0 = (blockIdx.x - pl * nyb) * YT;
     const int l = pl / (a.n + 1), ch = pl - l * (a.n + 1);
-    const float* cp = fac + (long long)l * a.Np + (long long)y * a.Wp;
-    const float* fr = ch < a.n ? a.f + (long long)ch * a.N + (long long)y * a.W : nullptr;
-    float* dst = a.planes + (long long)pl * a.Pp + (long long)y * a.Wp;
+    const float* cb = fac + (long long)l * a.Np;
+    const float* fb = ch < a.n ? a.f + (long long)ch * a.N : nullptr;
+    float* db = a.planes + (long long)pl * a.Pp;
+    const int t = threadIdx.x;
     const float B = a.yc[0], a1 = a.yc[1], a2 = a.yc[2], a3 = a.yc[3];
     float p1 = 0.0f, p2 = 0.0f, p3 = 0.0f;
-    for (int x = 0; x < a.W; ++x) {
-        const float u = fr != nullptr ? cp[x] * fr[x] : cp[x];
-        const float w = B * u + a1 * p1 + a2 * p2 + a3 * p3;
-        dst[x] = w;
-        p3 = p2;
-        p2 = p1;
-        p1 = w;
+    for (int x0 = 0; x0 < a.W; x0 += YT) {
+        const int x = x0 + t, cnt = min(YT, a.W - x0);
+        for (int r = 0; r < YT; ++r) {
+            const int y = y0 + r;
+            float u = 0.0f;
+            if (y < a.H && x < a.W) {
+                u = cb[(long long)y * a.Wp + x];
+                if (fb != nullptr) u *= fb[(long long)y * a.W + x];
+            }
+            tile[r][t] = u;
+        }
+        __syncthreads();
+        for (int k = 0; k < cnt; ++k) {  // causal: row t
+            const float w = B * tile[t][k] + a1 * p1 + a2 * p2 + a3 * p3;
+            tile[t][k] = w;
+            p3 = p2;
+            p2 = p1;
+            p1 = w;
+        }
+        __syncthreads();
+        for (int r = 0; r < YT; ++r) {
+            const int y = y0 + r;
+            if (y < a.H && x < a.W) db[(long long)y * a.Wp + x] = tile[r][t];
+        }
+        __syncthreads();
     }
     p1 = p2 = p3 = 0.0f;
-    for (int x = a.W - 1; x >= 0; --x) {
-        const float v = B * dst[x] + a1 * p1 + a2 * p2 + a3 * p3;
-        dst[x] = v;
-        p3 = p2;
-        p2 = p1;
-        p1 = v;
+    for (int x0 = (a.W - 1) / YT * YT; x0 >= 0; x0 -= YT) {
+        const int x = x0 + t, cnt = min(YT, a.W - x0);
+        for (int r = 0; r < YT; ++r) {
+            const int y = y0 + r;
+            tile[r][t] = (y < a.H && x < a.W) ? db[(long long)y * a.Wp + x] : 0.0f;
+        }
+        __syncthreads();
+        for (int k = cnt - 1; k >= 0; --k) {  // anti-causal: row t
+            const float v = B * tile[t][k] + a1 * p1 + a2 * p2 + a3 * p3;
+            tile[t][k] = v;
+            p3 = p2;
+            p2 = p1;
+            p1 = v;
+        }
+        __syncthreads();
+        for (int r = 0; r < YT; ++r) {
+            const int y = y0 + r;
+            if (y < a.H && x < a.W) db[(long long)y * a.Wp + x] = tile[r][t];
+        }
+        __syncthreads();
     }
 }
 
@@ -1852,11 +1890,11 @@ void filter_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, cons
     if (fp.spatial == FHD_SPATIAL_YOUNG) {  // recursive Gaussian (materialised weights, S = 0)
         const bool hard = fp.coef == FHD_COEF_HARD;
         const long long planes = (long long)fp.K * (fp.n + 1);
-        const long long nr = planes * fp.H, nc = planes * fp.W;
-        FHD_REQUIRE((nr + RT - 1) / RT < (1LL << 31) && (nc + RT - 1) / RT < (1LL << 31), FHD_EUNSUPPORTED,
+        const long long nr = planes * ((fp.H + YT - 1) / YT), nc = planes * fp.W;
+        FHD_REQUIRE(nr < (1LL << 31) && (nc + RT - 1) / RT < (1LL << 31), FHD_EUNSUPPORTED,
                     "too many plane rows for the recursive passes");
         hipEvent_t ty = c.stage_begin();
-        hipLaunchKernelGGL(row_young, dim3((unsigned)((nr + RT - 1) / RT)), dim3(RT), 0, st, a, hard ? Bpl : Cpl);
+        hipLaunchKernelGGL(row_young, dim3((unsigned)nr), dim3(YT), 0, st, a, hard ? Bpl : Cpl);
         c.stage_end(FHD_STAGE_ROW, ty);
         ty = c.stage_begin();
         hipLaunchKernelGGL(col_young, dim3((unsigned)((nc + RT - 1) / RT)), dim3(RT), 0, st, a);
