@@ -184,7 +184,9 @@ def young_1d(u, sigma, axis):
     """The recursive Gaussian along one axis of u (FP64): the causal pass
     w[t] = B u[t] + a1 w[t-1] + a2 w[t-2] + a3 w[t-3], then the anti-causal
     pass y[t] = B w[t] + a1 y[t+1] + a2 y[t+2] + a3 y[t+3], each from a zero
-    state at its own end of the image (reading A15 of the design notes)."""
+    state at its own end of the image (the paper does not say how the
+    recursions start at the borders; zero states match its zero extension of
+    the input, not of the causal output)."""
     B, a1, a2, a3 = young_coefficients(sigma)
     x = np.moveaxis(_f64(u), axis, 0)
     T = x.shape[0]
