@@ -136,8 +136,8 @@ def nlm_leg(torch, fhd, synth):
     """Nonlocal means on the 1024x1024 workload: the patch-PCA guide, then the
     filter with FP32 and FP16 distance contractions; PSNR against the GPU
     brute force on the same guide and, for denoising, against the clean image."""
-    c3 = synth.CONFIGS[3]
-    noisy, clean = synth.config_input(3)
+    c3 = synth.WORKLOADS["nlm_rgb_1024"]
+    noisy, clean = synth.workload_input("nlm_rgb_1024")
     x = torch.from_numpy(noisy).cuda()
     cl = torch.from_numpy(clean).cuda()
     N = c3["H"] * c3["W"]
@@ -189,8 +189,8 @@ def batch_leg(torch, np, fhd, synth):
     sigma_r gradients).  HBM fraction from the algorithmic bytes per pixel of
     the two-pass design (forward 4 [2n + 2 rho + 2K(n+1)], adjoint
     4 [4K(n+1) + 2K + 7n + 5 rho + 2])."""
-    c4 = synth.CONFIGS[4]
-    imgs = [torch.from_numpy(a).cuda() for a in synth.config_input(4)]
+    c4 = synth.WORKLOADS["bf_rgb_batch16"]
+    imgs = [torch.from_numpy(a).cuda() for a in synth.workload_input("bf_rgb_batch16")]
     flat, sizes = fhd.pack_batch(imgs)
     n, K, S = c4["n"], c4["K"], c4["S"]
     N = sum(h * w for h, w in sizes)
@@ -222,7 +222,7 @@ def batch_leg(torch, np, fhd, synth):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only: this build has no multi-GPU path "
+        print(f"bench.py measures one GPU only: the library has no multi-GPU path "
               f"(asked for --gpus {args.gpus})", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
@@ -234,10 +234,10 @@ def main():
     import paper_1811_02363_amd as fhd
     import synth
 
-    cfg = synth.CONFIGS[1]
+    cfg = synth.WORKLOADS["bf_rgb_2048"]
     H, W, n, K, S = cfg["H"], cfg["W"], cfg["n"], cfg["K"], cfg["S"]
     ss, sr = cfg["sigma_s"], cfg["sigma_r"]
-    f = synth.config_input(1)
+    f = synth.workload_input("bf_rgb_2048")
     x = torch.from_numpy(f).cuda()
     torch.cuda.synchronize()
 
@@ -328,8 +328,8 @@ def main():
                                   "dL/dsigma_r), same workload"}
 
         # BF16 vs FP32 contraction on the 512x512x32 hyperspectral workload
-        c2 = synth.CONFIGS[2]
-        h = torch.from_numpy(synth.config_input(2)).cuda()
+        c2 = synth.WORKLOADS["bf_hyper_512x32"]
+        h = torch.from_numpy(synth.workload_input("bf_hyper_512x32")).cuda()
         ref2 = fhd.bruteforce(h, sigma_s=c2["sigma_s"], sigma_r=c2["sigma_r"], radius=c2["S"])
         ms_b2 = timed(torch, lambda: fhd.bruteforce(h, sigma_s=c2["sigma_s"], sigma_r=c2["sigma_r"],
                                                     radius=c2["S"]), 3)

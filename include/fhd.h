@@ -51,7 +51,7 @@ typedef enum {
     FHD_ENOMEM = -2,        /* device/host allocation failed or caller workspace too small */
     FHD_EHIP = -3,          /* a HIP runtime error */
     FHD_ENUMERIC = -4,      /* strict mode: a non-positive normaliser or non-finite output */
-    FHD_EUNSUPPORTED = -5   /* valid but outside what this build implements */
+    FHD_EUNSUPPORTED = -5   /* valid but outside what this library implements */
 } fhd_status;
 
 /* Spatial window omega of eqs. (13)-(14): the Gaussian truncated at the
@@ -69,7 +69,7 @@ enum { FHD_CONTRACT_FP32 = 0, FHD_CONTRACT_BF16 = 1, FHD_CONTRACT_FP16 = 2 };
  * cluster indicator of eq. (17), which gives eq. (18). */
 enum { FHD_COEF_LSQ = 0, FHD_COEF_HARD = 1 };
 
-/* Limits of this build. */
+/* Limits of this library. */
 #define FHD_MAX_K 128        /* clusters */
 #define FHD_MAX_RHO 64       /* guide dimensions */
 #define FHD_MAX_N 64         /* image channels */

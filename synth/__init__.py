@@ -22,8 +22,8 @@ __all__ = [
     "voronoi_rgb",
     "hyperspectral",
     "batch_sizes",
-    "CONFIGS",
-    "config_input",
+    "WORKLOADS",
+    "workload_input",
 ]
 
 
@@ -119,39 +119,38 @@ def batch_sizes(count: int = 16, seed: int = 1004):
     return sizes
 
 
-# The five workloads.  sigma_s/S for the Gaussian follows S = ceil(3 sigma_s);
-# the box kernel of the nonlocal-means workload is 21x21, i.e. S = 10.
-CONFIGS = {
-    0: dict(name="bf_rgb_256", H=256, W=256, n=3, K=16, sigma_s=3.0, S=9,
-            sigma_r=0.1, spatial="gaussian", seeds=32, noise=0.05),
-    1: dict(name="bf_rgb_2048", H=2048, W=2048, n=3, K=32, sigma_s=5.0, S=15,
-            sigma_r=0.12, spatial="gaussian", seeds=256, noise=0.05),
-    2: dict(name="bf_hyper_512x32", H=512, W=512, n=32, K=64, sigma_s=4.0,
-            S=12, sigma_r=0.2, spatial="gaussian"),
-    3: dict(name="nlm_rgb_1024", H=1024, W=1024, n=3, K=32, sigma_s=None,
-            S=10, sigma_r=0.1 * np.sqrt(75.0), spatial="box", seeds=64,
-            noise=0.1, patch=5, dims=16),
-    4: dict(name="bf_rgb_batch16", n=3, K=32, sigma_s=3.0, S=9, sigma_r=0.1,
-            spatial="gaussian", seeds=32, noise=0.05),
+# The five workloads, by name.  sigma_s/S for the Gaussian follows
+# S = ceil(3 sigma_s); the box kernel of the nonlocal-means workload is 21x21,
+# i.e. S = 10.  ``seed`` seeds the workload's generator.
+WORKLOADS = {
+    "bf_rgb_256": dict(H=256, W=256, n=3, K=16, sigma_s=3.0, S=9, sigma_r=0.1,
+                       spatial="gaussian", seeds=32, noise=0.05, seed=1000),
+    "bf_rgb_2048": dict(H=2048, W=2048, n=3, K=32, sigma_s=5.0, S=15, sigma_r=0.12,
+                        spatial="gaussian", seeds=256, noise=0.05, seed=1001),
+    "bf_hyper_512x32": dict(H=512, W=512, n=32, K=64, sigma_s=4.0, S=12, sigma_r=0.2,
+                            spatial="gaussian", seed=1002),
+    "nlm_rgb_1024": dict(H=1024, W=1024, n=3, K=32, sigma_s=None, S=10,
+                         sigma_r=0.1 * np.sqrt(75.0), spatial="box", seeds=64,
+                         noise=0.1, patch=5, dims=16, seed=1003),
+    "bf_rgb_batch16": dict(n=3, K=32, sigma_s=3.0, S=9, sigma_r=0.1,
+                           spatial="gaussian", seeds=32, noise=0.05, seed=1004),
 }
 
 
-def config_input(c: int, H: int | None = None, W: int | None = None):
-    """The input image of workload ``c`` (seed 1000+c).
+def workload_input(name: str, H: int | None = None, W: int | None = None):
+    """The input image of workload ``name`` (its ``seed``).
 
     ``H``/``W`` override the size (same recipe, same seed) for reduced
-    parity cases.  Workload 4 returns a list of images (seeds 1400+b).
-    Workload 3 returns ``(noisy, clean)``.
+    parity cases.  The batch returns a list of images (seeds 1400+b); the
+    nonlocal-means workload returns ``(noisy, clean)``.
     """
-    cfg = CONFIGS[c]
-    if c == 2:
-        return hyperspectral(H or cfg["H"], W or cfg["W"], 32, 5, 0.5, 0.02,
-                             1000 + c)
-    if c == 4:
+    cfg = WORKLOADS[name]
+    if name == "bf_hyper_512x32":
+        return hyperspectral(H or cfg["H"], W or cfg["W"], 32, 5, 0.5, 0.02, cfg["seed"])
+    if name == "bf_rgb_batch16":
         return [voronoi_rgb(h, w, cfg["seeds"], cfg["noise"], 1400 + b)
                 for b, (h, w) in enumerate(batch_sizes())]
-    if c == 3:
-        return voronoi_rgb(H or cfg["H"], W or cfg["W"], cfg["seeds"],
-                           cfg["noise"], 1000 + c, return_clean=True)
-    return voronoi_rgb(H or cfg["H"], W or cfg["W"], cfg["seeds"], cfg["noise"],
-                       1000 + c)
+    if name == "nlm_rgb_1024":
+        return voronoi_rgb(H or cfg["H"], W or cfg["W"], cfg["seeds"], cfg["noise"], cfg["seed"],
+                           return_clean=True)
+    return voronoi_rgb(H or cfg["H"], W or cfg["W"], cfg["seeds"], cfg["noise"], cfg["seed"])

@@ -54,8 +54,8 @@ def _sampled_err(out, f, g, cen, ss, sr, S, spatial, ys, xs):
 def test_hyperspectral_full_size(fhd):
     """512x512x32, guide = image, K 64, S 12: FP32 and BF16 forms, and the
     tree against the oracle's."""
-    cfg = synth.CONFIGS[2]
-    f = synth.config_input(2)
+    cfg = synth.WORKLOADS["bf_hyper_512x32"]
+    f = synth.workload_input("bf_hyper_512x32")
     fd = _dev(f)
     ys, xs = _samples(512, 512, 120, 21)
     kw = dict(sigma_s=cfg["sigma_s"], sigma_r=cfg["sigma_r"], K=cfg["K"], radius=cfg["S"])
@@ -73,8 +73,8 @@ def test_nlm_full_size(fhd):
     """1024x1024 nonlocal means: the GPU's PCA guide against the oracle's,
     the tree of the GPU guide against the oracle's tree of the same guide,
     FP32 and FP16 sampled outputs."""
-    cfg = synth.CONFIGS[3]
-    noisy, clean = synth.config_input(3)
+    cfg = synth.WORKLOADS["nlm_rgb_1024"]
+    noisy, clean = synth.workload_input("nlm_rgb_1024")
     xd = _dev(noisy)
     g, ev = fhd.nlm_guide(xd, patch=cfg["patch"], dims=cfg["dims"], eigvals=True)
     gr, lam, basis, mean = oracle.nlm_guide(noisy, cfg["patch"], cfg["dims"])
@@ -101,8 +101,8 @@ def test_batch_full_size(fhd):
     """The 16-image ragged batch (384x384 .. 768x1024) in one batched call:
     sampled outputs of every image, and the trees of the smallest and the
     largest image against the oracle's."""
-    cfg = synth.CONFIGS[4]
-    imgs = synth.config_input(4)
+    cfg = synth.WORKLOADS["bf_rgb_batch16"]
+    imgs = synth.workload_input("bf_rgb_batch16")
     flat, sizes = fhd.pack_batch([_dev(x) for x in imgs])
     out, cen, keff = fhd.filter_batch(flat, sizes, 3, sigma_s=cfg["sigma_s"], sigma_r=cfg["sigma_r"],
                                       K=cfg["K"], radius=cfg["S"])
@@ -124,8 +124,8 @@ def test_c1_clustering_invariants_full_size(fhd):
     """2048x2048 RGB, K 32: labels cover the image, every center is the FP64
     mean of its members, E_K equals the sum of the leaves' SSE, and the tree
     equals the oracle's."""
-    cfg = synth.CONFIGS[1]
-    f = synth.config_input(1)
+    cfg = synth.WORKLOADS["bf_rgb_2048"]
+    f = synth.workload_input("bf_rgb_2048")
     cen, lab, info = fhd.cluster(_dev(f), cfg["K"], labels=True)
     lab = lab.cpu().numpy().ravel()
     K = cen.shape[0]
@@ -146,8 +146,8 @@ def test_c1_clustering_invariants_full_size(fhd):
 def test_adjoint_transpose_full_size(fhd):
     """<G, F(d)> = <F^T G, d> at 2048x2048 with a separate guide (the filter
     is linear in f), both sides from the GPU."""
-    cfg = synth.CONFIGS[1]
-    g = synth.config_input(1)
+    cfg = synth.WORKLOADS["bf_rgb_2048"]
+    g = synth.workload_input("bf_rgb_2048")
     rng = np.random.default_rng(31)
     f = rng.random(g.shape, dtype=np.float32)
     d = rng.standard_normal(g.shape).astype(np.float32)

@@ -170,7 +170,7 @@ def test_enough_clusters_matches_bruteforce(fhd):
 def test_filter_end_to_end_c0(fhd):
     """The whole of Algorithm 1 on the 256x256 RGB workload vs the oracle's
     own clustering and filter, and its PSNR vs the brute force, eq. (21)."""
-    f = synth.config_input(0)
+    f = synth.workload_input("bf_rgb_256")
     res = oracle.fhd_filter(f, f, 3.0, 0.1, 16, S=9)
     out, den, cen, info = fhd.filter(_dev(f), sigma_s=3.0, sigma_r=0.1, K=16, return_den=True,
                                      return_centers=True, info=True)
@@ -258,8 +258,8 @@ def test_c1_full_size_sampled(fhd):
     """The 2048x2048 RGB workload in the benchmark's configuration: sampled
     outputs against the oracle's eqs. (13)-(16) evaluated pixel by pixel with
     the GPU's centers, plus brute-force samples for the PSNR estimate."""
-    cfg = synth.CONFIGS[1]
-    f = synth.config_input(1)
+    cfg = synth.WORKLOADS["bf_rgb_2048"]
+    f = synth.workload_input("bf_rgb_2048")
     fd = _dev(f)
     out, cen, info = fhd.filter(fd, sigma_s=cfg["sigma_s"], sigma_r=cfg["sigma_r"], K=cfg["K"],
                                 return_centers=True, info=True)

@@ -368,8 +368,8 @@ def test_psnr_definition():
 
 
 def test_generators_deterministic():
-    a = synth.config_input(0)
-    b = synth.config_input(0)
+    a = synth.workload_input("bf_rgb_256")
+    b = synth.workload_input("bf_rgb_256")
     assert a.shape == (3, 256, 256) and a.dtype == np.float32
     assert np.array_equal(a, b)
     assert a.min() >= 0 and a.max() <= 1
