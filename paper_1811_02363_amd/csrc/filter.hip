@@ -1101,7 +1101,10 @@ __global__ __launch_bounds__(RT) void sum_blocks(const double* __restrict__ part
 // Row recursions: a block of YT threads takes YT rows of one plane and walks
 // them in YT x YT tiles staged in LDS (loaded and stored row-contiguously,
 // so the global accesses coalesce); thread t runs the recursion of row t
-// across each tile (pitch YT + 1: conflict-free in both directions).
+// across each tile (pitch YT + 1: conflict-free in both directions).  A
+// thread's YT loads of a tile column are issued together into registers
+// (addresses clamped into the plane, values outside it zero) before they
+// go to LDS, so they are in flight at once.
 constexpr int YT = 64;
 
 __global__ __launch_bounds__(YT) void row_young(FA a, const float* __restrict__ fac) {
@@ -1109,23 +1112,42 @@ __global__ __launch_bounds__(YT) void row_young(FA a, const float* __restrict__ 
     const int nyb = (a.H + YT - 1) / YT;
     const int pl = blockIdx.x / nyb, y0 = (blockIdx.x - pl * nyb) * YT;
     const int l = pl / (a.n + 1), ch = pl - l * (a.n + 1);
-    const float* cb = fac + (long long)l * a.Np;
-    const float* fb = ch < a.n ? a.f + (long long)ch * a.N : nullptr;
-    float* db = a.planes + (long long)pl * a.Pp;
+    const float* __restrict__ cb = fac + (long long)l * a.Np;
+    const float* __restrict__ fb = ch < a.n ? a.f + (long long)ch * a.N : nullptr;
+    float* __restrict__ db = a.planes + (long long)pl * a.Pp;
     const int t = threadIdx.x;
     const float B = a.yc[0], a1 = a.yc[1], a2 = a.yc[2], a3 = a.yc[3];
+    float v[YT];
+    // tile column x of rows y0 .. y0 + YT - 1 into v (zero outside the plane)
+    auto load_col = [&](const float* __restrict__ src, long long pitch, const float* __restrict__ mul, int x) {
+        const int xc = min(x, a.W - 1);
+#pragma unroll
+        for (int r = 0; r < YT; ++r) {
+            const int yc = min(y0 + r, a.H - 1);
+            v[r] = src[(long long)yc * pitch + xc];
+        }
+        if (mul != nullptr) {
+            float m[YT];
+#pragma unroll
+            for (int r = 0; r < YT; ++r) m[r] = mul[(long long)min(y0 + r, a.H - 1) * a.W + xc];
+#pragma unroll
+            for (int r = 0; r < YT; ++r) v[r] *= m[r];
+        }
+#pragma unroll
+        for (int r = 0; r < YT; ++r) tile[r][t] = (y0 + r < a.H && x < a.W) ? v[r] : 0.0f;
+    };
+    auto store_col = [&](int x) {
+#pragma unroll
+        for (int r = 0; r < YT; ++r) v[r] = tile[r][t];
+        if (x < a.W)
+#pragma unroll
+            for (int r = 0; r < YT; ++r)
+                if (y0 + r < a.H) db[(long long)(y0 + r) * a.Wp + x] = v[r];
+    };
     float p1 = 0.0f, p2 = 0.0f, p3 = 0.0f;
     for (int x0 = 0; x0 < a.W; x0 += YT) {
-        const int x = x0 + t, cnt = min(YT, a.W - x0);
-        for (int r = 0; r < YT; ++r) {
-            const int y = y0 + r;
-            float u = 0.0f;
-            if (y < a.H && x < a.W) {
-                u = cb[(long long)y * a.Wp + x];
-                if (fb != nullptr) u *= fb[(long long)y * a.W + x];
-            }
-            tile[r][t] = u;
-        }
+        const int cnt = min(YT, a.W - x0);
+        load_col(cb, a.Wp, fb, x0 + t);
         __syncthreads();
         for (int k = 0; k < cnt; ++k) {  // causal: row t
             const float w = B * tile[t][k] + a1 * p1 + a2 * p2 + a3 * p3;
@@ -1135,35 +1157,32 @@ __global__ __launch_bounds__(YT) void row_young(FA a, const float* __restrict__ 
             p1 = w;
         }
         __syncthreads();
-        for (int r = 0; r < YT; ++r) {
-            const int y = y0 + r;
-            if (y < a.H && x < a.W) db[(long long)y * a.Wp + x] = tile[r][t];
-        }
+        store_col(x0 + t);
         __syncthreads();
     }
     p1 = p2 = p3 = 0.0f;
     for (int x0 = (a.W - 1) / YT * YT; x0 >= 0; x0 -= YT) {
-        const int x = x0 + t, cnt = min(YT, a.W - x0);
-        for (int r = 0; r < YT; ++r) {
-            const int y = y0 + r;
-            tile[r][t] = (y < a.H && x < a.W) ? db[(long long)y * a.Wp + x] : 0.0f;
-        }
+        const int cnt = min(YT, a.W - x0);
+        load_col(db, a.Wp, nullptr, x0 + t);
         __syncthreads();
         for (int k = cnt - 1; k >= 0; --k) {  // anti-causal: row t
-            const float v = B * tile[t][k] + a1 * p1 + a2 * p2 + a3 * p3;
-            tile[t][k] = v;
+            const float w = B * tile[t][k] + a1 * p1 + a2 * p2 + a3 * p3;
+            tile[t][k] = w;
             p3 = p2;
             p2 = p1;
-            p1 = v;
+            p1 = w;
         }
         __syncthreads();
-        for (int r = 0; r < YT; ++r) {
-            const int y = y0 + r;
-            if (y < a.H && x < a.W) db[(long long)y * a.Wp + x] = tile[r][t];
-        }
+        store_col(x0 + t);
         __syncthreads();
     }
 }
+
+// Column recursions in place: one thread per plane column (adjacent threads
+// on adjacent columns), YC elements of the column loaded together into
+// registers per chunk (row indices clamped into the plane; elements past the
+// end only advance a state that is then dropped, and are not stored).
+constexpr int YC = 16;
 
 __global__ __launch_bounds__(RT) void col_young(FA a) {
     const long long t = (long long)blockIdx.x * RT + threadIdx.x;
@@ -1171,25 +1190,42 @@ __global__ __launch_bounds__(RT) void col_young(FA a) {
     if (t >= (long long)planes * a.W) return;
     const int x = (int)(t % a.W);
     const int pl = (int)(t / a.W);
-    float* col = a.planes + (long long)pl * a.Pp + x;
+    float* __restrict__ col = a.planes + (long long)pl * a.Pp + x;
     const float B = a.yc[0], a1 = a.yc[1], a2 = a.yc[2], a3 = a.yc[3];
+    const int H = a.H;
     float p1 = 0.0f, p2 = 0.0f, p3 = 0.0f;
-    for (int y = 0; y < a.H; ++y) {
-        float* e = col + (long long)y * a.Wp;
-        const float w = B * *e + a1 * p1 + a2 * p2 + a3 * p3;
-        *e = w;
-        p3 = p2;
-        p2 = p1;
-        p1 = w;
+    for (int y0 = 0; y0 < H; y0 += YC) {
+        float v[YC];
+#pragma unroll
+        for (int k = 0; k < YC; ++k) v[k] = col[(long long)min(y0 + k, H - 1) * a.Wp];
+#pragma unroll
+        for (int k = 0; k < YC; ++k) {
+            const float w = B * v[k] + a1 * p1 + a2 * p2 + a3 * p3;
+            v[k] = w;
+            p3 = p2;
+            p2 = p1;
+            p1 = w;
+        }
+#pragma unroll
+        for (int k = 0; k < YC; ++k)
+            if (y0 + k < H) col[(long long)(y0 + k) * a.Wp] = v[k];
     }
     p1 = p2 = p3 = 0.0f;
-    for (int y = a.H - 1; y >= 0; --y) {
-        float* e = col + (long long)y * a.Wp;
-        const float v = B * *e + a1 * p1 + a2 * p2 + a3 * p3;
-        *e = v;
-        p3 = p2;
-        p2 = p1;
-        p1 = v;
+    for (int y1 = H - 1; y1 >= 0; y1 -= YC) {  // rows y1, y1 - 1, ..., y1 - YC + 1
+        float v[YC];
+#pragma unroll
+        for (int k = 0; k < YC; ++k) v[k] = col[(long long)max(y1 - k, 0) * a.Wp];
+#pragma unroll
+        for (int k = 0; k < YC; ++k) {
+            const float w = B * v[k] + a1 * p1 + a2 * p2 + a3 * p3;
+            v[k] = w;
+            p3 = p2;
+            p2 = p1;
+            p1 = w;
+        }
+#pragma unroll
+        for (int k = 0; k < YC; ++k)
+            if (y1 - k >= 0) col[(long long)(y1 - k) * a.Wp] = v[k];
     }
 }
 

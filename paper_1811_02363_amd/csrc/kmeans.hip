@@ -190,6 +190,47 @@ __device__ __forceinline__ double block_sum(double v, double (*red)[64]) {
     return r;
 }
 
+// The assignment step's block record [sumA (rho), sumB (rho), nA, nB] in one
+// LDS round: per value the shuffle tree and the wave order of block_dims and
+// block_sum, so the same sums bit for bit.
+template <int LP, int D>
+__device__ __forceinline__ void block_lloyd_record(double (&sa)[D], double (&sb)[D], double na, double nb,
+                                                   double (*red)[2 * 64 + 2], int rho, RecRef out) {
+    constexpr int LPD = LP * D;
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int o = LP; o < 64; o <<= 1) {
+            sa[k] += __shfl_xor(sa[k], o, 64);
+            sb[k] += __shfl_xor(sb[k], o, 64);
+        }
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        na += __shfl_xor(na, o, 64);
+        nb += __shfl_xor(nb, o, 64);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane < LP)
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+            if (lane * D + k < 64) {
+                red[wave][lane * D + k] = sa[k];
+                red[wave][LPD + lane * D + k] = sb[k];
+            }
+    if (lane == 0) {
+        red[wave][2 * LPD] = na;
+        red[wave][2 * LPD + 1] = nb;
+    }
+    __syncthreads();
+    const int e = threadIdx.x;
+    if (e < 2 * rho + 2) {
+        const int src = e < rho ? e : (e < 2 * rho ? LPD + e - rho : 2 * LPD + e - 2 * rho);
+        double r = red[0][src];
+        for (int q = 1; q < KWAVES; ++q) r += red[q][src];
+        out[e] = r;
+    }
+}
+
 // Finalize helper: res[e] = reduction over the job's blocks of record entry
 // e0 + e, for e < E, with the operation opof(e) (0 sum, 1 min, 2 max).  A
 // fixed order: a power-of-two group of G threads per entry; thread `sub` of a
@@ -425,10 +466,11 @@ __device__ __forceinline__ void lloyd_final(const KmArgs& a, int job, int act, i
 // Record: sumA[rho], sumB[rho], nA, nB.
 template <int LP, int D>
 __global__ __launch_bounds__(KT) void km_lloyd(KmArgs a, int t) {
-    __shared__ double red[KWAVES][64];
+    __shared__ double red[KWAVES][2 * 64 + 2];
     __shared__ double tmp[KT];
     __shared__ double res[2 * FHD_MAX_RHO + 2];
     __shared__ double cen[2 * FHD_MAX_RHO];
+    __shared__ double cpv[2 * FHD_MAX_RHO];
     __shared__ int s_act;
     const int4 bt = a.btab[blockIdx.x];
     const int job = bjob(bt), s = bt.y, cnt = bt.z, rank = bt.w;
@@ -437,15 +479,22 @@ __global__ __launch_bounds__(KT) void km_lloyd(KmArgs a, int t) {
     int* stop_now = a.jstop + (long long)(t & 1) * a.mj + job;
     double* cnow = a.cst + ((long long)(t % 3) * a.mj + job) * 2 * rho;
     if (t > 0) {
-        if (a.jstop[(long long)((t - 1) & 1) * a.mj + job]) {
+        // The stop flag, the job's block count and the previous centers are
+        // fetched together; a job's blocks are contiguous in the block table,
+        // so its first block is this block's index less its rank.
+        const int nblk = a.ji[job * JI_W + JI_NBLK];
+        const int stopped = a.jstop[(long long)((t - 1) & 1) * a.mj + job];
+        const double* cprev = a.cst + ((long long)((t - 1) % 3) * a.mj + job) * 2 * rho;
+        const double cp = threadIdx.x < 2 * rho ? cprev[threadIdx.x] : 0.0;
+        if (stopped | (nblk < 0)) {  // (nblk is never negative: the test keeps its load ahead of the branch)
             if (lead && threadIdx.x == 0) *stop_now = 1;
             return;
         }
-        const int* ji = a.ji + job * JI_W;
-        reduce_records((t - 1) & 1 ? a.part2 : a.part, ji[JI_FIRST], ji[JI_NBLK], a.pst, 0, 2 * rho + 2,
+        reduce_records((t - 1) & 1 ? a.part2 : a.part, (int)blockIdx.x - rank, nblk, a.pst, 0, 2 * rho + 2,
                        [](int) { return 0; }, tmp, res);
-        const double* cprev = a.cst + ((long long)((t - 1) % 3) * a.mj + job) * 2 * rho;
-        if (threadIdx.x == 0) s_act = lloyd_act(res, cprev, rho, t - 1);
+        if (threadIdx.x < 2 * rho) cpv[threadIdx.x] = cp;
+        __syncthreads();
+        if (threadIdx.x == 0) s_act = lloyd_act(res, cpv, rho, t - 1);
         __syncthreads();
         const int act = s_act;
         if (act != 2) {
@@ -510,14 +559,7 @@ __global__ __launch_bounds__(KT) void km_lloyd(KmArgs a, int t) {
         }
     }
     const RecRef rec{(t & 1 ? a.part2 : a.part) + blockIdx.x, a.pst};
-    block_dims<LP, D, 0>(sa, red, rho, rec);
-    block_dims<LP, D, 0>(sb, red, rho, rec + rho);
-    const double tna = block_sum(na, red);
-    const double tnb = block_sum(nb, red);
-    if (threadIdx.x == 0) {
-        rec[2 * rho] = tna;
-        rec[2 * rho + 1] = tnb;
-    }
+    block_lloyd_record<LP, D>(sa, sb, na, nb, red, rho, rec);
 }
 
 // Final labels (assignment with fa, fb): per child member count, SSE around
