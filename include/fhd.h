@@ -273,6 +273,24 @@ fhd_status fhd_bruteforce(fhd_ctx* ctx, const float* f, int n, const float* guid
 fhd_status fhd_nlm_guide(fhd_ctx* ctx, const float* f, int n, int H, int W, int patch, int dims,
                          float* guide, double* eigvals);
 
+/* Anisotropic Gaussian range kernel (Sec. IV: one experiment, the low-light
+ * denoising of Sec. IV-E, uses a separate sigma_r per guide dimension):
+ *   phi(x) = exp(-sum_d x_d^2 / (2 sigma_d^2)).
+ * It equals the isotropic kernel with sigma_r = 1 on the guide scaled per
+ * dimension, so this call writes
+ *   out[d][i] = guide[d][i] / sigma_d      (FP32, correctly rounded)
+ * and every other entry point, given `out` and sigma_r = 1, filters with the
+ * anisotropic kernel; clustering and centers are then in the scaled units.
+ * The map is diagonal and linear, so the same call turns dL/d(out) into
+ * dL/d(guide).
+ *   guide, out  device rho x N (planar), N >= 0 (may be NULL when N == 0);
+ *               out == guide is allowed (in place), any other overlap is
+ *               rejected;
+ *   sigma_d     host array of rho finite values > 0;  1 <= rho <= FHD_MAX_RHO.
+ * Enqueued on the context's stream; does not synchronise. */
+fhd_status fhd_scale_guide(fhd_ctx* ctx, const float* guide, int rho, long long N, const float* sigma_d,
+                           float* out);
+
 /* Stage timing with HIP events on the context's stream (for benchmarks).
  * While enabled, every call records an event pair around each stage's
  * kernels; fhd_timing_read returns, per stage, the summed elapsed

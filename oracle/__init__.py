@@ -14,7 +14,9 @@ Two independent references, both in FP64:
   convolutions eqs. (13)-(14) and the recombination eqs. (15)-(16).
 
 Also: the hard-assignment variant eqs. (17)-(18), the patch-PCA guide for
-nonlocal means (Sec. IV-C), the PSNR of eq. (21).
+nonlocal means (Sec. IV-C), the anisotropic range kernel (Sec. IV, IV-E) as a
+direct brute force and as the scaled guide the method filters, the PSNR of
+eq. (21).
 
 The heavy loops (window sums) live in ``fhd_oracle.c`` (plain C + OpenMP),
 compiled with gcc into ``liboracle.so`` beside this file.
@@ -159,6 +161,50 @@ def bruteforce_at(f, guide, sigma_s, sigma_r, ys, xs, S=None, spatial="gaussian"
                                  float(sigma_r), _ip(ys), _ip(xs), M, _dp(out),
                                  _dp(den))
     return out, den
+
+
+def anisotropic_scale(guide, sigma_d):
+    """The guide as the method reads an anisotropic range kernel (Sec. IV;
+    the per-dimension sigma_r of Sec. IV-E): phi(x) = exp(-sum_d x_d^2 /
+    2 sigma_d^2) is the isotropic kernel with sigma_r = 1 of the guide divided
+    by sigma_d per dimension, so the clustering and the whole of Algorithm 1
+    run on that scaled guide.  Here the FP32 guide over the FP32 sigma_d,
+    rounded once to FP32 (the FP64 quotient of two FP32 numbers rounds to the
+    correctly rounded FP32 quotient)."""
+    g = np.asarray(guide, dtype=np.float32).astype(np.float64)
+    s = np.asarray(sigma_d, dtype=np.float32).astype(np.float64).reshape((-1,) + (1,) * (g.ndim - 1))
+    assert s.shape[0] == g.shape[0] and np.all(s > 0) and np.all(np.isfinite(s))
+    return (g / s).astype(np.float32)
+
+
+def bruteforce_anisotropic(f, guide, sigma_s, sigma_d, S=None, spatial="gaussian"):
+    """Eqs. (1)-(2) with the anisotropic range kernel exp(-sum_d x_d^2 /
+    2 sigma_d^2) (Sec. IV), written out in NumPy for small images: for every
+    window offset j the neighbour image p(i - j), its per-dimension weighted
+    squared distance to p(i), and both sums; out-of-image neighbours are left
+    out of both.  Returns (g, eta) in FP64."""
+    f = _f64(f)
+    p = _f64(guide)
+    n, H, W = f.shape
+    s2 = np.asarray(sigma_d, dtype=np.float64).reshape(-1, 1, 1) ** 2
+    if S is None:
+        S = default_radius(sigma_s)
+    om = spatial_kernel_2d(S, sigma_s, spatial)
+    num = np.zeros((n, H, W))
+    eta = np.zeros((H, W))
+    for jy in range(-S, S + 1):
+        for jx in range(-S, S + 1):
+            # pixels i = (y, x) whose neighbour (y - jy, x - jx) is inside
+            y0, y1 = max(0, jy), min(H, H + jy)
+            x0, x1 = max(0, jx), min(W, W + jx)
+            if y0 >= y1 or x0 >= x1:
+                continue
+            pi = p[:, y0:y1, x0:x1]
+            pq = p[:, y0 - jy:y1 - jy, x0 - jx:x1 - jx]
+            w = om[jy + S, jx + S] * np.exp(-(((pq - pi) ** 2) / (2.0 * s2)).sum(0))
+            num[:, y0:y1, x0:x1] += w * f[:, y0 - jy:y1 - jy, x0 - jx:x1 - jx]
+            eta[y0:y1, x0:x1] += w
+    return num / eta, eta
 
 
 def young_coefficients(sigma):

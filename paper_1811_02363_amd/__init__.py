@@ -19,7 +19,7 @@ __all__ = [
     "FHDError", "Params", "Info", "load", "lib_path", "symbols",
     "filter", "filter_centers", "filter_backward", "FilterFunction", "filter_autograd",
     "pack_batch", "filter_batch", "filter_batch_backward",
-    "cluster", "pinv", "bruteforce", "nlm_guide",
+    "cluster", "pinv", "bruteforce", "nlm_guide", "scale_guide", "ScaleGuide",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -37,7 +37,7 @@ symbols = [
     "fhd_default_params", "fhd_create", "fhd_destroy", "fhd_set_stream", "fhd_last_error",
     "fhd_workspace_size", "fhd_set_workspace", "fhd_cluster", "fhd_pinv",
     "fhd_filter_centers", "fhd_filter", "fhd_filter_backward", "fhd_filter_batch",
-    "fhd_filter_batch_backward", "fhd_bruteforce", "fhd_nlm_guide",
+    "fhd_filter_batch_backward", "fhd_bruteforce", "fhd_nlm_guide", "fhd_scale_guide",
     "fhd_timing_enable", "fhd_timing_read",
 ]
 STAGES = ("cluster", "weights", "row", "col", "brute")
@@ -108,6 +108,7 @@ def load():
                                               P(D), P(D)]),
             "fhd_bruteforce": (I, [V, V, I, V, I, I, I, pp, V, V]),
             "fhd_nlm_guide": (I, [V, V, I, I, I, I, I, V, V]),
+            "fhd_scale_guide": (I, [V, V, I, ctypes.c_longlong, V, V]),
             "fhd_timing_enable": (I, [V, I]),
             "fhd_timing_read": (I, [V, P(D), P(I)]),
         }
@@ -176,12 +177,34 @@ def _shape(f, guide):
     return f.shape[0], g.shape[0], f.shape[1], f.shape[2], g
 
 
+def _scalar(x):
+    if isinstance(x, torch.Tensor):
+        return x.dim() == 0
+    try:
+        len(x)
+    except TypeError:
+        return True
+    return False
+
+
+def _range(g, sigma_r):
+    """A scalar sigma_r passes through; one value per guide dimension (the
+    anisotropic kernel) becomes the guide scaled by fhd_scale_guide and
+    sigma_r = 1."""
+    if _scalar(sigma_r):
+        return g, sigma_r
+    return scale_guide(g, sigma_r), 1.0
+
+
 def filter(f, guide=None, sigma_s=3.0, sigma_r=0.1, K=16, spatial="gaussian", radius=None,
            contract="fp32", coef="lsq", kmeans_max_iter=20, return_den=False,
            return_centers=False, info=False, strict=False):
     """Algorithm 1 end to end: returns g_hat (n, H, W) [, den (H, W)]
-    [, centers (K_eff, rho) on the host] [, info dict]."""
+    [, centers (K_eff, rho) on the host] [, info dict].  ``sigma_r`` is a
+    number, or one value per guide dimension (anisotropic kernel; centers are
+    then in the units of the scaled guide, see :func:`scale_guide`)."""
     n, rho, H, W, g = _shape(f, guide)
+    g, sigma_r = _range(g, sigma_r)
     ctx = _ctx(f.device.index)
     p = make_params(sigma_s, sigma_r, K, spatial, radius, contract, coef, kmeans_max_iter,
                     strict=strict)
@@ -206,8 +229,10 @@ def filter(f, guide=None, sigma_s=3.0, sigma_r=0.1, K=16, spatial="gaussian", ra
 def filter_centers(f, guide, centers, sigma_s=3.0, sigma_r=0.1, spatial="gaussian", radius=None,
                    contract="fp32", coef="lsq", labels=None, return_den=False, info=False,
                    strict=False):
-    """Steps 2-5 with given centers (host or device (K, rho) float32)."""
+    """Steps 2-5 with given centers (host or device (K, rho) float32); a
+    per-dimension ``sigma_r`` as in :func:`filter` (centers in scaled units)."""
     n, rho, H, W, g = _shape(f, guide)
+    g, sigma_r = _range(g, sigma_r)
     ctx = _ctx(f.device.index)
     c = torch.as_tensor(centers, dtype=torch.float32).detach().cpu().contiguous()
     K = c.shape[0]
@@ -311,8 +336,13 @@ def filter_autograd(f, guide=None, sigma_s=3.0, sigma_r=0.1, K=16, spatial="gaus
                     radius=None, contract="fp32", centers=None, kmeans_max_iter=20):
     """Differentiable Algorithm 1: the centers come from the bisecting K-means
     of the (detached) guide unless given, then :class:`FilterFunction`.
-    ``sigma_r`` and ``sigma_s`` may be 0-d tensors that require grad."""
+    ``sigma_r`` and ``sigma_s`` may be 0-d tensors that require grad; a
+    ``sigma_r`` of one value per guide dimension (constants) filters the guide
+    scaled by :class:`ScaleGuide` with sigma_r = 1, gradients flowing back to
+    the unscaled guide."""
     g = f if guide is None else guide
+    if not _scalar(sigma_r):
+        g, sigma_r = ScaleGuide.apply(g, sigma_r), 1.0
     if centers is None:
         centers, _ = cluster(g.detach(), K, max_iter=kmeans_max_iter)
     return FilterFunction.apply(f, g, sigma_r, centers, sigma_s, spatial, radius, contract)
@@ -438,8 +468,10 @@ def pinv(centers, sigma_r, rtol=0.0):
 
 def bruteforce(f, guide=None, sigma_s=3.0, sigma_r=0.1, spatial="gaussian", radius=None,
                return_den=False):
-    """Eqs. (1)-(2) directly on the GPU (FP32)."""
+    """Eqs. (1)-(2) directly on the GPU (FP32); a per-dimension ``sigma_r`` as
+    in :func:`filter`."""
     n, rho, H, W, g = _shape(f, guide)
+    g, sigma_r = _range(g, sigma_r)
     ctx = _ctx(f.device.index)
     p = make_params(sigma_s, sigma_r, 1, spatial, radius)
     out = torch.empty_like(f)
@@ -463,6 +495,42 @@ def nlm_guide(f, patch=5, dims=16, eigvals=False):
     _check(load().fhd_nlm_guide(ctx, _dev(f, "f"), n, H, W, int(patch), int(dims), _dev(g, "guide"),
                                 ctypes.c_void_p(ev.data_ptr()) if eigvals else None), ctx)
     return (g, ev) if eigvals else g
+
+
+def scale_guide(guide, sigma_d, out=None):
+    """guide[d] / sigma_d per dimension on the device (``fhd_scale_guide``):
+    filtering the result with sigma_r = 1 filters ``guide`` with the
+    anisotropic range kernel exp(-sum_d x_d^2 / 2 sigma_d^2).  ``guide`` is
+    (rho, ...) float32 on the device; ``sigma_d`` holds rho positive values;
+    ``out`` may be ``guide`` itself."""
+    if not isinstance(guide, torch.Tensor) or not guide.is_cuda or guide.dim() < 1:
+        raise FHDError(FHD_EINVAL, "guide must be a (rho, ...) CUDA (HIP) tensor")
+    rho = guide.shape[0]
+    s = torch.as_tensor(sigma_d, dtype=torch.float32).detach().cpu().contiguous().reshape(-1)
+    if s.numel() != rho:
+        raise FHDError(FHD_EINVAL, f"sigma_d needs {rho} values (one per guide dimension)")
+    ctx = _ctx(guide.device.index)
+    res = torch.empty_like(guide) if out is None else out
+    if res.shape != guide.shape:
+        raise FHDError(FHD_EINVAL, "out must have the guide's shape")
+    N = guide.numel() // rho if rho else 0
+    _check(load().fhd_scale_guide(ctx, _dev(guide, "guide"), rho, N, ctypes.c_void_p(s.data_ptr()),
+                                  _dev(res, "out")), ctx)
+    return res
+
+
+class ScaleGuide(torch.autograd.Function):
+    """:func:`scale_guide` with its adjoint (the same diagonal map) for
+    gradients with respect to the unscaled guide; ``sigma_d`` is a constant."""
+
+    @staticmethod
+    def forward(ctx, guide, sigma_d):
+        ctx.sigma_d = torch.as_tensor(sigma_d, dtype=torch.float32).detach().cpu()
+        return scale_guide(guide.detach().contiguous(), ctx.sigma_d)
+
+    @staticmethod
+    def backward(ctx, grad):
+        return scale_guide(grad.contiguous(), ctx.sigma_d), None
 
 
 def timing_enable(device=0, enable=True):

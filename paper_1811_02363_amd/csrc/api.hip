@@ -252,6 +252,17 @@ fhd_status guarded(fhd_ctx* ctx, F&& body) {
     }
 }
 
+// out[d][i] = guide[d][i] / sigma_d, correctly rounded; one thread per entry.
+struct RangeScales {
+    float s[FHD_MAX_RHO];
+};
+__global__ __launch_bounds__(256) void scale_guide_kernel(const float* guide, long long N, int rho, RangeScales sc,
+                                                          float* out) {
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= N * rho) return;
+    out[e] = __fdiv_rn(guide[e], sc.s[(int)(e / N)]);
+}
+
 // Counts of non-positive normalisers and non-finite outputs (strict mode).
 __global__ void check_output(const float* out, long long count, const float* den, long long N,
                              unsigned long long* bad) {
@@ -876,6 +887,31 @@ fhd_status fhd_nlm_guide(fhd_ctx* ctx, const float* f, int n, int H, int W, int 
         Arena ws = c.arena(nlm_workspace(n, H, W, patch, dims));
         nlm_guide_run(c, ws, f, n, H, W, patch, dims, guide, eigvals);
         if (eigvals) FHD_HIP(hipStreamSynchronize(c.stream));
+    });
+}
+
+fhd_status fhd_scale_guide(fhd_ctx* ctx, const float* guide, int rho, long long N, const float* sigma_d,
+                           float* out) {
+    return guarded(ctx, [&](Ctx& c) {
+        FHD_REQUIRE(sigma_d != nullptr, FHD_EINVAL, "sigma_d is NULL");
+        FHD_REQUIRE(rho >= 1 && rho <= FHD_MAX_RHO, FHD_EINVAL, "rho must be in [1, FHD_MAX_RHO]");
+        FHD_REQUIRE(N >= 0, FHD_EINVAL, "N must be >= 0");
+        FHD_REQUIRE(N < (1LL << 38) / rho, FHD_EUNSUPPORTED, "guide has 2^38 entries or more");
+        RangeScales sc{};
+        for (int d = 0; d < rho; ++d) {
+            FHD_REQUIRE(std::isfinite(sigma_d[d]) && sigma_d[d] > 0.0f, FHD_EINVAL,
+                        "every sigma_d must be finite and > 0");
+            sc.s[d] = sigma_d[d];
+        }
+        if (N == 0) return;
+        FHD_REQUIRE(guide != nullptr && out != nullptr, FHD_EINVAL, "NULL pointer");
+        const size_t bytes = sizeof(float) * (size_t)N * rho;
+        FHD_REQUIRE(out == guide || !ranges_overlap(out, bytes, guide, bytes), FHD_EINVAL,
+                    "out overlaps guide without being equal to it");
+        const long long blocks = (N * rho + 255) / 256;
+        hipLaunchKernelGGL(scale_guide_kernel, dim3((unsigned)blocks), dim3(256), 0, c.stream, guide, N, rho, sc,
+                           out);
+        FHD_HIP(hipGetLastError());
     });
 }
 

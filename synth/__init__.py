@@ -100,6 +100,29 @@ def hyperspectral(H: int, W: int, bands: int, endmembers: int, alpha: float,
     return np.clip(cube, 0.0, 1.0).astype(np.float32)
 
 
+def lowlight_ir(H: int, W: int, seeds: int, gain: float, noise: float, ir_noise: float,
+                seed: int):
+    """A dim noisy color image and an infrared channel of the same scene.
+
+    Draw order from ``default_rng(seed)``: the clean scene as in
+    :func:`voronoi_rgb` (seed positions, seed colors; no noise draw), then
+    ``normal(0, noise, (3,H,W))`` for the color image and
+    ``normal(0, ir_noise, (H,W))`` for the infrared one.  The color image is
+    gain * clean + noise; the infrared image is the scene's mean over the
+    three colors plus its noise (it shares the scene's edges).  Both clipped
+    to [0,1], float32; returns (color (3,H,W), infrared (1,H,W)).
+    """
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(0.0, 1.0, size=(seeds, 2))
+    cols = rng.uniform(0.0, 1.0, size=(seeds, 3))
+    lab = _nearest_seed(H, W, pos[:, 0] * H, pos[:, 1] * W)
+    clean = np.transpose(cols[lab], (2, 0, 1))
+    low = gain * clean + rng.normal(0.0, noise, size=(3, H, W))
+    ir = clean.mean(axis=0) + rng.normal(0.0, ir_noise, size=(H, W))
+    return (np.clip(low, 0.0, 1.0).astype(np.float32),
+            np.clip(ir, 0.0, 1.0).astype(np.float32)[None])
+
+
 def batch_sizes(count: int = 16, seed: int = 1004):
     """Image sizes of the ragged batch.
 

@@ -1,0 +1,134 @@
+"""The anisotropic range kernel (Sec. IV; per-dimension sigma_r as in the
+low-light denoising of Sec. IV-E) through the C ABI: ``fhd_scale_guide``
+followed by the isotropic path with sigma_r = 1.
+
+* The scaled guide is bit-exact against the oracle's correctly rounded FP32
+  quotient (also in place and on ragged sizes).
+* Algorithm 1 on a low-light color image guided by six smooth dimensions plus
+  an infrared channel (sigma 5:1 between them, K 32, 17x17 box window as in
+  Sec. IV-E), end to end against the oracle on the same scaled guide: centers
+  max-abs 1e-6, output max-abs 1e-4 (the FP32 path's bar).
+* The GPU brute force with per-dimension sigma_r against the oracle's direct
+  NumPy brute force of the anisotropic kernel: max-abs 1e-4.
+* Gradients with respect to f and the unscaled guide through ``ScaleGuide``
+  against FP64 autograd of the oracle's filter on guide / sigma_d: relative
+  L2 1e-4.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle import autograd_ref as ar
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+SIGMA = [0.35] * 6 + [0.07]
+
+
+@pytest.fixture(scope="module")
+def fhd():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1811_02363_amd as m
+    m.load()
+    return m
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _lowlight(H, W, seed):
+    f, ir = synth.lowlight_ir(H, W, 20, 0.2, 0.03, 0.01, seed)
+    g6 = synth.hyperspectral(H, W, 6, 4, 0.5, 0.02, seed + 1)
+    return f, np.concatenate([g6, ir], 0)
+
+
+@pytest.mark.parametrize("rho,N", [(1, 1), (7, 1000), (3, 4096), (64, 333)])
+def test_scale_guide_bit_exact(fhd, rho, N):
+    rng = np.random.default_rng(rho * 1000 + N)
+    g = (rng.standard_normal((rho, N)) * rng.uniform(0.01, 100, (rho, 1))).astype(np.float32)
+    sd = rng.uniform(1e-3, 50, rho).astype(np.float32)
+    ref = oracle.anisotropic_scale(g, sd)
+    gd = _dev(g)
+    out = fhd.scale_guide(gd, sd)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().view(np.uint32), ref.view(np.uint32))
+    fhd.scale_guide(gd, sd, out=gd)  # in place
+    torch.cuda.synchronize()
+    assert np.array_equal(gd.cpu().numpy().view(np.uint32), ref.view(np.uint32))
+
+
+def test_scale_guide_rejections(fhd):
+    g = _dev(np.ones((3, 50)))
+    for bad in ([1.0, 0.0, 1.0], [1.0, -2.0, 1.0], [1.0, float("nan"), 1.0], [1.0, float("inf"), 1.0]):
+        with pytest.raises(fhd.FHDError) as e:
+            fhd.scale_guide(g, bad)
+        assert e.value.status == fhd.FHD_EINVAL
+    with pytest.raises(fhd.FHDError):
+        fhd.scale_guide(g, [1.0, 2.0])  # one value per dimension
+    with pytest.raises(fhd.FHDError) as e:
+        fhd.scale_guide(_dev(np.ones((65, 4))), np.ones(65))
+    assert e.value.status == fhd.FHD_EINVAL
+    buf = _dev(np.ones(201))
+    with pytest.raises(fhd.FHDError) as e:  # overlapping but not equal
+        fhd.scale_guide(buf[:200].view(2, 100), [1.0, 2.0], out=buf[1:201].view(2, 100))
+    assert e.value.status == fhd.FHD_EINVAL
+    empty = fhd.scale_guide(_dev(np.ones((3, 0))), [1.0, 2.0, 3.0])
+    assert empty.shape == (3, 0)
+
+
+def test_lowlight_ir_end_to_end(fhd):
+    f, g = _lowlight(72, 90, 31)
+    gs = oracle.anisotropic_scale(g, SIGMA)
+    res = oracle.fhd_filter(f, gs, None, 1.0, 32, S=8, spatial="box")
+    cond = float(np.linalg.cond(res.A))
+    out, cen = fhd.filter(_dev(f), _dev(g), sigma_r=SIGMA, K=32, spatial="box", radius=8,
+                          return_centers=True)
+    torch.cuda.synchronize()
+    cerr = np.abs(cen.numpy() - res.centers).max()
+    err = np.abs(out.cpu().numpy() - res.out).max()
+    bf, _ = oracle.bruteforce_anisotropic(f, g, None, SIGMA, S=8, spatial="box")
+    print(f"low-light + IR: cond(A) {cond:.0f}, centers {cerr:.2e}, max-abs {err:.2e}, "
+          f"PSNR vs anisotropic brute force {oracle.psnr(out.cpu().numpy(), bf):.2f} dB")
+    assert cond < 2e3
+    assert cerr < 1e-6 and err < TOL
+
+
+def test_anisotropic_bruteforce(fhd):
+    f, g = _lowlight(50, 61, 41)
+    ref, eta = oracle.bruteforce_anisotropic(f, g, None, SIGMA, S=8, spatial="box")
+    out, den = fhd.bruteforce(_dev(f), _dev(g), sigma_r=SIGMA, spatial="box", radius=8, return_den=True)
+    torch.cuda.synchronize()
+    err = np.abs(out.cpu().numpy() - ref).max()
+    derr = np.abs(den.cpu().numpy() - eta).max() / eta.max()
+    print(f"anisotropic brute force: max-abs {err:.2e}, eta rel {derr:.2e}")
+    assert err < TOL and derr < 1e-5
+
+
+def test_anisotropic_autograd(fhd):
+    f, g = _lowlight(34, 45, 51)
+    sd = np.array(SIGMA)
+    K, ss, S = 12, 2.0, 6
+    cen = oracle.bisecting_kmeans(oracle.anisotropic_scale(g, sd), K).centers.astype(np.float32)
+    fd = _dev(f).requires_grad_(True)
+    gd = _dev(g).requires_grad_(True)
+    out = fhd.filter_autograd(fd, gd, sigma_s=ss, sigma_r=sd, centers=torch.from_numpy(cen), radius=S)
+    G = np.random.default_rng(52).standard_normal(f.shape).astype(np.float32)
+    (out * _dev(G)).sum().backward()
+    ft = torch.tensor(f, dtype=torch.float64, requires_grad=True)
+    pt = torch.tensor(g, dtype=torch.float64, requires_grad=True)
+    scaled = pt / torch.tensor(sd, dtype=torch.float64)[:, None, None]
+    ro, _ = ar.fast_filter_torch(ft, scaled, cen.astype(np.float64), ss, 1.0, S)
+    (ro * torch.tensor(G, dtype=torch.float64)).sum().backward()
+
+    def rel(a, b):
+        return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+    ef = rel(fd.grad.cpu().numpy(), ft.grad.numpy())
+    eg = rel(gd.grad.cpu().numpy(), pt.grad.numpy())
+    print(f"anisotropic autograd: rel L2 df {ef:.2e}, dguide {eg:.2e}")
+    assert ef < TOL and eg < TOL
