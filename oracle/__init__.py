@@ -15,7 +15,8 @@ Two independent references, both in FP64:
 
 Also: the hard-assignment variant eqs. (17)-(18), the patch-PCA guide for
 nonlocal means (Sec. IV-C), the anisotropic range kernel (Sec. IV, IV-E) as a
-direct brute force and as the scaled guide the method filters, the PSNR of
+direct brute force and as the scaled guide the method filters, the error of
+the kernel approximation (eq. (10) at c = A^+ b, Sec. II-B), the PSNR of
 eq. (21).
 
 The heavy loops (window sums) live in ``fhd_oracle.c`` (plain C + OpenMP),
@@ -483,6 +484,40 @@ def fast_filter(f, guide, centers, P, sigma_s, sigma_r, S=None,
         v += C[:, k] * V[:n]
         r += C[:, k] * V[n]
     return (v / r).reshape(n, H, W), r.reshape(H, W)
+
+
+def approx_error(guide, centers, sigma_r, S, P=None):
+    """The error of the kernel approximation eq. (9) at the pixels' own
+    samples: for every pixel i, the objective of eq. (10) evaluated at the
+    coefficients the method uses, c(i) = A^+ b(i) (eqs. (11)-(12)),
+        err(i) = sum_{x in Theta_i} (phi(x - p(i)) - sum_k c_k(i) phi(x - mu_k))^2,
+    Theta_i the guide values of the in-image pixels of the (2S+1)^2 window
+    around i (A1; a multiset, A4).  Its mean over the pixels is the error
+    E_K of Sec. II-B.  Vectorised over the pixels, one window offset at a
+    time.  Returns (err (H, W) FP64, E_K)."""
+    p = _f64(guide)
+    rho, H, W = p.shape
+    mu = np.asarray(centers, dtype=np.float64).reshape(-1, rho)
+    K = mu.shape[0]
+    if P is None:
+        P, _, _ = pinv(kernel_matrix(mu, sigma_r))
+    X = p.reshape(rho, -1).T
+    B = phi(((X[:, None, :] - mu[None, :, :]) ** 2).sum(-1), sigma_r)  # b_k(i), N x K
+    Bimg = B.T.reshape(K, H, W)
+    Cimg = (B @ np.asarray(P, dtype=np.float64).T).T.reshape(K, H, W)  # c(i) = A^+ b(i)
+    err = np.zeros((H, W))
+    for jy in range(-S, S + 1):
+        for jx in range(-S, S + 1):
+            y0, y1 = max(0, jy), min(H, H + jy)
+            x0, x1 = max(0, jx), min(W, W + jx)
+            if y0 >= y1 or x0 >= x1:
+                continue
+            qy, qx = slice(y0 - jy, y1 - jy), slice(x0 - jx, x1 - jx)
+            iy, ix = slice(y0, y1), slice(x0, x1)
+            exact = phi(((p[:, qy, qx] - p[:, iy, ix]) ** 2).sum(0), sigma_r)
+            fit = (Cimg[:, iy, ix] * Bimg[:, qy, qx]).sum(0)  # phi(x - mu_k) = b_k(q)
+            err[iy, ix] += (exact - fit) ** 2
+    return err, float(err.mean())
 
 
 def fast_filter_at(f, guide, centers, P, sigma_s, sigma_r, ys, xs, S=None,
