@@ -41,7 +41,7 @@ FP32_VECTOR_PEAK = 157.3     # TFLOP/s, MI355X published FP32 vector (packed FMA
 # scaled by what the counters read for a 1 GiB device copy: 524,302 KiB
 # fetched, 1,048,576 KiB written), for the kernels as they are in this tree;
 # an entry is None when the counters have not been taken for that version.
-MEASURED_TRAFFIC = {"row": 2250146645, "col": 2495217834}
+MEASURED_TRAFFIC = {"row": 2250108458, "col": 2492437504}
 
 
 def parse():
@@ -181,6 +181,26 @@ def window_leg(torch, fhd, x, sr, K):
                          "psnr_vs_brute_db": round(psnr(o, brute), 2)}
         leg[f"sigma_s_{int(ss)}_S{S}"] = ent
     return leg
+
+
+def approx_error_leg(torch, fhd, synth):
+    """E_K (eq. (10) at c = A^+ b, averaged over the pixels) against K for a
+    3-dimensional and a 32-dimensional guide, clusters from the library's own
+    bisecting K-means: the fall of the approximation error with K (Sec. II-B)."""
+    legs = {}
+    for name, K_list in (("bf_rgb_256", (4, 8, 16, 32, 64)), ("bf_hyper_512x32", (8, 16, 32, 64))):
+        c = synth.WORKLOADS[name]
+        g = torch.from_numpy(synth.workload_input(name)).cuda()
+        row = {"guide": f"{name}: rho {g.shape[0]}, sigma_r {c['sigma_r']}, window {2 * c['S'] + 1}^2"}
+        for K in K_list:
+            cen, _ = fhd.cluster(g, K)
+            run = lambda: fhd.approx_error(g, cen, sigma_r=c["sigma_r"], radius=c["S"], spatial="box",
+                                           per_pixel=False)
+            _, EK = run()
+            ms = timed(torch, run, 2)
+            row[f"K{K}"] = {"E_K": float(f"{EK:.4e}"), "K_eff": int(cen.shape[0]), "ms": round(ms, 2)}
+        legs[name] = row
+    return legs
 
 
 def batch_leg(torch, np, fhd, synth):
@@ -350,6 +370,7 @@ def main():
         res["nlm"] = nlm_leg(torch, fhd, synth)
         res["batch"] = batch_leg(torch, np, fhd, synth)
         res["window"] = window_leg(torch, fhd, x, sr, K)
+        res["approx_error"] = approx_error_leg(torch, fhd, synth)
 
     if not args.no_cpu and not args.quick:
         res["cpu_baseline"] = cpu_baseline(f, cfg, args.cpu_crop)

@@ -273,6 +273,24 @@ fhd_status fhd_bruteforce(fhd_ctx* ctx, const float* f, int n, const float* guid
 fhd_status fhd_nlm_guide(fhd_ctx* ctx, const float* f, int n, int H, int W, int patch, int dims,
                          float* guide, double* eigvals);
 
+/* Error of the kernel approximation at each pixel's own samples (Sec. II-B):
+ * the objective of eq. (10) evaluated at the coefficients the method uses,
+ * c(i) = A^+ b(i) of eqs. (11)-(12),
+ *   err[i] = sum_{q} (phi(p(q) - p(i)) - sum_k c_k(i) phi(p(q) - mu_k))^2,
+ * q over the in-image pixels of the (2S+1)^2 window around i (the set Theta_i
+ * of eq. (10), counted with multiplicity).  Its pixel mean is the error E_K
+ * whose fall with K the paper plots.
+ *   guide    device rho x H x W;  centers host K x rho FP32, 1 <= K <= 64;
+ *   p        sigma_r, pinv_rtol and the window: radius (or ceil(3 sigma_s)
+ *            when radius < 0, Gaussian), box needs radius >= 0; the recursive
+ *            Gaussian is rejected (no finite window);
+ *   err      device H x W FP32 (output) or NULL;
+ *   mean     host, E_K (FP64 sum of the per-pixel FP64 sums) or NULL;
+ *            when given the call synchronises.  At least one of the two.
+ * Terms are FP32 and sums FP64.  Cost ~ K (2S+1)^2 (rho + 1) per pixel. */
+fhd_status fhd_approx_error(fhd_ctx* ctx, const float* guide, int rho, int H, int W, const float* centers, int K,
+                            const fhd_params* p, float* err, double* mean);
+
 /* Anisotropic Gaussian range kernel (Sec. IV: one experiment, the low-light
  * denoising of Sec. IV-E, uses a separate sigma_r per guide dimension):
  *   phi(x) = exp(-sum_d x_d^2 / (2 sigma_d^2)).

@@ -19,7 +19,7 @@ __all__ = [
     "FHDError", "Params", "Info", "load", "lib_path", "symbols",
     "filter", "filter_centers", "filter_backward", "FilterFunction", "filter_autograd",
     "pack_batch", "filter_batch", "filter_batch_backward",
-    "cluster", "pinv", "bruteforce", "nlm_guide", "scale_guide", "ScaleGuide",
+    "cluster", "pinv", "bruteforce", "nlm_guide", "scale_guide", "ScaleGuide", "approx_error",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -38,6 +38,7 @@ symbols = [
     "fhd_workspace_size", "fhd_set_workspace", "fhd_cluster", "fhd_pinv",
     "fhd_filter_centers", "fhd_filter", "fhd_filter_backward", "fhd_filter_batch",
     "fhd_filter_batch_backward", "fhd_bruteforce", "fhd_nlm_guide", "fhd_scale_guide",
+    "fhd_approx_error",
     "fhd_timing_enable", "fhd_timing_read",
 ]
 STAGES = ("cluster", "weights", "row", "col", "brute")
@@ -109,6 +110,7 @@ def load():
             "fhd_bruteforce": (I, [V, V, I, V, I, I, I, pp, V, V]),
             "fhd_nlm_guide": (I, [V, V, I, I, I, I, I, V, V]),
             "fhd_scale_guide": (I, [V, V, I, ctypes.c_longlong, V, V]),
+            "fhd_approx_error": (I, [V, V, I, I, I, V, I, pp, V, P(D)]),
             "fhd_timing_enable": (I, [V, I]),
             "fhd_timing_read": (I, [V, P(D), P(I)]),
         }
@@ -517,6 +519,27 @@ def scale_guide(guide, sigma_d, out=None):
     _check(load().fhd_scale_guide(ctx, _dev(guide, "guide"), rho, N, ctypes.c_void_p(s.data_ptr()),
                                   _dev(res, "out")), ctx)
     return res
+
+
+def approx_error(guide, centers, sigma_r=0.1, sigma_s=3.0, radius=None, spatial="gaussian",
+                 pinv_rtol=0.0, per_pixel=True):
+    """Error of the kernel approximation (``fhd_approx_error``): eq. (10) at
+    c(i) = A^+ b(i) per pixel and its mean E_K.  ``guide`` (rho, H, W) on the
+    device, ``centers`` (K, rho), K <= 64.  Returns (err (H, W) or None, E_K)."""
+    if not isinstance(guide, torch.Tensor) or not guide.is_cuda or guide.dim() != 3:
+        raise FHDError(FHD_EINVAL, "guide must be a (rho, H, W) CUDA (HIP) tensor")
+    rho, H, W = guide.shape
+    c = torch.as_tensor(centers, dtype=torch.float32).detach().cpu().contiguous()
+    if c.dim() != 2 or c.shape[1] != rho:
+        raise FHDError(FHD_EINVAL, "centers must be (K, rho)")
+    ctx = _ctx(guide.device.index)
+    p = make_params(sigma_s, sigma_r, c.shape[0], spatial, radius, pinv_rtol=pinv_rtol)
+    err = torch.empty((H, W), device=guide.device, dtype=torch.float32) if per_pixel else None
+    m = ctypes.c_double()
+    _check(load().fhd_approx_error(ctx, _dev(guide, "guide"), rho, H, W, ctypes.c_void_p(c.data_ptr()),
+                                   c.shape[0], ctypes.byref(p), _dev(err, "err") if err is not None else None,
+                                   ctypes.byref(m)), ctx)
+    return err, m.value
 
 
 class ScaleGuide(torch.autograd.Function):

@@ -890,6 +890,35 @@ fhd_status fhd_nlm_guide(fhd_ctx* ctx, const float* f, int n, int H, int W, int 
     });
 }
 
+fhd_status fhd_approx_error(fhd_ctx* ctx, const float* guide, int rho, int H, int W, const float* centers, int K,
+                            const fhd_params* p, float* err, double* mean) {
+    return guarded(ctx, [&](Ctx& c) {
+        FHD_REQUIRE(p != nullptr, FHD_EINVAL, "params is NULL");
+        FHD_REQUIRE(guide != nullptr && centers != nullptr, FHD_EINVAL, "NULL pointer");
+        FHD_REQUIRE(err != nullptr || mean != nullptr, FHD_EINVAL, "neither err nor mean requested");
+        FHD_REQUIRE(rho >= 1 && H >= 1 && W >= 1, FHD_EINVAL, "rho, H, W must be >= 1");
+        FHD_REQUIRE(rho <= FHD_MAX_RHO, FHD_EUNSUPPORTED, "rho exceeds FHD_MAX_RHO");
+        FHD_REQUIRE((long long)H * W < (1LL << 31), FHD_EUNSUPPORTED, "image has 2^31 pixels or more");
+        FHD_REQUIRE(K >= 1, FHD_EINVAL, "K must be >= 1");
+        FHD_REQUIRE(K <= 64, FHD_EUNSUPPORTED, "the approximation error takes at most 64 clusters");
+        FHD_REQUIRE(p->sigma_r > 0.0f && !std::isnan(p->sigma_r), FHD_EINVAL, "sigma_r must be > 0");
+        FHD_REQUIRE(p->spatial == FHD_SPATIAL_GAUSSIAN || p->spatial == FHD_SPATIAL_BOX, FHD_EINVAL,
+                    "the window of eq. (10) needs the Gaussian (radius from sigma_s) or box spatial kernel");
+        if (p->spatial == FHD_SPATIAL_GAUSSIAN && p->radius < 0)
+            FHD_REQUIRE(p->sigma_s > 0.0f && std::isfinite(p->sigma_s), FHD_EINVAL, "sigma_s must be > 0");
+        if (p->spatial == FHD_SPATIAL_BOX) FHD_REQUIRE(p->radius >= 0, FHD_EINVAL, "the box kernel needs radius >= 0");
+        const int S = resolve_radius(*p);
+        FHD_REQUIRE(S >= 0 && S <= FHD_MAX_RADIUS, FHD_EUNSUPPORTED, "radius exceeds FHD_MAX_RADIUS");
+        const long long N = (long long)H * W;
+        FHD_REQUIRE(!ranges_overlap(err, sizeof(float) * N, guide, sizeof(float) * N * rho), FHD_EINVAL,
+                    "err aliases the guide");
+        std::vector<float> P32;
+        solve(centers, K, rho, p->sigma_r, p->pinv_rtol, P32);
+        Arena ws = c.arena(approx_error_workspace(H, W, K, rho));
+        approx_error_run(c, ws, guide, rho, H, W, centers, P32.data(), K, S, p->sigma_r, err, mean);
+    });
+}
+
 fhd_status fhd_scale_guide(fhd_ctx* ctx, const float* guide, int rho, long long N, const float* sigma_d,
                            float* out) {
     return guarded(ctx, [&](Ctx& c) {

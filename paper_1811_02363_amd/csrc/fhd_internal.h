@@ -153,6 +153,12 @@ void adjoint_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const 
                  const float* den, const float* gout, float* gradf, float* gradp, double* gsig,
                  double* gsigs, double rtol, double* gmu);
 
+// Error of the kernel approximation (eq. (10) at c = A^+ b) per pixel (err,
+// may be null) and its pixel mean (mean, may be null; synchronises); K <= 64.
+size_t approx_error_workspace(int H, int W, int K, int rho);
+void approx_error_run(Ctx& c, Arena& ws, const float* guide, int rho, int H, int W, const float* centers_host,
+                      const float* Pfp32_host, int K, int S, float sigma_r, float* err, double* mean);
+
 // ---- nonlocal-means guide (nlm.hip) ----------------------------------------
 size_t nlm_workspace(int n, int H, int W, int m, int dims);
 void nlm_guide_run(Ctx& c, Arena& ws, const float* f, int n, int H, int W, int m, int dims, float* guide,

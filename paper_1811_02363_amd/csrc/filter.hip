@@ -1809,6 +1809,99 @@ size_t row_lds_bytes(const FilterPlan& fp, int tx) {
     return fl * sizeof(float);
 }
 
+// ---------------------------------------------------------------------------
+// Error of the kernel approximation at the pixels' own samples: eq. (10)
+// evaluated at the method's coefficients c(i) = A^+ b(i),
+//   err(i) = sum_{q in window(i), in image} (phi(p(q) - p(i)) - sum_k c_k(i) phi(p(q) - mu_k))^2.
+// One thread per pixel (16 x 8 pixels per block).  The centers (zero-padded
+// to RM dimensions) and A^+ sit in LDS, and so does each thread's c(i)
+// (layout [k][thread]: conflict-free); the pixel's guide vector and each
+// neighbour's stay in registers, zero beyond rho (padded dimensions add
+// (0 - 0)^2 = 0).  c(i) is formed without storing b(i): each b_k(i) is
+// recomputed per row of A^+ (K^2 exponentials against the window's K (2S+1)^2).
+// Terms in FP32, sums in FP64; every block writes the FP64 sum of its pixels.
+constexpr int AE_X = 16, AE_Y = 8, AE_T = AE_X * AE_Y;
+
+size_t approx_error_lds(int K, int RM) {
+    return sizeof(float) * ((size_t)K * RM + (size_t)K * K + (size_t)K * AE_T);
+}
+
+template <int RM>
+__global__ __launch_bounds__(AE_T) void approx_error_kernel(const float* __restrict__ guide, int rho, int H, int W,
+                                                            int K, int S, float inv2s2, const float* __restrict__ mu,
+                                                            const float* __restrict__ P, float* __restrict__ err,
+                                                            int gx, double* __restrict__ part) {
+    extern __shared__ float ae_smem[];
+    float* smu = ae_smem;           // K x RM
+    float* sP = smu + K * RM;       // K x K
+    float* sc = sP + K * K;         // K x AE_T
+    __shared__ double red[AE_T / 64];
+    const int t = threadIdx.x;
+    for (int e = t; e < K * RM; e += AE_T) {
+        const int k = e / RM, d = e - k * RM;
+        smu[e] = d < rho ? mu[k * rho + d] : 0.0f;
+    }
+    for (int e = t; e < K * K; e += AE_T) sP[e] = P[e];
+    __syncthreads();
+    const int bx = (int)(blockIdx.x % gx), by = (int)(blockIdx.x / gx);  // 1-D grid of gx-wide tile rows
+    const int x = bx * AE_X + (t % AE_X), y = by * AE_Y + (t / AE_X);
+    const long long N = (long long)H * W;
+    double acc = 0.0;
+    if (x < W && y < H) {
+        const long long i = (long long)y * W + x;
+        float pi[RM];
+#pragma unroll
+        for (int d = 0; d < RM; ++d) pi[d] = d < rho ? guide[d * N + i] : 0.0f;
+        auto phi_mu = [&](const float (&v)[RM], int k) {
+            float s = 0.0f;
+#pragma unroll
+            for (int d = 0; d < RM; ++d) {
+                const float u = v[d] - smu[k * RM + d];
+                s = fmaf(u, u, s);
+            }
+            return __expf(-s * inv2s2);
+        };
+        for (int l = 0; l < K; ++l) {  // c_l(i) = sum_k A^+_lk b_k(i)
+            float s = 0.0f;
+            for (int k = 0; k < K; ++k) s = fmaf(sP[l * K + k], phi_mu(pi, k), s);
+            sc[l * AE_T + t] = s;
+        }
+        for (int dy = -S; dy <= S; ++dy) {
+            const int yy = y - dy;
+            if (yy < 0 || yy >= H) continue;
+            for (int dx = -S; dx <= S; ++dx) {
+                const int xx = x - dx;
+                if (xx < 0 || xx >= W) continue;
+                const long long q = (long long)yy * W + xx;
+                float xq[RM];
+#pragma unroll
+                for (int d = 0; d < RM; ++d) xq[d] = d < rho ? guide[d * N + q] : 0.0f;
+                float s = 0.0f;
+#pragma unroll
+                for (int d = 0; d < RM; ++d) {
+                    const float u = xq[d] - pi[d];
+                    s = fmaf(u, u, s);
+                }
+                float fit = 0.0f;
+                for (int k = 0; k < K; ++k) fit = fmaf(sc[k * AE_T + t], phi_mu(xq, k), fit);
+                const double r = (double)(__expf(-s * inv2s2) - fit);
+                acc = fma(r, r, acc);
+            }
+        }
+        if (err != nullptr) err[i] = (float)acc;
+    }
+    double v = acc;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+    if ((t & 63) == 0) red[t >> 6] = v;
+    __syncthreads();
+    if (t == 0) {
+        double b = 0.0;
+        for (int w = 0; w < AE_T / 64; ++w) b += red[w];
+        part[blockIdx.x] = b;
+    }
+}
+
 }  // namespace
 
 size_t filter_consts_bytes(int K, int rho) {
@@ -2426,6 +2519,48 @@ void bruteforce_run(Ctx& c, const FilterPlan& fp, const float* f, const float* g
     }
     c.stage_end(FHD_STAGE_BRUTE, tb);
     FHD_HIP(hipGetLastError());
+}
+
+
+size_t approx_error_workspace(int H, int W, int K, int rho) {
+    const size_t blocks = (size_t)((W + AE_X - 1) / AE_X) * ((H + AE_Y - 1) / AE_Y);
+    return align_up(sizeof(double) * (blocks + 1), 256) + align_up(filter_consts_bytes(K, rho), 256) + 512;
+}
+
+void approx_error_run(Ctx& c, Arena& ws, const float* guide, int rho, int H, int W, const float* centers_host,
+                      const float* Pfp32_host, int K, int S, float sigma_r, float* err, double* mean) {
+    FHD_REQUIRE(K >= 1 && K <= 64, FHD_EUNSUPPORTED, "the approximation error takes at most 64 clusters");
+    const int RM = rho <= 4 ? 4 : (rho <= 16 ? 16 : 64);
+    const size_t lds = approx_error_lds(K, RM);
+    const size_t cb = filter_consts_bytes(K, rho);
+    char* dev = ws.take<char>(cb);
+    char* hs = static_cast<char*>(c.host_stage(1, cb));
+    filter_consts_fill(centers_host, Pfp32_host, K, rho, hs);
+    FHD_HIP(hipMemcpyAsync(dev, hs, cb, hipMemcpyHostToDevice, c.stream));
+    c.stage_done(1);
+    const FilterConsts kc = filter_consts_at(dev, K, rho);
+    const int gx = (W + AE_X - 1) / AE_X;
+    const int blocks = gx * ((H + AE_Y - 1) / AE_Y);
+    double* part = ws.take<double>((size_t)blocks + 1);
+    const float inv2s2 = std::isinf(sigma_r) ? 0.0f : (float)(1.0 / (2.0 * (double)sigma_r * sigma_r));
+    auto launch = [&](auto kern) {
+        FHD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(AE_T), lds, c.stream, guide, rho, H, W, K, S, inv2s2,
+                           kc.mu, kc.P, err, gx, part);
+    };
+    if (RM == 4) launch(approx_error_kernel<4>);
+    else if (RM == 16) launch(approx_error_kernel<16>);
+    else launch(approx_error_kernel<64>);
+    FHD_HIP(hipGetLastError());
+    if (mean != nullptr) {
+        sum_doubles(c, part, blocks, part + blocks);
+        double* hm = static_cast<double*>(c.host_stage(2, sizeof(double)));
+        FHD_HIP(hipMemcpyAsync(hm, part + blocks, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+        c.stage_done(2);
+        FHD_HIP(hipStreamSynchronize(c.stream));
+        *mean = *hm / ((double)H * W);
+    }
 }
 
 }  // namespace fhd
