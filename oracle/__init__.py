@@ -16,8 +16,8 @@ Two independent references, both in FP64:
 Also: the hard-assignment variant eqs. (17)-(18), the patch-PCA guide for
 nonlocal means (Sec. IV-C), the anisotropic range kernel (Sec. IV, IV-E) as a
 direct brute force and as the scaled guide the method filters, the error of
-the kernel approximation (eq. (10) at c = A^+ b, Sec. II-B), the PSNR of
-eq. (21).
+the kernel approximation (eq. (10) at c = A^+ b, Sec. II-B), the brute force
+and the fast filter on a 3-D domain (Sec. IV-F), the PSNR of eq. (21).
 
 The heavy loops (window sums) live in ``fhd_oracle.c`` (plain C + OpenMP),
 compiled with gcc into ``liboracle.so`` beside this file.
@@ -484,6 +484,84 @@ def fast_filter(f, guide, centers, P, sigma_s, sigma_r, S=None,
         v += C[:, k] * V[:n]
         r += C[:, k] * V[n]
     return (v / r).reshape(n, H, W), r.reshape(H, W)
+
+
+def _window_3d(S, sigma_s, spatial):
+    """omega(j) on [-S,S]^3: Gaussian exp(-|j|^2/2 sigma_s^2) or box (all 1)."""
+    j = np.arange(-S, S + 1, dtype=np.float64)
+    if _spatial_code(spatial) == BOX:
+        return np.ones((2 * S + 1,) * 3)
+    r2 = j[:, None, None] ** 2 + j[None, :, None] ** 2 + j[None, None, :] ** 2
+    return np.exp(-r2 / (2.0 * sigma_s ** 2))
+
+
+def _offsets_3d(D, H, W, S):
+    """Window offsets j = (jz, jy, jx) with the slices of the voxels i whose
+    neighbour i - j lies in the volume, and of those neighbours (A1)."""
+    for jz in range(-S, S + 1):
+        for jy in range(-S, S + 1):
+            for jx in range(-S, S + 1):
+                lo = [max(0, jz), max(0, jy), max(0, jx)]
+                hi = [min(D, D + jz), min(H, H + jy), min(W, W + jx)]
+                if any(a >= b for a, b in zip(lo, hi)):
+                    continue
+                iv = tuple(slice(a, b) for a, b in zip(lo, hi))
+                qv = tuple(slice(a - o, b - o) for a, b, o in zip(lo, hi, (jz, jy, jx)))
+                yield (jz, jy, jx), iv, qv
+
+
+def bruteforce_volume(f, guide, sigma_s, sigma_r, S, spatial="gaussian"):
+    """Eqs. (1)-(2) on a 3-D domain (Sec. IV-F filters a volume): the window
+    [-S,S]^3, omega as in 2-D over |j|, neighbours outside the volume left
+    out.  f (n, D, H, W), guide (rho, D, H, W).  Returns (g, eta) in FP64."""
+    f = _f64(f)
+    p = _f64(guide)
+    n, D, H, W = f.shape
+    om = _window_3d(S, sigma_s, spatial)
+    num = np.zeros_like(f)
+    eta = np.zeros((D, H, W))
+    for (jz, jy, jx), iv, qv in _offsets_3d(D, H, W, S):
+        w = om[jz + S, jy + S, jx + S] * phi(((p[(slice(None),) + qv] - p[(slice(None),) + iv]) ** 2).sum(0),
+                                             sigma_r)
+        num[(slice(None),) + iv] += w * f[(slice(None),) + qv]
+        eta[iv] += w
+    return num / eta, eta
+
+
+def fast_filter_volume(f, guide, centers, P, sigma_s, sigma_r, S, spatial="gaussian"):
+    """Algorithm 1 steps 3-5 on a 3-D domain in the paper's form: b_k(i) and
+    c(i) = A^+ b(i) per voxel (eq. (12)), the (n+1)K window sums of
+    omega(j) b_k(i - j) [f, 1](i - j) over [-S,S]^3 (eqs. (13)-(14), direct,
+    neighbours outside the volume left out), and the ratio of eqs. (15)-(16).
+    Returns (g, r_hat) in FP64."""
+    f = _f64(f)
+    p = _f64(guide)
+    n, D, H, W = f.shape
+    rho = p.shape[0]
+    mu = np.asarray(centers, dtype=np.float64).reshape(-1, rho)
+    K = mu.shape[0]
+    X = p.reshape(rho, -1).T
+    B = phi(((X[:, None, :] - mu[None, :, :]) ** 2).sum(-1), sigma_r).T.reshape(K, D, H, W)
+    C = (np.asarray(P, dtype=np.float64) @ B.reshape(K, -1)).reshape(K, D, H, W)
+    U = np.concatenate([B[:, None] * f[None], B[:, None]], axis=1)  # K x (n+1) x D x H x W
+    om = _window_3d(S, sigma_s, spatial)
+    V = np.zeros_like(U)
+    for (jz, jy, jx), iv, qv in _offsets_3d(D, H, W, S):
+        V[(slice(None), slice(None)) + iv] += om[jz + S, jy + S, jx + S] * U[(slice(None), slice(None)) + qv]
+    v = (C[:, None] * V).sum(0)
+    return v[:n] / v[n], v[n]
+
+
+def fhd_filter_volume(f, guide, sigma_s, sigma_r, K, S, spatial="gaussian", max_iter=20):
+    """The whole of Algorithm 1 on a 3-D domain: the bisecting K-means of the
+    voxels' guide vectors (the volume's voxels in (z, y, x) order, as one
+    set), A and A^+, then :func:`fast_filter_volume`."""
+    rho, D, H, W = np.asarray(guide).shape
+    cl = bisecting_kmeans(np.asarray(guide).reshape(rho, D * H, W), K, max_iter)
+    A = kernel_matrix(cl.centers, sigma_r)
+    P, rank, _ = pinv(A)
+    out, den = fast_filter_volume(f, guide, cl.centers, P, sigma_s, sigma_r, S, spatial)
+    return FilterResult(out, den, cl, cl.centers, A, P, rank)
 
 
 def approx_error(guide, centers, sigma_r, S, P=None):
