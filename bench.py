@@ -203,6 +203,26 @@ def approx_error_leg(torch, fhd, synth):
     return legs
 
 
+def volume_leg(torch, fhd, synth):
+    """Algorithm 1 on a 3-D domain: a 64 x 256 x 256 three-component vector
+    field (as many voxels as the 2048^2 image has pixels), window [-6,6]^3
+    (sigma_s 2), sigma_r 0.12, K 32; Mvox/s and the stage split."""
+    v = torch.from_numpy(synth.voronoi_volume(64, 256, 256, 256, 0.05, 1005)).cuda()
+    run = lambda: fhd.filter_volume(v, sigma_s=2.0, sigma_r=0.12, K=32)
+    run()
+    ms = timed(torch, run, 5)
+    fhd.timing_enable(0, True)
+    fhd.timing_read(0)
+    run()
+    st = fhd.timing_read(0)
+    fhd.timing_enable(0, False)
+    N = v.shape[1] * v.shape[2] * v.shape[3]
+    return {"workload": "volume_64x256x256: 3-component 3-D Voronoi field, noise 0.05, sigma_s 2 (S 6), "
+                        "sigma_r 0.12, K 32",
+            "mvox_s": round(N / ms / 1e3, 1), "ms": round(ms, 3),
+            "stage_ms": {k: round(t, 3) for k, (t, nl) in st.items() if nl}}
+
+
 def batch_leg(torch, np, fhd, synth):
     """The ragged batch of 16 RGB images (384x384 .. 768x1024): one batched
     forward call, then forward plus the batched adjoint (image, guide and
@@ -371,6 +391,7 @@ def main():
         res["batch"] = batch_leg(torch, np, fhd, synth)
         res["window"] = window_leg(torch, fhd, x, sr, K)
         res["approx_error"] = approx_error_leg(torch, fhd, synth)
+        res["volume"] = volume_leg(torch, fhd, synth)
 
     if not args.no_cpu and not args.quick:
         res["cpu_baseline"] = cpu_baseline(f, cfg, args.cpu_crop)

@@ -273,6 +273,22 @@ fhd_status fhd_bruteforce(fhd_ctx* ctx, const float* f, int n, const float* guid
 fhd_status fhd_nlm_guide(fhd_ctx* ctx, const float* f, int n, int H, int W, int patch, int dims,
                          float* guide, double* eigvals);
 
+/* All of Algorithm 1 on a 3-D domain (the flow-field denoising of Sec. IV-F
+ * filters a volume): the bisecting K-means of the voxels' guide vectors (all
+ * D H W voxels as one set, in (z, y, x) order), A and A^+, the weights and
+ * coefficients per voxel, the (n+1)K convolutions over the window
+ * [-S,S]^3 with omega(j) = exp(-|j|^2 / 2 sigma_s^2) (or 1, box), voxels
+ * outside the volume left out, and the recombination of eqs. (15)-(16).
+ *   f      device n x D x H x W;  guide device rho x D x H x W (may alias f);
+ *   out    device n x D x H x W;  den device D x H x W or NULL;
+ *   centers_out  host K x rho or NULL;  info or NULL.
+ * The parameters as for fhd_filter, limited to the Gaussian or box window,
+ * FP32 contraction and least-squares coefficients (FHD_EUNSUPPORTED
+ * otherwise); D * H <= 65535.  Enqueued on the context's stream; the
+ * clustering synchronises as in fhd_filter. */
+fhd_status fhd_filter_volume(fhd_ctx* ctx, const float* f, int n, const float* guide, int rho, int D, int H, int W,
+                             const fhd_params* p, float* out, float* centers_out, float* den, fhd_info* info);
+
 /* Error of the kernel approximation at each pixel's own samples (Sec. II-B):
  * the objective of eq. (10) evaluated at the coefficients the method uses,
  * c(i) = A^+ b(i) of eqs. (11)-(12),

@@ -890,6 +890,60 @@ fhd_status fhd_nlm_guide(fhd_ctx* ctx, const float* f, int n, int H, int W, int 
     });
 }
 
+fhd_status fhd_filter_volume(fhd_ctx* ctx, const float* f, int n, const float* guide, int rho, int D, int H, int W,
+                             const fhd_params* p, float* out, float* centers_out, float* den, fhd_info* info) {
+    return guarded(ctx, [&](Ctx& c) {
+        FHD_REQUIRE(D >= 1 && H >= 1, FHD_EINVAL, "D and H must be >= 1");
+        FHD_REQUIRE((long long)D * H <= 65535, FHD_EUNSUPPORTED, "a volume takes at most 65535 rows (D * H)");
+        check_params(p, n, rho, D * H, W);
+        FHD_REQUIRE(p->spatial != FHD_SPATIAL_YOUNG, FHD_EUNSUPPORTED,
+                    "volumes take the Gaussian or box window (finite, separable over [-S,S]^3)");
+        FHD_REQUIRE(p->contract == FHD_CONTRACT_FP32 && p->coef == FHD_COEF_LSQ, FHD_EUNSUPPORTED,
+                    "volumes take the FP32 least-squares form");
+        FHD_REQUIRE(f && guide && out, FHD_EINVAL, "NULL pointer");
+        const long long N = (long long)D * H * W;
+        FHD_REQUIRE(!ranges_overlap(out, sizeof(float) * N * n, f, sizeof(float) * N * n) &&
+                        !ranges_overlap(out, sizeof(float) * N * n, guide, sizeof(float) * N * rho) &&
+                        !ranges_overlap(den, sizeof(float) * N, f, sizeof(float) * N * n) &&
+                        !ranges_overlap(den, sizeof(float) * N, guide, sizeof(float) * N * rho) &&
+                        !ranges_overlap(den, sizeof(float) * N, out, sizeof(float) * N * n),
+                    FHD_EINVAL, "outputs alias inputs");
+        FHD_REQUIRE((long long)p->K * (n + 1) * N / 256 < (1LL << 31), FHD_EUNSUPPORTED,
+                    "too many plane voxels for one launch");
+        size_t need = 0;
+        {
+            const FilterPlan fp0 = make_plan(*p, n, rho, D * H, W, p->K);
+            need = kmeans_workspace(N, rho, p->K) + filter_volume_workspace(fp0) + 4096;
+        }
+        Arena ws = c.arena(need);
+        const auto t0 = clk::now();
+        KmResult km;
+        {
+            Arena kws = ws;  // the clustering scratch is dead once the centers are known
+            kmeans_run(c, kws, guide, rho, N, p->K, p->kmeans_max_iter, nullptr, km);
+        }
+        const double ms_cluster = ms_since(t0);
+        const int K = km.K_eff;
+        std::vector<float> c32((size_t)K * rho);
+        for (size_t q = 0; q < c32.size(); ++q) c32[q] = (float)km.centers[q];
+        if (centers_out) std::memcpy(centers_out, c32.data(), sizeof(float) * c32.size());
+        const auto t1 = clk::now();
+        std::vector<float> P32;
+        const PinvResult pr = solve(c32.data(), K, rho, p->sigma_r, p->pinv_rtol, P32);
+        const double ms_solve = ms_since(t1);
+        const auto t2 = clk::now();
+        const FilterPlan fp = make_plan(*p, n, rho, D * H, W, K);
+        filter_volume_run(c, ws, fp, D, f, guide, c32.data(), P32.data(), out, den);
+        if (p->strict) strict_check(c, ws, out, N * n, den, N);
+        double ms_filter = 0.0;
+        if (info) {
+            FHD_HIP(hipStreamSynchronize(c.stream));
+            ms_filter = ms_since(t2);
+        }
+        fill_info(info, K, pr, km.E_K, km.rounds, km.splits, ms_cluster, ms_solve, ms_filter);
+    });
+}
+
 fhd_status fhd_approx_error(fhd_ctx* ctx, const float* guide, int rho, int H, int W, const float* centers, int K,
                             const fhd_params* p, float* err, double* mean) {
     return guarded(ctx, [&](Ctx& c) {

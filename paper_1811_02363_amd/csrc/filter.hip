@@ -1810,6 +1810,94 @@ size_t row_lds_bytes(const FilterPlan& fp, int tx) {
 }
 
 // ---------------------------------------------------------------------------
+// 3-D domain (D slices of H x W, flattened to D H rows of the planes): the
+// (n+1)K convolutions over the window [-S,S]^3 as three 1-D passes, zero
+// outside the volume.  vol_fir_x runs along x, one output per thread, and
+// forms its input c_l [f, 1] from the C planes on the fly.  vol_fir_yz runs
+// along y within a slice (ax 1) or along z across slices (ax 2, a stride of
+// H rows): each thread takes VR consecutive outputs of one column and reads
+// the VR + 2S inputs they share once, so a plane element is loaded about
+// (VR + 2S) / VR times instead of 2S + 1.  A wave's 64 threads hold adjacent
+// x of the same rows (coalesced, and the tap index is wave-uniform).  Taps
+// are added in ascending offset order in both.  The planes have no halo
+// rows; recomb_young then recombines with b_l.
+constexpr int VR = 8;
+
+__global__ __launch_bounds__(RT) void vol_fir_x(FA a, const float* __restrict__ in, float* __restrict__ out) {
+    const long long e = (long long)blockIdx.x * RT + threadIdx.x;
+    const int planes = a.K * (a.n + 1);
+    const long long per = (long long)a.H * a.W;  // a.H = D * Hs
+    if (e >= planes * per) return;
+    const int pl = (int)(e / per);
+    const long long v = e - (long long)pl * per;
+    const int r = (int)(v / a.W), x = (int)(v - (long long)r * a.W);
+    const int S = a.S;
+    const int l = pl / (a.n + 1), ch = pl - l * (a.n + 1);
+    const float* cb = in + (long long)l * a.Np + (long long)r * a.Wp;
+    const float* fb = ch < a.n ? a.f + (long long)ch * a.N + (long long)r * a.W : nullptr;
+    const int t0 = max(-S, -x), t1 = min(S, a.W - 1 - x);
+    float acc = 0.0f;
+    for (int t = t0; t <= t1; t += 8) {  // eight taps' loads in flight (addresses clamped into the row)
+        float u[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) u[q] = cb[x + min(t + q, t1)];
+        if (fb != nullptr) {
+            float m[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) m[q] = fb[x + min(t + q, t1)];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) u[q] *= m[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (t + q <= t1) acc = fmaf(a.w[abs(t + q)], u[q], acc);
+    }
+    out[(long long)pl * a.Np + (long long)r * a.Wp + x] = acc;
+}
+
+__global__ __launch_bounds__(RT) void vol_fir_yz(FA a, int D, int Hs, int ax, const float* __restrict__ in,
+                                                float* __restrict__ out) {
+    const long long e = (long long)blockIdx.x * RT + threadIdx.x;
+    const int planes = a.K * (a.n + 1);
+    const int len = ax == 1 ? Hs : D;                    // extent along the axis
+    const int ng = (len + VR - 1) / VR;                  // output groups along it
+    const int other = ax == 1 ? D : Hs;                  // the remaining row coordinate
+    const long long per = (long long)ng * other * a.W;
+    if (e >= planes * per) return;
+    const int pl = (int)(e / per);
+    const long long v = e - (long long)pl * per;
+    const int gi = (int)(v / a.W), x = (int)(v - (long long)gi * a.W);
+    const int g = gi % ng, o2 = gi / ng;                 // group along the axis, other coordinate
+    const int c0 = g * VR;
+    // plane row of axis coordinate c
+    auto row = [&](int c) { return ax == 1 ? o2 * Hs + c : c * Hs + o2; };
+    const float* src = in + (long long)pl * a.Np + x;
+    const int S = a.S;
+    float acc[VR];
+#pragma unroll
+    for (int o = 0; o < VR; ++o) acc[o] = 0.0f;
+    const int u0 = max(c0 - S, 0), u1 = min(c0 + VR - 1 + S, len - 1);
+    for (int u = u0; u <= u1; u += 8) {  // eight inputs' loads in flight (rows clamped into the axis)
+        float val[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) val[q] = src[(long long)row(min(u + q, u1)) * a.Wp];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            if (u + q > u1) break;
+#pragma unroll
+            for (int o = 0; o < VR; ++o) {
+                const int t = u + q - (c0 + o);
+                if (t >= -S && t <= S) acc[o] = fmaf(a.w[abs(t)], val[q], acc[o]);
+            }
+        }
+    }
+    float* dst = out + (long long)pl * a.Np + x;
+#pragma unroll
+    for (int o = 0; o < VR; ++o)
+        if (c0 + o < len) dst[(long long)row(c0 + o) * a.Wp] = acc[o];
+}
+
+// ---------------------------------------------------------------------------
 // Error of the kernel approximation at the pixels' own samples: eq. (10)
 // evaluated at the method's coefficients c(i) = A^+ b(i),
 //   err(i) = sum_{q in window(i), in image} (phi(p(q) - p(i)) - sum_k c_k(i) phi(p(q) - mu_k))^2.
@@ -2563,4 +2651,67 @@ void approx_error_run(Ctx& c, Arena& ws, const float* guide, int rho, int H, int
     }
 }
 
+
+size_t filter_volume_workspace(const FilterPlan& fp) {
+    Arena probe;
+    const size_t Np = (size_t)fp.H * fp.Wp;
+    probe.take<char>(filter_consts_bytes(fp.K, fp.rho));
+    probe.take<float>((size_t)fp.K * Np);
+    probe.take<float>((size_t)fp.K * Np);
+    probe.take<float>((size_t)fp.K * (fp.n + 1) * Np);
+    probe.take<float>((size_t)fp.K * (fp.n + 1) * Np);
+    return probe.used + 256;
+}
+
+void filter_volume_run(Ctx& c, Arena& ws, const FilterPlan& fp, int D, const float* f, const float* guide,
+                       const float* centers_host, const float* Pfp32_host, float* out, float* den) {
+    FHD_REQUIRE(fp.H % D == 0, FHD_EINVAL, "internal: volume rows");
+    const int Hs = fp.H / D;
+    const size_t cb = filter_consts_bytes(fp.K, fp.rho);
+    char* dev = ws.take<char>(cb);
+    char* hs = static_cast<char*>(c.host_stage(1, cb));
+    filter_consts_fill(centers_host, Pfp32_host, fp.K, fp.rho, hs);
+    FHD_HIP(hipMemcpyAsync(dev, hs, cb, hipMemcpyHostToDevice, c.stream));
+    c.stage_done(1);
+    const FilterConsts kc = filter_consts_at(dev, fp.K, fp.rho);
+    const long long Np = (long long)fp.H * fp.Wp;
+    float* Bpl = ws.take<float>((size_t)fp.K * Np);
+    float* Cpl = ws.take<float>((size_t)fp.K * Np);
+    float* pa = ws.take<float>((size_t)fp.K * (fp.n + 1) * Np);
+    float* pb = ws.take<float>((size_t)fp.K * (fp.n + 1) * Np);
+    FA a = make_args(fp);
+    a.f = f;
+    a.p = guide;
+    a.mu = kc.mu;
+    a.P = kc.P;
+    a.out = out;
+    a.den = den;
+    a.Pp = Np;  // no halo rows
+    hipStream_t st = c.stream;
+    const int npx = weights_fp32_npx(fp.K);
+    const size_t lds = weights_fp32_lds(fp.K, fp.rho, npx);
+    FHD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(weights_fp32),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipEvent_t tw = c.stage_begin();
+    hipLaunchKernelGGL(weights_fp32, dim3((fp.W + npx - 1) / npx, fp.H), dim3(npx), lds, st, a, Bpl, Cpl);
+    c.stage_end(FHD_STAGE_WEIGHTS, tw);
+    FHD_HIP(hipGetLastError());
+    a.Bpl = Bpl;
+    a.Cpl = Cpl;
+    const long long planes = (long long)fp.K * (fp.n + 1);
+    const long long tot = planes * fp.N;
+    auto grid = [](long long threads) { return dim3((unsigned)((threads + RT - 1) / RT)); };
+    hipEvent_t tr = c.stage_begin();
+    hipLaunchKernelGGL(vol_fir_x, grid(tot), dim3(RT), 0, st, a, Cpl, pa);
+    c.stage_end(FHD_STAGE_ROW, tr);
+    hipEvent_t tc = c.stage_begin();
+    hipLaunchKernelGGL(vol_fir_yz, grid(planes * D * ((Hs + VR - 1) / VR) * fp.W), dim3(RT), 0, st, a, D, Hs, 1, pa,
+                       pb);
+    hipLaunchKernelGGL(vol_fir_yz, grid(planes * Hs * ((D + VR - 1) / VR) * fp.W), dim3(RT), 0, st, a, D, Hs, 2, pb,
+                       pa);
+    a.planes = pa;
+    hipLaunchKernelGGL(recomb_young, dim3((unsigned)((fp.N + RT - 1) / RT)), dim3(RT), 0, st, a, 0);
+    c.stage_end(FHD_STAGE_COL, tc);
+    FHD_HIP(hipGetLastError());
+}
 }  // namespace fhd

@@ -123,6 +123,33 @@ def lowlight_ir(H: int, W: int, seeds: int, gain: float, noise: float, ir_noise:
             np.clip(ir, 0.0, 1.0).astype(np.float32)[None])
 
 
+def voronoi_volume(D: int, H: int, W: int, seeds: int, noise: float, seed: int) -> np.ndarray:
+    """Piecewise-constant random 3-D Voronoi vector field (three components)
+    plus Gaussian noise: a stand-in for a flow field on a volume.
+
+    Draw order from ``default_rng(seed)``: seed positions
+    ``uniform(0,1,(seeds,3))`` scaled to [0,D) x [0,H) x [0,W) (columns z, y,
+    x), seed vectors ``uniform(0,1,(seeds,3))``, then noise
+    ``normal(0, noise, (3,D,H,W))``.  Each voxel centre takes the vector of its
+    nearest seed (ties: lowest index); clipped to [0,1], float32.
+    """
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(0.0, 1.0, size=(seeds, 3)) * np.array([D, H, W], dtype=np.float64)
+    vec = rng.uniform(0.0, 1.0, size=(seeds, 3))
+    lab = np.empty((D, H, W), dtype=np.int64)
+    ys = np.arange(H, dtype=np.float64) + 0.5
+    xs = np.arange(W, dtype=np.float64) + 0.5
+    for z in range(D):
+        dz = (z + 0.5 - pos[:, 0]) ** 2
+        for y0 in range(0, H, 64):
+            y1 = min(H, y0 + 64)
+            d = (dz[None, None, :] + (ys[y0:y1, None, None] - pos[None, None, :, 1]) ** 2
+                 + (xs[None, :, None] - pos[None, None, :, 2]) ** 2)
+            lab[z, y0:y1] = np.argmin(d, axis=2)
+    vol = np.transpose(vec[lab], (3, 0, 1, 2)) + rng.normal(0.0, noise, size=(3, D, H, W))
+    return np.clip(vol, 0.0, 1.0).astype(np.float32)
+
+
 def batch_sizes(count: int = 16, seed: int = 1004):
     """Image sizes of the ragged batch.
 
