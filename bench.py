@@ -217,10 +217,16 @@ def volume_leg(torch, fhd, synth):
     st = fhd.timing_read(0)
     fhd.timing_enable(0, False)
     N = v.shape[1] * v.shape[2] * v.shape[3]
+    out = run()
+    brute = lambda: fhd.bruteforce_volume(v, sigma_s=2.0, sigma_r=0.12)
+    ref = brute()
+    ms_b = timed(torch, brute, 2)
     return {"workload": "volume_64x256x256: 3-component 3-D Voronoi field, noise 0.05, sigma_s 2 (S 6), "
                         "sigma_r 0.12, K 32",
             "mvox_s": round(N / ms / 1e3, 1), "ms": round(ms, 3),
-            "stage_ms": {k: round(t, 3) for k, (t, nl) in st.items() if nl}}
+            "stage_ms": {k: round(t, 3) for k, (t, nl) in st.items() if nl},
+            "psnr_vs_brute_db": round(-10.0 * math.log10(float(((out.double() - ref.double()) ** 2).sum()) / N), 2),
+            "brute_force_mvox_s": round(N / ms_b / 1e3, 1)}
 
 
 def batch_leg(torch, np, fhd, synth):

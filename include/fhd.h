@@ -289,6 +289,14 @@ fhd_status fhd_nlm_guide(fhd_ctx* ctx, const float* f, int n, int H, int W, int 
 fhd_status fhd_filter_volume(fhd_ctx* ctx, const float* f, int n, const float* guide, int rho, int D, int H, int W,
                              const fhd_params* p, float* out, float* centers_out, float* den, fhd_info* info);
 
+/* Eqs. (1)-(2) on a 3-D domain, directly (the comparator of
+ * fhd_filter_volume): window [-S,S]^3, omega(j) = exp(-|j|^2 / 2 sigma_s^2)
+ * (the product of the 1-D taps) or 1, neighbours outside the volume left out.
+ * Arguments as for fhd_filter_volume (no clustering parameters used); FP32,
+ * cost (2S+1)^3 (rho + n) per voxel.  Enqueued on the context's stream. */
+fhd_status fhd_bruteforce_volume(fhd_ctx* ctx, const float* f, int n, const float* guide, int rho, int D, int H,
+                                 int W, const fhd_params* p, float* out, float* den);
+
 /* Error of the kernel approximation at each pixel's own samples (Sec. II-B):
  * the objective of eq. (10) evaluated at the coefficients the method uses,
  * c(i) = A^+ b(i) of eqs. (11)-(12),

@@ -20,7 +20,7 @@ __all__ = [
     "filter", "filter_centers", "filter_backward", "FilterFunction", "filter_autograd",
     "pack_batch", "filter_batch", "filter_batch_backward",
     "cluster", "pinv", "bruteforce", "nlm_guide", "scale_guide", "ScaleGuide", "approx_error",
-    "filter_volume",
+    "filter_volume", "bruteforce_volume",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -39,7 +39,7 @@ symbols = [
     "fhd_workspace_size", "fhd_set_workspace", "fhd_cluster", "fhd_pinv",
     "fhd_filter_centers", "fhd_filter", "fhd_filter_backward", "fhd_filter_batch",
     "fhd_filter_batch_backward", "fhd_bruteforce", "fhd_nlm_guide", "fhd_scale_guide",
-    "fhd_approx_error", "fhd_filter_volume",
+    "fhd_approx_error", "fhd_filter_volume", "fhd_bruteforce_volume",
     "fhd_timing_enable", "fhd_timing_read",
 ]
 STAGES = ("cluster", "weights", "row", "col", "brute")
@@ -113,6 +113,7 @@ def load():
             "fhd_scale_guide": (I, [V, V, I, ctypes.c_longlong, V, V]),
             "fhd_approx_error": (I, [V, V, I, I, I, V, I, pp, V, P(D)]),
             "fhd_filter_volume": (I, [V, V, I, V, I, I, I, I, pp, V, V, V, pi]),
+            "fhd_bruteforce_volume": (I, [V, V, I, V, I, I, I, I, pp, V, V]),
             "fhd_timing_enable": (I, [V, I]),
             "fhd_timing_read": (I, [V, P(D), P(I)]),
         }
@@ -260,6 +261,25 @@ def filter_volume(f, guide=None, sigma_s=3.0, sigma_r=0.1, K=16, spatial="gaussi
     if info:
         res.append(inf.as_dict())
     return res[0] if len(res) == 1 else tuple(res)
+
+
+def bruteforce_volume(f, guide=None, sigma_s=3.0, sigma_r=0.1, spatial="gaussian", radius=None,
+                      return_den=False):
+    """Eqs. (1)-(2) over [-S,S]^3 directly on the GPU (FP32); f (n, D, H, W)."""
+    if not isinstance(f, torch.Tensor) or not f.is_cuda or f.dim() != 4:
+        raise FHDError(FHD_EINVAL, "f must be an (n, D, H, W) CUDA (HIP) tensor; there is no CPU path")
+    g = f if guide is None else guide
+    if not isinstance(g, torch.Tensor) or g.dim() != 4 or g.shape[1:] != f.shape[1:]:
+        raise FHDError(FHD_EINVAL, "guide must be (rho, D, H, W) with the volume's D, H, W")
+    n, D, H, W = f.shape
+    ctx = _ctx(f.device.index)
+    p = make_params(sigma_s, sigma_r, 1, spatial, radius)
+    out = torch.empty_like(f)
+    den = torch.empty((D, H, W), device=f.device, dtype=torch.float32) if return_den else None
+    _check(load().fhd_bruteforce_volume(ctx, _dev(f, "f"), n, _dev(g, "guide"), g.shape[0], D, H, W,
+                                        ctypes.byref(p), _dev(out, "out"),
+                                        _dev(den, "den") if den is not None else None), ctx)
+    return (out, den) if return_den else out
 
 
 def filter_centers(f, guide, centers, sigma_s=3.0, sigma_r=0.1, spatial="gaussian", radius=None,

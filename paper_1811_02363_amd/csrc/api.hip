@@ -944,6 +944,31 @@ fhd_status fhd_filter_volume(fhd_ctx* ctx, const float* f, int n, const float* g
     });
 }
 
+fhd_status fhd_bruteforce_volume(fhd_ctx* ctx, const float* f, int n, const float* guide, int rho, int D, int H,
+                                 int W, const fhd_params* p, float* out, float* den) {
+    return guarded(ctx, [&](Ctx& c) {
+        FHD_REQUIRE(D >= 1 && H >= 1, FHD_EINVAL, "D and H must be >= 1");
+        FHD_REQUIRE((long long)D * H <= 65535, FHD_EUNSUPPORTED, "a volume takes at most 65535 rows (D * H)");
+        check_params(p, n, rho, D * H, W);
+        FHD_REQUIRE(p->spatial != FHD_SPATIAL_YOUNG, FHD_EUNSUPPORTED,
+                    "the brute force evaluates eqs. (1)-(2) with a finite window");
+        FHD_REQUIRE(f && guide && out, FHD_EINVAL, "NULL pointer");
+        const long long N = (long long)D * H * W;
+        FHD_REQUIRE(!ranges_overlap(out, sizeof(float) * N * n, f, sizeof(float) * N * n) &&
+                        !ranges_overlap(out, sizeof(float) * N * n, guide, sizeof(float) * N * rho) &&
+                        !ranges_overlap(den, sizeof(float) * N, f, sizeof(float) * N * n) &&
+                        !ranges_overlap(den, sizeof(float) * N, guide, sizeof(float) * N * rho) &&
+                        !ranges_overlap(den, sizeof(float) * N, out, sizeof(float) * N * n),
+                    FHD_EINVAL, "outputs alias inputs");
+        const FilterPlan fp = make_plan(*p, n, rho, D * H, W, 1);
+        bruteforce_volume_run(c, fp, D, f, guide, out, den);
+        if (p->strict) {
+            Arena ws = c.arena(4096);
+            strict_check(c, ws, out, N * n, den, N);
+        }
+    });
+}
+
 fhd_status fhd_approx_error(fhd_ctx* ctx, const float* guide, int rho, int H, int W, const float* centers, int K,
                             const fhd_params* p, float* err, double* mean) {
     return guarded(ctx, [&](Ctx& c) {

@@ -159,6 +159,8 @@ void adjoint_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const 
 size_t filter_volume_workspace(const FilterPlan& fp);
 void filter_volume_run(Ctx& c, Arena& ws, const FilterPlan& fp, int D, const float* f, const float* guide,
                        const float* centers_host, const float* Pfp32_host, float* out, float* den);
+void bruteforce_volume_run(Ctx& c, const FilterPlan& fp, int D, const float* f, const float* guide, float* out,
+                           float* den);
 // Error of the kernel approximation (eq. (10) at c = A^+ b) per pixel (err,
 // may be null) and its pixel mean (mean, may be null; synchronises); K <= 64.
 size_t approx_error_workspace(int H, int W, int K, int rho);

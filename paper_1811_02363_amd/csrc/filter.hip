@@ -1897,6 +1897,55 @@ __global__ __launch_bounds__(RT) void vol_fir_yz(FA a, int D, int Hs, int ax, co
         if (c0 + o < len) dst[(long long)row(c0 + o) * a.Wp] = acc[o];
 }
 
+// Brute force on a 3-D domain (eqs. (1)-(2) over [-S,S]^3): one thread per
+// voxel, the window walked directly (neighbours outside the volume left out),
+// omega as the product of the 1-D taps, channels in groups of four (the
+// range weights recomputed per group).  FP32, a comparator for the volume
+// filter, not on its path.
+__global__ __launch_bounds__(RT) void brute_volume(FA a, int D, int Hs, float* __restrict__ out,
+                                                  float* __restrict__ den) {
+    const long long i = (long long)blockIdx.x * RT + threadIdx.x;
+    if (i >= a.N) return;
+    const int W = a.W;
+    const int x = (int)(i % W);
+    const long long zy = i / W;
+    const int y = (int)(zy % Hs), z = (int)(zy / Hs);
+    const int S = a.S, n = a.n, rho = a.rho;
+    const long long N = a.N;
+    for (int c0 = 0; c0 < n; c0 += 4) {
+        float num[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        float eta = 0.0f;
+        for (int jz = -S; jz <= S; ++jz) {
+            const int zz = z - jz;
+            if (zz < 0 || zz >= D) continue;
+            for (int jy = -S; jy <= S; ++jy) {
+                const int yy = y - jy;
+                if (yy < 0 || yy >= Hs) continue;
+                const float wzy = a.w[abs(jz)] * a.w[abs(jy)];
+                for (int jx = -S; jx <= S; ++jx) {
+                    const int xx = x - jx;
+                    if (xx < 0 || xx >= W) continue;
+                    const long long q = ((long long)zz * Hs + yy) * W + xx;
+                    float d2 = 0.0f;
+                    for (int d = 0; d < rho; ++d) {
+                        const float t = a.p[d * N + q] - a.p[d * N + i];
+                        d2 = fmaf(t, t, d2);
+                    }
+                    const float w = wzy * a.w[abs(jx)] * __expf(-d2 * a.inv2s2);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (c0 + k < n) num[k] = fmaf(w, a.f[(c0 + k) * N + q], num[k]);
+                    eta += w;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (c0 + k < n) out[(c0 + k) * N + i] = num[k] / eta;
+        if (c0 == 0 && den != nullptr) den[i] = eta;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Error of the kernel approximation at the pixels' own samples: eq. (10)
 // evaluated at the method's coefficients c(i) = A^+ b(i),
@@ -2712,6 +2761,19 @@ void filter_volume_run(Ctx& c, Arena& ws, const FilterPlan& fp, int D, const flo
     a.planes = pa;
     hipLaunchKernelGGL(recomb_young, dim3((unsigned)((fp.N + RT - 1) / RT)), dim3(RT), 0, st, a, 0);
     c.stage_end(FHD_STAGE_COL, tc);
+    FHD_HIP(hipGetLastError());
+}
+
+void bruteforce_volume_run(Ctx& c, const FilterPlan& fp, int D, const float* f, const float* guide, float* out,
+                           float* den) {
+    FHD_REQUIRE(fp.H % D == 0, FHD_EINVAL, "internal: volume rows");
+    FA a = make_args(fp);
+    a.f = f;
+    a.p = guide;
+    hipEvent_t tb = c.stage_begin();
+    hipLaunchKernelGGL(brute_volume, dim3((unsigned)((fp.N + RT - 1) / RT)), dim3(RT), 0, c.stream, a, D, fp.H / D,
+                       out, den);
+    c.stage_end(FHD_STAGE_BRUTE, tb);
     FHD_HIP(hipGetLastError());
 }
 }  // namespace fhd

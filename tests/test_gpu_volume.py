@@ -2,7 +2,8 @@
 the FP64 oracle: the clustering tree (centers equal in FP32) and the output
 of the oracle's own run of the whole algorithm, max-abs 1e-4 (the FP32
 path's bar; cond(A) checked so that the bar is meaningful).  One slice equals
-the 2-D path within the same bar.
+the 2-D path within the same bar.  The GPU brute force on volumes against
+the oracle's, max-abs 1e-4 (and its normaliser 1e-5 relative).
 """
 import numpy as np
 import pytest
@@ -66,6 +67,21 @@ def test_volume_end_to_end(fhd, case):
           f"{oracle.psnr(res.out, bf):.2f} dB")
     assert cond < 2e4
     assert cerr < 1e-6 and err < TOL and derr < 1e-5
+
+
+@pytest.mark.parametrize("spatial,ss,radius", [("gaussian", 1.3, None), ("box", None, 2)])
+def test_bruteforce_volume(fhd, spatial, ss, radius):
+    f = _rgb_volume(5, 18, 22, 900)
+    g = np.stack([synth.hyperspectral(18, 22, 4, 3, 0.5, 0.02, 950 + z) for z in range(5)], axis=1)
+    S = radius if radius is not None else oracle.default_radius(ss)
+    ref, eta = oracle.bruteforce_volume(f, g, ss, 0.25, S, spatial)
+    out, den = fhd.bruteforce_volume(_dev(f), _dev(g), sigma_s=ss if ss else 3.0, sigma_r=0.25, spatial=spatial,
+                                     radius=radius, return_den=True)
+    torch.cuda.synchronize()
+    err = np.abs(out.cpu().numpy() - ref).max()
+    derr = np.abs(den.cpu().numpy() - eta).max() / eta.max()
+    print(f"3-D brute force {spatial}: max-abs {err:.2e}, eta rel {derr:.2e}")
+    assert err < TOL and derr < 1e-5
 
 
 def test_one_slice_equals_the_2d_path(fhd):
