@@ -186,7 +186,7 @@ def window_leg(torch, fhd, x, sr, K):
 def approx_error_leg(torch, fhd, synth):
     """E_K (eq. (10) at c = A^+ b, averaged over the pixels) against K for a
     3-dimensional and a 32-dimensional guide, clusters from the library's own
-    bisecting K-means: the fall of the approximation error with K (Sec. II-B)."""
+    bisecting K-means: the fall of the approximation error with K (Sec. II-A)."""
     legs = {}
     for name, K_list in (("bf_rgb_256", (4, 8, 16, 32, 64)), ("bf_hyper_512x32", (8, 16, 32, 64))):
         c = synth.WORKLOADS[name]

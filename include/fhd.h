@@ -8,7 +8,7 @@
  *     g(i) = sum_{j in W} w(j) phi(p(i-j) - p(i)) f(i-j) / eta(i),
  *     eta(i) = sum_{j in W} w(j) phi(p(i-j) - p(i)),   W = [-S, S]^2,
  * with a Gaussian range kernel phi(x) = exp(-|x|^2 / 2 sigma_r^2) and a
- * Gaussian (bilateral) or box (nonlocal means) spatial kernel w (Sec. IV).
+ * Gaussian (bilateral) or box (nonlocal means) spatial kernel w (Sec. III).
  * The library computes the approximation of Algorithm 1 (Sec. II-B): cluster
  * the guide vectors into K centers (bisecting K-means, Sec. II-C), solve the
  * K x K least-squares system of eqs. (11)-(12) once, form the per-pixel
@@ -56,7 +56,7 @@ typedef enum {
 
 /* Spatial window omega of eqs. (13)-(14): the Gaussian truncated at the
  * radius, the box, or the recursive Gaussian of Young and van Vliet (1995),
- * the O(1) convolution the paper uses (Sec. III): per axis a causal and an
+ * the O(1) convolution the paper uses (Sec. II-C): per axis a causal and an
  * anti-causal third-order recursion, each from a zero state at its end of
  * the image, rows then columns; no radius, cost independent of sigma_s
  * (sigma_s >= 0.5; forward filter only: the adjoint and the brute force
@@ -77,7 +77,7 @@ enum { FHD_COEF_LSQ = 0, FHD_COEF_HARD = 1 };
 
 typedef struct {
     float sigma_s;        /* Gaussian spatial std (pixels), > 0 (>= 0.5 recursive); ignored for box */
-    int radius;           /* S; < 0 means ceil(3 sigma_s) (Sec. IV); required (>= 0) for box;
+    int radius;           /* S; < 0 means ceil(3 sigma_s) (Sec. III); required (>= 0) for box;
                              ignored for the recursive Gaussian */
     float sigma_r;        /* range std, > 0; +INFINITY allowed (phi == 1) */
     int K;                /* requested clusters, 1..FHD_MAX_K; fewer are used when the
@@ -259,7 +259,7 @@ fhd_status fhd_filter_batch_backward(fhd_ctx* ctx, int B, const int* H, const in
 fhd_status fhd_bruteforce(fhd_ctx* ctx, const float* f, int n, const float* guide, int rho,
                           int H, int W, const fhd_params* p, float* out, float* den);
 
-/* The guide of nonlocal means (Sec. I-A; PCA of patches as in Sec. IV-C):
+/* The guide of nonlocal means (Sec. I-A; PCA of patches as in Sec. III-C):
  * every pixel's patch x (patch x patch x n values, half-sample symmetric
  * extension at the borders, flattened in (dy, dx, channel) order) is
  * projected onto the `dims` leading eigenvectors of the patch covariance
@@ -273,7 +273,7 @@ fhd_status fhd_bruteforce(fhd_ctx* ctx, const float* f, int n, const float* guid
 fhd_status fhd_nlm_guide(fhd_ctx* ctx, const float* f, int n, int H, int W, int patch, int dims,
                          float* guide, double* eigvals);
 
-/* All of Algorithm 1 on a 3-D domain (the flow-field denoising of Sec. IV-F
+/* All of Algorithm 1 on a 3-D domain (the flow-field denoising of Sec. III-F
  * filters a volume): the bisecting K-means of the voxels' guide vectors (all
  * D H W voxels as one set, in (z, y, x) order), A and A^+, the weights and
  * coefficients per voxel, the (n+1)K convolutions over the window
@@ -297,7 +297,7 @@ fhd_status fhd_filter_volume(fhd_ctx* ctx, const float* f, int n, const float* g
 fhd_status fhd_bruteforce_volume(fhd_ctx* ctx, const float* f, int n, const float* guide, int rho, int D, int H,
                                  int W, const fhd_params* p, float* out, float* den);
 
-/* Error of the kernel approximation at each pixel's own samples (Sec. II-B):
+/* Error of the kernel approximation at each pixel's own samples (Sec. II-A):
  * the objective of eq. (10) evaluated at the coefficients the method uses,
  * c(i) = A^+ b(i) of eqs. (11)-(12),
  *   err[i] = sum_{q} (phi(p(q) - p(i)) - sum_k c_k(i) phi(p(q) - mu_k))^2,
@@ -315,8 +315,8 @@ fhd_status fhd_bruteforce_volume(fhd_ctx* ctx, const float* f, int n, const floa
 fhd_status fhd_approx_error(fhd_ctx* ctx, const float* guide, int rho, int H, int W, const float* centers, int K,
                             const fhd_params* p, float* err, double* mean);
 
-/* Anisotropic Gaussian range kernel (Sec. IV: one experiment, the low-light
- * denoising of Sec. IV-E, uses a separate sigma_r per guide dimension):
+/* Anisotropic Gaussian range kernel (Sec. III: one experiment, the low-light
+ * denoising of Sec. III-E, uses a separate sigma_r per guide dimension):
  *   phi(x) = exp(-sum_d x_d^2 / (2 sigma_d^2)).
  * It equals the isotropic kernel with sigma_r = 1 on the guide scaled per
  * dimension, so this call writes

@@ -14,10 +14,10 @@ Two independent references, both in FP64:
   convolutions eqs. (13)-(14) and the recombination eqs. (15)-(16).
 
 Also: the hard-assignment variant eqs. (17)-(18), the patch-PCA guide for
-nonlocal means (Sec. IV-C), the anisotropic range kernel (Sec. IV, IV-E) as a
+nonlocal means (Sec. III-C), the anisotropic range kernel (Sec. III, III-E) as a
 direct brute force and as the scaled guide the method filters, the error of
-the kernel approximation (eq. (10) at c = A^+ b, Sec. II-B), the brute force
-and the fast filter on a 3-D domain (Sec. IV-F), the PSNR of eq. (21).
+the kernel approximation (eq. (10) at c = A^+ b, Sec. II-A), the brute force
+and the fast filter on a 3-D domain (Sec. III-F), the PSNR of eq. (21).
 
 The heavy loops (window sums) live in ``fhd_oracle.c`` (plain C + OpenMP),
 compiled with gcc into ``liboracle.so`` beside this file.
@@ -99,12 +99,12 @@ def _spatial_code(spatial):
 
 
 def default_radius(sigma_s: float) -> int:
-    """Window half-width S = 3 sigma_s (Sec. IV), rounded up to an integer."""
+    """Window half-width S = 3 sigma_s (Sec. III), rounded up to an integer."""
     return int(np.ceil(3.0 * sigma_s - 1e-12))
 
 
 # --------------------------------------------------------------------------
-# Kernels (Sec. IV)
+# Kernels (Sec. III)
 # --------------------------------------------------------------------------
 
 def phi(d2, sigma_r):
@@ -165,8 +165,8 @@ def bruteforce_at(f, guide, sigma_s, sigma_r, ys, xs, S=None, spatial="gaussian"
 
 
 def anisotropic_scale(guide, sigma_d):
-    """The guide as the method reads an anisotropic range kernel (Sec. IV;
-    the per-dimension sigma_r of Sec. IV-E): phi(x) = exp(-sum_d x_d^2 /
+    """The guide as the method reads an anisotropic range kernel (Sec. III;
+    the per-dimension sigma_r of Sec. III-E): phi(x) = exp(-sum_d x_d^2 /
     2 sigma_d^2) is the isotropic kernel with sigma_r = 1 of the guide divided
     by sigma_d per dimension, so the clustering and the whole of Algorithm 1
     run on that scaled guide.  Here the FP32 guide over the FP32 sigma_d,
@@ -180,7 +180,7 @@ def anisotropic_scale(guide, sigma_d):
 
 def bruteforce_anisotropic(f, guide, sigma_s, sigma_d, S=None, spatial="gaussian"):
     """Eqs. (1)-(2) with the anisotropic range kernel exp(-sum_d x_d^2 /
-    2 sigma_d^2) (Sec. IV), written out in NumPy for small images: for every
+    2 sigma_d^2) (Sec. III), written out in NumPy for small images: for every
     window offset j the neighbour image p(i - j), its per-dimension weighted
     squared distance to p(i), and both sums; out-of-image neighbours are left
     out of both.  Returns (g, eta) in FP64."""
@@ -210,7 +210,7 @@ def bruteforce_anisotropic(f, guide, sigma_s, sigma_d, S=None, spatial="gaussian
 
 def young_coefficients(sigma):
     """Coefficients of the recursive Gaussian of Young and van Vliet (1995),
-    the O(1) convolution the paper uses for Gaussian windows (Sec. III):
+    the O(1) convolution the paper uses for Gaussian windows (Sec. II-C):
     q from sigma (two published branches), then b0..b3 and the gain
     B = 1 - (b1 + b2 + b3) / b0.  Returns (B, b1/b0, b2/b0, b3/b0)."""
     s = float(sigma)
@@ -511,7 +511,7 @@ def _offsets_3d(D, H, W, S):
 
 
 def bruteforce_volume(f, guide, sigma_s, sigma_r, S, spatial="gaussian"):
-    """Eqs. (1)-(2) on a 3-D domain (Sec. IV-F filters a volume): the window
+    """Eqs. (1)-(2) on a 3-D domain (Sec. III-F filters a volume): the window
     [-S,S]^3, omega as in 2-D over |j|, neighbours outside the volume left
     out.  f (n, D, H, W), guide (rho, D, H, W).  Returns (g, eta) in FP64."""
     f = _f64(f)
@@ -571,7 +571,7 @@ def approx_error(guide, centers, sigma_r, S, P=None):
         err(i) = sum_{x in Theta_i} (phi(x - p(i)) - sum_k c_k(i) phi(x - mu_k))^2,
     Theta_i the guide values of the in-image pixels of the (2S+1)^2 window
     around i (A1; a multiset, A4).  Its mean over the pixels is the error
-    E_K of Sec. II-B.  Vectorised over the pixels, one window offset at a
+    E_K of Sec. II-A.  Vectorised over the pixels, one window offset at a
     time.  Returns (err (H, W) FP64, E_K)."""
     p = _f64(guide)
     rho, H, W = p.shape
@@ -653,7 +653,7 @@ def fhd_filter(f, guide, sigma_s, sigma_r, K, S=None, spatial="gaussian",
 
 
 # --------------------------------------------------------------------------
-# Nonlocal-means guide: PCA of color patches (Sec. I-A, Sec. IV-C)
+# Nonlocal-means guide: PCA of color patches (Sec. I-A, Sec. III-C)
 # --------------------------------------------------------------------------
 
 def patches(f, m):

@@ -17,7 +17,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-/* Spatial kernel, Sec. IV: Gaussian exp(-|j|^2 / 2 sigma_s^2) for the
+/* Spatial kernel, Sec. III: Gaussian exp(-|j|^2 / 2 sigma_s^2) for the
  * bilateral filter, box (weight 1) for nonlocal means. */
 static double omega2(int jy, int jx, int spatial, double sigma_s)
 {
@@ -43,7 +43,7 @@ static double *omega_table(int S, int spatial, double sigma_s)
     return t;
 }
 
-/* Range kernel, Sec. IV: isotropic Gaussian of the squared distance.
+/* Range kernel, Sec. III: isotropic Gaussian of the squared distance.
  * sigma_r = +inf gives phi == 1. */
 static double phi(double d2, double sigma_r)
 {

@@ -1740,7 +1740,7 @@ const Dispatch& dispatch() {
 }
 
 // The recursive Gaussian of Young and van Vliet (1995), the O(1) Gaussian
-// convolution the paper uses (Sec. III): q from sigma (two published
+// convolution the paper uses (Sec. II-C): q from sigma (two published
 // branches, sigma >= 0.5), the polynomial coefficients b0..b3, the gain
 // B = 1 - (b1 + b2 + b3) / b0.  c = {B, b1/b0, b2/b0, b3/b0}.
 void young_coefficients(double sigma, double* c) {

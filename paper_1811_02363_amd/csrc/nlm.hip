@@ -1,4 +1,4 @@
-// The guide of nonlocal means (Sec. I-A, Sec. IV-C): every pixel's m x m x n
+// The guide of nonlocal means (Sec. I-A, Sec. III-C): every pixel's m x m x n
 // patch, projected onto the leading principal directions of all patches.
 //
 //   moments pass:  per block of pixels, sums of x and of x x^T (upper

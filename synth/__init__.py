@@ -10,7 +10,7 @@ Layout: planar ``(C, H, W)`` float32, C-contiguous, values in [0, 1].
 
 The paper filters natural color images (Kodak, Barbara, Lena, HD photos),
 33/200-band hyperspectral images and noisy color images for nonlocal means
-(Sec. IV).  None of them is available here; these generators stand in for
+(Sec. III).  None of them is available here; these generators stand in for
 them with the same channel counts, value range and piecewise-smooth
 structure.
 """

@@ -1,12 +1,12 @@
-"""The anisotropic range kernel (Sec. IV; per-dimension sigma_r as in the
-low-light denoising of Sec. IV-E) through the C ABI: ``fhd_scale_guide``
+"""The anisotropic range kernel (Sec. III; per-dimension sigma_r as in the
+low-light denoising of Sec. III-E) through the C ABI: ``fhd_scale_guide``
 followed by the isotropic path with sigma_r = 1.
 
 * The scaled guide is bit-exact against the oracle's correctly rounded FP32
   quotient (also in place and on ragged sizes).
 * Algorithm 1 on a low-light color image guided by six smooth dimensions plus
   an infrared channel (sigma 5:1 between them, K 32, 17x17 box window as in
-  Sec. IV-E), end to end against the oracle on the same scaled guide: centers
+  Sec. III-E), end to end against the oracle on the same scaled guide: centers
   max-abs 1e-6, output max-abs 1e-4 (the FP32 path's bar).
 * The GPU brute force with per-dimension sigma_r against the oracle's direct
   NumPy brute force of the anisotropic kernel: max-abs 1e-4.

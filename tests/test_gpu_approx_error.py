@@ -1,5 +1,5 @@
 """The error of the kernel approximation (fhd_approx_error: eq. (10) at
-c(i) = A^+ b(i), its pixel mean E_K of Sec. II-B) through the C ABI, against
+c(i) = A^+ b(i), its pixel mean E_K of Sec. II-A) through the C ABI, against
 the FP64 oracle fed the same FP32 centers.
 
 Tolerance.  The GPU forms every residual r = phi(x - p(i)) - sum_k c_k phi(x -

@@ -1,5 +1,5 @@
-"""Pins of the oracle's anisotropic range kernel (Sec. IV; the per-dimension
-sigma_r of Sec. IV-E).
+"""Pins of the oracle's anisotropic range kernel (Sec. III; the per-dimension
+sigma_r of Sec. III-E).
 
 * The direct NumPy brute force with exp(-sum_d x_d^2 / 2 sigma_d^2) equals
   the C brute force (isotropic, sigma_r = 1) of the guide divided by sigma_d:

@@ -1,5 +1,5 @@
 """Pins of the oracle's kernel-approximation error (eq. (10) evaluated at the
-method's coefficients c(i) = A^+ b(i); its pixel mean is E_K of Sec. II-B).
+method's coefficients c(i) = A^+ b(i); its pixel mean is E_K of Sec. II-A).
 
 * A plain triple loop over pixels, window offsets and centers on tiny images
   (math.exp, scalar sums) gives the same per-pixel errors as the vectorised

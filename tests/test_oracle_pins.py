@@ -335,7 +335,7 @@ def test_o2_torch_transcription_agrees():
 
 
 # ---------------------------------------------------------------------------
-# X12: patch-PCA guide (Sec. IV-C)
+# X12: patch-PCA guide (Sec. III-C)
 # ---------------------------------------------------------------------------
 
 def test_patches_and_pca():

@@ -1,4 +1,4 @@
-"""Pins of the oracle on a 3-D domain (Sec. IV-F filters a volume).
+"""Pins of the oracle on a 3-D domain (Sec. III-F filters a volume).
 
 * One slice (D = 1) reduces the 3-D brute force to the C brute force of
   eqs. (1)-(2) and the 3-D fast filter to the 2-D fast filter (both pinned

@@ -1,5 +1,5 @@
 """Pins of the oracle's recursive Gaussian (Young and van Vliet 1995, the O(1)
-convolution the paper uses for Gaussian windows, Sec. III).
+convolution the paper uses for Gaussian windows, Sec. II-C).
 
 The published method fixes: unit DC gain (B = 1 - (b1 + b2 + b3) / b0 makes
 each pass sum to 1 on an unbounded signal), an impulse response symmetric
