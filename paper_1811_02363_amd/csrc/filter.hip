@@ -1812,8 +1812,9 @@ size_t row_lds_bytes(const FilterPlan& fp, int tx) {
 // ---------------------------------------------------------------------------
 // 3-D domain (D slices of H x W, flattened to D H rows of the planes): the
 // (n+1)K convolutions over the window [-S,S]^3 as three 1-D passes, zero
-// outside the volume.  vol_fir_x runs along x, one output per thread, and
-// forms its input c_l [f, 1] from the C planes on the fly.  vol_fir_yz runs
+// outside the volume.  vol_fir_x runs along x, one output position of all
+// n + 1 planes of a cluster per thread, forming its input c_l [f, 1] from the
+// C planes on the fly.  vol_fir_yz runs
 // along y within a slice (ax 1) or along z across slices (ax 2, a stride of
 // H rows): each thread takes VR consecutive outputs of one column and reads
 // the VR + 2S inputs they share once, so a plane element is loaded about
@@ -1825,34 +1826,36 @@ constexpr int VR = 8;
 
 __global__ __launch_bounds__(RT) void vol_fir_x(FA a, const float* __restrict__ in, float* __restrict__ out) {
     const long long e = (long long)blockIdx.x * RT + threadIdx.x;
-    const int planes = a.K * (a.n + 1);
     const long long per = (long long)a.H * a.W;  // a.H = D * Hs
-    if (e >= planes * per) return;
-    const int pl = (int)(e / per);
-    const long long v = e - (long long)pl * per;
+    if (e >= (long long)a.K * per) return;
+    const int l = (int)(e / per);
+    const long long v = e - (long long)l * per;
     const int r = (int)(v / a.W), x = (int)(v - (long long)r * a.W);
     const int S = a.S;
-    const int l = pl / (a.n + 1), ch = pl - l * (a.n + 1);
     const float* cb = in + (long long)l * a.Np + (long long)r * a.Wp;
-    const float* fb = ch < a.n ? a.f + (long long)ch * a.N + (long long)r * a.W : nullptr;
     const int t0 = max(-S, -x), t1 = min(S, a.W - 1 - x);
-    float acc = 0.0f;
-    for (int t = t0; t <= t1; t += 8) {  // eight taps' loads in flight (addresses clamped into the row)
-        float u[8];
+    // all n + 1 planes of cluster l: the row of c_l is read from the caches
+    // after the first channel
+    for (int ch = 0; ch <= a.n; ++ch) {
+        const float* fb = ch < a.n ? a.f + (long long)ch * a.N + (long long)r * a.W : nullptr;
+        float acc = 0.0f;
+        for (int t = t0; t <= t1; t += 8) {  // eight taps' loads in flight (addresses clamped into the row)
+            float u[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) u[q] = cb[x + min(t + q, t1)];
-        if (fb != nullptr) {
-            float m[8];
+            for (int q = 0; q < 8; ++q) u[q] = cb[x + min(t + q, t1)];
+            if (fb != nullptr) {
+                float m[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) m[q] = fb[x + min(t + q, t1)];
+                for (int q = 0; q < 8; ++q) m[q] = fb[x + min(t + q, t1)];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) u[q] *= m[q];
+                for (int q = 0; q < 8; ++q) u[q] *= m[q];
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (t + q <= t1) acc = fmaf(a.w[abs(t + q)], u[q], acc);
         }
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-            if (t + q <= t1) acc = fmaf(a.w[abs(t + q)], u[q], acc);
+        out[(long long)(l * (a.n + 1) + ch) * a.Np + (long long)r * a.Wp + x] = acc;
     }
-    out[(long long)pl * a.Np + (long long)r * a.Wp + x] = acc;
 }
 
 __global__ __launch_bounds__(RT) void vol_fir_yz(FA a, int D, int Hs, int ax, const float* __restrict__ in,
@@ -2748,10 +2751,9 @@ void filter_volume_run(Ctx& c, Arena& ws, const FilterPlan& fp, int D, const flo
     a.Bpl = Bpl;
     a.Cpl = Cpl;
     const long long planes = (long long)fp.K * (fp.n + 1);
-    const long long tot = planes * fp.N;
     auto grid = [](long long threads) { return dim3((unsigned)((threads + RT - 1) / RT)); };
     hipEvent_t tr = c.stage_begin();
-    hipLaunchKernelGGL(vol_fir_x, grid(tot), dim3(RT), 0, st, a, Cpl, pa);
+    hipLaunchKernelGGL(vol_fir_x, grid((long long)fp.K * fp.N), dim3(RT), 0, st, a, Cpl, pa);
     c.stage_end(FHD_STAGE_ROW, tr);
     hipEvent_t tc = c.stage_begin();
     hipLaunchKernelGGL(vol_fir_yz, grid(planes * D * ((Hs + VR - 1) / VR) * fp.W), dim3(RT), 0, st, a, D, Hs, 1, pa,

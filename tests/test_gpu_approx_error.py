@@ -59,6 +59,7 @@ CASES = [
     ("rho7_45x50_K20", "hyper", 45, 50, 7, 20, 0.3, "gaussian", 1.5, None),
     ("rho32_40x37_K24_box", "hyper", 40, 37, 32, 24, 0.4, "box", None, 3),
     ("one_pixel_K1", "rgb", 1, 1, 3, 1, 0.1, "gaussian", 2.0, None),
+    ("rho33_24x21_K64_box", "hyper", 24, 21, 33, 64, 0.5, "box", None, 2),  # largest LDS footprint
 ]
 
 

@@ -84,6 +84,23 @@ def test_bruteforce_volume(fhd, spatial, ss, radius):
     assert err < TOL and derr < 1e-5
 
 
+def test_volume_six_channels(fhd):
+    """n = 6 (the brute force's two channel groups, six planes per cluster)."""
+    f = np.stack([synth.hyperspectral(15, 18, 6, 3, 0.5, 0.02, 980 + z) for z in range(4)], axis=1)
+    res = oracle.fhd_filter_volume(f, f, 1.0, 0.3, 10, 3)
+    out, cen = fhd.filter_volume(_dev(f), sigma_s=1.0, sigma_r=0.3, K=10, return_centers=True)
+    ref, _ = oracle.bruteforce_volume(f, f, 1.0, 0.3, 3)
+    bf = fhd.bruteforce_volume(_dev(f), sigma_s=1.0, sigma_r=0.3)
+    torch.cuda.synchronize()
+    cerr = np.abs(cen.numpy() - res.centers).max()
+    err = np.abs(out.cpu().numpy() - res.out).max()
+    berr = np.abs(bf.cpu().numpy() - ref).max()
+    print(f"six channels: cond(A) {np.linalg.cond(res.A):.0f}, centers {cerr:.2e}, max-abs {err:.2e}, "
+          f"brute force max-abs {berr:.2e}")
+    assert np.linalg.cond(res.A) < 2e4
+    assert cerr < 1e-6 and err < TOL and berr < TOL
+
+
 def test_one_slice_equals_the_2d_path(fhd):
     f = synth.voronoi_rgb(40, 52, 10, 0.05, 77)
     a = fhd.filter_volume(_dev(f[:, None]), sigma_s=2.0, sigma_r=0.15, K=12)
