@@ -237,7 +237,7 @@ __device__ __forceinline__ void block_lloyd_record(double (&sa)[D], double (&sb)
 // group folds records sub, sub + G, sub + 2G, ... (adjacent threads read
 // adjacent blocks' entries; sixteen loads in flight)
 // into four partials by slot (q mod 4), combined as (p0 op p1) op (p2 op p3);
-// then a pairwise tree over the group in LDS.  Called by all FT threads.
+// then a pairwise tree over the group.  Called by all FT threads.
 template <class OpOf>
 __device__ void reduce_records(const double* part, int first, int nblk, long long pst, int e0, int E, OpOf opof,
                                double* tmp, double* res) {
@@ -264,13 +264,25 @@ __device__ void reduce_records(const double* part, int first, int nblk, long lon
             }
             acc = fold(op, fold(op, p[0], p[1]), fold(op, p[2], p[3]));
         }
-        tmp[t] = acc;
-        __syncthreads();
-        for (int h = G >> 1; h >= 1; h >>= 1) {
-            if (act && sub < h) tmp[t] = fold(op, tmp[t], tmp[t + h]);
+        // pairwise tree over the group: levels of 64 and more through LDS,
+        // the rest within the wave by shuffles (the same pairs, so the same
+        // sums); a group of at most 64 threads lies in one wave
+        double v = acc;
+        int h = G >> 1;
+        if (G > 64) {
+            tmp[t] = v;
             __syncthreads();
+            for (; h >= 64; h >>= 1) {
+                if (act && sub < h) tmp[t] = fold(op, tmp[t], tmp[t + h]);
+                __syncthreads();
+            }
+            v = tmp[t];
         }
-        if (t < Ec) res[base + t] = tmp[t * G];
+        for (; h >= 1; h >>= 1) {
+            const double o = __shfl_down(v, h, 64);
+            if (sub < h) v = fold(op, v, o);
+        }
+        if (act && sub == 0) res[base + t / G] = v;
         __syncthreads();
     }
 }
