@@ -122,7 +122,11 @@ fhd_status fhd_set_stream(fhd_ctx* ctx, void* hip_stream);
 const char* fhd_last_error(const fhd_ctx* ctx);
 
 /* Device workspace (bytes) that fhd_filter needs for one image of this
- * shape with these parameters (an upper bound for the other calls). */
+ * shape with these parameters; it also covers fhd_filter_centers,
+ * fhd_cluster and fhd_bruteforce on that image.  The adjoint, batch, volume
+ * and approximation-error calls have needs of their own: with a caller
+ * workspace that is too small they fail with FHD_ENOMEM (and say so in
+ * fhd_last_error); with the library's own workspace it grows as needed. */
 fhd_status fhd_workspace_size(const fhd_params* p, int n, int rho, int H, int W,
                               size_t* bytes);
 /* Hand the library a caller-owned device buffer of `bytes` bytes (aligned to
