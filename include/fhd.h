@@ -286,9 +286,9 @@ fhd_status fhd_nlm_guide(fhd_ctx* ctx, const float* f, int n, int H, int W, int 
  *   f      device n x D x H x W;  guide device rho x D x H x W (may alias f);
  *   out    device n x D x H x W;  den device D x H x W or NULL;
  *   centers_out  host K x rho or NULL;  info or NULL.
- * The parameters as for fhd_filter, limited to the Gaussian or box window,
- * FP32 contraction and least-squares coefficients (FHD_EUNSUPPORTED
- * otherwise); D * H <= 65535.  Enqueued on the context's stream; the
+ * The parameters as for fhd_filter, limited to the Gaussian or box window
+ * and the FP32 contraction (FHD_EUNSUPPORTED otherwise); coef selects least
+ * squares or the hard variant of eqs. (17)-(18); D * H <= 65535.  Enqueued on the context's stream; the
  * clustering synchronises as in fhd_filter. */
 fhd_status fhd_filter_volume(fhd_ctx* ctx, const float* f, int n, const float* guide, int rho, int D, int H, int W,
                              const fhd_params* p, float* out, float* centers_out, float* den, fhd_info* info);

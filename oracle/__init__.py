@@ -528,11 +528,14 @@ def bruteforce_volume(f, guide, sigma_s, sigma_r, S, spatial="gaussian"):
     return num / eta, eta
 
 
-def fast_filter_volume(f, guide, centers, P, sigma_s, sigma_r, S, spatial="gaussian"):
+def fast_filter_volume(f, guide, centers, P, sigma_s, sigma_r, S, spatial="gaussian", coef="lsq",
+                       labels=None):
     """Algorithm 1 steps 3-5 on a 3-D domain in the paper's form: b_k(i) and
     c(i) = A^+ b(i) per voxel (eq. (12)), the (n+1)K window sums of
     omega(j) b_k(i - j) [f, 1](i - j) over [-S,S]^3 (eqs. (13)-(14), direct,
     neighbours outside the volume left out), and the ratio of eqs. (15)-(16).
+    ``coef='hard'`` takes c_k(i) = 1 iff voxel i is in cluster k (eq. (17),
+    ``labels`` per voxel in (z, y, x) order), which gives eq. (18).
     Returns (g, r_hat) in FP64."""
     f = _f64(f)
     p = _f64(guide)
@@ -542,7 +545,14 @@ def fast_filter_volume(f, guide, centers, P, sigma_s, sigma_r, S, spatial="gauss
     K = mu.shape[0]
     X = p.reshape(rho, -1).T
     B = phi(((X[:, None, :] - mu[None, :, :]) ** 2).sum(-1), sigma_r).T.reshape(K, D, H, W)
-    C = (np.asarray(P, dtype=np.float64) @ B.reshape(K, -1)).reshape(K, D, H, W)
+    if coef == "lsq":
+        C = (np.asarray(P, dtype=np.float64) @ B.reshape(K, -1)).reshape(K, D, H, W)
+    elif coef == "hard":
+        C = np.zeros((K, D * H * W))
+        C[np.asarray(labels).reshape(-1), np.arange(D * H * W)] = 1.0
+        C = C.reshape(K, D, H, W)
+    else:
+        raise ValueError(coef)
     U = np.concatenate([B[:, None] * f[None], B[:, None]], axis=1)  # K x (n+1) x D x H x W
     om = _window_3d(S, sigma_s, spatial)
     V = np.zeros_like(U)
@@ -552,15 +562,17 @@ def fast_filter_volume(f, guide, centers, P, sigma_s, sigma_r, S, spatial="gauss
     return v[:n] / v[n], v[n]
 
 
-def fhd_filter_volume(f, guide, sigma_s, sigma_r, K, S, spatial="gaussian", max_iter=20):
+def fhd_filter_volume(f, guide, sigma_s, sigma_r, K, S, spatial="gaussian", max_iter=20, coef="lsq"):
     """The whole of Algorithm 1 on a 3-D domain: the bisecting K-means of the
     voxels' guide vectors (the volume's voxels in (z, y, x) order, as one
-    set), A and A^+, then :func:`fast_filter_volume`."""
+    set), A and A^+, then :func:`fast_filter_volume` (least squares or the
+    hard variant with the clustering's labels)."""
     rho, D, H, W = np.asarray(guide).shape
     cl = bisecting_kmeans(np.asarray(guide).reshape(rho, D * H, W), K, max_iter)
     A = kernel_matrix(cl.centers, sigma_r)
     P, rank, _ = pinv(A)
-    out, den = fast_filter_volume(f, guide, cl.centers, P, sigma_s, sigma_r, S, spatial)
+    out, den = fast_filter_volume(f, guide, cl.centers, P, sigma_s, sigma_r, S, spatial, coef,
+                                  cl.labels.reshape(-1) if coef == "hard" else None)
     return FilterResult(out, den, cl, cl.centers, A, P, rank)
 
 

@@ -232,7 +232,8 @@ def filter(f, guide=None, sigma_s=3.0, sigma_r=0.1, K=16, spatial="gaussian", ra
 
 
 def filter_volume(f, guide=None, sigma_s=3.0, sigma_r=0.1, K=16, spatial="gaussian", radius=None,
-                  kmeans_max_iter=20, return_den=False, return_centers=False, info=False, strict=False):
+                  kmeans_max_iter=20, coef="lsq", return_den=False, return_centers=False, info=False,
+                  strict=False):
     """Algorithm 1 on a volume: f (n, D, H, W), guide (rho, D, H, W) or None
     (the volume itself), window [-S,S]^3.  Returns g_hat [, den (D, H, W)]
     [, centers (K_eff, rho) on the host] [, info dict]."""
@@ -244,7 +245,7 @@ def filter_volume(f, guide=None, sigma_s=3.0, sigma_r=0.1, K=16, spatial="gaussi
     n, D, H, W = f.shape
     rho = g.shape[0]
     ctx = _ctx(f.device.index)
-    p = make_params(sigma_s, sigma_r, K, spatial, radius, "fp32", "lsq", kmeans_max_iter, strict=strict)
+    p = make_params(sigma_s, sigma_r, K, spatial, radius, "fp32", coef, kmeans_max_iter, strict=strict)
     out = torch.empty_like(f)
     den = torch.empty((D, H, W), device=f.device, dtype=torch.float32) if return_den else None
     cen = torch.zeros((K, rho), dtype=torch.float32)

@@ -898,8 +898,7 @@ fhd_status fhd_filter_volume(fhd_ctx* ctx, const float* f, int n, const float* g
         check_params(p, n, rho, D * H, W);
         FHD_REQUIRE(p->spatial != FHD_SPATIAL_YOUNG, FHD_EUNSUPPORTED,
                     "volumes take the Gaussian or box window (finite, separable over [-S,S]^3)");
-        FHD_REQUIRE(p->contract == FHD_CONTRACT_FP32 && p->coef == FHD_COEF_LSQ, FHD_EUNSUPPORTED,
-                    "volumes take the FP32 least-squares form");
+        FHD_REQUIRE(p->contract == FHD_CONTRACT_FP32, FHD_EUNSUPPORTED, "volumes take the FP32 form");
         FHD_REQUIRE(f && guide && out, FHD_EINVAL, "NULL pointer");
         const long long N = (long long)D * H * W;
         FHD_REQUIRE(!ranges_overlap(out, sizeof(float) * N * n, f, sizeof(float) * N * n) &&
@@ -913,14 +912,17 @@ fhd_status fhd_filter_volume(fhd_ctx* ctx, const float* f, int n, const float* g
         size_t need = 0;
         {
             const FilterPlan fp0 = make_plan(*p, n, rho, D * H, W, p->K);
-            need = kmeans_workspace(N, rho, p->K) + filter_volume_workspace(fp0) + 4096;
+            need = kmeans_workspace(N, rho, p->K) + filter_volume_workspace(fp0) +
+                   align_up(sizeof(int) * (size_t)N, 256) + 4096;
         }
         Arena ws = c.arena(need);
+        const bool hard = p->coef == FHD_COEF_HARD;
+        int* labels = hard ? ws.take<int>((size_t)N) : nullptr;
         const auto t0 = clk::now();
         KmResult km;
         {
             Arena kws = ws;  // the clustering scratch is dead once the centers are known
-            kmeans_run(c, kws, guide, rho, N, p->K, p->kmeans_max_iter, nullptr, km);
+            kmeans_run(c, kws, guide, rho, N, p->K, p->kmeans_max_iter, labels, km);
         }
         const double ms_cluster = ms_since(t0);
         const int K = km.K_eff;
@@ -933,7 +935,7 @@ fhd_status fhd_filter_volume(fhd_ctx* ctx, const float* f, int n, const float* g
         const double ms_solve = ms_since(t1);
         const auto t2 = clk::now();
         const FilterPlan fp = make_plan(*p, n, rho, D * H, W, K);
-        filter_volume_run(c, ws, fp, D, f, guide, c32.data(), P32.data(), out, den);
+        filter_volume_run(c, ws, fp, D, f, guide, c32.data(), P32.data(), labels, out, den);
         if (p->strict) strict_check(c, ws, out, N * n, den, N);
         double ms_filter = 0.0;
         if (info) {

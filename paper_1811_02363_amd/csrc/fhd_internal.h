@@ -153,12 +153,13 @@ void adjoint_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const 
                  const float* den, const float* gout, float* gradf, float* gradp, double* gsig,
                  double* gsigs, double rtol, double* gmu);
 
-// A 3-D domain: the plan's H is D slices of H / D rows; FP32 least-squares
-// weights materialised, three 1-D passes over [-S,S]^3, then the
-// recombination (S = fp.S, no halo rows).
+// A 3-D domain: the plan's H is D slices of H / D rows; FP32 weights
+// materialised, three 1-D passes over [-S,S]^3, then the recombination
+// (S = fp.S, no halo rows); labels (per voxel) for the hard variant.
 size_t filter_volume_workspace(const FilterPlan& fp);
 void filter_volume_run(Ctx& c, Arena& ws, const FilterPlan& fp, int D, const float* f, const float* guide,
-                       const float* centers_host, const float* Pfp32_host, float* out, float* den);
+                       const float* centers_host, const float* Pfp32_host, const int* labels, float* out,
+                       float* den);
 void bruteforce_volume_run(Ctx& c, const FilterPlan& fp, int D, const float* f, const float* guide, float* out,
                            float* den);
 // Error of the kernel approximation (eq. (10) at c = A^+ b) per pixel (err,

@@ -1814,7 +1814,8 @@ size_t row_lds_bytes(const FilterPlan& fp, int tx) {
 // (n+1)K convolutions over the window [-S,S]^3 as three 1-D passes, zero
 // outside the volume.  vol_fir_x runs along x, one output position of all
 // n + 1 planes of a cluster per thread, forming its input c_l [f, 1] from the
-// C planes on the fly.  vol_fir_yz runs
+// C planes (or b_l [f, 1] from the B planes, hard variant) on the fly.
+// vol_fir_yz runs
 // along y within a slice (ax 1) or along z across slices (ax 2, a stride of
 // H rows): each thread takes VR consecutive outputs of one column and reads
 // the VR + 2S inputs they share once, so a plane element is loaded about
@@ -2716,8 +2717,11 @@ size_t filter_volume_workspace(const FilterPlan& fp) {
 }
 
 void filter_volume_run(Ctx& c, Arena& ws, const FilterPlan& fp, int D, const float* f, const float* guide,
-                       const float* centers_host, const float* Pfp32_host, float* out, float* den) {
+                       const float* centers_host, const float* Pfp32_host, const int* labels, float* out,
+                       float* den) {
     FHD_REQUIRE(fp.H % D == 0, FHD_EINVAL, "internal: volume rows");
+    const bool hard = fp.coef == FHD_COEF_HARD;
+    FHD_REQUIRE(!hard || labels != nullptr, FHD_EINVAL, "internal: the hard variant needs labels");
     const int Hs = fp.H / D;
     const size_t cb = filter_consts_bytes(fp.K, fp.rho);
     char* dev = ws.take<char>(cb);
@@ -2738,6 +2742,7 @@ void filter_volume_run(Ctx& c, Arena& ws, const FilterPlan& fp, int D, const flo
     a.P = kc.P;
     a.out = out;
     a.den = den;
+    a.labels = labels;
     a.Pp = Np;  // no halo rows
     hipStream_t st = c.stream;
     const int npx = weights_fp32_npx(fp.K);
@@ -2745,7 +2750,8 @@ void filter_volume_run(Ctx& c, Arena& ws, const FilterPlan& fp, int D, const flo
     FHD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(weights_fp32),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipEvent_t tw = c.stage_begin();
-    hipLaunchKernelGGL(weights_fp32, dim3((fp.W + npx - 1) / npx, fp.H), dim3(npx), lds, st, a, Bpl, Cpl);
+    hipLaunchKernelGGL(weights_fp32, dim3((fp.W + npx - 1) / npx, fp.H), dim3(npx), lds, st, a, Bpl,
+                       hard ? nullptr : Cpl);
     c.stage_end(FHD_STAGE_WEIGHTS, tw);
     FHD_HIP(hipGetLastError());
     a.Bpl = Bpl;
@@ -2753,7 +2759,9 @@ void filter_volume_run(Ctx& c, Arena& ws, const FilterPlan& fp, int D, const flo
     const long long planes = (long long)fp.K * (fp.n + 1);
     auto grid = [](long long threads) { return dim3((unsigned)((threads + RT - 1) / RT)); };
     hipEvent_t tr = c.stage_begin();
-    hipLaunchKernelGGL(vol_fir_x, grid((long long)fp.K * fp.N), dim3(RT), 0, st, a, Cpl, pa);
+    // the convolved factor: c_l [f, 1] (least squares, transposed form) or
+    // b_l [f, 1] (hard variant, eqs. (17)-(18))
+    hipLaunchKernelGGL(vol_fir_x, grid((long long)fp.K * fp.N), dim3(RT), 0, st, a, hard ? Bpl : Cpl, pa);
     c.stage_end(FHD_STAGE_ROW, tr);
     hipEvent_t tc = c.stage_begin();
     hipLaunchKernelGGL(vol_fir_yz, grid(planes * D * ((Hs + VR - 1) / VR) * fp.W), dim3(RT), 0, st, a, D, Hs, 1, pa,
@@ -2761,7 +2769,7 @@ void filter_volume_run(Ctx& c, Arena& ws, const FilterPlan& fp, int D, const flo
     hipLaunchKernelGGL(vol_fir_yz, grid(planes * Hs * ((D + VR - 1) / VR) * fp.W), dim3(RT), 0, st, a, D, Hs, 2, pb,
                        pa);
     a.planes = pa;
-    hipLaunchKernelGGL(recomb_young, dim3((unsigned)((fp.N + RT - 1) / RT)), dim3(RT), 0, st, a, 0);
+    hipLaunchKernelGGL(recomb_young, dim3((unsigned)((fp.N + RT - 1) / RT)), dim3(RT), 0, st, a, hard ? 1 : 0);
     c.stage_end(FHD_STAGE_COL, tc);
     FHD_HIP(hipGetLastError());
 }

@@ -101,6 +101,20 @@ def test_volume_six_channels(fhd):
     assert cerr < 1e-6 and err < TOL and berr < TOL
 
 
+def test_volume_hard_variant(fhd):
+    """Eqs. (17)-(18) on a volume: the indicator of each voxel's own cluster
+    (labels from the library's clustering, equal to the oracle's)."""
+    f = _rgb_volume(5, 21, 26, 820)
+    res = oracle.fhd_filter_volume(f, f, 1.5, 0.15, 12, 4, coef="hard")
+    out, cen = fhd.filter_volume(_dev(f), sigma_s=1.5, sigma_r=0.15, K=12, radius=4, coef="hard",
+                                 return_centers=True)
+    torch.cuda.synchronize()
+    cerr = np.abs(cen.numpy() - res.centers).max()
+    err = np.abs(out.cpu().numpy() - res.out).max()
+    print(f"hard variant on a volume: centers {cerr:.2e}, max-abs {err:.2e}")
+    assert cerr < 1e-6 and err < TOL
+
+
 def test_one_slice_equals_the_2d_path(fhd):
     f = synth.voronoi_rgb(40, 52, 10, 0.05, 77)
     a = fhd.filter_volume(_dev(f[:, None]), sigma_s=2.0, sigma_r=0.15, K=12)

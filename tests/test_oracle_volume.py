@@ -64,6 +64,28 @@ def test_enough_clusters_is_the_bruteforce():
     assert np.max(np.abs(res.out - ref)) < 1e-9
 
 
+def test_hard_variant():
+    """Eqs. (17)-(18) on a volume: one slice is the 2-D hard variant, and with
+    every voxel equal to its cluster's center (E_K = 0) it is the brute force
+    (Theorem 1's bound vanishes)."""
+    f = synth.voronoi_rgb(12, 14, 5, 0.05, 8)
+    cl = oracle.bisecting_kmeans(f, 4)
+    P, _, _ = oracle.pinv(oracle.kernel_matrix(cl.centers, 0.2))
+    g3, _ = oracle.fast_filter_volume(f[:, None], f[:, None], cl.centers, P, 1.5, 0.2, 3, coef="hard",
+                                      labels=cl.labels)
+    g2, _ = oracle.fast_filter(f, f, cl.centers, P, 1.5, 0.2, 3, conv_method="direct", coef="hard",
+                               labels=cl.labels)
+    assert np.max(np.abs(g3[:, 0] - g2)) < 1e-10
+    rng = np.random.default_rng(6)
+    vals = rng.uniform(0, 1, (4, 2))
+    lab = rng.integers(0, 4, (3, 7, 8))
+    g = np.transpose(vals[lab], (3, 0, 1, 2))
+    fv = rng.uniform(0, 1, (2, 3, 7, 8))
+    res = oracle.fhd_filter_volume(fv, g, 1.0, 0.25, 4, 2, coef="hard")
+    ref, _ = oracle.bruteforce_volume(fv, g, 1.0, 0.25, 2)
+    assert np.max(np.abs(res.out - ref)) < 1e-7
+
+
 def test_constant_volume():
     f = np.full((2, 3, 5, 4), 0.37)
     out, _ = oracle.fast_filter_volume(f, f, np.array([[0.37, 0.37]]), np.array([[1.0]]), 1.0, 0.1, 2)
