@@ -41,7 +41,7 @@ FP32_VECTOR_PEAK = 157.3     # TFLOP/s, MI355X published FP32 vector (packed FMA
 # scaled by what the counters read for a 1 GiB device copy: 524,302 KiB
 # fetched, 1,048,576 KiB written), for the kernels as they are in this tree;
 # an entry is None when the counters have not been taken for that version.
-MEASURED_TRAFFIC = {"row": 2250144128, "col": 2495911466}
+MEASURED_TRAFFIC = {"row": 2250091136, "col": 2494573909}
 
 
 def parse():
