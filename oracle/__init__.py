@@ -341,6 +341,12 @@ def _two_means(node, X, X32, max_iter):
     return A, B
 
 
+def _split_key(nd):
+    """Order of the split candidates (Sec. II-C, reading A6): the largest SSE
+    first (not SSE per member), ties to the lower heap id."""
+    return (-nd.sse, nd.heap)
+
+
 def bisecting_kmeans(guide, K, max_iter=20, batched=False):
     """Bisecting K-means of the multiset {p(i)} (eq. (8)) into at most K
     clusters (Sec. II-C).
@@ -366,7 +372,7 @@ def bisecting_kmeans(guide, K, max_iter=20, batched=False):
         cand = [nd for nd in leaves.values() if nd.splittable and nd.sse > 0.0]
         if not cand:
             return None
-        return min(cand, key=lambda nd: (-nd.sse, nd.heap))
+        return min(cand, key=_split_key)
 
     while len(leaves) < K:
         if batched:
@@ -445,7 +451,7 @@ def range_weights(guide, centers, sigma_r):
 
 def fast_filter(f, guide, centers, P, sigma_s, sigma_r, S=None,
                 spatial="gaussian", conv_method="direct", coef="lsq",
-                labels=None):
+                labels=None, return_terms=False):
     """Algorithm 1 from the centers on: b, c = P b, the convolutions
     v_k = omega * (b_k f), r_k = omega * b_k (eqs. (13)-(14)) and the
     recombination g = sum_k c_k v_k / sum_k c_k r_k (eqs. (15)-(16)).
@@ -454,7 +460,11 @@ def fast_filter(f, guide, centers, P, sigma_s, sigma_r, S=None,
     (:func:`young_conv`, no radius).
     ``coef='hard'`` uses c_k(i) = 1 iff pixel i is in cluster k (eq. (17)),
     which gives eq. (18); ``labels`` must then be given.
-    Returns (g (n,H,W), r_hat (H,W)) in FP64.
+    Returns (g (n,H,W), r_hat (H,W)) in FP64.  With ``return_terms`` it also
+    returns the numerator v (n,H,W) of eq. (15) and the magnitudes of the
+    sums that form v and r_hat, sum_k |c_k(i)| |v_k(i)| (n,H,W) and
+    sum_k |c_k(i)| |r_k(i)| (H,W): the scale of the rounding error any
+    finite-precision evaluation of the two sums carries.
     """
     f = _f64(f)
     n, H, W = f.shape
@@ -473,6 +483,8 @@ def fast_filter(f, guide, centers, P, sigma_s, sigma_r, S=None,
     F = f.reshape(n, -1)
     v = np.zeros((n, H * W))
     r = np.zeros(H * W)
+    mv = np.zeros((n, H * W)) if return_terms else None
+    mr = np.zeros(H * W) if return_terms else None
     for k in range(K):
         U = np.empty((n + 1, H * W))
         U[:n] = B[:, k] * F
@@ -483,7 +495,13 @@ def fast_filter(f, guide, centers, P, sigma_s, sigma_r, S=None,
             V = conv(U.reshape(n + 1, H, W), S, sigma_s, spatial, conv_method).reshape(n + 1, -1)
         v += C[:, k] * V[:n]
         r += C[:, k] * V[n]
-    return (v / r).reshape(n, H, W), r.reshape(H, W)
+        if return_terms:
+            mv += np.abs(C[:, k]) * np.abs(V[:n])
+            mr += np.abs(C[:, k]) * np.abs(V[n])
+    g, rh = (v / r).reshape(n, H, W), r.reshape(H, W)
+    if return_terms:
+        return g, rh, v.reshape(n, H, W), mv.reshape(n, H, W), mr.reshape(H, W)
+    return g, rh
 
 
 def _window_3d(S, sigma_s, spatial):
@@ -582,9 +600,11 @@ def approx_error(guide, centers, sigma_r, S, P=None):
     coefficients the method uses, c(i) = A^+ b(i) (eqs. (11)-(12)),
         err(i) = sum_{x in Theta_i} (phi(x - p(i)) - sum_k c_k(i) phi(x - mu_k))^2,
     Theta_i the guide values of the in-image pixels of the (2S+1)^2 window
-    around i (A1; a multiset, A4).  Its mean over the pixels is the error
-    E_K of Sec. II-A.  Vectorised over the pixels, one window offset at a
-    time.  Returns (err (H, W) FP64, E_K)."""
+    around i (A1; a multiset, A4).  Its mean over the pixels is the averaged
+    least-squares error of Sec. II-A (E_ls here; the paper writes a script E
+    indexed by K, distinct from the clustering error E_K of eq. (20)).
+    Vectorised over the pixels, one window offset at a time.  Returns
+    (err (H, W) FP64, E_ls)."""
     p = _f64(guide)
     rho, H, W = p.shape
     mu = np.asarray(centers, dtype=np.float64).reshape(-1, rho)

@@ -1,5 +1,6 @@
 """Pins of the oracle's kernel-approximation error (eq. (10) evaluated at the
-method's coefficients c(i) = A^+ b(i); its pixel mean is E_K of Sec. II-A).
+method's coefficients c(i) = A^+ b(i); its pixel mean is the averaged
+least-squares error E_ls of Sec. II-A, not the clustering error E_K).
 
 * A plain triple loop over pixels, window offsets and centers on tiny images
   (math.exp, scalar sums) gives the same per-pixel errors as the vectorised
@@ -48,10 +49,10 @@ def test_matches_loops_on_tiny_images():
     g = synth.voronoi_rgb(6, 7, 5, 0.05, 77).astype(np.float64)
     cen = oracle.bisecting_kmeans(g, 4).centers
     for sr in (0.3, 0.08):
-        err, EK = oracle.approx_error(g, cen, sr, 2)
+        err, Els = oracle.approx_error(g, cen, sr, 2)
         ref = _loops(g, cen, sr, 2)
         assert np.max(np.abs(err - ref)) < 1e-12 * max(1.0, ref.max())
-        assert abs(EK - ref.mean()) < 1e-12 * max(1.0, ref.mean())
+        assert abs(Els - ref.mean()) < 1e-12 * max(1.0, ref.mean())
         assert ref.max() > 1e-6  # not a trivially exact case
     # rank-deficient A: two coincident centers
     cen2 = np.vstack([cen[:3], cen[2:3]])
@@ -64,11 +65,11 @@ def test_exact_cases():
     vals = rng.uniform(0, 1, (5, 3))
     lab = rng.integers(0, 5, (9, 11))
     g = np.transpose(vals[lab], (2, 0, 1))
-    err, EK = oracle.approx_error(g, vals, 0.4, 3)
-    assert EK < 1e-18 and err.max() < 1e-16
+    err, Els = oracle.approx_error(g, vals, 0.4, 3)
+    assert Els < 1e-18 and err.max() < 1e-16
     g2 = synth.voronoi_rgb(10, 9, 6, 0.05, 3)
     cen = oracle.bisecting_kmeans(g2, 3).centers
-    err, EK = oracle.approx_error(g2, cen, np.inf, 2)
+    err, Els = oracle.approx_error(g2, cen, np.inf, 2)
     assert err.max() < 1e-20
 
 

@@ -197,6 +197,41 @@ def test_bisecting_hand_worked(golden_dir):
     assert cl.labels.tolist() == g["labels"]
 
 
+def _golden_select(golden_dir):
+    return json.load(open(os.path.join(golden_dir, "bisect_select.json")))["cases"]
+
+
+@pytest.mark.parametrize("batched", [False, True])
+def test_bisecting_split_selection_golden(golden_dir, batched):
+    """The split-selection rule, hand-worked (tests/golden/bisect_select.json):
+    the largest SSE is split even when another leaf has the larger SSE per
+    member, and equal SSEs go to the lower heap id."""
+    for g in _golden_select(golden_dir):
+        pts = np.array(g["points"], dtype=np.float32).reshape(1, 1, -1)
+        cl = oracle.bisecting_kmeans(pts, g["K"], batched=batched)
+        assert cl.leaf_heap == g["leaf_heap"], g["name"]
+        assert cl.split_order == g["split_order"], g["name"]
+        np.testing.assert_array_equal(cl.centers.ravel(), g["centers"])
+        np.testing.assert_array_equal(cl.leaf_sse, g["leaf_sse"])
+        assert cl.E_K == g["E_K"]
+        assert cl.labels.tolist() == g["labels"]
+
+
+@pytest.mark.parametrize("wrong", ["variance", "higher_heap"])
+def test_bisecting_split_selection_golden_discriminates(golden_dir, monkeypatch, wrong):
+    """A plausible misreading planted in the oracle (split the largest SSE per
+    member, or break ties towards the higher heap id) fails the golden."""
+    key = {"variance": lambda nd: (-nd.sse / len(nd.idx), nd.heap),
+           "higher_heap": lambda nd: (-nd.sse, -nd.heap)}[wrong]
+    monkeypatch.setattr(oracle, "_split_key", key)
+    mismatched = 0
+    for g in _golden_select(golden_dir):
+        pts = np.array(g["points"], dtype=np.float32).reshape(1, 1, -1)
+        cl = oracle.bisecting_kmeans(pts, g["K"])
+        mismatched += cl.leaf_heap != g["leaf_heap"]
+    assert mismatched >= 1
+
+
 def test_bisecting_invariants():
     f = _rgb(40, 44, 9, 0.05, 3)
     K = 20
