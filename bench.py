@@ -184,7 +184,8 @@ def window_leg(torch, fhd, x, sr, K):
 
 
 def approx_error_leg(torch, fhd, synth):
-    """E_K (eq. (10) at c = A^+ b, averaged over the pixels) against K for a
+    """E_ls (eq. (10) at c = A^+ b, averaged over the pixels: the least-squares
+    error of Sec. II-A, not the clustering error E_K of eq. (20)) against K for a
     3-dimensional and a 32-dimensional guide, clusters from the library's own
     bisecting K-means: the fall of the approximation error with K (Sec. II-A)."""
     legs = {}
@@ -196,9 +197,9 @@ def approx_error_leg(torch, fhd, synth):
             cen, _ = fhd.cluster(g, K)
             run = lambda: fhd.approx_error(g, cen, sigma_r=c["sigma_r"], radius=c["S"], spatial="box",
                                            per_pixel=False)
-            _, EK = run()
+            _, Els = run()
             ms = timed(torch, run, 2)
-            row[f"K{K}"] = {"E_K": float(f"{EK:.4e}"), "K_eff": int(cen.shape[0]), "ms": round(ms, 2)}
+            row[f"K{K}"] = {"E_ls": float(f"{Els:.4e}"), "K_eff": int(cen.shape[0]), "ms": round(ms, 2)}
         legs[name] = row
     return legs
 

@@ -88,8 +88,9 @@ typedef struct {
     int kmeans_max_iter;  /* 2-means assignment steps per split (default 20) */
     double pinv_rtol;     /* <= 0: singular values above K * s_max * 2^-52 are kept
                              (the MATLAB pinv default); else rtol * s_max */
-    int strict;           /* nonzero: FHD_ENUMERIC if a normaliser is <= 0 or an output
-                             is not finite (needs a synchronising check) */
+    int strict;           /* nonzero: FHD_ENUMERIC if a normaliser is <= 0 (or NaN) or an
+                             output is not finite (the reduction that fills fhd_info's
+                             normaliser fields; synchronises); the outputs are written */
 } fhd_params;
 
 /* Diagnostics of one call (host struct, filled when non-NULL). */
@@ -105,6 +106,15 @@ typedef struct {
     float ms_solve;         /* wall time of the K x K solve */
     float ms_filter;        /* wall time from the solve to the end of the filter passes
                                (only when the call synchronises) */
+    /* The normaliser r_hat of eq. (16) and the output g_hat = v / r_hat.  The
+     * least-squares coefficients can be negative, so r_hat (exactly >= 1 for
+     * the filter it approximates) can come out tiny or non-positive; the
+     * ratio is not guarded.  Counted on the device by one reduction over the
+     * whole output (filter calls only; zero elsewhere). */
+    float den_min;          /* smallest r_hat (NaN values are skipped) */
+    long long den_nonpos;   /* pixels with r_hat <= 0 or NaN */
+    long long den_small;    /* pixels with r_hat < 1e-3 (the non-positive ones included) */
+    long long nonfinite;    /* output values that are not finite */
 } fhd_info;
 
 /* Fill `p` with defaults: sigma_s 3, radius -1, sigma_r 0.1, K 16, Gaussian,
@@ -157,7 +167,9 @@ fhd_status fhd_cluster(fhd_ctx* ctx, const float* guide, int rho, int H, int W, 
  * pseudo-inverse in FP64 (symmetric eigen-decomposition, singular values
  * |lambda| above the tolerance of fhd_params.pinv_rtol kept).
  *   centers host K x rho FP32;  Apinv host K x K FP64 (row-major), or NULL;
- *   A host K x K FP64 or NULL;  rank host or NULL. */
+ *   A host K x K FP64 or NULL;  rank host or NULL.
+ * FHD_ENUMERIC when the eigen-decomposition does not converge (non-finite
+ * centers); every call that solves for A^+ reports the same. */
 fhd_status fhd_pinv(const float* centers, int K, int rho, double sigma_r, double rtol,
                     double* A, double* Apinv, int* rank, double* cond);
 
@@ -306,14 +318,16 @@ fhd_status fhd_bruteforce_volume(fhd_ctx* ctx, const float* f, int n, const floa
  * c(i) = A^+ b(i) of eqs. (11)-(12),
  *   err[i] = sum_{q} (phi(p(q) - p(i)) - sum_k c_k(i) phi(p(q) - mu_k))^2,
  * q over the in-image pixels of the (2S+1)^2 window around i (the set Theta_i
- * of eq. (10), counted with multiplicity).  Its pixel mean is the error E_K
- * whose fall with K the paper plots.
+ * of eq. (10), counted with multiplicity).  Its pixel mean is the averaged
+ * least-squares error (a script E indexed by K in Sec. II-A, written E_ls
+ * here; not the clustering error E_K of eq. (20)) whose fall with K the
+ * paper plots.
  *   guide    device rho x H x W;  centers host K x rho FP32, 1 <= K <= 64;
  *   p        sigma_r, pinv_rtol and the window: radius (or ceil(3 sigma_s)
  *            when radius < 0, Gaussian), box needs radius >= 0; the recursive
  *            Gaussian is rejected (no finite window);
  *   err      device H x W FP32 (output) or NULL;
- *   mean     host, E_K (FP64 sum of the per-pixel FP64 sums) or NULL;
+ *   mean     host, E_ls (FP64 sum of the per-pixel FP64 sums / N) or NULL;
  *            when given the call synchronises.  At least one of the two.
  * Terms are FP32 and sums FP64.  Cost ~ K (2S+1)^2 (rho + 1) per pixel. */
 fhd_status fhd_approx_error(fhd_ctx* ctx, const float* guide, int rho, int H, int W, const float* centers, int K,

@@ -66,6 +66,8 @@ class Info(ctypes.Structure):
         ("kmeans_splits", ctypes.c_int), ("E_K", ctypes.c_double), ("cond_A", ctypes.c_double),
         ("pinv_norm", ctypes.c_double), ("ms_cluster", ctypes.c_float),
         ("ms_solve", ctypes.c_float), ("ms_filter", ctypes.c_float),
+        ("den_min", ctypes.c_float), ("den_nonpos", ctypes.c_longlong),
+        ("den_small", ctypes.c_longlong), ("nonfinite", ctypes.c_longlong),
     ]
 
     def as_dict(self):
@@ -432,7 +434,7 @@ def _batch_arrays(sizes):
 
 def filter_batch(flat_f, sizes, n, flat_guide=None, rho=None, sigma_s=3.0, sigma_r=0.1, K=16,
                  spatial="gaussian", radius=None, contract="fp32", coef="lsq", kmeans_max_iter=20,
-                 return_den=False, info=False):
+                 return_den=False, info=False, strict=False):
     """Algorithm 1 on a ragged batch in the flat layout of :func:`pack_batch`.
     Returns (out flat, [den flat], centers (B, K, rho) host, K_eff list [, info list])."""
     B, Ha, Wa, Oa, N = _batch_arrays(sizes)
@@ -441,7 +443,7 @@ def filter_batch(flat_f, sizes, n, flat_guide=None, rho=None, sigma_s=3.0, sigma
     if flat_f.numel() != n * N or g.numel() != rho * N:
         raise FHDError(FHD_EINVAL, "flat buffers do not match the sizes")
     ctx = _ctx(flat_f.device.index)
-    p = make_params(sigma_s, sigma_r, K, spatial, radius, contract, coef, kmeans_max_iter)
+    p = make_params(sigma_s, sigma_r, K, spatial, radius, contract, coef, kmeans_max_iter, strict=strict)
     out = torch.empty_like(flat_f)
     den = torch.empty(N, device=flat_f.device, dtype=torch.float32) if return_den else None
     cen = torch.zeros((B, K, rho), dtype=torch.float32)
@@ -579,8 +581,10 @@ def scale_guide(guide, sigma_d, out=None):
 def approx_error(guide, centers, sigma_r=0.1, sigma_s=3.0, radius=None, spatial="gaussian",
                  pinv_rtol=0.0, per_pixel=True):
     """Error of the kernel approximation (``fhd_approx_error``): eq. (10) at
-    c(i) = A^+ b(i) per pixel and its mean E_K.  ``guide`` (rho, H, W) on the
-    device, ``centers`` (K, rho), K <= 64.  Returns (err (H, W) or None, E_K)."""
+    c(i) = A^+ b(i) per pixel and its pixel mean E_ls (the averaged
+    least-squares error of Sec. II-A, not the clustering error E_K of
+    eq. (20)).  ``guide`` (rho, H, W) on the device, ``centers`` (K, rho),
+    K <= 64.  Returns (err (H, W) or None, E_ls)."""
     if not isinstance(guide, torch.Tensor) or not guide.is_cuda or guide.dim() != 3:
         raise FHDError(FHD_EINVAL, "guide must be a (rho, H, W) CUDA (HIP) tensor")
     rho, H, W = guide.shape

@@ -9,6 +9,7 @@
 #include <mutex>
 #include <new>
 #include <thread>
+#include <string>
 #include <vector>
 
 #include "fhd_internal.h"
@@ -132,6 +133,8 @@ void Ctx::release() {
         }
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     ev_pool.clear();
+    if (switch_ev != nullptr) (void)hipEventDestroy(switch_ev);
+    switch_ev = nullptr;
     for (int s = 0; s < 3; ++s) {
         if (pinned[s] != nullptr) (void)hipHostFree(pinned[s]);
         if (pinned_ev[s] != nullptr) (void)hipEventDestroy(pinned_ev[s]);
@@ -263,31 +266,109 @@ __global__ __launch_bounds__(256) void scale_guide_kernel(const float* guide, lo
     out[e] = __fdiv_rn(guide[e], sc.s[(int)(e / N)]);
 }
 
-// Counts of non-positive normalisers and non-finite outputs (strict mode).
-__global__ void check_output(const float* out, long long count, const float* den, long long N,
-                             unsigned long long* bad) {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long b = 0;
-    if (i < count && !isfinite(out[i])) b = 1;
-    if (den != nullptr && i < N && !(den[i] > 0.0f)) b = 1;
-    if (b) atomicAdd(bad, 1ull);
+// Diagnostics of the normaliser r_hat of eq. (16) and of the output (the
+// least-squares coefficients may be negative, so r_hat can come out tiny or
+// non-positive; the ratio is not guarded): per block, the smallest r_hat and
+// the counts of r_hat <= 0 (or NaN), r_hat < 1e-3 and non-finite outputs.
+// The blocks' records are reduced on the host in a fixed order.
+constexpr int STAT_T = 256, STAT_BLOCKS = 512;
+struct StatRec {
+    float dmin;
+    unsigned pad;
+    unsigned long long nonpos, small, nonfinite;
+};
+struct OutStats {
+    float den_min = INFINITY;
+    long long nonpos = 0, small = 0, nonfinite = 0;
+};
+
+__global__ __launch_bounds__(STAT_T) void out_stats_kernel(const float* __restrict__ out, long long count,
+                                                           const float* __restrict__ den, long long N,
+                                                           StatRec* __restrict__ part) {
+    float mn = INFINITY;
+    unsigned long long np = 0, sm = 0, nf = 0;
+    const long long stride = (long long)gridDim.x * STAT_T;
+    const long long i0 = (long long)blockIdx.x * STAT_T + threadIdx.x;
+    if (den != nullptr)
+        for (long long i = i0; i < N; i += stride) {
+            const float d = den[i];
+            mn = fminf(mn, d);
+            np += !(d > 0.0f);
+            sm += !(d >= 1e-3f);
+        }
+    for (long long i = i0; i < count; i += stride) nf += !isfinite(out[i]);
+    for (int o = 32; o > 0; o >>= 1) {
+        mn = fminf(mn, __shfl_xor(mn, o));
+        np += __shfl_xor(np, o);
+        sm += __shfl_xor(sm, o);
+        nf += __shfl_xor(nf, o);
+    }
+    __shared__ StatRec w[STAT_T / 64];
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) w[wave] = StatRec{mn, 0u, np, sm, nf};
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        StatRec r = w[0];
+        for (int q = 1; q < STAT_T / 64; ++q) {
+            r.dmin = fminf(r.dmin, w[q].dmin);
+            r.nonpos += w[q].nonpos;
+            r.small += w[q].small;
+            r.nonfinite += w[q].nonfinite;
+        }
+        part[blockIdx.x] = r;
+    }
 }
 
-void strict_check(Ctx& c, Arena& ws, const float* out, long long count, const float* den, long long N) {
-    unsigned long long* bad = ws.take<unsigned long long>(1);
-    FHD_HIP(hipMemsetAsync(bad, 0, sizeof(unsigned long long), c.stream));
-    hipLaunchKernelGGL(check_output, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, c.stream, out,
-                       count, den, N, bad);
+size_t stats_workspace(long long N) {
+    return align_up(sizeof(float) * (size_t)N, 256) + align_up(sizeof(StatRec) * STAT_BLOCKS, 256);
+}
+
+// Enqueues the statistics of `count` outputs and N normalisers (den may be
+// null: outputs only) into a block of STAT_BLOCKS records.
+void out_stats_launch(Ctx& c, const float* out, long long count, const float* den, long long N, StatRec* part) {
+    hipLaunchKernelGGL(out_stats_kernel, dim3(STAT_BLOCKS), dim3(STAT_T), 0, c.stream, out, count, den, N, part);
     FHD_HIP(hipGetLastError());
-    unsigned long long h = 0;
-    FHD_HIP(hipMemcpyAsync(&h, bad, sizeof(h), hipMemcpyDeviceToHost, c.stream));
+}
+
+OutStats out_stats_reduce(const StatRec* h) {
+    OutStats s;
+    for (int b = 0; b < STAT_BLOCKS; ++b) {
+        s.den_min = std::fmin(s.den_min, h[b].dmin);
+        s.nonpos += (long long)h[b].nonpos;
+        s.small += (long long)h[b].small;
+        s.nonfinite += (long long)h[b].nonfinite;
+    }
+    return s;
+}
+
+// One image's statistics; synchronises the stream.
+OutStats out_stats(Ctx& c, Arena& ws, const float* out, long long count, const float* den, long long N) {
+    StatRec* part = ws.take<StatRec>(STAT_BLOCKS);
+    out_stats_launch(c, out, count, den, N, part);
+    std::vector<StatRec> h(STAT_BLOCKS);
+    FHD_HIP(hipMemcpyAsync(h.data(), part, sizeof(StatRec) * STAT_BLOCKS, hipMemcpyDeviceToHost, c.stream));
     FHD_HIP(hipStreamSynchronize(c.stream));
-    FHD_REQUIRE(h == 0, FHD_ENUMERIC, "non-positive normaliser or non-finite output");
+    return out_stats_reduce(h.data());
+}
+
+void strict_verdict(const OutStats& s) {
+    FHD_REQUIRE(s.nonpos == 0 && s.nonfinite == 0, FHD_ENUMERIC,
+                "non-positive normaliser (" + std::to_string(s.nonpos) + " pixels) or non-finite output (" +
+                    std::to_string(s.nonfinite) + " values)");
+}
+
+void fill_stats(fhd_info* info, const OutStats& s) {
+    if (info == nullptr) return;
+    info->den_min = s.den_min;
+    info->den_nonpos = s.nonpos;
+    info->den_small = s.small;
+    info->nonfinite = s.nonfinite;
 }
 
 void fill_info(fhd_info* info, int K_eff, const PinvResult& pr, double E_K, int rounds, int splits,
                double ms_cluster, double ms_solve, double ms_filter) {
     if (info == nullptr) return;
+    std::memset(info, 0, sizeof(*info));
     info->K_eff = K_eff;
     info->pinv_rank = pr.rank;
     info->kmeans_rounds = rounds;
@@ -438,7 +519,16 @@ fhd_status fhd_set_stream(fhd_ctx* ctx, void* hip_stream) {
                 FHD_HIP(hipEventSynchronize(c.pinned_ev[s]));
                 c.pinned_pending[s] = false;
             }
-        c.stream = static_cast<hipStream_t>(hip_stream);
+        hipStream_t ns = static_cast<hipStream_t>(hip_stream);
+        if (ns != c.stream) {
+            // work already enqueued on the old stream still reads and writes
+            // the context's workspace: the new stream starts after it
+            if (c.switch_ev == nullptr)
+                FHD_HIP(hipEventCreateWithFlags(&c.switch_ev, hipEventDisableTiming));
+            FHD_HIP(hipEventRecord(c.switch_ev, c.stream));
+            FHD_HIP(hipStreamWaitEvent(ns, c.switch_ev, 0));
+        }
+        c.stream = ns;
     });
 }
 
@@ -455,7 +545,8 @@ fhd_status fhd_workspace_size(const fhd_params* p, int n, int rho, int H, int W,
         size_t b = kmeans_workspace(fp.N, rho, p->K);
         b += filter_workspace(fp);
         b += align_up(sizeof(int) * (size_t)fp.N, 256);  // labels
-        b += 4096;                                       // strict-mode counter, slack
+        b += stats_workspace(fp.N);                      // normaliser statistics (info, strict)
+        b += 4096;                                       // slack
         *bytes = b;
         return FHD_OK;
     } catch (const Error& e) {
@@ -514,6 +605,8 @@ fhd_status fhd_pinv(const float* centers, int K, int rho, double sigma_r, double
         if (rank) *rank = r.rank;
         if (cond) *cond = r.cond;
         return FHD_OK;
+    } catch (const Error& e) {
+        return e.status;
     } catch (...) {
         return FHD_ENOMEM;
     }
@@ -535,20 +628,25 @@ fhd_status fhd_filter_centers(fhd_ctx* ctx, const float* f, int n, const float* 
                         !ranges_overlap(den, sizeof(float) * N, out, sizeof(float) * N * n),
                     FHD_EINVAL, "outputs alias inputs");
         const FilterPlan fp = make_plan(*p, n, rho, H, W, K);
-        Arena ws = c.arena(filter_workspace(fp) + 4096);
+        Arena ws = c.arena(filter_workspace(fp) + stats_workspace(N) + 4096);
+        const bool stats = info != nullptr || p->strict;
+        float* dn = (stats && den == nullptr) ? ws.take<float>((size_t)N) : den;
         const auto t0 = clk::now();
         std::vector<float> P32;
         const PinvResult pr = solve(centers, K, rho, p->sigma_r, p->pinv_rtol, P32);
         const double ms_solve = ms_since(t0);
         const auto t1 = clk::now();
-        filter_run(c, ws, fp, f, guide, centers, P32.data(), labels, out, den);
-        if (p->strict) strict_check(c, ws, out, N * n, den, N);
+        filter_run(c, ws, fp, f, guide, centers, P32.data(), labels, out, dn);
         double ms_filter = 0.0;
         if (info) {
             FHD_HIP(hipStreamSynchronize(c.stream));
             ms_filter = ms_since(t1);
         }
+        OutStats st;
+        if (stats) st = out_stats(c, ws, out, N * n, dn, N);
         fill_info(info, K, pr, 0.0, 0, 0, 0.0, ms_solve, ms_filter);
+        fill_stats(info, st);
+        if (p->strict) strict_verdict(st);
     });
 }
 
@@ -568,11 +666,13 @@ fhd_status fhd_filter(fhd_ctx* ctx, const float* f, int n, const float* guide, i
         {
             const FilterPlan fp0 = make_plan(*p, n, rho, H, W, p->K);
             need = kmeans_workspace(N, rho, p->K) + filter_workspace(fp0) +
-                   align_up(sizeof(int) * (size_t)N, 256) + 4096;
+                   align_up(sizeof(int) * (size_t)N, 256) + stats_workspace(N) + 4096;
         }
         Arena ws = c.arena(need);
         const bool hard = p->coef == FHD_COEF_HARD;
         int* labels = hard ? ws.take<int>((size_t)N) : nullptr;
+        const bool stats = info != nullptr || p->strict;
+        float* dn = (stats && den == nullptr) ? ws.take<float>((size_t)N) : den;
         const auto t0 = clk::now();
         KmResult km;
         {
@@ -590,14 +690,17 @@ fhd_status fhd_filter(fhd_ctx* ctx, const float* f, int n, const float* guide, i
         const double ms_solve = ms_since(t1);
         const auto t2 = clk::now();
         const FilterPlan fp = make_plan(*p, n, rho, H, W, K);
-        filter_run(c, ws, fp, f, guide, c32.data(), P32.data(), labels, out, den);
-        if (p->strict) strict_check(c, ws, out, N * n, den, N);
+        filter_run(c, ws, fp, f, guide, c32.data(), P32.data(), labels, out, dn);
         double ms_filter = 0.0;
         if (info) {
             FHD_HIP(hipStreamSynchronize(c.stream));
             ms_filter = ms_since(t2);
         }
+        OutStats st;
+        if (stats) st = out_stats(c, ws, out, N * n, dn, N);
         fill_info(info, K, pr, km.E_K, km.rounds, km.splits, ms_cluster, ms_solve, ms_filter);
+        fill_stats(info, st);
+        if (p->strict) strict_verdict(st);
     });
 }
 
@@ -667,10 +770,14 @@ fhd_status fhd_filter_batch(fhd_ctx* ctx, int B, const int* H, const int* W, con
         passes = align_up(passes, 256);
         const size_t fws = batched ? filter_batch_workspace(B, kplans.data()) : ns * passes;
         const size_t need = std::max(kmeans_workspace(N, rho, K, B), (size_t)B * cb + fws + 512) +
-                            align_up(sizeof(int) * (size_t)N, 256) + 4096;
+                            align_up(sizeof(int) * (size_t)N, 256) + stats_workspace(N) +
+                            align_up(sizeof(StatRec) * STAT_BLOCKS * (size_t)B, 256) + 4096;
         Arena ws = c.arena(need);
         const bool hard = p->coef == FHD_COEF_HARD;
         int* labels = hard ? ws.take<int>((size_t)N) : nullptr;
+        const bool stats = info != nullptr || p->strict;
+        float* dn = (stats && den == nullptr) ? ws.take<float>((size_t)N) : den;
+        StatRec* part = stats ? ws.take<StatRec>((size_t)STAT_BLOCKS * B) : nullptr;
         const auto t0 = clk::now();
         std::vector<KmResult> km;
         {
@@ -710,11 +817,11 @@ fhd_status fhd_filter_batch(fhd_ctx* ctx, int B, const int* H, const int* W, con
                 gb[b] = guide + (size_t)rho * o;
                 lb[b] = hard ? labels + o : nullptr;
                 ob[b] = out + (size_t)n * o;
-                db[b] = den ? den + o : nullptr;
+                db[b] = dn ? dn + o : nullptr;
                 kc[b] = filter_consts_at(dev + (size_t)b * cb, km[b].K_eff, rho);
             }
             filter_passes_batch(c, ws, B, plans.data(), fb.data(), gb.data(), kc.data(), hard ? lb.data() : nullptr,
-                                ob.data(), den ? db.data() : nullptr);
+                                ob.data(), dn ? db.data() : nullptr);
         } else {
             // one scratch region per stream; stream order makes it reusable image after image
             char* region = ws.take<char>((size_t)ns * passes);
@@ -728,18 +835,32 @@ fhd_status fhd_filter_batch(fhd_ctx* ctx, int B, const int* H, const int* W, con
                 const long long o = px_offset[b];
                 filter_passes(c, pws, fp, f + (size_t)n * o, guide + (size_t)rho * o,
                               filter_consts_at(dev + (size_t)b * cb, km[b].K_eff, rho),
-                              hard ? labels + o : nullptr, out + (size_t)n * o, den ? den + o : nullptr);
+                              hard ? labels + o : nullptr, out + (size_t)n * o, dn ? dn + o : nullptr);
             }
         }
-        if (p->strict) strict_check(c, ws, out, N * n, den, N);
         double ms_filter = 0.0;
         if (info) {
             FHD_HIP(hipStreamSynchronize(c.stream));
             ms_filter = ms_since(t2);
+        }
+        std::vector<OutStats> st(B);
+        if (stats) {
             for (int b = 0; b < B; ++b)
+                out_stats_launch(c, out + (size_t)n * px_offset[b], cnt[b] * n, dn + px_offset[b], cnt[b],
+                                 part + (size_t)b * STAT_BLOCKS);
+            std::vector<StatRec> h((size_t)STAT_BLOCKS * B);
+            FHD_HIP(hipMemcpyAsync(h.data(), part, sizeof(StatRec) * h.size(), hipMemcpyDeviceToHost, c.stream));
+            FHD_HIP(hipStreamSynchronize(c.stream));
+            for (int b = 0; b < B; ++b) st[b] = out_stats_reduce(h.data() + (size_t)b * STAT_BLOCKS);
+        }
+        if (info)
+            for (int b = 0; b < B; ++b) {
                 fill_info(info + b, km[b].K_eff, pr[b], km[b].E_K, km[b].rounds, km[b].splits, ms_cluster, ms_solve,
                           ms_filter);
-        }
+                fill_stats(info + b, st[b]);
+            }
+        if (p->strict)
+            for (int b = 0; b < B; ++b) strict_verdict(st[b]);
     });
 }
 
@@ -869,8 +990,8 @@ fhd_status fhd_bruteforce(fhd_ctx* ctx, const float* f, int n, const float* guid
         const FilterPlan fp = make_plan(*p, n, rho, H, W, 1);
         bruteforce_run(c, fp, f, guide, out, den);
         if (p->strict) {
-            Arena ws = c.arena(4096);
-            strict_check(c, ws, out, N * n, den, N);
+            Arena ws = c.arena(stats_workspace(0) + 4096);
+            strict_verdict(out_stats(c, ws, out, N * n, den, N));
         }
     });
 }
@@ -913,11 +1034,13 @@ fhd_status fhd_filter_volume(fhd_ctx* ctx, const float* f, int n, const float* g
         {
             const FilterPlan fp0 = make_plan(*p, n, rho, D * H, W, p->K);
             need = kmeans_workspace(N, rho, p->K) + filter_volume_workspace(fp0) +
-                   align_up(sizeof(int) * (size_t)N, 256) + 4096;
+                   align_up(sizeof(int) * (size_t)N, 256) + stats_workspace(N) + 4096;
         }
         Arena ws = c.arena(need);
         const bool hard = p->coef == FHD_COEF_HARD;
         int* labels = hard ? ws.take<int>((size_t)N) : nullptr;
+        const bool stats = info != nullptr || p->strict;
+        float* dn = (stats && den == nullptr) ? ws.take<float>((size_t)N) : den;
         const auto t0 = clk::now();
         KmResult km;
         {
@@ -935,14 +1058,17 @@ fhd_status fhd_filter_volume(fhd_ctx* ctx, const float* f, int n, const float* g
         const double ms_solve = ms_since(t1);
         const auto t2 = clk::now();
         const FilterPlan fp = make_plan(*p, n, rho, D * H, W, K);
-        filter_volume_run(c, ws, fp, D, f, guide, c32.data(), P32.data(), labels, out, den);
-        if (p->strict) strict_check(c, ws, out, N * n, den, N);
+        filter_volume_run(c, ws, fp, D, f, guide, c32.data(), P32.data(), labels, out, dn);
         double ms_filter = 0.0;
         if (info) {
             FHD_HIP(hipStreamSynchronize(c.stream));
             ms_filter = ms_since(t2);
         }
+        OutStats st;
+        if (stats) st = out_stats(c, ws, out, N * n, dn, N);
         fill_info(info, K, pr, km.E_K, km.rounds, km.splits, ms_cluster, ms_solve, ms_filter);
+        fill_stats(info, st);
+        if (p->strict) strict_verdict(st);
     });
 }
 
@@ -965,8 +1091,8 @@ fhd_status fhd_bruteforce_volume(fhd_ctx* ctx, const float* f, int n, const floa
         const FilterPlan fp = make_plan(*p, n, rho, D * H, W, 1);
         bruteforce_volume_run(c, fp, D, f, guide, out, den);
         if (p->strict) {
-            Arena ws = c.arena(4096);
-            strict_check(c, ws, out, N * n, den, N);
+            Arena ws = c.arena(stats_workspace(0) + 4096);
+            strict_verdict(out_stats(c, ws, out, N * n, den, N));
         }
     });
 }

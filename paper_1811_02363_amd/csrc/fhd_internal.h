@@ -87,8 +87,13 @@ void pinv_sigma_derivative(const float* centers, int K, int rho, double sigma_r,
 void centers_gradient(const float* centers, int K, int rho, double sigma_r, double rtol, const double* Gm,
                       const double* S1, const double* S2, double* grad);
 // Symmetric eigen-decomposition (t destroyed): eigenvalues lam (unsorted),
-// column i of v (row-major n x n) the i-th unit eigenvector.
-void sym_eigen(std::vector<double>& t, int n, std::vector<double>& lam, std::vector<double>& v);
+// column i of v (row-major n x n) the i-th unit eigenvector.  false: the QR
+// iteration did not converge (or produced non-finite eigenvalues).
+bool sym_eigen(std::vector<double>& t, int n, std::vector<double>& lam, std::vector<double>& v);
+// sym_eigen, failing with FHD_ENUMERIC ("eigen-decomposition of <what> ...")
+// when it does not converge.
+void sym_eigen_checked(std::vector<double>& t, int n, std::vector<double>& lam, std::vector<double>& v,
+                       const char* what);
 
 // ---- filter passes (filter.hip) --------------------------------------------
 struct FilterPlan {
@@ -190,6 +195,8 @@ struct Ctx {
     size_t pinned_bytes[3] = {0, 0, 0};
     hipEvent_t pinned_ev[3] = {nullptr, nullptr, nullptr};
     bool pinned_pending[3] = {false, false, false};
+    // orders a new stream (fhd_set_stream) after the work on the previous one
+    hipEvent_t switch_ev = nullptr;
 
     // stage timing (fhd_timing_enable)
     bool timing = false;

@@ -689,6 +689,7 @@ __global__ __launch_bounds__(RT) void col_generic(FA a) {
     const ColTile tile = col_tile(a, TY, (int)blockIdx.x);
     if (!tile.block_active) return;
     if (MODE == WM_INLINE) col_stage_guide(a, tile.bx0, tile.by0, TY, sp);
+    __syncthreads();  // every wave reads guide rows staged by the others
     float* tb = sp + (MODE == WM_INLINE ? a.rho * TY * TXC : 0);
     const int n = a.n, K = a.K, S = a.S;
     const int rows = TY + 2 * S;

@@ -6,6 +6,7 @@
 // v v^T / lambda.
 #include <algorithm>
 #include <cmath>
+#include <string>
 #include <vector>
 
 #include "fhd_internal.h"
@@ -35,8 +36,11 @@ void kernel_matrix(const float* centers, int K, int rho, double sigma_r, double*
 // with the Wilkinson shift, the Givens rotations applied to the band of the
 // tridiagonal matrix (plus its one-element bulge) and accumulated into the
 // orthogonal factor.  On return lam[i] are the eigenvalues and column i of v
-// (row-major n x n) the corresponding unit eigenvectors (unsorted).
-void sym_eigen(std::vector<double>& t, int n, std::vector<double>& lam, std::vector<double>& v) {
+// (row-major n x n) the corresponding unit eigenvectors (unsorted).  Returns
+// false when the off-diagonal band has not vanished after 64 n QR steps (a
+// matrix with non-finite entries never converges); the caller then rejects
+// the result.
+bool sym_eigen(std::vector<double>& t, int n, std::vector<double>& lam, std::vector<double>& v) {
     auto T = [&](int i, int j) -> double& { return t[(size_t)i * n + j]; };
     v.assign((size_t)n * n, 0.0);
     for (int i = 0; i < n; ++i) v[(size_t)i * n + i] = 1.0;
@@ -127,11 +131,21 @@ void sym_eigen(std::vector<double>& t, int n, std::vector<double>& lam, std::vec
     }
     lam.resize(n);
     for (int i = 0; i < n; ++i) lam[i] = T(i, i);
+    if (hi > 0) return false;
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(lam[i])) return false;
+    return true;
+}
+
+void sym_eigen_checked(std::vector<double>& t, int n, std::vector<double>& lam, std::vector<double>& v,
+                       const char* what) {
+    FHD_REQUIRE(sym_eigen(t, n, lam, v), FHD_ENUMERIC,
+                std::string("eigen-decomposition of ") + what + " did not converge (non-finite entries?)");
 }
 
 PinvResult pinv_symmetric(const double* A, int K, double rtol, double* P) {
     std::vector<double> a(A, A + (size_t)K * K), lam, v;
-    sym_eigen(a, K, lam, v);
+    sym_eigen_checked(a, K, lam, v, "the kernel matrix A");
     double smax = 0.0;
     for (double x : lam) smax = std::max(smax, std::fabs(x));
     const double tol = (rtol > 0.0 ? rtol : (double)K * 0x1p-52) * smax;
@@ -208,7 +222,7 @@ static void pinv_directional(const std::vector<double>& lam, const std::vector<d
 static void pinv_spectrum(const std::vector<double>& A, int K, double rtol, std::vector<double>& lam,
                           std::vector<double>& V, std::vector<char>& kept) {
     std::vector<double> t = A;
-    sym_eigen(t, K, lam, V);
+    sym_eigen_checked(t, K, lam, V, "the kernel matrix A");
     double smax = 0.0;
     for (double x : lam) smax = std::max(smax, std::fabs(x));
     const double tol = (rtol > 0.0 ? rtol : (double)K * 0x1p-52) * smax;

@@ -185,7 +185,7 @@ void nlm_guide_run(Ctx& c, Arena& ws, const float* f, int n, int H, int W, int m
             }
     }
     std::vector<double> lam, V;
-    sym_eigen(cov, D, lam, V);
+    sym_eigen_checked(cov, D, lam, V, "the patch covariance");
     std::vector<int> order(D);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return lam[a] > lam[b]; });

@@ -88,6 +88,21 @@ def test_pinv_duplicate_centers_rank():
     assert np.abs(P @ A @ P - P).max() < 1e-12
 
 
+def test_pinv_non_finite_centers_report_numeric_error():
+    """A NaN center makes A non-finite; the symmetric QR iteration then never
+    deflates, and the solve reports FHD_ENUMERIC instead of returning
+    eigenpairs that did not converge."""
+    mu = np.array([[0.1, 0.2, 0.3], [np.nan, 0.5, 0.5], [0.9, 0.1, 0.4]], np.float32)
+    with pytest.raises(fhd.FHDError) as e:
+        fhd.pinv(mu, 0.2)
+    assert e.value.status == fhd.FHD_ENUMERIC
+    # an infinite coordinate is not an error: phi of an infinite distance is
+    # 0, so that center is uncoupled (A = blocks with a unit diagonal)
+    mu[1, 0] = np.inf
+    A, P, rank, _ = fhd.pinv(mu, 0.2)
+    assert rank == 3 and np.isfinite(P.numpy()).all() and P[1, 1] == 1.0
+
+
 def test_filter_without_gpu_fails_loudly():
     import torch
     if torch.cuda.is_available():

@@ -1,5 +1,5 @@
 """The error of the kernel approximation (fhd_approx_error: eq. (10) at
-c(i) = A^+ b(i), its pixel mean E_K of Sec. II-A) through the C ABI, against
+c(i) = A^+ b(i), its pixel mean E_ls of Sec. II-A) through the C ABI, against
 the FP64 oracle fed the same FP32 centers.
 
 Tolerance.  The GPU forms every residual r = phi(x - p(i)) - sum_k c_k phi(x -
@@ -8,7 +8,7 @@ b_k(i)) with tau = 1e-6 (a few FP32 roundings and the fast exponential's
 relative error on the terms that make up c and the fit).  By the triangle
 inequality on the vector of a pixel's residuals, |sqrt(err_gpu) -
 sqrt(err_ref)| <= sqrt(|Theta_i|) times that bound; the test checks this per
-pixel (the terms come from the oracle) and E_K within the bound's mean.
+pixel (the terms come from the oracle) and E_ls within the bound's mean.
 """
 import math
 
@@ -72,7 +72,7 @@ def test_approx_error_parity(fhd, case):
         g = synth.hyperspectral(H, W, rho, 4, 0.5, 0.02, 400 + rho)
     cen = oracle.bisecting_kmeans(g, K).centers.astype(np.float32)
     S = radius if radius is not None else oracle.default_radius(ss)
-    ref, EK = oracle.approx_error(g, cen, sr, S)
+    ref, Els = oracle.approx_error(g, cen, sr, S)
     err, m = fhd.approx_error(_dev(g), cen, sigma_r=sr, sigma_s=ss if ss else 3.0, radius=radius,
                               spatial=spatial)
     torch.cuda.synchronize()
@@ -81,10 +81,10 @@ def test_approx_error_parity(fhd, case):
     dev = np.abs(np.sqrt(e) - np.sqrt(ref))
     ratio = float((dev / bnd).max())
     mbound = float(np.mean(bnd * (2.0 * np.sqrt(ref) + bnd)))
-    print(f"{name}: E_K gpu {m:.6e} oracle {EK:.6e}; max |sqrt err diff| / bound {ratio:.3f}")
+    print(f"{name}: E_ls gpu {m:.6e} oracle {Els:.6e}; max |sqrt err diff| / bound {ratio:.3f}")
     assert ratio <= 1.0
-    assert abs(m - EK) <= mbound
-    # the per-pixel values the GPU returned average to its own E_K
+    assert abs(m - Els) <= mbound
+    # the per-pixel values the GPU returned average to its own E_ls
     assert abs(e.mean() - m) <= 1e-6 * max(m, 1e-30) + 1e-12
 
 
