@@ -189,6 +189,30 @@ fhd_status fhd_filter_centers(fhd_ctx* ctx, const float* f, int n, const float* 
                               const int* labels, const fhd_params* p, float* out,
                               float* den, fhd_info* info);
 
+/* Bytes of device scratch that fhd_filter_centers_noalloc can use. */
+#define FHD_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* fhd_filter_centers for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * kernels and arguments, without `info`, with every device scratch buffer
+ * (the intermediate planes, the weight planes, the constants) taken from a
+ * static device array of FHD_NOALLOC_SCRATCH_BYTES that each GPU holds until
+ * the process ends, and the constants staged through a pinned buffer that
+ * fhd_create made.  The call allocates no device or pinned memory and creates
+ * no HIP objects (stage timing does not record it).
+ *   The caller still passes inputs and outputs.  An image whose scratch need
+ *   exceeds FHD_NOALLOC_SCRATCH_BYTES fails with FHD_ENOMEM (fhd_last_error
+ *   gives both sizes); K(n+1) planes of (H + 2 radius) x W floats dominate, so
+ *   the limit is met e.g. by 256 x 256 RGB with K = 32 and radius 15.
+ *   strict: as for fhd_filter_centers (the check's buffers also come from
+ *   the scratch; synchronises).
+ *   Every call on one GPU shares that GPU's array, which keeps the last call's
+ *   contents: calls that overlap on one GPU (contexts on different streams)
+ *   race; calls on one context are ordered by its stream. */
+fhd_status fhd_filter_centers_noalloc(fhd_ctx* ctx, const float* f, int n, const float* guide, int rho, int H,
+                                      int W, const float* centers, int K, const int* labels, const fhd_params* p,
+                                      float* out, float* den);
+
 /* The whole of Algorithm 1: fhd_cluster then fhd_filter_centers.
  *   centers_out host K x rho FP32 (the K_eff centers used), or NULL.
  *   den         device H x W normaliser, or NULL.

@@ -17,7 +17,7 @@ import torch
 
 __all__ = [
     "FHDError", "Params", "Info", "load", "lib_path", "symbols",
-    "filter", "filter_centers", "filter_backward", "FilterFunction", "filter_autograd",
+    "filter", "filter_centers", "filter_centers_noalloc", "filter_backward", "FilterFunction", "filter_autograd",
     "pack_batch", "filter_batch", "filter_batch_backward",
     "cluster", "pinv", "bruteforce", "nlm_guide", "scale_guide", "ScaleGuide", "approx_error",
     "filter_volume", "bruteforce_volume",
@@ -37,7 +37,7 @@ COEF = {"lsq": 0, "hard": 1}
 symbols = [
     "fhd_default_params", "fhd_create", "fhd_destroy", "fhd_set_stream", "fhd_last_error",
     "fhd_workspace_size", "fhd_set_workspace", "fhd_cluster", "fhd_pinv",
-    "fhd_filter_centers", "fhd_filter", "fhd_filter_backward", "fhd_filter_batch",
+    "fhd_filter_centers", "fhd_filter_centers_noalloc", "fhd_filter", "fhd_filter_backward", "fhd_filter_batch",
     "fhd_filter_batch_backward", "fhd_bruteforce", "fhd_nlm_guide", "fhd_scale_guide",
     "fhd_approx_error", "fhd_filter_volume", "fhd_bruteforce_volume",
     "fhd_timing_enable", "fhd_timing_read",
@@ -105,6 +105,7 @@ def load():
             "fhd_cluster": (I, [V, V, I, I, I, I, I, V, V, P(I), pi]),
             "fhd_pinv": (I, [V, I, I, D, D, V, V, P(I), P(D)]),
             "fhd_filter_centers": (I, [V, V, I, V, I, I, I, V, I, V, pp, V, V, pi]),
+            "fhd_filter_centers_noalloc": (I, [V, V, I, V, I, I, I, V, I, V, pp, V, V]),
             "fhd_filter": (I, [V, V, I, V, I, I, I, pp, V, V, V, pi]),
             "fhd_filter_backward": (I, [V, V, I, V, I, I, I, V, I, pp, V, V, V, V, V, P(D), P(D), V]),
             "fhd_filter_batch": (I, [V, I, V, V, V, V, I, V, I, pp, V, V, V, V, pi]),
@@ -313,6 +314,30 @@ def filter_centers(f, guide, centers, sigma_s=3.0, sigma_r=0.1, spatial="gaussia
     if info:
         res.append(inf.as_dict())
     return res[0] if len(res) == 1 else tuple(res)
+
+
+def filter_centers_noalloc(f, guide, centers, sigma_s=3.0, sigma_r=0.1, spatial="gaussian", radius=None,
+                           contract="fp32", coef="lsq", labels=None, out=None, den=None, strict=False):
+    """:func:`filter_centers` through ``fhd_filter_centers_noalloc``: the
+    library allocates nothing (its scratch is a static device array of
+    FHD_NOALLOC_SCRATCH_BYTES).  ``out`` (n, H, W) and ``den`` (H, W) may be
+    given (then nothing is allocated here either); returns (out, den or None)."""
+    n, rho, H, W, g = _shape(f, guide)
+    if not _scalar(sigma_r):
+        raise FHDError(FHD_EINVAL, "the allocation-free call takes a scalar sigma_r")
+    ctx = _ctx(f.device.index)
+    c = torch.as_tensor(centers, dtype=torch.float32).detach().cpu().contiguous()
+    K = c.shape[0]
+    if c.dim() != 2 or c.shape[1] != rho:
+        raise FHDError(FHD_EINVAL, "centers must be (K, rho)")
+    p = make_params(sigma_s, sigma_r, K, spatial, radius, contract, coef, strict=strict)
+    out = torch.empty_like(f) if out is None else out
+    lab = _dev(labels, "labels", torch.int32) if labels is not None else None
+    _check(load().fhd_filter_centers_noalloc(ctx, _dev(f, "f"), n, _dev(g, "guide"), rho, H, W,
+                                             ctypes.c_void_p(c.data_ptr()), K, lab, ctypes.byref(p),
+                                             _dev(out, "out"), _dev(den, "den") if den is not None else None),
+           ctx)
+    return out, den
 
 
 def filter_backward(f, guide, centers, out, den, grad_out, sigma_s=3.0, sigma_r=0.1,

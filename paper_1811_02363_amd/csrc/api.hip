@@ -14,6 +14,12 @@
 
 #include "fhd_internal.h"
 
+// Scratch of fhd_filter_centers_noalloc: a file-scope device array, one copy
+// per GPU, held until the process ends.  Host code never uses its name as an
+// address: each device's copy is looked up once with hipGetSymbolAddress
+// (fhd::noalloc_scratch_address) and that pointer is what kernels receive.
+static __device__ __align__(256) char scratch[FHD_NOALLOC_SCRATCH_BYTES];
+
 namespace fhd {
 
 Arena Ctx::arena(size_t need) {
@@ -135,6 +141,11 @@ void Ctx::release() {
     ev_pool.clear();
     if (switch_ev != nullptr) (void)hipEventDestroy(switch_ev);
     switch_ev = nullptr;
+    if (noalloc_ev != nullptr) (void)hipEventDestroy(noalloc_ev);
+    noalloc_ev = nullptr;
+    if (noalloc_pinned != nullptr) (void)hipHostFree(noalloc_pinned);
+    noalloc_pinned = nullptr;
+    noalloc_scratch = nullptr;
     for (int s = 0; s < 3; ++s) {
         if (pinned[s] != nullptr) (void)hipHostFree(pinned[s]);
         if (pinned_ev[s] != nullptr) (void)hipEventDestroy(pinned_ev[s]);
@@ -460,6 +471,24 @@ std::vector<long long> batch_counts(int B, const int* H, const int* W, const lon
     return cnt;
 }
 
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex noalloc_mutex;
+char* noalloc_addr[NOALLOC_MAX_DEVICES] = {};
+
+// The address of `scratch` on `device` (which must be the current device).
+char* noalloc_scratch_address(int device) {
+    FHD_REQUIRE(device >= 0 && device < NOALLOC_MAX_DEVICES, FHD_EUNSUPPORTED, "device index too large");
+    std::lock_guard<std::mutex> g(noalloc_mutex);
+    if (noalloc_addr[device] == nullptr) {
+        void* ptr = nullptr;
+        FHD_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        FHD_REQUIRE(ptr != nullptr && (reinterpret_cast<uintptr_t>(ptr) & 255) == 0, FHD_EHIP,
+                    "static scratch has no usable device address");
+        noalloc_addr[device] = static_cast<char*>(ptr);
+    }
+    return noalloc_addr[device];
+}
+
 }  // namespace
 }  // namespace fhd
 
@@ -494,6 +523,22 @@ fhd_status fhd_create(fhd_ctx** out, int device, void* hip_stream) {
     if (c == nullptr) return FHD_ENOMEM;
     c->impl.device = device;
     c->impl.stream = static_cast<hipStream_t>(hip_stream);
+    // set-up of the allocation-free entry point on this device: the static
+    // scratch's address and the pinned constants buffer
+    const fhd_status st = guarded(c, [&](Ctx& x) {
+        x.noalloc_scratch = noalloc_scratch_address(device);
+        const size_t cb = filter_consts_bytes(FHD_MAX_K, FHD_MAX_RHO);
+        if (hipHostMalloc(&x.noalloc_pinned, cb, hipHostMallocDefault) != hipSuccess) {
+            x.noalloc_pinned = nullptr;
+            (void)hipGetLastError();
+            throw Error(FHD_ENOMEM, "pinned host allocation failed");
+        }
+        FHD_HIP(hipEventCreateWithFlags(&x.noalloc_ev, hipEventDisableTiming));
+    });
+    if (st != FHD_OK) {
+        fhd_destroy(c);
+        return st;
+    }
     *out = c;
     return FHD_OK;
 }
@@ -647,6 +692,60 @@ fhd_status fhd_filter_centers(fhd_ctx* ctx, const float* f, int n, const float* 
         fill_info(info, K, pr, 0.0, 0, 0, 0.0, ms_solve, ms_filter);
         fill_stats(info, st);
         if (p->strict) strict_verdict(st);
+    });
+}
+
+fhd_status fhd_filter_centers_noalloc(fhd_ctx* ctx, const float* f, int n, const float* guide, int rho, int H,
+                                      int W, const float* centers, int K, const int* labels, const fhd_params* p,
+                                      float* out, float* den) {
+    return guarded(ctx, [&](Ctx& c) {
+        check_params(p, n, rho, H, W);
+        FHD_REQUIRE(f && guide && centers && out, FHD_EINVAL, "NULL pointer");
+        FHD_REQUIRE(K >= 1 && K <= FHD_MAX_K, FHD_EINVAL, "K must be in [1, FHD_MAX_K]");
+        FHD_REQUIRE(p->coef != FHD_COEF_HARD || labels != nullptr, FHD_EINVAL, "hard coefficients need labels");
+        FHD_REQUIRE(c.noalloc_scratch != nullptr && c.noalloc_pinned != nullptr, FHD_EINVAL,
+                    "context was not set up for the allocation-free call");
+        const long long N = (long long)H * W;
+        FHD_REQUIRE(!ranges_overlap(out, sizeof(float) * N * n, f, sizeof(float) * N * n) &&
+                        !ranges_overlap(out, sizeof(float) * N * n, guide, sizeof(float) * N * rho) &&
+                        !ranges_overlap(den, sizeof(float) * N, f, sizeof(float) * N * n) &&
+                        !ranges_overlap(den, sizeof(float) * N, guide, sizeof(float) * N * rho) &&
+                        !ranges_overlap(den, sizeof(float) * N, out, sizeof(float) * N * n),
+                    FHD_EINVAL, "outputs alias inputs");
+        const FilterPlan fp = make_plan(*p, n, rho, H, W, K);
+        const size_t cb = filter_consts_bytes(K, rho);
+        const size_t need = align_up(cb, 256) + filter_passes_workspace(fp) + (p->strict ? stats_workspace(N) : 0) + 1024;
+        FHD_REQUIRE(need <= FHD_NOALLOC_SCRATCH_BYTES, FHD_ENOMEM,
+                    "this image needs " + std::to_string(need) + " bytes of scratch; the static scratch holds " +
+                        std::to_string((size_t)FHD_NOALLOC_SCRATCH_BYTES));
+        Arena ws;
+        ws.base = c.noalloc_scratch;
+        ws.cap = FHD_NOALLOC_SCRATCH_BYTES;
+        std::vector<float> P32;
+        (void)solve(centers, K, rho, p->sigma_r, p->pinv_rtol, P32);
+        // constants through the context's fixed pinned buffer, once the
+        // previous copy out of it has ended
+        if (c.noalloc_pending) {
+            FHD_HIP(hipEventSynchronize(c.noalloc_ev));
+            c.noalloc_pending = false;
+        }
+        char* dev = ws.take<char>(cb);
+        filter_consts_fill(centers, P32.data(), K, rho, static_cast<char*>(c.noalloc_pinned));
+        FHD_HIP(hipMemcpyAsync(dev, c.noalloc_pinned, cb, hipMemcpyHostToDevice, c.stream));
+        FHD_HIP(hipEventRecord(c.noalloc_ev, c.stream));
+        c.noalloc_pending = true;
+        // stage timing would create events: off for this call
+        const bool timing = c.timing;
+        c.timing = false;
+        try {
+            float* dn = (p->strict && den == nullptr) ? ws.take<float>((size_t)N) : den;
+            filter_passes(c, ws, fp, f, guide, filter_consts_at(dev, K, rho), labels, out, dn);
+            if (p->strict) strict_verdict(out_stats(c, ws, out, N * n, dn, N));
+        } catch (...) {
+            c.timing = timing;
+            throw;
+        }
+        c.timing = timing;
     });
 }
 

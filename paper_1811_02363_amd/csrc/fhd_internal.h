@@ -197,6 +197,14 @@ struct Ctx {
     bool pinned_pending[3] = {false, false, false};
     // orders a new stream (fhd_set_stream) after the work on the previous one
     hipEvent_t switch_ev = nullptr;
+    // allocation-free entry point: the device address of this GPU's static
+    // scratch array, and a pinned buffer for the constants (made by
+    // fhd_create, sized for FHD_MAX_K and FHD_MAX_RHO) with the event that
+    // marks the end of the last copy out of it
+    char* noalloc_scratch = nullptr;
+    void* noalloc_pinned = nullptr;
+    hipEvent_t noalloc_ev = nullptr;
+    bool noalloc_pending = false;
 
     // stage timing (fhd_timing_enable)
     bool timing = false;
