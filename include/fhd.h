@@ -378,19 +378,28 @@ fhd_status fhd_scale_guide(fhd_ctx* ctx, const float* guide, int rho, long long 
 /* Stage timing with HIP events on the context's stream (for benchmarks).
  * While enabled, every call records an event pair around each stage's
  * kernels; fhd_timing_read returns, per stage, the summed elapsed
- * milliseconds and the number of recorded launches since the last read, then
- * forgets them (it synchronises the stream).  Stages: */
+ * milliseconds and the number of kernel launches between the recorded pairs
+ * since the last read, then forgets them (it synchronises the stream).
+ * Stages: */
 enum {
     FHD_STAGE_CLUSTER = 0,  /* all clustering kernels of one call (first to last) */
     FHD_STAGE_WEIGHTS = 1,  /* weights pass (materialised b and c planes) */
     FHD_STAGE_ROW = 2,      /* row pass of the convolutions */
     FHD_STAGE_COL = 3,      /* column pass with the recombination */
     FHD_STAGE_BRUTE = 4,    /* brute force */
-    FHD_NUM_STAGES = 5
+    FHD_STAGE_LLOYD = 5,    /* the 2-means assignment steps of the clustering (inside
+                               FHD_STAGE_CLUSTER): one event pair around each round's
+                               chain of kmeans_max_iter launches */
+    FHD_NUM_STAGES = 6
 };
 fhd_status fhd_timing_enable(fhd_ctx* ctx, int enable);
 /* ms and launches: host arrays of FHD_NUM_STAGES entries. */
 fhd_status fhd_timing_read(fhd_ctx* ctx, double* ms, int* launches);
+/* Algorithmic work per stage recorded while timing is enabled, since the
+ * last call (host array of FHD_NUM_STAGES; then reset): for FHD_STAGE_LLOYD
+ * the guide points streamed by the assignment steps (a job's points once per
+ * step it ran before stopping), 0 for the other stages. */
+fhd_status fhd_timing_units(fhd_ctx* ctx, long long* units);
 
 #ifdef __cplusplus
 }

@@ -74,8 +74,23 @@ def _load():
         for fn in ("oracle_bruteforce", "oracle_bruteforce_at", "oracle_conv2d",
                    "oracle_conv_separable", "oracle_cluster_images_at"):
             getattr(lib, fn).restype = None
+        lib.oracle_set_threads.argtypes = [c_int]
+        lib.oracle_set_threads.restype = None
+        lib.oracle_get_threads.argtypes = []
+        lib.oracle_get_threads.restype = c_int
         _lib = lib
     return _lib
+
+
+def set_threads(t):
+    """Threads of the C window sums (OpenMP); returns the previous count."""
+    prev = _load().oracle_get_threads()
+    _load().oracle_set_threads(int(t))
+    return prev
+
+
+def threads():
+    return _load().oracle_get_threads()
 
 
 def _dp(a):

@@ -14,8 +14,14 @@
  * zero-extended).  Kernels are unnormalised (peak value 1).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Threads of the OpenMP loops below (the CPU baseline times one thread as
+ * well as all of them). */
+void oracle_set_threads(int t) { omp_set_num_threads(t > 0 ? t : 1); }
+int oracle_get_threads(void) { return omp_get_max_threads(); }
 
 /* Spatial kernel, Sec. III: Gaussian exp(-|j|^2 / 2 sigma_s^2) for the
  * bilateral filter, box (weight 1) for nonlocal means. */

@@ -20,7 +20,7 @@ __all__ = [
     "filter", "filter_centers", "filter_centers_noalloc", "filter_backward", "FilterFunction", "filter_autograd",
     "pack_batch", "filter_batch", "filter_batch_backward",
     "cluster", "pinv", "bruteforce", "nlm_guide", "scale_guide", "ScaleGuide", "approx_error",
-    "filter_volume", "bruteforce_volume",
+    "filter_volume", "bruteforce_volume", "timing_enable", "timing_read", "timing_units",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -40,9 +40,9 @@ symbols = [
     "fhd_filter_centers", "fhd_filter_centers_noalloc", "fhd_filter", "fhd_filter_backward", "fhd_filter_batch",
     "fhd_filter_batch_backward", "fhd_bruteforce", "fhd_nlm_guide", "fhd_scale_guide",
     "fhd_approx_error", "fhd_filter_volume", "fhd_bruteforce_volume",
-    "fhd_timing_enable", "fhd_timing_read",
+    "fhd_timing_enable", "fhd_timing_read", "fhd_timing_units",
 ]
-STAGES = ("cluster", "weights", "row", "col", "brute")
+STAGES = ("cluster", "weights", "row", "col", "brute", "lloyd")
 
 
 class FHDError(RuntimeError):
@@ -119,6 +119,7 @@ def load():
             "fhd_bruteforce_volume": (I, [V, V, I, V, I, I, I, I, pp, V, V]),
             "fhd_timing_enable": (I, [V, I]),
             "fhd_timing_read": (I, [V, P(D), P(I)]),
+            "fhd_timing_units": (I, [V, P(ctypes.c_longlong)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -653,3 +654,12 @@ def timing_read(device=0):
     n = (ctypes.c_int * len(STAGES))()
     _check(load().fhd_timing_read(ctx, ms, n), ctx)
     return {s: (ms[i], n[i]) for i, s in enumerate(STAGES)}
+
+
+def timing_units(device=0):
+    """{stage: algorithmic units} recorded since the last call (the points
+    streamed by the clustering's assignment steps for "lloyd")."""
+    ctx = _ctx(device)
+    u = (ctypes.c_longlong * len(STAGES))()
+    _check(load().fhd_timing_units(ctx, u), ctx)
+    return {s: int(u[i]) for i, s in enumerate(STAGES)}

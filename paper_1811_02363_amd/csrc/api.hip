@@ -94,11 +94,11 @@ hipEvent_t Ctx::stage_begin() {
     return e;
 }
 
-void Ctx::stage_end(int stage, hipEvent_t begin) {
+void Ctx::stage_end(int stage, hipEvent_t begin, int launches) {
     if (!timing || begin == nullptr) return;
     hipEvent_t e = take_event();
     FHD_HIP(hipEventRecord(e, stream));
-    ev_rec[stage].emplace_back(begin, e);
+    ev_rec[stage].push_back(EvPair{begin, e, launches});
 }
 
 void Ctx::fork(int n) {
@@ -134,8 +134,8 @@ void Ctx::release() {
     own_ws = nullptr;
     for (auto& v : ev_rec)
         for (auto& pr : v) {
-            ev_pool.push_back(pr.first);
-            ev_pool.push_back(pr.second);
+            ev_pool.push_back(pr.begin);
+            ev_pool.push_back(pr.end);
         }
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     ev_pool.clear();
@@ -1254,21 +1254,33 @@ fhd_status fhd_timing_enable(fhd_ctx* ctx, int enable) {
     return guarded(ctx, [&](Ctx& c) { c.timing = enable != 0; });
 }
 
+fhd_status fhd_timing_units(fhd_ctx* ctx, long long* units) {
+    return guarded(ctx, [&](Ctx& c) {
+        FHD_REQUIRE(units != nullptr, FHD_EINVAL, "NULL pointer");
+        for (int s = 0; s < FHD_NUM_STAGES; ++s) {
+            units[s] = c.units[s];
+            c.units[s] = 0;
+        }
+    });
+}
+
 fhd_status fhd_timing_read(fhd_ctx* ctx, double* ms, int* launches) {
     return guarded(ctx, [&](Ctx& c) {
         FHD_REQUIRE(ms != nullptr && launches != nullptr, FHD_EINVAL, "NULL pointer");
         FHD_HIP(hipStreamSynchronize(c.stream));
         for (int s = 0; s < FHD_NUM_STAGES; ++s) {
             double tot = 0.0;
+            int nl = 0;
             for (auto& pr : c.ev_rec[s]) {
                 float t = 0.0f;
-                FHD_HIP(hipEventElapsedTime(&t, pr.first, pr.second));
+                FHD_HIP(hipEventElapsedTime(&t, pr.begin, pr.end));
                 tot += t;
-                c.ev_pool.push_back(pr.first);
-                c.ev_pool.push_back(pr.second);
+                nl += pr.launches;
+                c.ev_pool.push_back(pr.begin);
+                c.ev_pool.push_back(pr.end);
             }
             ms[s] = tot;
-            launches[s] = (int)c.ev_rec[s].size();
+            launches[s] = nl;
             c.ev_rec[s].clear();
         }
     });

@@ -209,11 +209,16 @@ struct Ctx {
     // stage timing (fhd_timing_enable)
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_rec[FHD_NUM_STAGES];
+    struct EvPair {
+        hipEvent_t begin, end;
+        int launches;  // kernel launches between the two events
+    };
+    std::vector<EvPair> ev_rec[FHD_NUM_STAGES];
+    long long units[FHD_NUM_STAGES] = {};  // algorithmic work per stage (fhd_timing_units)
     hipEvent_t take_event();
     // Records the start of `stage` now; returns the event (null when off).
     hipEvent_t stage_begin();
-    void stage_end(int stage, hipEvent_t begin);
+    void stage_end(int stage, hipEvent_t begin, int launches = 1);
 
     // auxiliary streams (default priority) for the independent per-image
     // work of a batch: fork(n) makes aux[0..n) wait for what `stream` has

@@ -1064,14 +1064,178 @@ __global__ __launch_bounds__(RT) void adj_final(FA a, const float* __restrict__ 
                    parts != nullptr ? parts + blockIdx.x : nullptr, (int)blockIdx.x);
 }
 
-// one launch for every image (at most 32 clusters: a single cluster range);
-// the block partials of all images follow one another in `part`
-__global__ __launch_bounds__(RT) void adj_final_batch(const FA* __restrict__ fas, const int* __restrict__ pre, int B,
-                                                      float sig3inv, double* __restrict__ part) {
+// The same end of the adjoint on the matrix cores, for short guides (rho <= 8,
+// b recomputed inline) and K <= 32.  A wave takes 32 pixels at a time and
+// forms the two K x K products of all of them as 16 steps each of the
+// 32 x 32 x 2 FP32 matrix product:
+//   C1[l][j] = sum_m A^+[l][m] gamma_m(j),   C2[l][j] = sum_m M[l][m] gamma_m(j)
+// (lane t supplies A^+[t % 32][2s + t / 32] and M[...] from registers loaded
+// once per block, and gamma_{2s + t / 32} of pixel t % 32; the matrices are
+// zero-padded to 32).  Lane t then holds both products for pixel t % 32 and
+// the 16 clusters l = 8 (r / 4) + 4 (t / 32) + r % 4, r < 16, and finishes
+// those (pixel, cluster) pairs in place, loading beta_l (consecutive lanes:
+// consecutive pixels of one plane):
+//   dL/db_l = beta_l + C1[l],  w_l = dL/db_l b_l,
+//   share of dL/dsigma_r = sum_l w_l |p - mu_l|^2 / sigma_r^3 + b_l C2[l]
+// (M symmetric: gamma . (M b) = b . (M gamma)), and dL/dp from sum_l w_l and
+// sum_l w_l mu_l, the two lanes of a pixel added by a swap across the wave
+// halves.  FP64 shares: per lane in pixel-group order, then the fixed shuffle
+// tree and wave order.
+constexpr int AF_GROUPS = 8;              // 32-pixel groups per wave
+constexpr int AF_PIX = RT / 2 * AF_GROUPS; // pixels per block
+
+// 32-bit byte offsets from a uniform base (the planes of one image span less
+// than 4 GiB where this is used): one register per address, and the load
+// takes the scalar base directly
+__device__ __forceinline__ float ld_off(const float* base, unsigned byte_off) {
+    return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
+__device__ __forceinline__ void adj_final_mfma_body(const FA& a, const float* __restrict__ Md, float sig3inv,
+                                                    float* __restrict__ gradp, double* part_slot,
+                                                    double* parts_slot, int blk) {
+    __shared__ float smu[KMAX_INLINE * RHO_INLINE];
+    __shared__ double red[RT / 64], reds[RT / 64];
+    const int K = a.K, rho = a.rho;
+    for (int t = threadIdx.x; t < KMAX_INLINE * RHO_INLINE; t += RT) {
+        const int l = t / RHO_INLINE, r = t - l * RHO_INLINE;
+        smu[t] = (l < K && r < rho) ? a.mu[l * rho + r] : 0.0f;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int jl = lane & 31, kh = lane >> 5;
+    // A operands: A^+[jl][2s + kh] and M[jl][2s + kh]
+    float Pa[16], Ma[16];
+#pragma unroll
+    for (int s2 = 0; s2 < 16; ++s2) {
+        const int m = 2 * s2 + kh;
+        const bool in = jl < K && m < K;
+        Pa[s2] = in ? a.P[jl * K + m] : 0.0f;
+        Ma[s2] = in ? Md[jl * K + m] : 0.0f;
+    }
+    __syncthreads();
+    const float m2s = -2.0f * a.inv2s2;
+    const unsigned np4 = (unsigned)a.Np * 4u, n4 = (unsigned)a.N * 4u;
+    double sig = 0.0, sigs = 0.0;
+#pragma unroll 1
+    for (int grp = 0; grp < AF_GROUPS; ++grp) {
+        // an offset the compiler cannot see through keeps the centers as LDS
+        // reads inside the loop (hoisted out of it they take 128 registers)
+        int lo = 0;
+        asm volatile("" : "+v"(lo));
+        const float* smq = smu + lo;
+        const long long i = ((long long)blk * (RT / 64) + wave) * (32LL * AF_GROUPS) + grp * 32 + jl;
+        const bool valid = i < a.N;
+        const int ii = valid ? (int)i : 0;  // loads stay in bounds; invalid lanes are zeroed after
+        const int y = ii / a.W, x = ii - y * a.W;
+        const unsigned po4 = (unsigned)(y * a.Wp + x) * 4u, pi4 = (unsigned)ii * 4u;
+        // running offsets, clamped to the last plane (the value is zeroed there)
+        const unsigned last = po4 + (unsigned)(K - 1) * np4;
+        float gv[16];
+        unsigned og = po4 + (unsigned)kh * np4;
+#pragma unroll
+        for (int s2 = 0; s2 < 16; ++s2) {
+            const int m = 2 * s2 + kh;
+            const float v = ld_off(a.gamma, min(og, last));
+            gv[s2] = (valid && m < K) ? v : 0.0f;
+            og += 2u * np4;
+        }
+        float pr[RHO_INLINE];
+#pragma unroll
+        for (int r = 0; r < RHO_INLINE; ++r) {
+            const float v = ld_off(a.p, pi4 + (unsigned)min(r, rho - 1) * n4);
+            pr[r] = (valid && r < rho) ? v : 0.0f;
+        }
+        f32x16 c1, c2;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) c1[r] = c2[r] = 0.0f;
+#pragma unroll
+        for (int s2 = 0; s2 < 16; ++s2) {
+            c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(Pa[s2], gv[s2], c1, 0, 0, 0);
+            c2 = __builtin_amdgcn_mfma_f32_32x32x2f32(Ma[s2], gv[s2], c2, 0, 0, 0);
+        }
+        float bt[16], bs[16];
+        unsigned ob = po4 + 4u * (unsigned)kh * np4;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int l = 8 * (r >> 2) + 4 * kh + (r & 3);
+            const unsigned off = min(ob, last);
+            ob += ((r & 3) == 3 ? 5u : 1u) * np4;  // l runs 4 kh + 0..3, then 8 on
+            const float v = ld_off(a.beta, off);
+            bt[r] = (valid && l < K) ? v : 0.0f;
+            bs[r] = 0.0f;
+            if (a.betas != nullptr) {
+                const float vs = ld_off(a.betas, off);
+                bs[r] = (valid && l < K) ? vs : 0.0f;
+            }
+        }
+        float wsum = 0.0f, sw[RHO_INLINE];
+#pragma unroll
+        for (int r = 0; r < RHO_INLINE; ++r) sw[r] = 0.0f;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int l = 8 * (r >> 2) + 4 * kh + (r & 3);
+            float mu8[RHO_INLINE];
+#pragma unroll
+            for (int q = 0; q < RHO_INLINE; ++q) mu8[q] = smq[l * RHO_INLINE + q];
+            float d2 = 0.0f;
+#pragma unroll
+            for (int q = 0; q < RHO_INLINE; ++q) {  // padded entries: (0 - 0)^2
+                const float d = pr[q] - mu8[q];
+                d2 = fmaf(d, d, d2);
+            }
+            // b_l exactly as the weights pass and the inline row pass form it
+            const float bl = (valid && l < K) ? __expf(-d2 * a.inv2s2) : 0.0f;
+            const float w = (bt[r] + c1[r]) * bl;
+            sig += (double)w * d2 * sig3inv + (double)bl * c2[r];
+            sigs += (double)bl * bs[r];
+            wsum += w;
+#pragma unroll
+            for (int q = 0; q < RHO_INLINE; ++q) sw[q] = fmaf(w, mu8[q], sw[q]);
+        }
+        // the pixel's other 16 clusters sit in the lane 32 apart
+        wsum += __shfl_xor(wsum, 32, 64);
+#pragma unroll
+        for (int q = 0; q < RHO_INLINE; ++q) sw[q] += __shfl_xor(sw[q], 32, 64);
+        if (valid && kh == 0 && gradp != nullptr) {
+#pragma unroll
+            for (int q = 0; q < RHO_INLINE; ++q)
+                if (q < rho) gradp[(long long)q * a.N + ii] = m2s * (pr[q] * wsum - sw[q]);
+        }
+    }
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        sig += __shfl_xor(sig, o, 64);
+        sigs += __shfl_xor(sigs, o, 64);
+    }
+    if (lane == 0) {
+        red[wave] = sig;
+        reds[wave] = sigs;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0, ts = 0.0;
+        for (int q = 0; q < RT / 64; ++q) {
+            t += red[q];
+            ts += reds[q];
+        }
+        *part_slot = t;
+        if (parts_slot != nullptr) *parts_slot = ts;
+    }
+}
+
+__global__ __launch_bounds__(RT) void adj_final_mfma(FA a, const float* __restrict__ Md, float sig3inv,
+                                                     float* __restrict__ gradp, double* __restrict__ part,
+                                                     double* __restrict__ parts) {
+    adj_final_mfma_body(a, Md, sig3inv, gradp, part + blockIdx.x, parts != nullptr ? parts + blockIdx.x : nullptr,
+                        (int)blockIdx.x);
+}
+
+__global__ __launch_bounds__(RT) void adj_final_mfma_batch(const FA* __restrict__ fas, const int* __restrict__ pre,
+                                                           int B, float sig3inv, double* __restrict__ part) {
     int b;
     const int t = batch_block(pre, B, b);
     const FA& a = fas[b];
-    adj_final_body(a, a.Md, sig3inv, 0, 0, a.gradp, part + blockIdx.x, nullptr, t);
+    adj_final_mfma_body(a, a.Md, sig3inv, a.gradp, part + blockIdx.x, nullptr, t);
 }
 
 __global__ __launch_bounds__(RT) void sum_blocks(const double* __restrict__ part, int nb, double* __restrict__ out) {
@@ -2331,6 +2495,12 @@ size_t adjoint_workspace(const FilterPlan& fp, bool with_s, bool with_mu) {
            align_up(sizeof(double) * (2 + (size_t)centers_sum_entries(fp.K, fp.rho)), 256) + 512;
 }
 
+// adj_final_mfma addresses a K-plane set and the guide with 32-bit byte offsets
+bool adj_final_mfma_fits(const FilterPlan& fp) {
+    const long long Np = (long long)fp.H * fp.Wp;
+    return (long long)fp.K * Np * 4 < (1LL << 32) && fp.N * fp.rho * 4 < (1LL << 32);
+}
+
 void adjoint_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const float* guide,
                  const float* centers_host, const float* Pfp32_host, const float* M_host, const float* out,
                  const float* den, const float* gout, float* gradf, float* gradp, double* gsig, double* gsigs,
@@ -2481,12 +2651,20 @@ void adjoint_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, con
     FHD_HIP(hipGetLastError());
     const float sig3inv =
         std::isinf(fp.sigma_r) ? 0.0f : (float)(1.0 / ((double)fp.sigma_r * fp.sigma_r * fp.sigma_r));
-    const int halves = (fp.K + KF - 1) / KF;
-    for (int h = 0; h < halves; ++h)
-        hipLaunchKernelGGL(adj_final, dim3(nb), dim3(RT), 0, st, a, Md, sig3inv, h * KF, h, gradp,
-                           part + (size_t)h * nb, with_s ? parts + (size_t)h * nb : nullptr);
-    hipLaunchKernelGGL(sum_blocks, dim3(1), dim3(RT), 0, st, part, halves * nb, sig_dev);
-    if (with_s) hipLaunchKernelGGL(sum_blocks, dim3(1), dim3(RT), 0, st, parts, halves * nb, sigs_dev);
+    if (inl && adj_final_mfma_fits(fp)) {  // rho <= 8, K <= 32: the matrix-core form
+        const int nb32 = (int)((fp.N + AF_PIX - 1) / AF_PIX);
+        hipLaunchKernelGGL(adj_final_mfma, dim3(nb32), dim3(RT), 0, st, a, Md, sig3inv, gradp, part,
+                           with_s ? parts : nullptr);
+        hipLaunchKernelGGL(sum_blocks, dim3(1), dim3(RT), 0, st, part, nb32, sig_dev);
+        if (with_s) hipLaunchKernelGGL(sum_blocks, dim3(1), dim3(RT), 0, st, parts, nb32, sigs_dev);
+    } else {
+        const int halves = (fp.K + KF - 1) / KF;
+        for (int h = 0; h < halves; ++h)
+            hipLaunchKernelGGL(adj_final, dim3(nb), dim3(RT), 0, st, a, Md, sig3inv, h * KF, h, gradp,
+                               part + (size_t)h * nb, with_s ? parts + (size_t)h * nb : nullptr);
+        hipLaunchKernelGGL(sum_blocks, dim3(1), dim3(RT), 0, st, part, halves * nb, sig_dev);
+        if (with_s) hipLaunchKernelGGL(sum_blocks, dim3(1), dim3(RT), 0, st, parts, halves * nb, sigs_dev);
+    }
     if (mu_dev != nullptr) {
         // the pixel sums of the centers gradient (beta and gamma are complete)
         FHD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(adj_centers),
@@ -2499,7 +2677,7 @@ void adjoint_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, con
 
 bool adjoint_batch_supported(const FilterPlan& fp) {
     return fp.S >= 1 && fp.S <= MAXS_T && fp.rho <= RHO_INLINE && fp.K <= KMAX_INLINE &&
-           fp.coef == FHD_COEF_LSQ && fp.H + 2 * fp.S <= 65535;
+           fp.coef == FHD_COEF_LSQ && fp.H + 2 * fp.S <= 65535 && adj_final_mfma_fits(fp);
 }
 
 size_t adjoint_batch_workspace(int B, const FilterPlan* plans) {
@@ -2586,7 +2764,7 @@ void adjoint_passes_batch(Ctx& c, Arena& ws, int B, const FilterPlan* plans, con
         pre_w[b + 1] = pre_w[b] + ((fp.W + npx - 1) / npx) * fp.H;
         pre_r[b + 1] = pre_r[b] + ((fp.W + tx - 1) / tx) * (fp.H + 2 * fp.S);
         pre_c[b + 1] = pre_c[b] + a.xcd_groups * 8;
-        pre_f[b + 1] = pre_f[b] + (int)((fp.N + RT - 1) / RT);
+        pre_f[b + 1] = pre_f[b] + (int)((fp.N + AF_PIX - 1) / AF_PIX);
     }
     double* part = ws.take<double>((size_t)pre_f[B] + 1);
     FA* dfa = ws.take<FA>(3 * (size_t)B);
@@ -2633,7 +2811,7 @@ void adjoint_passes_batch(Ctx& c, Arena& ws, int B, const FilterPlan* plans, con
     const float sig3inv = std::isinf(plans[0].sigma_r)
                               ? 0.0f
                               : (float)(1.0 / ((double)plans[0].sigma_r * plans[0].sigma_r * plans[0].sigma_r));
-    hipLaunchKernelGGL(adj_final_batch, dim3(pre_f[B]), dim3(RT), 0, st, fa2, df, B, sig3inv, part);
+    hipLaunchKernelGGL(adj_final_mfma_batch, dim3(pre_f[B]), dim3(RT), 0, st, fa2, df, B, sig3inv, part);
     hipLaunchKernelGGL(sum_blocks, dim3(1), dim3(RT), 0, st, part, pre_f[B], sig_dev);
     FHD_HIP(hipGetLastError());
 }

@@ -52,7 +52,7 @@ constexpr int unr_lloyd() { return D <= 4 ? 16 : 8; }
 // per-job integer state
 enum { JI_START, JI_COUNT, JI_BUF, JI_FIRST, JI_NBLK, JI_NA, JI_W = 8 };
 // per-job FP64 results
-enum { JD_SSEA, JD_SSEB, JD_NA, JD_NB, JD_SPLA, JD_SPLB, JD_W = 6 };
+enum { JD_SSEA, JD_SSEB, JD_NA, JD_NB, JD_SPLA, JD_SPLB, JD_STEPS, JD_W = 7 };
 
 struct KmArgs {
     float* pts[2];
@@ -456,6 +456,7 @@ __device__ __forceinline__ int lloyd_act(const double* res, const double* c, int
 // centroids (ca, cb).  Threads < rho.
 __device__ __forceinline__ void lloyd_final(const KmArgs& a, int job, int act, int st, const double* res) {
     const int rho = a.rho, t = threadIdx.x;
+    if (t == 0) a.jd[job * JD_W + JD_STEPS] = st + 1;  // assignment steps that streamed the job's points
     if (t >= rho) return;
     const double* c = a.cst + ((long long)(st % 3) * a.mj + job) * 2 * rho;             // c_st
     const double* l = a.cst + ((long long)((st + 2) % 3) * a.mj + job) * 2 * rho;       // c_{st-1}
@@ -1192,7 +1193,9 @@ void kmeans_run_batch(Ctx& c, Arena& ws, const float* guide, int rho, int images
             hipLaunchKernelGGL(fin_far, gj, dim3(KT), 0, st, a, 0);
             launch_pass(rho, P_FAR, g, st, a, 1);
             hipLaunchKernelGGL(fin_far, gj, dim3(KT), 0, st, a, 1);
+            hipEvent_t tl = c.stage_begin();
             for (int it = 0; it < max_iter; ++it) launch_pass(rho, P_LLOYD, g, st, a, it);
+            c.stage_end(FHD_STAGE_LLOYD, tl, max_iter);
             hipLaunchKernelGGL(fin_lloyd, gj, dim3(FT), 0, st, a, max_iter);
             launch_pass(rho, P_SPLIT, g, st, a);
             hipLaunchKernelGGL(fin_split, gj, dim3(FT), 0, st, a);
@@ -1213,6 +1216,7 @@ void kmeans_run_batch(Ctx& c, Arena& ws, const float* guide, int rho, int images
                 L.nB = (int)jd[JD_NB];
                 L.splA = jd[JD_SPLA] != 0.0;
                 L.splB = jd[JD_SPLB] != 0.0;
+                if (c.timing) c.units[FHD_STAGE_LLOYD] += (long long)jd[JD_STEPS] * L.count;
                 FHD_REQUIRE(L.nA > 0 && L.nB > 0 && L.nA + L.nB == L.count, FHD_ENUMERIC,
                             "internal: degenerate 2-means split");
                 ++splits[L.img];
