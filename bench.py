@@ -289,15 +289,20 @@ def leg_fwd_bwd(torch, fhd, np, x, f, cfg, steps):
     K, S, ss, sr = cfg["K"], cfg["S"], cfg["sigma_s"], cfg["sigma_r"]
     N = cfg["H"] * cfg["W"]
     G = torch.from_numpy(np.random.default_rng(7).standard_normal(f.shape).astype(np.float32)).cuda()
+    # the forward call keeps its row-filtered planes and coefficients for the adjoint
+    sv = fhd.saved_buffer(cfg["n"], cfg["n"], cfg["H"], cfg["W"], K, sigma_s=ss, sigma_r=sr, radius=S)
 
     def fb():
-        o, d, c = fhd.filter(x, sigma_s=ss, sigma_r=sr, K=K, radius=S, return_den=True, return_centers=True)
-        fhd.filter_backward(x, x, c, o, d, G, sigma_s=ss, sigma_r=sr, radius=S)
+        o, d, c = fhd.filter(x, sigma_s=ss, sigma_r=sr, K=K, radius=S, return_den=True, return_centers=True,
+                             saved=sv)
+        fhd.filter_backward(x, x, c, o, d, G, sigma_s=ss, sigma_r=sr, radius=S, saved=sv)
 
     fb()
     ms = timed(torch, fb, max(3, steps // 4))
     return {"mpix_s": round(N / ms / 1e3, 2), "ms_per_step": round(ms, 3),
-            "note": "one forward call plus one adjoint call (dL/df, dL/dguide, dL/dsigma_r), same workload"}
+            "saved_bytes": sv.numel(),
+            "note": "one forward call (keeping its intermediates for the adjoint) plus one adjoint call "
+                    "(dL/df, dL/dguide, dL/dsigma_r), same workload"}
 
 
 def equal_psnr(sweep, form, ref_form, K_ref):
@@ -413,13 +418,15 @@ def leg_batch(torch, np, fhd, oracle, synth):
     N = sum(h * w for h, w in sizes)
     kw = dict(sigma_s=c4["sigma_s"], sigma_r=c4["sigma_r"], radius=S)
     G = torch.from_numpy(np.random.default_rng(11).standard_normal(flat.numel()).astype(np.float32)).cuda()
+    sv = fhd.saved_buffer(n, n, [h for h, _ in sizes], [w for _, w in sizes], K, **kw)
 
     def fwd():
         return fhd.filter_batch(flat, sizes, n, K=K, return_den=True, **kw)
 
     def fb():
-        out, den, cen, keff = fwd()
-        fhd.filter_batch_backward(flat, sizes, n, cen, keff, out, den, G, **kw)
+        # the forward call keeps its intermediates for the adjoint
+        out, den, cen, keff = fhd.filter_batch(flat, sizes, n, K=K, return_den=True, saved=sv, **kw)
+        fhd.filter_batch_backward(flat, sizes, n, cen, keff, out, den, G, saved=sv, **kw)
 
     fb()
     ms_f = timed(torch, fwd, 5)
@@ -439,7 +446,7 @@ def leg_batch(torch, np, fhd, oracle, synth):
                         "sigma_r 0.1, K 32",
             "pixels": N, "fwd_mpix_s": round(N / ms_f / 1e3, 2), "fwd_ms": round(ms_f, 3),
             "fwd_bwd_mpix_s": round(N / ms_fb / 1e3, 2), "fwd_bwd_ms": round(ms_fb, 3),
-            "fwd_bwd_model_bytes_per_px": bf + bb, "fwd_bwd_hbm_gbs": round(gbs, 1),
+            "fwd_bwd_model_bytes_per_px": bf + bb, "fwd_bwd_hbm_gbs": round(gbs, 1), "saved_bytes": sv.numel(),
             "fwd_bwd_hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
             "max_abs_vs_oracle_sampled": worst}
 

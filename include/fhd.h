@@ -144,6 +144,29 @@ fhd_status fhd_workspace_size(const fhd_params* p, int n, int rho, int H, int W,
  * library's own.  Calls whose need exceeds it fail with FHD_ENOMEM. */
 fhd_status fhd_set_workspace(fhd_ctx* ctx, void* dev, size_t bytes);
 
+/* Intermediates a forward call can keep for its adjoint (the `saved`
+ * arguments below).  The adjoint of eqs. (13)-(16) needs, per cluster l,
+ * Q_l = w * (c_l [f, 1]) and the coefficients c_l(i) = (A^+ b(i))_l; the
+ * forward call forms both (the row-filtered planes of its first pass and the
+ * coefficients it computes for them), so a forward call given a saved buffer
+ * writes them there, and fhd_filter_backward / fhd_filter_batch_backward
+ * given the same buffer skip recomputing them (one row pass and the weights
+ * pass).  fhd_saved_size gives the bytes for one image at p->K clusters
+ * (K(n+1) planes of (H + 2 radius) x W floats plus K planes of H x W, twice K
+ * for guides of more than 8 dimensions or more than 32 clusters);
+ * fhd_saved_size_batch for a ragged batch.  Only for what the adjoint
+ * covers: FP32 contraction, least-squares coefficients, the Gaussian or box
+ * window with radius 1..32, K <= 64 (FHD_EUNSUPPORTED otherwise).
+ * The context records which forward call wrote a buffer (the image and guide
+ * pointers, shape, window, sigmas and centers); an adjoint call whose
+ * arguments differ, or a buffer another call has since overwritten, is
+ * rejected with FHD_EINVAL.  The contents of the image and guide are not
+ * checked: changing them between the two calls gives the adjoint of the
+ * forward call's inputs. */
+fhd_status fhd_saved_size(const fhd_params* p, int n, int rho, int H, int W, size_t* bytes);
+fhd_status fhd_saved_size_batch(const fhd_params* p, int B, const int* H, const int* W, int n, int rho,
+                                size_t* bytes);
+
 /* Step 1 of Algorithm 1: bisecting K-means of the range space eq. (8)
  * (Sec. II-C), on the GPU with FP64 centroid and distance arithmetic.
  * The leaf with the largest SSE (sum of squared distances to its centroid;
@@ -182,12 +205,14 @@ fhd_status fhd_pinv(const float* centers, int K, int rho, double sigma_r, double
  *   den     device H x W: the normaliser r_hat of eq. (16), or NULL.
  *   labels  device H x W cluster index per pixel; required for FHD_COEF_HARD,
  *           else ignored (may be NULL).
+ *   saved   device buffer of saved_bytes (fhd_saved_size) for the adjoint's
+ *           intermediates, or NULL (saved_bytes ignored).
  * Returns with the filter in flight unless `info` or strict mode asks for
  * host results. */
 fhd_status fhd_filter_centers(fhd_ctx* ctx, const float* f, int n, const float* guide,
                               int rho, int H, int W, const float* centers, int K,
                               const int* labels, const fhd_params* p, float* out,
-                              float* den, fhd_info* info);
+                              float* den, fhd_info* info, void* saved, size_t saved_bytes);
 
 /* Bytes of device scratch that fhd_filter_centers_noalloc can use. */
 #define FHD_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
@@ -216,12 +241,14 @@ fhd_status fhd_filter_centers_noalloc(fhd_ctx* ctx, const float* f, int n, const
 /* The whole of Algorithm 1: fhd_cluster then fhd_filter_centers.
  *   centers_out host K x rho FP32 (the K_eff centers used), or NULL.
  *   den         device H x W normaliser, or NULL.
+ *   saved       device buffer for the adjoint's intermediates (sized by
+ *               fhd_saved_size at p->K), or NULL.
  * Synchronises once per clustering round (the greedy split selection runs on
  * the host); returns with the filter passes in flight unless `info` or strict
  * mode asks for host results. */
 fhd_status fhd_filter(fhd_ctx* ctx, const float* f, int n, const float* guide, int rho,
                       int H, int W, const fhd_params* p, float* out, float* centers_out,
-                      float* den, fhd_info* info);
+                      float* den, fhd_info* info, void* saved, size_t saved_bytes);
 
 /* Ragged batch: Algorithm 1 on B independent images of one shape family
  * (n channels, rho guide dimensions, sizes H[b] x W[b]), one clustering tree
@@ -236,11 +263,14 @@ fhd_status fhd_filter(fhd_ctx* ctx, const float* f, int n, const float* guide, i
  *           element px_offset[b], or NULL.
  *   centers_out host B x K x rho (rows K_eff[b]..K-1 of image b untouched) or
  *           NULL;  K_eff host B or NULL;  info host B or NULL.
+ *   saved   device buffer for the adjoint's intermediates
+ *           (fhd_saved_size_batch), or NULL.
  * Synchronises once per clustering round. */
 fhd_status fhd_filter_batch(fhd_ctx* ctx, int B, const int* H, const int* W,
                             const long long* px_offset, const float* f, int n,
                             const float* guide, int rho, const fhd_params* p, float* out,
-                            float* centers_out, int* K_eff, float* den, fhd_info* info);
+                            float* centers_out, int* K_eff, float* den, fhd_info* info, void* saved,
+                            size_t saved_bytes);
 
 /* Adjoint of fhd_filter_centers for least-squares coefficients (the paper
  * does not differentiate its filter; this is the exact gradient of the
@@ -271,13 +301,16 @@ fhd_status fhd_filter_batch(fhd_ctx* ctx, int B, const int* H, const int* W,
  *            centers held fixed.  Synchronises when non-NULL; one more pass
  *            over beta and gamma; FHD_EUNSUPPORTED when its K x K + K(rho+1)
  *            sums exceed the LDS of a block (K = 64 with rho near 64).
+ *   saved    the buffer a forward call with these arguments filled (see
+ *            fhd_saved_size), or NULL to recompute its contents.
  * Gradient outputs must not alias inputs.  Workspace: five K-plane sets plus
  * the intermediate planes of the forward call. */
 fhd_status fhd_filter_backward(fhd_ctx* ctx, const float* f, int n, const float* guide, int rho,
                                int H, int W, const float* centers, int K, const fhd_params* p,
                                const float* out, const float* den, const float* grad_out,
                                float* grad_f, float* grad_guide, double* grad_sigma_r,
-                               double* grad_sigma_s, double* grad_centers);
+                               double* grad_sigma_s, double* grad_centers, const void* saved,
+                               size_t saved_bytes);
 
 /* Adjoint of fhd_filter_batch (least-squares coefficients), laid out like
  * it: centers host B x K x rho and K_eff host B as returned by the forward
@@ -285,13 +318,15 @@ fhd_status fhd_filter_backward(fhd_ctx* ctx, const float* f, int n, const float*
  * device in the layouts of f and guide (gradient outputs may be NULL);
  * grad_sigma_r and grad_sigma_s host, the sums over the images, or NULL
  * (synchronise when non-NULL; with grad_sigma_s the images' adjoints run one
- * by one on the auxiliary streams).  Same limits as fhd_filter_backward. */
+ * by one on the auxiliary streams); saved as filled by the forward call, or
+ * NULL.  Same limits as fhd_filter_backward. */
 fhd_status fhd_filter_batch_backward(fhd_ctx* ctx, int B, const int* H, const int* W,
                                      const long long* px_offset, const float* f, int n,
                                      const float* guide, int rho, const float* centers,
                                      const int* K_eff, const fhd_params* p, const float* out,
                                      const float* den, const float* grad_out, float* grad_f,
-                                     float* grad_guide, double* grad_sigma_r, double* grad_sigma_s);
+                                     float* grad_guide, double* grad_sigma_r, double* grad_sigma_s,
+                                     const void* saved, size_t saved_bytes);
 
 /* The brute-force filter of eqs. (1)-(2) on the GPU (FP32), the reference
  * the approximation is measured against.  out device n x H x W; den device

@@ -17,7 +17,7 @@ import torch
 
 __all__ = [
     "FHDError", "Params", "Info", "load", "lib_path", "symbols",
-    "filter", "filter_centers", "filter_centers_noalloc", "filter_backward", "FilterFunction", "filter_autograd",
+    "filter", "filter_centers", "filter_centers_noalloc", "filter_backward", "saved_buffer", "FilterFunction", "filter_autograd",
     "pack_batch", "filter_batch", "filter_batch_backward",
     "cluster", "pinv", "bruteforce", "nlm_guide", "scale_guide", "ScaleGuide", "approx_error",
     "filter_volume", "bruteforce_volume", "timing_enable", "timing_read", "timing_units",
@@ -36,7 +36,7 @@ COEF = {"lsq": 0, "hard": 1}
 # Every entry point declared in include/fhd.h.
 symbols = [
     "fhd_default_params", "fhd_create", "fhd_destroy", "fhd_set_stream", "fhd_last_error",
-    "fhd_workspace_size", "fhd_set_workspace", "fhd_cluster", "fhd_pinv",
+    "fhd_workspace_size", "fhd_saved_size", "fhd_saved_size_batch", "fhd_set_workspace", "fhd_cluster", "fhd_pinv",
     "fhd_filter_centers", "fhd_filter_centers_noalloc", "fhd_filter", "fhd_filter_backward", "fhd_filter_batch",
     "fhd_filter_batch_backward", "fhd_bruteforce", "fhd_nlm_guide", "fhd_scale_guide",
     "fhd_approx_error", "fhd_filter_volume", "fhd_bruteforce_volume",
@@ -102,15 +102,18 @@ def load():
             "fhd_last_error": (ctypes.c_char_p, [V]),
             "fhd_workspace_size": (I, [pp, I, I, I, I, P(ctypes.c_size_t)]),
             "fhd_set_workspace": (I, [V, V, ctypes.c_size_t]),
+            "fhd_saved_size": (I, [pp, I, I, I, I, P(ctypes.c_size_t)]),
+            "fhd_saved_size_batch": (I, [pp, I, V, V, I, I, P(ctypes.c_size_t)]),
             "fhd_cluster": (I, [V, V, I, I, I, I, I, V, V, P(I), pi]),
             "fhd_pinv": (I, [V, I, I, D, D, V, V, P(I), P(D)]),
-            "fhd_filter_centers": (I, [V, V, I, V, I, I, I, V, I, V, pp, V, V, pi]),
+            "fhd_filter_centers": (I, [V, V, I, V, I, I, I, V, I, V, pp, V, V, pi, V, ctypes.c_size_t]),
             "fhd_filter_centers_noalloc": (I, [V, V, I, V, I, I, I, V, I, V, pp, V, V]),
-            "fhd_filter": (I, [V, V, I, V, I, I, I, pp, V, V, V, pi]),
-            "fhd_filter_backward": (I, [V, V, I, V, I, I, I, V, I, pp, V, V, V, V, V, P(D), P(D), V]),
-            "fhd_filter_batch": (I, [V, I, V, V, V, V, I, V, I, pp, V, V, V, V, pi]),
+            "fhd_filter": (I, [V, V, I, V, I, I, I, pp, V, V, V, pi, V, ctypes.c_size_t]),
+            "fhd_filter_backward": (I, [V, V, I, V, I, I, I, V, I, pp, V, V, V, V, V, P(D), P(D), V, V,
+                                        ctypes.c_size_t]),
+            "fhd_filter_batch": (I, [V, I, V, V, V, V, I, V, I, pp, V, V, V, V, pi, V, ctypes.c_size_t]),
             "fhd_filter_batch_backward": (I, [V, I, V, V, V, V, I, V, I, V, V, pp, V, V, V, V, V,
-                                              P(D), P(D)]),
+                                              P(D), P(D), V, ctypes.c_size_t]),
             "fhd_bruteforce": (I, [V, V, I, V, I, I, I, pp, V, V]),
             "fhd_nlm_guide": (I, [V, V, I, I, I, I, I, V, V]),
             "fhd_scale_guide": (I, [V, V, I, ctypes.c_longlong, V, V]),
@@ -205,18 +208,47 @@ def _range(g, sigma_r):
     return scale_guide(g, sigma_r), 1.0
 
 
+def _saved_arg(saved):
+    """(pointer, bytes) of a saved buffer: a uint8 device tensor, 256-byte aligned."""
+    if saved is None:
+        return None, 0
+    if not isinstance(saved, torch.Tensor) or not saved.is_cuda or saved.dtype != torch.uint8:
+        raise FHDError(FHD_EINVAL, "saved must be a uint8 CUDA (HIP) tensor (see saved_buffer)")
+    if saved.data_ptr() % 256 != 0 or not saved.is_contiguous():
+        raise FHDError(FHD_EINVAL, "saved must be contiguous and 256-byte aligned")
+    return ctypes.c_void_p(saved.data_ptr()), saved.numel()
+
+
+def saved_buffer(n, rho, H, W, K, device=0, sigma_s=3.0, sigma_r=0.1, spatial="gaussian", radius=None):
+    """A device buffer (uint8 tensor) for a forward call to keep its
+    intermediates for the adjoint (``fhd_saved_size``); ``H``, ``W`` lists for
+    a batch (``fhd_saved_size_batch``)."""
+    p = make_params(sigma_s, sigma_r, K, spatial, radius)
+    b = ctypes.c_size_t()
+    if isinstance(H, (list, tuple)):
+        B = len(H)
+        Ha, Wa = (ctypes.c_int * B)(*H), (ctypes.c_int * B)(*W)
+        _check(load().fhd_saved_size_batch(ctypes.byref(p), B, Ha, Wa, n, rho, ctypes.byref(b)), None)
+    else:
+        _check(load().fhd_saved_size(ctypes.byref(p), n, rho, H, W, ctypes.byref(b)), None)
+    return torch.empty(b.value, dtype=torch.uint8, device=torch.device("cuda", device))
+
+
 def filter(f, guide=None, sigma_s=3.0, sigma_r=0.1, K=16, spatial="gaussian", radius=None,
            contract="fp32", coef="lsq", kmeans_max_iter=20, return_den=False,
-           return_centers=False, info=False, strict=False):
+           return_centers=False, info=False, strict=False, saved=None):
     """Algorithm 1 end to end: returns g_hat (n, H, W) [, den (H, W)]
     [, centers (K_eff, rho) on the host] [, info dict].  ``sigma_r`` is a
     number, or one value per guide dimension (anisotropic kernel; centers are
-    then in the units of the scaled guide, see :func:`scale_guide`)."""
+    then in the units of the scaled guide, see :func:`scale_guide`).  ``saved``
+    (from :func:`saved_buffer`) keeps the intermediates for
+    :func:`filter_backward`."""
     n, rho, H, W, g = _shape(f, guide)
     g, sigma_r = _range(g, sigma_r)
     ctx = _ctx(f.device.index)
     p = make_params(sigma_s, sigma_r, K, spatial, radius, contract, coef, kmeans_max_iter,
                     strict=strict)
+    sp, sb = _saved_arg(saved)
     out = torch.empty_like(f)
     den = torch.empty((H, W), device=f.device, dtype=torch.float32) if return_den else None
     cen = torch.zeros((K, rho), dtype=torch.float32)
@@ -224,7 +256,7 @@ def filter(f, guide=None, sigma_s=3.0, sigma_r=0.1, K=16, spatial="gaussian", ra
     _check(load().fhd_filter(ctx, _dev(f, "f"), n, _dev(g, "guide"), rho, H, W, ctypes.byref(p),
                              _dev(out, "out"), ctypes.c_void_p(cen.data_ptr()),
                              _dev(den, "den") if den is not None else None,
-                             ctypes.byref(inf) if (info or return_centers) else None), ctx)
+                             ctypes.byref(inf) if (info or return_centers) else None, sp, sb), ctx)
     res = [out]
     if return_den:
         res.append(den)
@@ -289,7 +321,7 @@ def bruteforce_volume(f, guide=None, sigma_s=3.0, sigma_r=0.1, spatial="gaussian
 
 def filter_centers(f, guide, centers, sigma_s=3.0, sigma_r=0.1, spatial="gaussian", radius=None,
                    contract="fp32", coef="lsq", labels=None, return_den=False, info=False,
-                   strict=False):
+                   strict=False, saved=None):
     """Steps 2-5 with given centers (host or device (K, rho) float32); a
     per-dimension ``sigma_r`` as in :func:`filter` (centers in scaled units)."""
     n, rho, H, W, g = _shape(f, guide)
@@ -304,11 +336,12 @@ def filter_centers(f, guide, centers, sigma_s=3.0, sigma_r=0.1, spatial="gaussia
     den = torch.empty((H, W), device=f.device, dtype=torch.float32) if return_den else None
     inf = Info()
     lab = _dev(labels, "labels", torch.int32) if labels is not None else None
+    sp, sb = _saved_arg(saved)
     _check(load().fhd_filter_centers(ctx, _dev(f, "f"), n, _dev(g, "guide"), rho, H, W,
                                      ctypes.c_void_p(c.data_ptr()), K, lab, ctypes.byref(p),
                                      _dev(out, "out"),
                                      _dev(den, "den") if den is not None else None,
-                                     ctypes.byref(inf) if info else None), ctx)
+                                     ctypes.byref(inf) if info else None, sp, sb), ctx)
     res = [out]
     if return_den:
         res.append(den)
@@ -343,7 +376,7 @@ def filter_centers_noalloc(f, guide, centers, sigma_s=3.0, sigma_r=0.1, spatial=
 
 def filter_backward(f, guide, centers, out, den, grad_out, sigma_s=3.0, sigma_r=0.1,
                     spatial="gaussian", radius=None, need_f=True, need_guide=True, need_sigma_r=True,
-                    need_sigma_s=False, need_centers=False):
+                    need_sigma_s=False, need_centers=False, saved=None):
     """Adjoint of :func:`filter_centers` (least-squares coefficients): given
     G = dL/dg_hat and the forward call's (g_hat, r_hat), returns
     (dL/df or None, dL/dguide or None, dL/dsigma_r as float or None),
@@ -369,7 +402,7 @@ def filter_backward(f, guide, centers, out, den, grad_out, sigma_s=3.0, sigma_r=
         _dev(gg, "grad_guide") if gg is not None else None,
         ctypes.byref(gs) if need_sigma_r else None,
         ctypes.byref(gss) if need_sigma_s else None,
-        ctypes.c_void_p(gmu.data_ptr()) if need_centers else None), ctx)
+        ctypes.c_void_p(gmu.data_ptr()) if need_centers else None, *_saved_arg(saved)), ctx)
     res = (gf, gg, (gs.value if need_sigma_r else None))
     if need_sigma_s:
         res += (gss.value,)
@@ -385,10 +418,21 @@ class FilterFunction(torch.autograd.Function):
     filtering of an image by itself: autograd adds the two contributions."""
 
     @staticmethod
-    def forward(ctx, f, guide, sigma_r, centers, sigma_s, spatial, radius, contract):
+    def forward(ctx, f, guide, sigma_r, centers, sigma_s, spatial, radius, contract, keep=True):
         sr, ss = float(sigma_r), float(sigma_s)
+        saved = None
+        if keep and contract == "fp32":
+            # the forward's intermediates for the adjoint, where the adjoint can use them
+            try:
+                saved = saved_buffer(f.shape[0], guide.shape[0], f.shape[1], f.shape[2], len(centers),
+                                     f.device.index, sigma_s=ss, sigma_r=sr, spatial=spatial, radius=radius)
+            except FHDError as e:
+                if e.status != FHD_EUNSUPPORTED:
+                    raise
         out, den = filter_centers(f.detach(), guide.detach(), centers, sigma_s=ss, sigma_r=sr,
-                                  spatial=spatial, radius=radius, contract=contract, return_den=True)
+                                  spatial=spatial, radius=radius, contract=contract, return_den=True,
+                                  saved=saved)
+        ctx.saved_buf = saved
         ctx.save_for_backward(f, guide, out, den)
         ctx.conf = (centers, ss, sr, spatial, radius)
         ctx.sr_tensor = isinstance(sigma_r, torch.Tensor)
@@ -407,30 +451,31 @@ class FilterFunction(torch.autograd.Function):
                               grad_out.contiguous(), sigma_s=sigma_s, sigma_r=sr,
                               spatial=spatial, radius=radius, need_f=need_f, need_guide=need_g,
                               need_sigma_r=need_s and ctx.sr_tensor, need_sigma_s=need_ss,
-                              need_centers=need_mu)
+                              need_centers=need_mu, saved=ctx.saved_buf)
         gf, gg, gs = res[:3]
         gsr = torch.tensor(gs, dtype=torch.float32) if need_s and ctx.sr_tensor else None
         gss = torch.tensor(res[3], dtype=torch.float32) if need_ss else None
         gmu = None
         if need_mu:
             gmu = res[-1].to(dtype=centers.dtype, device=centers.device)
-        return gf, gg, gsr, gmu, gss, None, None, None
+        return gf, gg, gsr, gmu, gss, None, None, None, None
 
 
 def filter_autograd(f, guide=None, sigma_s=3.0, sigma_r=0.1, K=16, spatial="gaussian",
-                    radius=None, contract="fp32", centers=None, kmeans_max_iter=20):
+                    radius=None, contract="fp32", centers=None, kmeans_max_iter=20, keep=True):
     """Differentiable Algorithm 1: the centers come from the bisecting K-means
     of the (detached) guide unless given, then :class:`FilterFunction`.
     ``sigma_r`` and ``sigma_s`` may be 0-d tensors that require grad; a
     ``sigma_r`` of one value per guide dimension (constants) filters the guide
     scaled by :class:`ScaleGuide` with sigma_r = 1, gradients flowing back to
-    the unscaled guide."""
+    the unscaled guide.  ``keep`` lets the forward call keep its intermediates
+    for the adjoint (:func:`saved_buffer`), where the adjoint can use them."""
     g = f if guide is None else guide
     if not _scalar(sigma_r):
         g, sigma_r = ScaleGuide.apply(g, sigma_r), 1.0
     if centers is None:
         centers, _ = cluster(g.detach(), K, max_iter=kmeans_max_iter)
-    return FilterFunction.apply(f, g, sigma_r, centers, sigma_s, spatial, radius, contract)
+    return FilterFunction.apply(f, g, sigma_r, centers, sigma_s, spatial, radius, contract, keep)
 
 
 def pack_batch(images):
@@ -460,7 +505,7 @@ def _batch_arrays(sizes):
 
 def filter_batch(flat_f, sizes, n, flat_guide=None, rho=None, sigma_s=3.0, sigma_r=0.1, K=16,
                  spatial="gaussian", radius=None, contract="fp32", coef="lsq", kmeans_max_iter=20,
-                 return_den=False, info=False, strict=False):
+                 return_den=False, info=False, strict=False, saved=None):
     """Algorithm 1 on a ragged batch in the flat layout of :func:`pack_batch`.
     Returns (out flat, [den flat], centers (B, K, rho) host, K_eff list [, info list])."""
     B, Ha, Wa, Oa, N = _batch_arrays(sizes)
@@ -478,7 +523,7 @@ def filter_batch(flat_f, sizes, n, flat_guide=None, rho=None, sigma_s=3.0, sigma
     _check(load().fhd_filter_batch(ctx, B, Ha, Wa, Oa, _dev(flat_f, "f"), n, _dev(g, "guide"), rho,
                                    ctypes.byref(p), _dev(out, "out"), ctypes.c_void_p(cen.data_ptr()),
                                    keff, _dev(den, "den") if den is not None else None,
-                                   infos if info else None), ctx)
+                                   infos if info else None, *_saved_arg(saved)), ctx)
     res = [out]
     if return_den:
         res.append(den)
@@ -490,7 +535,7 @@ def filter_batch(flat_f, sizes, n, flat_guide=None, rho=None, sigma_s=3.0, sigma
 
 def filter_batch_backward(flat_f, sizes, n, centers, K_eff, out, den, grad_out, flat_guide=None,
                           rho=None, sigma_s=3.0, sigma_r=0.1, spatial="gaussian", radius=None,
-                          need_f=True, need_guide=True, need_sigma_r=True, need_sigma_s=False):
+                          need_f=True, need_guide=True, need_sigma_r=True, need_sigma_s=False, saved=None):
     """Adjoint of :func:`filter_batch`: (dL/df flat or None, dL/dguide flat or
     None, dL/dsigma_r summed over the images or None), and dL/dsigma_s summed
     over the images as a fourth entry when ``need_sigma_s``."""
@@ -512,7 +557,7 @@ def filter_batch_backward(flat_f, sizes, n, centers, K_eff, out, den, grad_out, 
         _dev(gf, "grad_f") if gf is not None else None,
         _dev(gg, "grad_guide") if gg is not None else None,
         ctypes.byref(gs) if need_sigma_r else None,
-        ctypes.byref(gss) if need_sigma_s else None), ctx)
+        ctypes.byref(gss) if need_sigma_s else None, *_saved_arg(saved)), ctx)
     res = (gf, gg, (gs.value if need_sigma_r else None))
     return res + (gss.value,) if need_sigma_s else res
 

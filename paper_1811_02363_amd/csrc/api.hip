@@ -471,6 +471,88 @@ std::vector<long long> batch_counts(int B, const int* H, const int* W, const lon
     return cnt;
 }
 
+// ---- intermediates saved by a forward call for its adjoint ------------------
+
+// The forward call's requirements on a saved buffer: the adjoint's window,
+// FP32 contraction, least-squares coefficients, K <= 64.
+void saved_check_ptr(const void* saved) {
+    FHD_REQUIRE((reinterpret_cast<uintptr_t>(saved) & 255) == 0, FHD_EINVAL, "saved buffer must be 256-byte aligned");
+}
+
+void saved_check_params(const fhd_params* p, int K) {
+    FHD_REQUIRE(p->contract == FHD_CONTRACT_FP32, FHD_EUNSUPPORTED,
+                "saving for the adjoint needs the FP32 contraction (the adjoint differentiates it)");
+    FHD_REQUIRE(p->coef == FHD_COEF_LSQ, FHD_EUNSUPPORTED, "saving for the adjoint needs least-squares coefficients");
+    FHD_REQUIRE(p->spatial == FHD_SPATIAL_GAUSSIAN || p->spatial == FHD_SPATIAL_BOX, FHD_EUNSUPPORTED,
+                "saving for the adjoint needs the truncated Gaussian or box window");
+    const int S = resolve_radius(*p);
+    FHD_REQUIRE(S >= 1 && S <= 32, FHD_EUNSUPPORTED, "saving for the adjoint needs radius 1..32");
+    FHD_REQUIRE(K <= 64, FHD_EUNSUPPORTED, "saving for the adjoint needs K <= 64");
+}
+
+// the forward plan whose layout the saved buffer follows (FP32 contraction)
+FilterPlan saved_plan(const fhd_params& p, int n, int rho, int H, int W, int K) {
+    return make_plan(p, n, rho, H, W, K);
+}
+
+// byte offsets of the images' regions in a batch's saved buffer (sized with
+// the requested K, so forward and adjoint agree before K_eff is known)
+std::vector<size_t> saved_offsets(const fhd_params& p, int B, const int* H, const int* W, int n, int rho) {
+    std::vector<size_t> off(B + 1, 0);
+    for (int b = 0; b < B; ++b)
+        off[b + 1] = off[b] + align_up(saved_planes_bytes(saved_plan(p, n, rho, H[b], W[b], p.K)), 256);
+    return off;
+}
+
+Ctx::SavedDesc saved_desc(const void* ptr, size_t bytes, const float* f, const float* guide, int n, int rho,
+                          const fhd_params& p) {
+    Ctx::SavedDesc d;
+    d.ptr = ptr;
+    d.bytes = bytes;
+    d.f = f;
+    d.guide = guide;
+    d.n = n;
+    d.rho = rho;
+    d.K = p.K;
+    d.S = resolve_radius(p);
+    d.spatial = p.spatial;
+    d.sigma_s = p.spatial == FHD_SPATIAL_BOX ? 0.0f : p.sigma_s;  // the box ignores it
+    d.sigma_r = p.sigma_r;
+    d.rtol = p.pinv_rtol;
+    return d;
+}
+
+void saved_register(Ctx& c, Ctx::SavedDesc d) {
+    const char* lo = static_cast<const char*>(d.ptr);
+    const char* hi = lo + d.bytes;
+    auto& v = c.saved;
+    v.erase(std::remove_if(v.begin(), v.end(),
+                           [&](const Ctx::SavedDesc& e) {
+                               const char* a = static_cast<const char*>(e.ptr);
+                               return a < hi && lo < a + e.bytes;  // overwritten
+                           }),
+            v.end());
+    v.push_back(std::move(d));
+    if (v.size() > 16) v.erase(v.begin());
+}
+
+void saved_verify(const Ctx& c, const Ctx::SavedDesc& want) {
+    for (auto it = c.saved.rbegin(); it != c.saved.rend(); ++it) {
+        if (it->ptr != want.ptr) continue;
+        const Ctx::SavedDesc& d = *it;
+        FHD_REQUIRE(d.f == want.f && d.guide == want.guide && d.n == want.n && d.rho == want.rho &&
+                        d.K == want.K && d.S == want.S && d.spatial == want.spatial && d.sigma_s == want.sigma_s &&
+                        d.sigma_r == want.sigma_r && d.rtol == want.rtol && d.H == want.H && d.W == want.W &&
+                        d.Keff == want.Keff && d.centers == want.centers,
+                    FHD_EINVAL,
+                    "saved buffer was written by a forward call with other arguments (image, guide, shape, "
+                    "window, sigmas or centers)");
+        FHD_REQUIRE(want.bytes <= d.bytes, FHD_EINVAL, "saved buffer smaller than the forward call's");
+        return;
+    }
+    throw Error(FHD_EINVAL, "saved buffer was not written by a forward call on this context (or was overwritten since)");
+}
+
 constexpr int NOALLOC_MAX_DEVICES = 64;
 std::mutex noalloc_mutex;
 char* noalloc_addr[NOALLOC_MAX_DEVICES] = {};
@@ -601,6 +683,35 @@ fhd_status fhd_workspace_size(const fhd_params* p, int n, int rho, int H, int W,
     }
 }
 
+fhd_status fhd_saved_size(const fhd_params* p, int n, int rho, int H, int W, size_t* bytes) {
+    if (bytes == nullptr) return FHD_EINVAL;
+    try {
+        check_params(p, n, rho, H, W);
+        saved_check_params(p, p->K);
+        *bytes = saved_planes_bytes(saved_plan(*p, n, rho, H, W, p->K));
+        return FHD_OK;
+    } catch (const Error& e) {
+        return e.status;
+    } catch (...) {
+        return FHD_EINVAL;
+    }
+}
+
+fhd_status fhd_saved_size_batch(const fhd_params* p, int B, const int* H, const int* W, int n, int rho,
+                                size_t* bytes) {
+    if (bytes == nullptr || H == nullptr || W == nullptr || B < 1) return FHD_EINVAL;
+    try {
+        for (int b = 0; b < B; ++b) check_params(p, n, rho, H[b], W[b]);
+        saved_check_params(p, p->K);
+        *bytes = saved_offsets(*p, B, H, W, n, rho)[B];
+        return FHD_OK;
+    } catch (const Error& e) {
+        return e.status;
+    } catch (...) {
+        return FHD_EINVAL;
+    }
+}
+
 fhd_status fhd_set_workspace(fhd_ctx* ctx, void* dev, size_t bytes) {
     return guarded(ctx, [&](Ctx& c) {
         FHD_REQUIRE(dev == nullptr || (reinterpret_cast<uintptr_t>(dev) & 255) == 0, FHD_EINVAL,
@@ -659,7 +770,7 @@ fhd_status fhd_pinv(const float* centers, int K, int rho, double sigma_r, double
 
 fhd_status fhd_filter_centers(fhd_ctx* ctx, const float* f, int n, const float* guide, int rho, int H,
                               int W, const float* centers, int K, const int* labels, const fhd_params* p,
-                              float* out, float* den, fhd_info* info) {
+                              float* out, float* den, fhd_info* info, void* saved, size_t saved_bytes) {
     return guarded(ctx, [&](Ctx& c) {
         check_params(p, n, rho, H, W);
         FHD_REQUIRE(f && guide && centers && out, FHD_EINVAL, "NULL pointer");
@@ -673,6 +784,18 @@ fhd_status fhd_filter_centers(fhd_ctx* ctx, const float* f, int n, const float* 
                         !ranges_overlap(den, sizeof(float) * N, out, sizeof(float) * N * n),
                     FHD_EINVAL, "outputs alias inputs");
         const FilterPlan fp = make_plan(*p, n, rho, H, W, K);
+        SavedPlanes sv{};
+        if (saved != nullptr) {
+            saved_check_ptr(saved);
+            saved_check_params(p, K);
+            FHD_REQUIRE(saved_bytes >= saved_planes_bytes(fp), FHD_EINVAL, "saved buffer too small (fhd_saved_size)");
+            FHD_REQUIRE(!ranges_overlap(saved, saved_bytes, f, sizeof(float) * N * n) &&
+                            !ranges_overlap(saved, saved_bytes, guide, sizeof(float) * N * rho) &&
+                            !ranges_overlap(saved, saved_bytes, out, sizeof(float) * N * n) &&
+                            !ranges_overlap(saved, saved_bytes, den, sizeof(float) * N),
+                        FHD_EINVAL, "saved buffer aliases an input or output");
+            sv = saved_at(static_cast<char*>(saved), fp);
+        }
         Arena ws = c.arena(filter_workspace(fp) + stats_workspace(N) + 4096);
         const bool stats = info != nullptr || p->strict;
         float* dn = (stats && den == nullptr) ? ws.take<float>((size_t)N) : den;
@@ -681,7 +804,16 @@ fhd_status fhd_filter_centers(fhd_ctx* ctx, const float* f, int n, const float* 
         const PinvResult pr = solve(centers, K, rho, p->sigma_r, p->pinv_rtol, P32);
         const double ms_solve = ms_since(t0);
         const auto t1 = clk::now();
-        filter_run(c, ws, fp, f, guide, centers, P32.data(), labels, out, dn);
+        filter_run(c, ws, fp, f, guide, centers, P32.data(), labels, out, dn, saved != nullptr ? &sv : nullptr);
+        if (saved != nullptr) {
+            Ctx::SavedDesc d = saved_desc(saved, saved_bytes, f, guide, n, rho, *p);
+            d.K = K;
+            d.H = {H};
+            d.W = {W};
+            d.Keff = {K};
+            d.centers.assign(centers, centers + (size_t)K * rho);
+            saved_register(c, std::move(d));
+        }
         double ms_filter = 0.0;
         if (info) {
             FHD_HIP(hipStreamSynchronize(c.stream));
@@ -750,7 +882,8 @@ fhd_status fhd_filter_centers_noalloc(fhd_ctx* ctx, const float* f, int n, const
 }
 
 fhd_status fhd_filter(fhd_ctx* ctx, const float* f, int n, const float* guide, int rho, int H, int W,
-                      const fhd_params* p, float* out, float* centers_out, float* den, fhd_info* info) {
+                      const fhd_params* p, float* out, float* centers_out, float* den, fhd_info* info, void* saved,
+                      size_t saved_bytes) {
     return guarded(ctx, [&](Ctx& c) {
         check_params(p, n, rho, H, W);
         FHD_REQUIRE(f && guide && out, FHD_EINVAL, "NULL pointer");
@@ -766,6 +899,17 @@ fhd_status fhd_filter(fhd_ctx* ctx, const float* f, int n, const float* guide, i
             const FilterPlan fp0 = make_plan(*p, n, rho, H, W, p->K);
             need = kmeans_workspace(N, rho, p->K) + filter_workspace(fp0) +
                    align_up(sizeof(int) * (size_t)N, 256) + stats_workspace(N) + 4096;
+        }
+        if (saved != nullptr) {
+            saved_check_ptr(saved);
+            saved_check_params(p, p->K);
+            FHD_REQUIRE(saved_bytes >= saved_planes_bytes(make_plan(*p, n, rho, H, W, p->K)), FHD_EINVAL,
+                        "saved buffer too small (fhd_saved_size)");
+            FHD_REQUIRE(!ranges_overlap(saved, saved_bytes, f, sizeof(float) * N * n) &&
+                            !ranges_overlap(saved, saved_bytes, guide, sizeof(float) * N * rho) &&
+                            !ranges_overlap(saved, saved_bytes, out, sizeof(float) * N * n) &&
+                            !ranges_overlap(saved, saved_bytes, den, sizeof(float) * N),
+                        FHD_EINVAL, "saved buffer aliases an input or output");
         }
         Arena ws = c.arena(need);
         const bool hard = p->coef == FHD_COEF_HARD;
@@ -789,7 +933,18 @@ fhd_status fhd_filter(fhd_ctx* ctx, const float* f, int n, const float* guide, i
         const double ms_solve = ms_since(t1);
         const auto t2 = clk::now();
         const FilterPlan fp = make_plan(*p, n, rho, H, W, K);
-        filter_run(c, ws, fp, f, guide, c32.data(), P32.data(), labels, out, dn);
+        SavedPlanes sv{};
+        if (saved != nullptr) sv = saved_at(static_cast<char*>(saved), fp);
+        filter_run(c, ws, fp, f, guide, c32.data(), P32.data(), labels, out, dn, saved != nullptr ? &sv : nullptr);
+        if (saved != nullptr) {
+            Ctx::SavedDesc d = saved_desc(saved, saved_bytes, f, guide, n, rho, *p);
+            d.K = K;
+            d.H = {H};
+            d.W = {W};
+            d.Keff = {K};
+            d.centers = c32;
+            saved_register(c, std::move(d));
+        }
         double ms_filter = 0.0;
         if (info) {
             FHD_HIP(hipStreamSynchronize(c.stream));
@@ -806,7 +961,8 @@ fhd_status fhd_filter(fhd_ctx* ctx, const float* f, int n, const float* guide, i
 fhd_status fhd_filter_backward(fhd_ctx* ctx, const float* f, int n, const float* guide, int rho, int H, int W,
                                const float* centers, int K, const fhd_params* p, const float* out,
                                const float* den, const float* grad_out, float* grad_f, float* grad_guide,
-                               double* grad_sigma_r, double* grad_sigma_s, double* grad_centers) {
+                               double* grad_sigma_r, double* grad_sigma_s, double* grad_centers, const void* saved,
+                               size_t saved_bytes) {
     return guarded(ctx, [&](Ctx& c) {
         check_params(p, n, rho, H, W);
         FHD_REQUIRE(grad_sigma_s == nullptr || p->spatial == FHD_SPATIAL_GAUSSIAN, FHD_EUNSUPPORTED,
@@ -835,14 +991,31 @@ fhd_status fhd_filter_backward(fhd_ctx* ctx, const float* f, int n, const float*
         pinv_sigma_derivative(centers, K, rho, p->sigma_r, p->pinv_rtol, M.data());
         std::vector<float> M32(M.size());
         for (size_t q = 0; q < M.size(); ++q) M32[q] = (float)M[q];
+        SavedPlanes sv{};
+        if (saved != nullptr) {
+            const FilterPlan ffp = saved_plan(*p, n, rho, H, W, K);
+            Ctx::SavedDesc want = saved_desc(saved, saved_planes_bytes(ffp), f, guide, n, rho, *p);
+            want.K = K;
+            want.H = {H};
+            want.W = {W};
+            want.Keff = {K};
+            want.centers.assign(centers, centers + (size_t)K * rho);
+            saved_verify(c, want);
+            FHD_REQUIRE(saved_bytes >= want.bytes, FHD_EINVAL, "saved buffer too small");
+            FHD_REQUIRE(!ranges_overlap(saved, saved_bytes, grad_f, fb) &&
+                            !ranges_overlap(saved, saved_bytes, grad_guide, gb),
+                        FHD_EINVAL, "gradient outputs alias the saved buffer");
+            sv = saved_at(static_cast<char*>(const_cast<void*>(saved)), ffp);
+        }
         adjoint_run(c, ws, fp, f, guide, centers, P32.data(), M32.data(), out, den, grad_out, grad_f, grad_guide,
-                    grad_sigma_r, grad_sigma_s, p->pinv_rtol, grad_centers);
+                    grad_sigma_r, grad_sigma_s, p->pinv_rtol, grad_centers, saved != nullptr ? &sv : nullptr);
     });
 }
 
 fhd_status fhd_filter_batch(fhd_ctx* ctx, int B, const int* H, const int* W, const long long* px_offset,
                             const float* f, int n, const float* guide, int rho, const fhd_params* p, float* out,
-                            float* centers_out, int* K_eff, float* den, fhd_info* info) {
+                            float* centers_out, int* K_eff, float* den, fhd_info* info, void* saved,
+                            size_t saved_bytes) {
     return guarded(ctx, [&](Ctx& c) {
         const std::vector<long long> cnt = batch_counts(B, H, W, px_offset);
         for (int b = 0; b < B; ++b) check_params(p, n, rho, H[b], W[b]);
@@ -856,6 +1029,18 @@ fhd_status fhd_filter_batch(fhd_ctx* ctx, int B, const int* H, const int* W, con
                         !ranges_overlap(den, sizeof(float) * N, out, sizeof(float) * N * n),
                     FHD_EINVAL, "outputs alias inputs");
         const int K = p->K;
+        std::vector<size_t> soff;
+        if (saved != nullptr) {
+            saved_check_ptr(saved);
+            saved_check_params(p, K);
+            soff = saved_offsets(*p, B, H, W, n, rho);
+            FHD_REQUIRE(saved_bytes >= soff[B], FHD_EINVAL, "saved buffer too small (fhd_saved_size_batch)");
+            FHD_REQUIRE(!ranges_overlap(saved, saved_bytes, f, sizeof(float) * N * n) &&
+                            !ranges_overlap(saved, saved_bytes, guide, sizeof(float) * N * rho) &&
+                            !ranges_overlap(saved, saved_bytes, out, sizeof(float) * N * n) &&
+                            !ranges_overlap(saved, saved_bytes, den, sizeof(float) * N),
+                        FHD_EINVAL, "saved buffer aliases an input or output");
+        }
         size_t passes = 0;
         std::vector<FilterPlan> kplans(B);  // plans at the requested K (an upper bound for K_eff)
         bool batched = true;                // one launch per pass for all images
@@ -903,6 +1088,9 @@ fhd_status fhd_filter_batch(fhd_ctx* ctx, int B, const int* H, const int* W, con
         FHD_HIP(hipMemcpyAsync(dev, hs, (size_t)B * cb, hipMemcpyHostToDevice, c.stream));
         c.stage_done(1);
         const auto t2 = clk::now();
+        std::vector<SavedPlanes> sv(saved != nullptr ? B : 0);
+        for (int b = 0; b < (int)sv.size(); ++b)
+            sv[b] = saved_at(static_cast<char*>(saved) + soff[b], make_plan(*p, n, rho, H[b], W[b], km[b].K_eff));
         if (batched) {
             std::vector<FilterPlan> plans(B);
             std::vector<const float*> fb(B), gb(B);
@@ -920,7 +1108,7 @@ fhd_status fhd_filter_batch(fhd_ctx* ctx, int B, const int* H, const int* W, con
                 kc[b] = filter_consts_at(dev + (size_t)b * cb, km[b].K_eff, rho);
             }
             filter_passes_batch(c, ws, B, plans.data(), fb.data(), gb.data(), kc.data(), hard ? lb.data() : nullptr,
-                                ob.data(), dn ? db.data() : nullptr);
+                                ob.data(), dn ? db.data() : nullptr, saved != nullptr ? sv.data() : nullptr);
         } else {
             // one scratch region per stream; stream order makes it reusable image after image
             char* region = ws.take<char>((size_t)ns * passes);
@@ -934,8 +1122,20 @@ fhd_status fhd_filter_batch(fhd_ctx* ctx, int B, const int* H, const int* W, con
                 const long long o = px_offset[b];
                 filter_passes(c, pws, fp, f + (size_t)n * o, guide + (size_t)rho * o,
                               filter_consts_at(dev + (size_t)b * cb, km[b].K_eff, rho),
-                              hard ? labels + o : nullptr, out + (size_t)n * o, dn ? dn + o : nullptr);
+                              hard ? labels + o : nullptr, out + (size_t)n * o, dn ? dn + o : nullptr,
+                              saved != nullptr ? &sv[b] : nullptr);
             }
+        }
+        if (saved != nullptr) {
+            Ctx::SavedDesc d = saved_desc(saved, saved_bytes, f, guide, n, rho, *p);
+            d.K = K;
+            d.H.assign(H, H + B);
+            d.W.assign(W, W + B);
+            for (int b = 0; b < B; ++b) {
+                d.Keff.push_back(km[b].K_eff);
+                for (size_t q = 0; q < km[b].centers.size(); ++q) d.centers.push_back((float)km[b].centers[q]);
+            }
+            saved_register(c, std::move(d));
         }
         double ms_filter = 0.0;
         if (info) {
@@ -967,7 +1167,7 @@ fhd_status fhd_filter_batch_backward(fhd_ctx* ctx, int B, const int* H, const in
                                      const float* f, int n, const float* guide, int rho, const float* centers,
                                      const int* K_eff, const fhd_params* p, const float* out, const float* den,
                                      const float* grad_out, float* grad_f, float* grad_guide, double* grad_sigma_r,
-                                     double* grad_sigma_s) {
+                                     double* grad_sigma_s, const void* saved, size_t saved_bytes) {
     return guarded(ctx, [&](Ctx& c) {
         const std::vector<long long> cnt = batch_counts(B, H, W, px_offset);
         for (int b = 0; b < B; ++b) check_params(p, n, rho, H[b], W[b]);
@@ -1000,6 +1200,26 @@ fhd_status fhd_filter_batch_backward(fhd_ctx* ctx, int B, const int* H, const in
             plans[b].materialize = true;
             passes = std::max(passes, adjoint_passes_workspace(plans[b], with_s, false));
             batched = batched && adjoint_batch_supported(plans[b]);
+        }
+        std::vector<SavedPlanes> sv;
+        if (saved != nullptr) {
+            const std::vector<size_t> soff = saved_offsets(*p, B, H, W, n, rho);
+            Ctx::SavedDesc want = saved_desc(saved, soff[B], f, guide, n, rho, *p);
+            want.K = K;
+            want.H.assign(H, H + B);
+            want.W.assign(W, W + B);
+            want.Keff.assign(K_eff, K_eff + B);
+            for (int b = 0; b < B; ++b)
+                want.centers.insert(want.centers.end(), centers + (size_t)b * K * rho,
+                                    centers + (size_t)b * K * rho + (size_t)K_eff[b] * rho);
+            saved_verify(c, want);
+            FHD_REQUIRE(saved_bytes >= soff[B], FHD_EINVAL, "saved buffer too small");
+            FHD_REQUIRE(!ranges_overlap(saved, saved_bytes, grad_f, fb) &&
+                            !ranges_overlap(saved, saved_bytes, grad_guide, gb),
+                        FHD_EINVAL, "gradient outputs alias the saved buffer");
+            for (int b = 0; b < B; ++b)
+                sv.push_back(saved_at(static_cast<char*>(const_cast<void*>(saved)) + soff[b],
+                                      saved_plan(*p, n, rho, H[b], W[b], K_eff[b])));
         }
         const size_t cb = adjoint_consts_bytes(K, rho);
         const int ns = std::min(B, Ctx::NAUX);
@@ -1043,7 +1263,8 @@ fhd_status fhd_filter_batch_backward(fhd_ctx* ctx, int B, const int* H, const in
                 ggb[b] = grad_guide ? grad_guide + (size_t)rho * o : nullptr;
             }
             adjoint_passes_batch(c, ws, B, plans.data(), fb_.data(), gb_.data(), kc.data(), Mb.data(), ob.data(),
-                                 db_.data(), gob.data(), gfb.data(), ggb.data(), sig + B);
+                                 db_.data(), gob.data(), gfb.data(), ggb.data(), sig + B,
+                                 saved != nullptr ? sv.data() : nullptr);
         } else {
             char* region = ws.take<char>((size_t)ns * passes);
             Spread sp(c, B);
@@ -1060,7 +1281,7 @@ fhd_status fhd_filter_batch_backward(fhd_ctx* ctx, int B, const int* H, const in
                                reinterpret_cast<const float*>(d + filter_consts_bytes(Kb, rho)), out + (size_t)n * o,
                                den + o, grad_out + (size_t)n * o, grad_f ? grad_f + (size_t)n * o : nullptr,
                                grad_guide ? grad_guide + (size_t)rho * o : nullptr, sig + b,
-                               with_s ? sigs + b : nullptr, nullptr);
+                               with_s ? sigs + b : nullptr, nullptr, saved != nullptr ? &sv[b] : nullptr);
             }
         }
         if (grad_sigma_r != nullptr) {

@@ -104,9 +104,19 @@ struct FilterPlan {
     bool materialize;      // B and C planes are computed by a separate pass
 };
 size_t filter_workspace(const FilterPlan& fp);
+// The forward's intermediates kept for the adjoint in a caller buffer: the
+// row-filtered planes (the layout of the intermediate planes), the C planes
+// and, when the weights are materialised, the B planes (each K x H x Wp).
+struct SavedPlanes {
+    float* planes;
+    float* C;
+    float* B;
+};
+size_t saved_planes_bytes(const FilterPlan& fp);
+SavedPlanes saved_at(char* base, const FilterPlan& fp);
 void filter_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const float* guide,
                 const float* centers_host, const float* Pfp32_host, const int* labels,
-                float* out, float* den);
+                float* out, float* den, const SavedPlanes* sv = nullptr);
 // Device copies of one image's constants: centers (K x rho), A^+ (K x K) and
 // the contraction offset (rho), FP32, in one block of filter_consts_bytes.
 struct FilterConsts {
@@ -123,9 +133,10 @@ bool filter_batch_supported(const FilterPlan& fp);
 size_t filter_batch_workspace(int B, const FilterPlan* plans);
 void filter_passes_batch(Ctx& c, Arena& ws, int B, const FilterPlan* plans, const float* const* f,
                          const float* const* guide, const FilterConsts* kc, const int* const* labels,
-                         float* const* out, float* const* den);
+                         float* const* out, float* const* den, const SavedPlanes* sv = nullptr);
 void filter_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const float* guide,
-                   const FilterConsts& kc, const int* labels, float* out, float* den);
+                   const FilterConsts& kc, const int* labels, float* out, float* den,
+                   const SavedPlanes* sv = nullptr);
 void bruteforce_run(Ctx& c, const FilterPlan& fp, const float* f, const float* guide,
                     float* out, float* den);
 // with_s: also the dL/dsigma_s passes (one more K-plane set)
@@ -141,7 +152,7 @@ size_t adjoint_passes_workspace(const FilterPlan& fp, bool with_s, bool with_mu)
 void adjoint_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const float* guide,
                     const FilterConsts& kc, const float* Md, const float* out, const float* den,
                     const float* gout, float* gradf, float* gradp, double* sig_dev, double* sigs_dev,
-                    double* mu_dev);
+                    double* mu_dev, const SavedPlanes* sv = nullptr);
 // One launch per pass for the adjoint of all images of a batch (guides of at
 // most 8 dimensions, at most 32 clusters, radius 1..32); per-image pointers;
 // the sigma_r gradient summed over all images goes to sig_dev.
@@ -150,13 +161,14 @@ size_t adjoint_batch_workspace(int B, const FilterPlan* plans);
 void adjoint_passes_batch(Ctx& c, Arena& ws, int B, const FilterPlan* plans, const float* const* f,
                           const float* const* guide, const FilterConsts* kc, const float* const* Md,
                           const float* const* out, const float* const* den, const float* const* gout,
-                          float* const* gradf, float* const* gradp, double* sig_dev);
+                          float* const* gradf, float* const* gradp, double* sig_dev,
+                          const SavedPlanes* sv = nullptr);
 // out_dev[0] = v[0] + ... + v[count-1] (fixed order), on the ctx stream
 void sum_doubles(Ctx& c, const double* v, int count, double* out_dev);
 void adjoint_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const float* guide,
                  const float* centers_host, const float* Pfp32_host, const float* M_host, const float* out,
                  const float* den, const float* gout, float* gradf, float* gradp, double* gsig,
-                 double* gsigs, double rtol, double* gmu);
+                 double* gsigs, double rtol, double* gmu, const SavedPlanes* sv = nullptr);
 
 // A 3-D domain: the plan's H is D slices of H / D rows; FP32 weights
 // materialised, three 1-D passes over [-S,S]^3, then the recombination
@@ -197,6 +209,21 @@ struct Ctx {
     bool pinned_pending[3] = {false, false, false};
     // orders a new stream (fhd_set_stream) after the work on the previous one
     hipEvent_t switch_ev = nullptr;
+    // what the recent forward calls wrote into caller buffers for their
+    // adjoints (most recent last): the adjoint accepts a saved buffer only
+    // with the arguments of the forward call that wrote it
+    struct SavedDesc {
+        const void* ptr = nullptr;
+        size_t bytes = 0;
+        const float* f = nullptr;
+        const float* guide = nullptr;
+        int n = 0, rho = 0, K = 0, S = 0, spatial = 0;
+        float sigma_s = 0.0f, sigma_r = 0.0f;
+        double rtol = 0.0;
+        std::vector<int> H, W, Keff;     // per image (one for the single-image calls)
+        std::vector<float> centers;      // the K_eff rows of every image
+    };
+    std::vector<SavedDesc> saved;
     // allocation-free entry point: the device address of this GPU's static
     // scratch array, and a pinned buffer for the constants (made by
     // fhd_create, sized for FHD_MAX_K and FHD_MAX_RHO) with the event that

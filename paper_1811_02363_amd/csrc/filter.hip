@@ -62,6 +62,7 @@ struct FA {
     long long Pp;       // stride of the intermediate planes: H + 2S rows of Wp, row y at y + S
     float inv2s2;       // 1 / (2 sigma_r^2), 0 for sigma_r = inf
     float* betas;       // adjoint, dL/dsigma_s: K planes of Y . (d omega / d sigma_s) * (c_l [f, 1]), or null
+    float* Csave;       // row pass with inline weights: also store c_l of the block's own pixels (K planes), or null
     int bacc;           // adjoint column pass: add to the output planes instead of overwriting
     float w[FHD_MAX_RADIUS + 1];   // 1-D spatial taps w[|j|]
     float wd[FHD_MAX_RADIUS + 1];  // their derivative d w[|j|] / d sigma_s = w j^2 / sigma_s^3
@@ -247,6 +248,15 @@ __device__ __forceinline__ void row_gauss_body(const FA& a, int bx, int by) {
     float* smu = fs + (a.n + 1) * csp;
     float* sP = smu + a.K * RHO_INLINE;
     row_factors(a, y, x0, hw, csp, cs, fs, smu, sP);
+    if (a.Csave != nullptr) {
+        // the coefficients c_l of this block's own pixels, kept for the adjoint
+        const int w = min(a.tx, a.W - x0);
+        float* dst = a.Csave + (long long)y * a.Wp + x0;
+        for (int t = threadIdx.x; t < a.K * w; t += RT) {
+            const int l = t / w, h = t - l * w;
+            dst[(long long)l * a.Np + h] = cs[l * csp + pidx(S + h)];
+        }
+    }
     const int nseg = a.tx / R;
     const int n = a.n;
     for (int task = threadIdx.x; task < a.K * nseg; task += RT) {
@@ -2249,13 +2259,27 @@ size_t filter_passes_workspace(const FilterPlan& fp) {
     return probe.used;
 }
 
+size_t saved_planes_bytes(const FilterPlan& fp) {
+    const size_t kp = align_up(sizeof(float) * (size_t)fp.K * fp.H * fp.Wp, 256);
+    return align_up(sizeof(float) * plane_floats(fp), 256) + kp + (fp.materialize ? kp : 0);
+}
+
+SavedPlanes saved_at(char* base, const FilterPlan& fp) {
+    SavedPlanes s;
+    const size_t kp = align_up(sizeof(float) * (size_t)fp.K * fp.H * fp.Wp, 256);
+    s.planes = reinterpret_cast<float*>(base);
+    s.C = reinterpret_cast<float*>(base + align_up(sizeof(float) * plane_floats(fp), 256));
+    s.B = fp.materialize ? reinterpret_cast<float*>(reinterpret_cast<char*>(s.C) + kp) : nullptr;
+    return s;
+}
+
 size_t filter_workspace(const FilterPlan& fp) {
     return filter_passes_workspace(fp) + filter_consts_bytes(fp.K, fp.rho) + 256;
 }
 
 void filter_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const float* guide,
                 const float* centers_host, const float* Pfp32_host, const int* labels, float* out,
-                float* den) {
+                float* den, const SavedPlanes* sv) {
     // stage the constants through pinned memory (async, stream ordered)
     const size_t cb = filter_consts_bytes(fp.K, fp.rho);
     char* dev = ws.take<char>(cb);
@@ -2263,18 +2287,21 @@ void filter_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const f
     filter_consts_fill(centers_host, Pfp32_host, fp.K, fp.rho, hs);
     FHD_HIP(hipMemcpyAsync(dev, hs, cb, hipMemcpyHostToDevice, c.stream));
     c.stage_done(1);
-    filter_passes(c, ws, fp, f, guide, filter_consts_at(dev, fp.K, fp.rho), labels, out, den);
+    filter_passes(c, ws, fp, f, guide, filter_consts_at(dev, fp.K, fp.rho), labels, out, den, sv);
 }
 
 void filter_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const float* guide,
-                   const FilterConsts& kc, const int* labels, float* out, float* den) {
+                   const FilterConsts& kc, const int* labels, float* out, float* den, const SavedPlanes* sv) {
     const long long Np = (long long)fp.H * fp.Wp;
-    float* planes = ws.take<float>(plane_floats(fp));
+    FHD_REQUIRE(sv == nullptr || (fp.S >= 1 && fp.S <= MAXS_T && fp.spatial != FHD_SPATIAL_YOUNG &&
+                                  fp.coef == FHD_COEF_LSQ && fp.contract == FHD_CONTRACT_FP32),
+                FHD_EINVAL, "internal: saved planes need the adjoint's window, FP32 and least squares");
+    float* planes = sv != nullptr ? sv->planes : ws.take<float>(plane_floats(fp));
     float* Bpl = nullptr;
     float* Cpl = nullptr;
     if (fp.materialize) {
-        Bpl = ws.take<float>((size_t)fp.K * Np);
-        Cpl = ws.take<float>((size_t)fp.K * Np);
+        Bpl = sv != nullptr ? sv->B : ws.take<float>((size_t)fp.K * Np);
+        Cpl = sv != nullptr ? sv->C : ws.take<float>((size_t)fp.K * Np);
     }
     const float* mu = kc.mu;
     const float* P = kc.P;
@@ -2290,6 +2317,7 @@ void filter_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, cons
     a.planes = planes;
     a.out = out;
     a.den = den;
+    a.Csave = (sv != nullptr && !fp.materialize) ? sv->C : nullptr;
 
     if (fp.materialize && fp.contract != FHD_CONTRACT_FP32) {
         const size_t plds = sizeof(float) * (size_t)fp.K * pad8(fp.K);
@@ -2408,7 +2436,7 @@ size_t filter_batch_workspace(int B, const FilterPlan* plans) {
 // 1..32: weights inline).
 void filter_passes_batch(Ctx& c, Arena& ws, int B, const FilterPlan* plans, const float* const* f,
                          const float* const* guide, const FilterConsts* kc, const int* const* labels,
-                         float* const* out, float* const* den) {
+                         float* const* out, float* const* den, const SavedPlanes* sv) {
     const int S = plans[0].S;
     const bool hard = plans[0].coef == FHD_COEF_HARD;
     std::vector<FA> fas(B);
@@ -2426,7 +2454,8 @@ void filter_passes_batch(Ctx& c, Arena& ws, int B, const FilterPlan* plans, cons
         a.mu = kc[b].mu;
         a.P = kc[b].P;
         a.labels = labels ? labels[b] : nullptr;
-        a.planes = ws.take<float>(plane_floats(fp));
+        a.planes = sv != nullptr ? sv[b].planes : ws.take<float>(plane_floats(fp));
+        a.Csave = sv != nullptr ? sv[b].C : nullptr;
         a.out = out[b];
         a.den = den ? den[b] : nullptr;
         int tx = row_tx(fp.K, fp.S, R_ROW);
@@ -2504,7 +2533,7 @@ bool adj_final_mfma_fits(const FilterPlan& fp) {
 void adjoint_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const float* guide,
                  const float* centers_host, const float* Pfp32_host, const float* M_host, const float* out,
                  const float* den, const float* gout, float* gradf, float* gradp, double* gsig, double* gsigs,
-                 double rtol, double* gmu) {
+                 double rtol, double* gmu, const SavedPlanes* sv) {
     const size_t cb = adjoint_consts_bytes(fp.K, fp.rho);
     char* dev = ws.take<char>(cb);
     char* hs = static_cast<char*>(c.host_stage(1, cb));
@@ -2516,7 +2545,7 @@ void adjoint_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const 
     double* sig = ws.take<double>(2 + (size_t)E);
     adjoint_passes(c, ws, fp, f, guide, filter_consts_at(dev, fp.K, fp.rho),
                    reinterpret_cast<const float*>(dev + filter_consts_bytes(fp.K, fp.rho)), out, den, gout, gradf,
-                   gradp, sig, gsigs != nullptr ? sig + 1 : nullptr, gmu != nullptr ? sig + 2 : nullptr);
+                   gradp, sig, gsigs != nullptr ? sig + 1 : nullptr, gmu != nullptr ? sig + 2 : nullptr, sv);
     if (gsig != nullptr || gsigs != nullptr || gmu != nullptr) {
         std::vector<double> h(2 + (size_t)E);
         FHD_HIP(hipMemcpyAsync(h.data(), sig, sizeof(double) * (gmu != nullptr ? 2 + E : 2), hipMemcpyDeviceToHost,
@@ -2535,15 +2564,23 @@ void adjoint_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const 
 
 void adjoint_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const float* guide,
                     const FilterConsts& kc, const float* Md, const float* out, const float* den, const float* gout,
-                    float* gradf, float* gradp, double* sig_dev, double* sigs_dev, double* mu_dev) {
+                    float* gradf, float* gradp, double* sig_dev, double* sigs_dev, double* mu_dev,
+                    const SavedPlanes* sv) {
     FHD_REQUIRE(fp.S >= 1 && fp.S <= MAXS_T, FHD_EUNSUPPORTED, "the adjoint supports radii 1..32");
     FHD_REQUIRE(fp.K <= 64, FHD_EUNSUPPORTED, "the adjoint supports K <= 64");
     FHD_REQUIRE(fp.coef == FHD_COEF_LSQ, FHD_EUNSUPPORTED, "the adjoint covers least-squares coefficients");
     FHD_REQUIRE(fp.materialize, FHD_EINVAL, "internal: adjoint plan must materialise weights");
     const long long Np = (long long)fp.H * fp.Wp;
     float* planes = ws.take<float>(plane_floats(fp));
+    // with the forward's saved intermediates: its row-filtered planes of
+    // c_l [f, 1] (the first row pass below) and its C (and B) planes (the
+    // weights pass) are reused
     float* Bpl = ws.take<float>((size_t)fp.K * Np);
     float* Cpl = ws.take<float>((size_t)fp.K * Np);
+    if (sv != nullptr) {
+        Cpl = sv->C;
+        if (sv->B != nullptr) Bpl = sv->B;
+    }
     float* beta = ws.take<float>((size_t)fp.K * Np);
     float* gamma = ws.take<float>((size_t)fp.K * Np);
     const int nb = (int)((fp.N + RT - 1) / RT);
@@ -2577,7 +2614,9 @@ void adjoint_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, con
     // planes: the row passes form c and b per halo pixel as the forward row
     // pass does, and the final kernel recomputes b.
     const bool inl = fp.rho <= RHO_INLINE && fp.K <= KMAX_INLINE;
-    {
+    FHD_REQUIRE(sv == nullptr || inl == (sv->B == nullptr), FHD_EINVAL,
+                "internal: saved planes were written for the other weights layout");
+    if (sv == nullptr) {
         const int npx = weights_fp32_npx(fp.K);
         const size_t lds = weights_fp32_lds(fp.K, fp.rho, npx);
         FHD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(weights_fp32),
@@ -2609,12 +2648,18 @@ void adjoint_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, con
     const int per = (gx * gy + 7) / 8;
     a.xcd_groups = per;
     const dim3 cg(per * 8);
-    // dL/db_l from the recombination: recompute Q_l = w * (c_l [f, 1])
+    // dL/db_l from the recombination: Q_l = w * (c_l [f, 1]), its row half
+    // saved by the forward call or recomputed here
     a.fmode = 0;
     a.factor_b = 0;
-    hipEvent_t t0 = c.stage_begin();
-    hipLaunchKernelGGL(rowk, rg, dim3(RT), lds, st, a);
-    c.stage_end(FHD_STAGE_ROW, t0);
+    hipEvent_t t0 = nullptr;
+    if (sv != nullptr) {
+        a.planes = sv->planes;
+    } else {
+        t0 = c.stage_begin();
+        hipLaunchKernelGGL(rowk, rg, dim3(RT), lds, st, a);
+        c.stage_end(FHD_STAGE_ROW, t0);
+    }
     t0 = c.stage_begin();
     if (with_s) {
         // beta_l, and the first half of (d omega / d sigma_s) = w' (x) w + w (x) w':
@@ -2624,11 +2669,13 @@ void adjoint_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, con
         c.stage_end(FHD_STAGE_COL, t0);
         // the second half: row derivative taps, then the column taps, added
         FA ad = a;
+        ad.planes = planes;
         for (int j = 0; j <= fp.S; ++j) ad.w[j] = a.wd[j];
         t0 = c.stage_begin();
         hipLaunchKernelGGL(rowk, rg, dim3(RT), lds, st, ad);
         c.stage_end(FHD_STAGE_ROW, t0);
         FA ab = a;
+        ab.planes = planes;
         ab.beta = betas;
         ab.betas = nullptr;
         ab.bacc = 1;
@@ -2639,6 +2686,7 @@ void adjoint_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, con
     }
     c.stage_end(FHD_STAGE_COL, t0);
     // the adjoint convolution of dL/dQ_l = b_l Y
+    a.planes = planes;
     a.fmode = 1;
     a.factor_b = 1;
     t0 = c.stage_begin();
@@ -2705,7 +2753,7 @@ size_t adjoint_batch_workspace(int B, const FilterPlan* plans) {
 void adjoint_passes_batch(Ctx& c, Arena& ws, int B, const FilterPlan* plans, const float* const* f,
                           const float* const* guide, const FilterConsts* kc, const float* const* Md,
                           const float* const* out, const float* const* den, const float* const* gout,
-                          float* const* gradf, float* const* gradp, double* sig_dev) {
+                          float* const* gradf, float* const* gradp, double* sig_dev, const SavedPlanes* sv) {
     const int S = plans[0].S;
     std::vector<FA> fas(3 * (size_t)B);
     std::vector<int> pre(4 * (size_t)(B + 1), 0);
@@ -2728,6 +2776,7 @@ void adjoint_passes_batch(Ctx& c, Arena& ws, int B, const FilterPlan* plans, con
         a.P = kc[b].P;
         a.planes = ws.take<float>(plane_floats(fp));
         float* Cpl = ws.take<float>((size_t)fp.K * Np);
+        if (sv != nullptr) Cpl = sv[b].C;
         a.beta = ws.take<float>((size_t)fp.K * Np);
         a.gamma = ws.take<float>((size_t)fp.K * Np);
         a.gout = gout[b];
@@ -2756,6 +2805,7 @@ void adjoint_passes_batch(Ctx& c, Arena& ws, int B, const FilterPlan* plans, con
         a.fmode = 0;
         a.factor_b = 0;
         fas[b] = a;                 // first row pass, BETA column pass
+        if (sv != nullptr) fas[b].planes = sv[b].planes;  // the forward's row-filtered planes
         a.fmode = 1;
         a.factor_b = 1;
         fas[B + b] = a;             // second row pass
@@ -2784,19 +2834,25 @@ void adjoint_passes_batch(Ctx& c, Arena& ws, int B, const FilterPlan* plans, con
     const int* dr = dpre + (B + 1);
     const int* dc = dpre + 2 * (B + 1);
     const int* df = dpre + 3 * (B + 1);
-    FHD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(weights_fp32_batch),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)wlds));
-    hipEvent_t t0 = c.stage_begin();
-    hipLaunchKernelGGL(weights_fp32_batch, dim3(pre_w[B]), dim3(npx), wlds, st, fa2, dw, B);
-    c.stage_end(FHD_STAGE_WEIGHTS, t0);
-    FHD_HIP(hipGetLastError());
+    hipEvent_t t0 = nullptr;
+    if (sv == nullptr) {  // else the forward's C planes
+        FHD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(weights_fp32_batch),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)wlds));
+        t0 = c.stage_begin();
+        hipLaunchKernelGGL(weights_fp32_batch, dim3(pre_w[B]), dim3(npx), wlds, st, fa2, dw, B);
+        c.stage_end(FHD_STAGE_WEIGHTS, t0);
+        FHD_HIP(hipGetLastError());
+    }
     BatchFn rowk = dispatch().rowb[S];
     FHD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(rowk), hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)rlds));
-    // dL/db_l from the recombination: recompute Q_l = w * (c_l [f, 1])
-    t0 = c.stage_begin();
-    hipLaunchKernelGGL(rowk, dim3(pre_r[B]), dim3(RT), rlds, st, fa0, dr, B);
-    c.stage_end(FHD_STAGE_ROW, t0);
+    // dL/db_l from the recombination: Q_l = w * (c_l [f, 1]), its row half
+    // saved by the forward call or recomputed here
+    if (sv == nullptr) {
+        t0 = c.stage_begin();
+        hipLaunchKernelGGL(rowk, dim3(pre_r[B]), dim3(RT), rlds, st, fa0, dr, B);
+        c.stage_end(FHD_STAGE_ROW, t0);
+    }
     t0 = c.stage_begin();
     hipLaunchKernelGGL(dispatch().adjb[S][AM_BETA], dim3(pre_c[B]), dim3(RT), 0, st, fa0, dc, B);
     c.stage_end(FHD_STAGE_COL, t0);

@@ -140,6 +140,6 @@ def test_batch_rejects_gaps(fhd):
     Oa = (ctypes.c_longlong * 2)(0, 60)   # a gap of 10 pixels
     ctx = fhd._ctx(0)
     st = lib.fhd_filter_batch(ctx, 2, Ha, Wa, Oa, ctypes.c_void_p(x.data_ptr()), 3, ctypes.c_void_p(x.data_ptr()),
-                              3, ctypes.byref(p), ctypes.c_void_p(o.data_ptr()), None, None, None, None)
+                              3, ctypes.byref(p), ctypes.c_void_p(o.data_ptr()), None, None, None, None, None, 0)
     assert st == fhd.FHD_EINVAL
     assert b"back to back" in lib.fhd_last_error(ctx)

@@ -251,7 +251,7 @@ def test_invalid_arguments(fhd):
         ctx = fhd._ctx(0)
         fhd._check(fhd.load().fhd_filter(ctx, fhd._dev(f, "f"), 3, fhd._dev(g, "g"), 3, 16, 16,
                                          __import__("ctypes").byref(p), fhd._dev(f, "out"),
-                                         None, None, None), ctx)
+                                         None, None, None, None, 0), ctx)
 
 
 def test_c1_full_size_sampled(fhd):
