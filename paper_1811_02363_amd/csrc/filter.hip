@@ -1970,10 +1970,13 @@ size_t plane_floats(const FilterPlan& fp) {
 
 // Row-pass run length: the halo run tx + 2S fits the 256 threads when the
 // radius allows, so the per-pixel coefficient work is one round.
-int row_tx(int K, int S, int R) {
+int row_tx(int K, int S, int R, int W) {
     int tx = (RT - 2 * S) / R * R;
     if (tx < 64) tx = K <= 32 ? 256 : 128;
-    return tx;
+    // the same number of runs per row, of (nearly) equal length: no short
+    // run at the right end of the row
+    const int runs = (W + tx - 1) / tx;
+    return std::min(tx, (W + runs * R - 1) / (runs * R) * R);
 }
 
 size_t row_lds_bytes(const FilterPlan& fp, int tx) {
@@ -2374,7 +2377,7 @@ void filter_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, cons
     // window with every tap 1); the generic kernels cover the rest
     const bool unrolled = fp.S >= 1 && fp.S <= MAXS_T;
     const int rR = unrolled ? R_ROW : 16;
-    int tx = row_tx(fp.K, fp.S, rR);
+    int tx = row_tx(fp.K, fp.S, rR, fp.W);
     size_t lds = row_lds_bytes(fp, tx);
     while (lds > 150 * 1024 && tx > 4 * rR) {
         tx = std::max(4 * rR, tx / 2 / rR * rR);
@@ -2458,7 +2461,7 @@ void filter_passes_batch(Ctx& c, Arena& ws, int B, const FilterPlan* plans, cons
         a.Csave = sv != nullptr ? sv[b].C : nullptr;
         a.out = out[b];
         a.den = den ? den[b] : nullptr;
-        int tx = row_tx(fp.K, fp.S, R_ROW);
+        int tx = row_tx(fp.K, fp.S, R_ROW, fp.W);
         size_t l = row_lds_bytes(fp, tx);
         while (l > 150 * 1024 && tx > 4 * R_ROW) {
             tx = std::max(4 * R_ROW, tx / 2 / R_ROW * R_ROW);
@@ -2631,7 +2634,7 @@ void adjoint_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, con
     a.Cpl = inl ? nullptr : Cpl;   // row passes: null = factors formed inline
     FilterPlan rp = fp;
     rp.materialize = !inl;
-    int tx = row_tx(fp.K, fp.S, R_ROW);
+    int tx = row_tx(fp.K, fp.S, R_ROW, fp.W);
     size_t lds = row_lds_bytes(rp, tx);
     while (lds > 150 * 1024 && tx > 4 * R_ROW) {
         tx = std::max(4 * R_ROW, tx / 2 / R_ROW * R_ROW);
@@ -2789,7 +2792,7 @@ void adjoint_passes_batch(Ctx& c, Arena& ws, int B, const FilterPlan* plans, con
         a.Cpl = nullptr;
         FilterPlan rp = fp;
         rp.materialize = false;
-        int tx = row_tx(fp.K, fp.S, R_ROW);
+        int tx = row_tx(fp.K, fp.S, R_ROW, fp.W);
         size_t l = row_lds_bytes(rp, tx);
         while (l > 150 * 1024 && tx > 4 * R_ROW) {
             tx = std::max(4 * R_ROW, tx / 2 / R_ROW * R_ROW);
