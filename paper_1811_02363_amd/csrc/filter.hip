@@ -231,6 +231,18 @@ __device__ __forceinline__ bool row_halo(const FA& a, int S, int by, int& y, int
     return true;
 }
 
+// The coefficients c_l of the block's own pixels (halo index S + h), kept
+// for the adjoint when the call saves its intermediates.
+__device__ __forceinline__ void row_save_coefs(const FA& a, int y, int x0, int S, int csp, const float* cs) {
+    if (a.Csave == nullptr) return;
+    const int w = min(a.tx, a.W - x0);
+    float* dst = a.Csave + (long long)y * a.Wp + x0;
+    for (int t = threadIdx.x; t < a.K * w; t += RT) {
+        const int l = t / w, h = t - l * w;
+        dst[(long long)l * a.Np + h] = cs[l * csp + pidx(S + h)];
+    }
+}
+
 // Gaussian row pass, radius S known at compile time: each task filters R
 // outputs of one cluster from a register window of R + 2S inputs.
 template <int S>
@@ -248,15 +260,7 @@ __device__ __forceinline__ void row_gauss_body(const FA& a, int bx, int by) {
     float* smu = fs + (a.n + 1) * csp;
     float* sP = smu + a.K * RHO_INLINE;
     row_factors(a, y, x0, hw, csp, cs, fs, smu, sP);
-    if (a.Csave != nullptr) {
-        // the coefficients c_l of this block's own pixels, kept for the adjoint
-        const int w = min(a.tx, a.W - x0);
-        float* dst = a.Csave + (long long)y * a.Wp + x0;
-        for (int t = threadIdx.x; t < a.K * w; t += RT) {
-            const int l = t / w, h = t - l * w;
-            dst[(long long)l * a.Np + h] = cs[l * csp + pidx(S + h)];
-        }
-    }
+    row_save_coefs(a, y, x0, S, csp, cs);
     const int nseg = a.tx / R;
     const int n = a.n;
     for (int task = threadIdx.x; task < a.K * nseg; task += RT) {
@@ -362,14 +366,14 @@ __global__ __launch_bounds__(RT) void row_generic(FA a) {
         auto U = [&](int h) { return (ch < n || a.fmode != 0) ? cl[pidx(h)] * fc[pidx(h)] : cl[pidx(h)]; };
         float o[R];
         const int h0 = seg * R;  // halo index of the window start for output x
-        if (BOX) {
-            float s = 0.0f;
-            for (int q = 0; q <= 2 * S; ++q) s += U(h0 + q);
-            o[0] = s;
+        if (BOX) {  // running sum in FP64, as in row_box
+            double s = 0.0;
+            for (int q = 0; q <= 2 * S; ++q) s += (double)U(h0 + q);
+            o[0] = (float)s;
 #pragma unroll
             for (int t = 1; t < R; ++t) {
-                s += U(h0 + t + 2 * S) - U(h0 + t - 1);
-                o[t] = s;
+                s += (double)U(h0 + t + 2 * S) - (double)U(h0 + t - 1);
+                o[t] = (float)s;
             }
         } else {
 #pragma unroll
@@ -382,6 +386,162 @@ __global__ __launch_bounds__(RT) void row_generic(FA a) {
         float* dst = a.planes + ((long long)l * (n + 1) + ch) * a.Pp + (long long)(y + S) * a.Wp;
         store_row(a, dst, x, o, R);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Box row pass, any radius: the window sums of u = g_l [f, 1] along the halo
+// run as running sums, the O(1) box convolution of Sec. II-C.  A wave takes
+// CH_BOX vector entries of one cluster l (one read of g_l serves them all,
+// and their scans are independent); lane i takes the RB_BOX consecutive
+// outputs o = c0 + RB_BOX i + t of a chunk of 64 RB_BOX.  With the
+// differences d(o) = u(o + 2S) - u(o - 1), the window sum at o is the sum at
+// the chunk's first output plus the inclusive prefix of d over the chunk: a
+// scan within the lane, then one across the wave with DPP row shifts and row
+// broadcasts.  The first window sum is a wave reduction of u(0 .. 2S); each
+// chunk hands its last sum to the next.  The work per output does not grow
+// with S.  The sums run in FP64 (the vector units issue FP64 adds at the
+// FP32 rate; the differences of FP32 products are exact in FP64) and each
+// output is rounded to FP32 once, so a window sum carries the rounding of its
+// own terms only, not that of the larger sums the scan passed on its way.
+constexpr int RB_BOX = 4;
+constexpr int CH_BOX = 4;
+
+// v of the lane that the DPP control CTRL names; 0 where that lane lies
+// outside the row (or the wave) or the lane's row is not in the mask ROWS
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_in(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROWS, 0xF, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROWS, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// inclusive prefix sums over the 64 lanes of the wave (all lanes active), of
+// CH_BOX independent values per lane
+__device__ __forceinline__ void wave_scan(double (&v)[CH_BOX]) {
+#pragma unroll
+    for (int c = 0; c < CH_BOX; ++c) v[c] += dpp_in<0x111, 0xF>(v[c]);  // row_shr:1
+#pragma unroll
+    for (int c = 0; c < CH_BOX; ++c) v[c] += dpp_in<0x112, 0xF>(v[c]);  // row_shr:2
+#pragma unroll
+    for (int c = 0; c < CH_BOX; ++c) v[c] += dpp_in<0x114, 0xF>(v[c]);  // row_shr:4
+#pragma unroll
+    for (int c = 0; c < CH_BOX; ++c) v[c] += dpp_in<0x118, 0xF>(v[c]);  // row_shr:8: prefix within rows of 16
+#pragma unroll
+    for (int c = 0; c < CH_BOX; ++c) v[c] += dpp_in<0x142, 0xA>(v[c]);  // row_bcast:15: rows 1, 3 add rows 0, 2
+#pragma unroll
+    for (int c = 0; c < CH_BOX; ++c) v[c] += dpp_in<0x143, 0xC>(v[c]);  // row_bcast:31: rows 2, 3 add lane 31
+}
+
+__device__ __forceinline__ double lane63(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 63);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ __forceinline__ void row_box_body(const FA& a, int bx, int by) {
+    extern __shared__ float lds[];
+    const int S = a.S;
+    const int x0 = bx * a.tx;
+    int y;
+    if (row_halo(a, S, by, y, x0)) return;
+    const int hw = a.tx + 2 * S;
+    const int csp = pidx(hw - 1) + 1;
+    float* cs = lds;
+    float* fs = cs + a.K * csp;
+    float* smu = fs + (a.n + 1) * csp;
+    float* sP = smu + a.K * RHO_INLINE;
+    row_factors(a, y, x0, hw, csp, cs, fs, smu, sP);
+    row_save_coefs(a, y, x0, S, csp, cs);
+    const int n = a.n, w = min(a.tx, a.W - x0);
+    const int lane = threadIdx.x & 63;
+    const int chunks = (n + 1 + CH_BOX - 1) / CH_BOX;
+    const long long rowp = (long long)(y + S) * a.Wp + x0;
+    for (int task = threadIdx.x >> 6; task < a.K * chunks; task += RT / 64) {  // uniform per wave
+        const int l = task / chunks, e0 = (task - l * chunks) * CH_BOX;
+        const float* cl = cs + l * csp;
+        // u of entry e0 + c at halo index h: g_l f_c, or g_l for the constant
+        // last entry 1 of the forward vector (entries past n read as 0)
+        auto U = [&](double (&u)[CH_BOX], int h) {
+            const int ph = pidx(h);
+            const float g = cl[ph];
+#pragma unroll
+            for (int c = 0; c < CH_BOX; ++c) {
+                const int e = e0 + c;
+                const float v = e > n ? 0.0f : (e < n || a.fmode != 0) ? g * fs[e * csp + ph] : g;
+                u[c] = (double)v;
+            }
+        };
+        double carry[CH_BOX];
+#pragma unroll
+        for (int c = 0; c < CH_BOX; ++c) carry[c] = 0.0;
+        for (int q = lane; q <= 2 * S; q += 64) {
+            double u[CH_BOX];
+            U(u, q);
+#pragma unroll
+            for (int c = 0; c < CH_BOX; ++c) carry[c] += u[c];
+        }
+        wave_scan(carry);
+#pragma unroll
+        for (int c = 0; c < CH_BOX; ++c) carry[c] = lane63(carry[c]);  // the window sums at output 0
+        float* dst = a.planes + ((long long)l * (n + 1) + e0) * a.Pp + rowp;
+        for (int c0 = 0; c0 < w; c0 += 64 * RB_BOX) {
+            const int ob = c0 + lane * RB_BOX;
+            double d[RB_BOX][CH_BOX];
+#pragma unroll
+            for (int t = 0; t < RB_BOX; ++t) {
+                const int o = ob + t;
+                if (o >= 1 && o < w) {
+                    double ui[CH_BOX], uo[CH_BOX];
+                    U(ui, o + 2 * S);
+                    U(uo, o - 1);
+#pragma unroll
+                    for (int c = 0; c < CH_BOX; ++c) d[t][c] = ui[c] - uo[c];
+                } else {
+#pragma unroll
+                    for (int c = 0; c < CH_BOX; ++c) d[t][c] = 0.0;
+                }
+                if (t > 0) {
+#pragma unroll
+                    for (int c = 0; c < CH_BOX; ++c) d[t][c] += d[t - 1][c];
+                }
+            }
+            double incl[CH_BOX];
+#pragma unroll
+            for (int c = 0; c < CH_BOX; ++c) incl[c] = d[RB_BOX - 1][c];
+            wave_scan(incl);
+            static_assert(RB_BOX == 4, "one float4 store per lane and entry");
+#pragma unroll
+            for (int c = 0; c < CH_BOX; ++c) {
+                const double base = carry[c] + dpp_in<0x138, 0xF>(incl[c]);  // wave_shr:1: the lanes below
+                float o4[RB_BOX];
+#pragma unroll
+                for (int t = 0; t < RB_BOX; ++t) o4[t] = (float)(base + d[t][c]);
+                if (e0 + c <= n) {
+                    float* dp = dst + (long long)c * a.Pp;
+                    if (ob + RB_BOX <= w && (a.Wp & 3) == 0) {
+                        *reinterpret_cast<float4*>(dp + ob) = make_float4(o4[0], o4[1], o4[2], o4[3]);
+                    } else {
+#pragma unroll
+                        for (int t = 0; t < RB_BOX; ++t)
+                            if (ob + t < w) dp[ob + t] = o4[t];
+                    }
+                }
+                carry[c] += lane63(incl[c]);
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(RT) void row_box(FA a) { row_box_body(a, (int)blockIdx.x, (int)blockIdx.y); }
+
+__global__ __launch_bounds__(RT) void row_box_batch(const FA* __restrict__ fas, const int* __restrict__ pre, int B) {
+    int b;
+    const int t = batch_block(pre, B, b);
+    const FA& a = fas[b];
+    const int gx = (a.W + a.tx - 1) / a.tx;
+    row_box_body(a, t % gx, t / gx);
 }
 
 // ---------------------------------------------------------------------------
@@ -548,13 +708,64 @@ struct PlaneSeq {
     }
 };
 
-template <int S, int MODE>
-__device__ __forceinline__ void col_gauss_body(const FA& a, int blk) {
-    constexpr int R = R_COL;
-    constexpr int TY = TYC;
-    constexpr int ROWS = TY + 2 * S;
-    constexpr int PER = (ROWS * TXC + RT - 1) / RT;  // staged values per thread and plane
-    constexpr int WIN = R + 2 * S;
+// The 1-D window of the column pass, as a policy of col_body: R outputs per
+// thread, tiles of TY rows, PER staged values per thread and plane (the tile
+// plus its 2S halo rows), and filter(), which forms a thread's R window sums
+// from its column of the staged tile (tile row q = image row y0 - S + q).
+//
+// ColFir: taps w[|j|] at radius S known at compile time (Gaussian, or the box
+// as unit taps), from a register window of R + 2S inputs.
+template <int S>
+struct ColFir {
+    static constexpr int R = R_COL;
+    static constexpr int TY = TYC;
+    static constexpr int PER = ((TY + 2 * S) * TXC + RT - 1) / RT;
+    __device__ static int rows(const FA&) { return TY + 2 * S; }
+    __device__ static void filter(const FA& a, const float* col, float (&s)[R]) {
+        constexpr int WIN = R + 2 * S;
+        float win[WIN];
+#pragma unroll
+        for (int q = 0; q < WIN; ++q) win[q] = col[q * TXC];
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            float v = a.w[0] * win[t + S];
+#pragma unroll
+            for (int j = 1; j <= S; ++j) v = fmaf(a.w[j], win[t + S - j] + win[t + S + j], v);
+            s[t] = v;
+        }
+    }
+};
+
+// ColBox: the box window of any radius S <= SB as a running sum down the
+// column (Sec. II-C): the first window sum directly, then one add and one
+// subtract per output, in FP64 (as in the box row pass: each output carries
+// the rounding of its own window's terms only).
+template <int SB>
+struct ColBox {
+    static constexpr int R = R_COL;
+    static constexpr int TY = TYC;
+    static constexpr int PER = ((TY + 2 * SB) * TXC + RT - 1) / RT;
+    __device__ static int rows(const FA& a) { return TY + 2 * a.S; }
+    __device__ static void filter(const FA& a, const float* col, float (&s)[R]) {
+        const int S2 = 2 * a.S;
+        double v = 0.0;
+#pragma unroll 4
+        for (int q = 0; q <= S2; ++q) v += (double)col[q * TXC];
+        s[0] = (float)v;
+#pragma unroll
+        for (int t = 1; t < R; ++t) {
+            v += (double)col[(t + S2) * TXC] - (double)col[(t - 1) * TXC];
+            s[t] = (float)v;
+        }
+    }
+};
+
+template <class F, int MODE>
+__device__ __forceinline__ void col_body(const FA& a, int blk) {
+    constexpr int R = F::R;
+    constexpr int TY = F::TY;
+    constexpr int PER = F::PER;  // staged values per thread and plane
+    const int ROWS = F::rows(a);
     __shared__ float tbuf[PER * RT];
     extern __shared__ float sp[];
     const ColTile tile = col_tile(a, TY, blk);
@@ -596,17 +807,7 @@ __device__ __forceinline__ void col_gauss_body(const FA& a, int blk) {
         int nph = ph, ng = sg, nl = sl, nc = sc;
         const bool more = seq.next(nph, ng, nl, nc);
         if (more) fetch(plane_index(n, ng, nl, nc), pre);
-        const float* col = tbuf + ly0 * TXC + lx;
-        float win[WIN];
-#pragma unroll
-        for (int q = 0; q < WIN; ++q) win[q] = col[q * TXC];
-#pragma unroll
-        for (int t = 0; t < R; ++t) {
-            float v = a.w[0] * win[t + S];
-#pragma unroll
-            for (int j = 1; j <= S; ++j) v = fmaf(a.w[j], win[t + S - j] + win[t + S + j], v);
-            s[t] = v;
-        }
+        F::filter(a, tbuf + ly0 * TXC + lx, s);
         // one LDS copy of a plane: the next plane waits in registers while
         // this one is filtered
         __syncthreads();
@@ -678,7 +879,7 @@ __device__ __forceinline__ void col_gauss_body(const FA& a, int blk) {
 
 template <int S, int MODE>
 __global__ __launch_bounds__(RT) void col_gauss(FA a) {
-    col_gauss_body<S, MODE>(a, (int)blockIdx.x);
+    col_body<ColFir<S>, MODE>(a, (int)blockIdx.x);
 }
 
 template <int S, int MODE>
@@ -686,7 +887,19 @@ __global__ __launch_bounds__(RT) void col_gauss_batch(const FA* __restrict__ fas
                                                       int B) {
     int b;
     const int t = batch_block(pre, B, b);
-    col_gauss_body<S, MODE>(fas[b], t);
+    col_body<ColFir<S>, MODE>(fas[b], t);
+}
+
+template <int SB, int MODE>
+__global__ __launch_bounds__(RT) void col_box(FA a) {
+    col_body<ColBox<SB>, MODE>(a, (int)blockIdx.x);
+}
+
+template <int SB, int MODE>
+__global__ __launch_bounds__(RT) void col_box_batch(const FA* __restrict__ fas, const int* __restrict__ pre, int B) {
+    int b;
+    const int t = batch_block(pre, B, b);
+    col_body<ColBox<SB>, MODE>(fas[b], t);
 }
 
 // Column pass for any radius (box as a running sum, Gaussian tap by tap),
@@ -729,14 +942,14 @@ __global__ __launch_bounds__(RT) void col_generic(FA a) {
                     tb[e] = src[(long long)(e / TXC) * a.Wp + (e & (TXC - 1))];
                 __syncthreads();
                 const float* col = tb + ly0 * TXC + lx;  // tile row ly0 + q = image row y0 - S + q
-                if (BOX) {
-                    float s = 0.0f;
-                    for (int q = 0; q <= 2 * S; ++q) s += col[q * TXC];
-                    acc[c][0] = fmaf(hl[0], s, acc[c][0]);
+                if (BOX) {  // running sum in FP64, as in ColBox
+                    double s = 0.0;
+                    for (int q = 0; q <= 2 * S; ++q) s += (double)col[q * TXC];
+                    acc[c][0] = fmaf(hl[0], (float)s, acc[c][0]);
 #pragma unroll
                     for (int t = 1; t < R; ++t) {
-                        s += col[(t + 2 * S) * TXC] - col[(t - 1) * TXC];
-                        acc[c][t] = fmaf(hl[t], s, acc[c][t]);
+                        s += (double)col[(t + 2 * S) * TXC] - (double)col[(t - 1) * TXC];
+                        acc[c][t] = fmaf(hl[t], (float)s, acc[c][t]);
                     }
                 } else {
 #pragma unroll
@@ -1914,6 +2127,39 @@ const Dispatch& dispatch() {
     return d;
 }
 
+// Box windows as running sums (row_box, col_box) or as the unit-tap FIR
+// kernels, whichever pass is faster at the radius (measured on 2048 x 2048
+// RGB and 1024 x 1024 16-d guides, K 32): the FIR row pass wins below radius
+// 26, where its few taps hide behind the coefficient work of the pass, the
+// FIR column pass below radius 8.  Beyond the unrolled radii the running
+// sums replace the generic tap-by-tap kernels; col_box covers radii up to
+// COL_BOX_MAX_S, col_generic the rest.
+constexpr int ROW_BOX_MIN_S = 26;
+constexpr int COL_BOX_MIN_S = 8;
+constexpr int COL_BOX_MAX_S = 64;
+
+bool box_rows(const FilterPlan& fp) { return fp.spatial == FHD_SPATIAL_BOX && fp.S >= ROW_BOX_MIN_S; }
+bool box_cols(const FilterPlan& fp) {
+    return fp.spatial == FHD_SPATIAL_BOX && fp.S >= COL_BOX_MIN_S && fp.S <= COL_BOX_MAX_S;
+}
+
+// Radius tiers of the column running sum (the staged tile has TYC + 2 SB
+// rows).
+
+KernFn col_box_kernel(int S, int mode) {
+    static const KernFn k[3][3] = {{col_box<16, WM_INLINE>, col_box<16, WM_PLANES>, col_box<16, WM_HARD>},
+                                   {col_box<32, WM_INLINE>, col_box<32, WM_PLANES>, col_box<32, WM_HARD>},
+                                   {col_box<COL_BOX_MAX_S, WM_INLINE>, col_box<COL_BOX_MAX_S, WM_PLANES>,
+                                    col_box<COL_BOX_MAX_S, WM_HARD>}};
+    return k[S <= 16 ? 0 : S <= 32 ? 1 : 2][mode];
+}
+
+BatchFn col_box_batch_kernel(int S, bool hard) {
+    static const BatchFn k[2][2] = {{col_box_batch<16, WM_INLINE>, col_box_batch<16, WM_HARD>},
+                                    {col_box_batch<MAXS_T, WM_INLINE>, col_box_batch<MAXS_T, WM_HARD>}};
+    return k[S <= 16 ? 0 : 1][hard ? 1 : 0];
+}
+
 // The recursive Gaussian of Young and van Vliet (1995), the O(1) Gaussian
 // convolution the paper uses (Sec. II-C): q from sigma (two published
 // branches, sigma >= 0.5), the polynomial coefficients b0..b3, the gain
@@ -2387,7 +2633,9 @@ void filter_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, cons
     a.tx = tx;
     FHD_REQUIRE(fp.H + 2 * fp.S <= 65535, FHD_EUNSUPPORTED, "image height plus 2 radius exceeds 65535");
     const dim3 rg((fp.W + tx - 1) / tx, fp.H + 2 * fp.S);
-    KernFn rowk = unrolled ? dispatch().row[fp.S] : (box ? row_generic<true> : row_generic<false>);
+    KernFn rowk = box_rows(fp) ? row_box
+                  : unrolled   ? dispatch().row[fp.S]
+                               : (box ? row_generic<true> : row_generic<false>);
     FHD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(rowk),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipEvent_t tr = c.stage_begin();
@@ -2396,7 +2644,11 @@ void filter_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, cons
     FHD_HIP(hipGetLastError());
 
     // column pass + recombination
-    const int ty = unrolled ? TYC : 16 * (RT / TXC);
+    // the double-buffered tile kernels (col_body): unrolled radii, and box
+    // windows up to COL_BOX_MAX_S as running sums
+    const bool colbox = box_cols(fp);
+    const bool tiled = unrolled || colbox;
+    const int ty = tiled ? TYC : 16 * (RT / TXC);
     const int gx = (fp.W + TXC - 1) / TXC, gy = (fp.H + ty - 1) / ty;
     const int total = gx * gy;
     const int per = (total + 7) / 8;
@@ -2404,15 +2656,15 @@ void filter_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, cons
     // too few tiles to fill the chip: split each tile's channel groups over
     // several blocks (each extra part also filters the normaliser planes)
     const int groups = (fp.n + 1 + CG - 1) / CG;
-    a.gsplit = unrolled ? std::max(1, std::min(groups, 1024 / (per * 8))) : 1;
+    a.gsplit = tiled ? std::max(1, std::min(groups, 1024 / (per * 8))) : 1;
     const dim3 cg(per * 8 * a.gsplit);
     size_t clds = (fp.materialize || fp.coef == FHD_COEF_HARD) ? 0 : sizeof(float) * fp.rho * ty * TXC;
-    if (!unrolled) clds += sizeof(float) * (size_t)(ty + 2 * fp.S) * TXC;
+    if (!tiled) clds += sizeof(float) * (size_t)(ty + 2 * fp.S) * TXC;
     const int mode = fp.coef == FHD_COEF_HARD ? WM_HARD : (fp.materialize ? WM_PLANES : WM_INLINE);
     static const KernFn gen[2][3] = {
         {col_generic<false, WM_INLINE>, col_generic<false, WM_PLANES>, col_generic<false, WM_HARD>},
         {col_generic<true, WM_INLINE>, col_generic<true, WM_PLANES>, col_generic<true, WM_HARD>}};
-    KernFn colk = unrolled ? dispatch().col[fp.S][mode] : gen[box ? 1 : 0][mode];
+    KernFn colk = colbox ? col_box_kernel(fp.S, mode) : unrolled ? dispatch().col[fp.S][mode] : gen[box ? 1 : 0][mode];
     FHD_REQUIRE(clds <= 150 * 1024, FHD_EUNSUPPORTED, "column pass does not fit in LDS");
     FHD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(colk),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)clds));
@@ -2447,8 +2699,9 @@ void filter_passes_batch(Ctx& c, Arena& ws, int B, const FilterPlan* plans, cons
     size_t lds = 0;
     for (int b = 0; b < B; ++b) {
         const FilterPlan& fp = plans[b];
-        FHD_REQUIRE(filter_batch_supported(fp) && fp.S == S && (fp.coef == FHD_COEF_HARD) == hard, FHD_EINVAL,
-                    "internal: batch plans differ");
+        FHD_REQUIRE(filter_batch_supported(fp) && fp.S == S && (fp.coef == FHD_COEF_HARD) == hard &&
+                        fp.spatial == plans[0].spatial,
+                    FHD_EINVAL, "internal: batch plans differ");
         FHD_REQUIRE(fp.H + 2 * fp.S <= 65535, FHD_EUNSUPPORTED, "image height plus 2 radius exceeds 65535");
         FA& a = fas[b];
         a = make_args(fp);
@@ -2487,7 +2740,7 @@ void filter_passes_batch(Ctx& c, Arena& ws, int B, const FilterPlan* plans, cons
     FHD_HIP(hipMemcpyAsync(dfa, hs, fab, hipMemcpyHostToDevice, st));
     FHD_HIP(hipMemcpyAsync(dpre, hs + align_up(fab, 256), 2 * prb, hipMemcpyHostToDevice, st));
     c.stage_done(2);
-    BatchFn rowk = dispatch().rowb[S];
+    BatchFn rowk = box_rows(plans[0]) ? row_box_batch : dispatch().rowb[S];
     FHD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(rowk), hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds));
     hipEvent_t t0 = c.stage_begin();
@@ -2496,7 +2749,7 @@ void filter_passes_batch(Ctx& c, Arena& ws, int B, const FilterPlan* plans, cons
     FHD_HIP(hipGetLastError());
     const int mode = hard ? WM_HARD : WM_INLINE;
     const size_t clds = hard ? 0 : sizeof(float) * plans[0].rho * TYC * TXC;
-    BatchFn colk = dispatch().colb[S][mode];
+    BatchFn colk = box_cols(plans[0]) ? col_box_batch_kernel(S, hard) : dispatch().colb[S][mode];
     FHD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(colk), hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)clds));
     t0 = c.stage_begin();
@@ -2644,7 +2897,7 @@ void adjoint_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, con
     a.tx = tx;
     FHD_REQUIRE(fp.H + 2 * fp.S <= 65535, FHD_EUNSUPPORTED, "image height plus 2 radius exceeds 65535");
     const dim3 rg((fp.W + tx - 1) / tx, fp.H + 2 * fp.S);
-    KernFn rowk = dispatch().row[fp.S];
+    KernFn rowk = box_rows(fp) ? row_box : dispatch().row[fp.S];  // the forward's row kernel
     FHD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(rowk), hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds));
     const int gx = (fp.W + TXC - 1) / TXC, gy = (fp.H + TYC - 1) / TYC;
@@ -2768,8 +3021,9 @@ void adjoint_passes_batch(Ctx& c, Arena& ws, int B, const FilterPlan* plans, con
     const int npx = RT;
     for (int b = 0; b < B; ++b) {
         const FilterPlan& fp = plans[b];
-        FHD_REQUIRE(adjoint_batch_supported(fp) && fp.S == S && fp.sigma_r == plans[0].sigma_r, FHD_EINVAL,
-                    "internal: batch adjoint plans differ");
+        FHD_REQUIRE(adjoint_batch_supported(fp) && fp.S == S && fp.sigma_r == plans[0].sigma_r &&
+                        fp.spatial == plans[0].spatial,
+                    FHD_EINVAL, "internal: batch adjoint plans differ");
         FHD_REQUIRE(weights_fp32_npx(fp.K) == npx, FHD_EINVAL, "internal: weights block size");
         const long long Np = (long long)fp.H * fp.Wp;
         FA a = make_args(fp);
@@ -2846,7 +3100,7 @@ void adjoint_passes_batch(Ctx& c, Arena& ws, int B, const FilterPlan* plans, con
         c.stage_end(FHD_STAGE_WEIGHTS, t0);
         FHD_HIP(hipGetLastError());
     }
-    BatchFn rowk = dispatch().rowb[S];
+    BatchFn rowk = box_rows(plans[0]) ? row_box_batch : dispatch().rowb[S];  // the forward's row kernel
     FHD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(rowk), hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)rlds));
     // dL/db_l from the recombination: Q_l = w * (c_l [f, 1]), its row half

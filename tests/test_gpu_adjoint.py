@@ -73,6 +73,7 @@ CASES = [
     (37, 53, 3, 16, 2.0, 6, 0.3, "gaussian"),
     (29, 70, 5, 48, 1.5, 4, 0.15, "gaussian"),  # K > 32: two final-kernel launches
     (33, 41, 12, 24, None, 3, 0.3, "box"),
+    (40, 47, 3, 12, None, 28, 0.3, "box"),   # the running-sum row pass
     (45, 38, 3, 8, 3.0, 9, 0.25, "gaussian"),
 ]
 

@@ -42,18 +42,26 @@ def _split(flat, sizes, C):
     return outs
 
 
-@pytest.mark.parametrize("coef", ["lsq", "hard"])
-def test_batch_equals_single_image_calls(fhd, coef):
+@pytest.mark.parametrize("spatial,coef,S", [("gaussian", "lsq", 9), ("gaussian", "hard", 9), ("box", "lsq", 9),
+                                            ("box", "hard", 9), ("box", "lsq", 28), ("box", "hard", 28)])
+def test_batch_equals_single_image_calls(fhd, spatial, coef, S):
     imgs = _images()
     dev = [torch.from_numpy(x).cuda() for x in imgs]
     flat, sizes = fhd.pack_batch(dev)
-    out, den, cen, keff = fhd.filter_batch(flat, sizes, 3, sigma_s=3.0, sigma_r=0.1, K=16, radius=9,
-                                           coef=coef, return_den=True)
+    kw = dict(sigma_s=3.0, sigma_r=0.1, K=16, radius=S, spatial=spatial, coef=coef)
+    out, den, cen, keff = fhd.filter_batch(flat, sizes, 3, return_den=True, **kw)
     outs = _split(out, sizes, 3)
     dens = _split(den, sizes, 1)
+    if spatial == "box":  # the running-sum kernels against the oracle's direct window sums
+        for b, x in enumerate(imgs):
+            c = cen[b, :keff[b]].numpy().astype(np.float64)
+            P, _, _ = oracle.pinv(oracle.kernel_matrix(c, 0.1))
+            lab = oracle.bisecting_kmeans(x, 16).labels if coef == "hard" else None
+            ref = oracle.fast_filter(x, x, c, P, None, 0.1, S, "box", coef=coef, labels=lab)[0]
+            err = float(np.abs(outs[b].cpu().numpy() - ref).max())
+            assert err < 1e-4, f"image {b}: max-abs {err:.3e} against the oracle"
     for b, x in enumerate(dev):
-        o1, d1, c1 = fhd.filter(x, sigma_s=3.0, sigma_r=0.1, K=16, radius=9, coef=coef, return_den=True,
-                                return_centers=True)
+        o1, d1, c1 = fhd.filter(x, return_den=True, return_centers=True, **kw)
         assert keff[b] == c1.shape[0]
         assert torch.equal(cen[b, :keff[b]], c1), f"image {b}: centers differ"
         assert torch.equal(outs[b], o1), f"image {b}: output differs"
@@ -79,25 +87,24 @@ def test_batch_against_oracle(fhd):
     assert worst < 1e-4
 
 
-@pytest.mark.parametrize("K", [32, 48])
-def test_batch_backward_equals_per_image(fhd, K):
+@pytest.mark.parametrize("K,spatial,S", [(32, "gaussian", 9), (48, "gaussian", 9), (32, "box", 9), (32, "box", 28)])
+def test_batch_backward_equals_per_image(fhd, K, spatial, S):
     """K 32: one launch per pass for all images; K 48: the images spread over
     streams, one adjoint each."""
     imgs = _images(1600)
     dev = [torch.from_numpy(x).cuda() for x in imgs]
     flat, sizes = fhd.pack_batch(dev)
-    out, den, cen, keff = fhd.filter_batch(flat, sizes, 3, sigma_s=3.0, sigma_r=0.1, K=K, radius=9,
-                                           return_den=True)
+    kw = dict(sigma_s=3.0, sigma_r=0.1, radius=S, spatial=spatial)
+    out, den, cen, keff = fhd.filter_batch(flat, sizes, 3, K=K, return_den=True, **kw)
     G = torch.from_numpy(np.random.default_rng(3).standard_normal(flat.numel()).astype(np.float32)).cuda()
-    gf, gg, gs = fhd.filter_batch_backward(flat, sizes, 3, cen, keff, out, den, G, sigma_s=3.0, sigma_r=0.1,
-                                           radius=9)
+    gf, gg, gs = fhd.filter_batch_backward(flat, sizes, 3, cen, keff, out, den, G, **kw)
     gfs, ggs, Gs = _split(gf, sizes, 3), _split(gg, sizes, 3), _split(G, sizes, 3)
     outs, dens = _split(out, sizes, 3), _split(den, sizes, 1)
     total = 0.0
     for b, x in enumerate(dev):
         c = cen[b, :keff[b]]
         f1, g1, s1 = fhd.filter_backward(x, x, c, outs[b].contiguous(), dens[b][0].contiguous(),
-                                         Gs[b].contiguous(), sigma_s=3.0, sigma_r=0.1, radius=9)
+                                         Gs[b].contiguous(), **kw)
         assert torch.equal(gfs[b], f1) and torch.equal(ggs[b], g1), f"image {b}: gradients differ"
         total += s1
     print(f"batch dsigma_r {gs:.10e} vs per-image sum {total:.10e}")

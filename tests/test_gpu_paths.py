@@ -1,10 +1,16 @@
 """Parity of the window forms and call paths that the workloads do not reach,
 through the C ABI, against the FP64 oracle fed the same FP32 centers.
 
-* The generic column and row kernels: the box window as a running sum and the
-  Gaussian tap by tap at radius 40 (beyond the unrolled radii 1..32), with
-  inline weights (3-d guide), materialised weight planes (12-d guide) and the
-  hard variant of eq. (17), on ragged sizes, some smaller than the window.
+* The box window (Sec. II-C) on every kernel that forms it: unit taps of the
+  FIR kernels (rows below radius 26, columns below 8), the row pass's
+  wave-scan running sum (radius 26 and above), the column running sum
+  (radii 8..64, tiers up to 16, 32 and 64) and the generic column kernel
+  beyond; rows split into several runs, ragged tiles, windows wider than the
+  image.
+* The generic Gaussian kernels (tap by tap) at radii beyond the unrolled
+  1..32, with inline weights (3-d guide), materialised weight planes (12-d
+  guide) and the hard variant of eq. (17), on ragged sizes, some smaller than
+  the window.
 * Radius 0 (the window is the pixel itself: g_hat = f wherever r_hat != 0).
 * The normaliser diagnostics of fhd_info (den_min, den_nonpos, den_small,
   nonfinite) against the returned r_hat and output, and strict mode's
@@ -54,7 +60,21 @@ def _o2(f, guide, centers, ss, sr, S, spatial, coef="lsq", labels=None, terms=Fa
 
 GENERIC = [
     # name, H, W, guide dims, K, spatial, S, sigma_s, sigma_r, coef
+    ("box_S1_inline_50x77", 50, 77, 3, 8, "box", 1, None, 0.15, "lsq"),
+    ("box_S2_planes_45x61", 45, 61, 12, 9, "box", 2, None, 0.3, "lsq"),
+    ("box_S10_inline_131x500", 131, 500, 3, 16, "box", 10, None, 0.15, "lsq"),
+    ("box_S10_planes_97x301", 97, 301, 12, 10, "box", 10, None, 0.3, "lsq"),
+    ("box_S10_hard_88x150", 88, 150, 3, 12, "box", 10, None, 0.15, "hard"),
+    ("box_S16_hard_64x64", 64, 64, 3, 7, "box", 16, None, 0.15, "hard"),
+    ("box_S17_inline_70x260", 70, 260, 3, 10, "box", 17, None, 0.15, "lsq"),
+    ("box_S26_inline_90x530", 90, 530, 3, 12, "box", 26, None, 0.15, "lsq"),
+    ("box_S28_hard_70x130", 70, 130, 3, 9, "box", 28, None, 0.15, "hard"),
+    ("box_S32_inline_100x90", 100, 90, 3, 8, "box", 32, None, 0.2, "lsq"),
+    ("box_S32_planes_40x300", 40, 300, 12, 8, "box", 32, None, 0.3, "lsq"),
     ("box_S40_inline_75x97", 75, 97, 3, 8, "box", 40, None, 0.15, "lsq"),
+    ("box_S64_inline_150x140", 150, 140, 3, 8, "box", 64, None, 0.15, "lsq"),
+    ("box_S70_planes_160x90", 160, 90, 12, 8, "box", 70, None, 0.3, "lsq"),
+    ("box_S70_hard_150x150", 150, 150, 3, 8, "box", 70, None, 0.15, "hard"),
     ("box_S40_inline_150x131", 150, 131, 3, 12, "box", 40, None, 0.12, "lsq"),
     ("box_S33_planes_90x70", 90, 70, 12, 10, "box", 33, None, 0.3, "lsq"),
     ("box_S40_hard_80x101", 80, 101, 3, 9, "box", 40, None, 0.15, "hard"),

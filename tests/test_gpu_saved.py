@@ -44,6 +44,7 @@ CASES = [
     # name, H, W, guide dims, K, spatial, S, sigma_s
     ("rgb_inline_97x131", 97, 131, 3, 16, "gaussian", 6, 2.0),
     ("box_inline_64x90", 64, 90, 3, 12, "box", 5, None),
+    ("box_rows_inline_60x150", 60, 150, 3, 12, "box", 28, None),
     ("planes_rho12_70x66", 70, 66, 12, 20, "gaussian", 4, 1.5),
     ("planes_K40_80x72", 80, 72, 3, 40, "gaussian", 5, 1.7),
 ]
