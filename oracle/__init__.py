@@ -16,7 +16,8 @@ Two independent references, both in FP64:
 Also: the hard-assignment variant eqs. (17)-(18), the patch-PCA guide for
 nonlocal means (Sec. III-C), the anisotropic range kernel (Sec. III, III-E) as a
 direct brute force and as the scaled guide the method filters, the error of
-the kernel approximation (eq. (10) at c = A^+ b, Sec. II-A), the brute force
+the kernel approximation (eq. (10) at c = A^+ b, Sec. II-A), the per-pixel
+minimisers of eq. (10) themselves (Sec. II-A's exact least squares), the brute force
 and the fast filter on a 3-D domain (Sec. III-F), the PSNR of eq. (21).
 
 The heavy loops (window sums) live in ``fhd_oracle.c`` (plain C + OpenMP),
@@ -439,7 +440,7 @@ def pinv(A, rtol=None):
     Sec. II-C), or above rtol * s_max when rtol is given.
     Returns (A_pinv, rank, s)."""
     A = np.asarray(A, dtype=np.float64)
-    U, s, Vt = np.linalg.svd(A)
+    U, s, Vt = np.linalg.svd(A, full_matrices=False)  # the kept columns are those of the full SVD
     tol = (max(A.shape) * np.finfo(np.float64).eps if rtol is None else rtol) * s[0]
     keep = s > tol
     Ap = (Vt[keep].T / s[keep]) @ U[:, keep].T
@@ -475,6 +476,8 @@ def fast_filter(f, guide, centers, P, sigma_s, sigma_r, S=None,
     (:func:`young_conv`, no radius).
     ``coef='hard'`` uses c_k(i) = 1 iff pixel i is in cluster k (eq. (17)),
     which gives eq. (18); ``labels`` must then be given.
+    ``coef='exact'`` uses the per-pixel minimisers of eq. (10) over the
+    filter's window (:func:`exact_ls`) in place of c = A^+ b of eq. (11).
     Returns (g (n,H,W), r_hat (H,W)) in FP64.  With ``return_terms`` it also
     returns the numerator v (n,H,W) of eq. (15) and the magnitudes of the
     sums that form v and r_hat, sum_k |c_k(i)| |v_k(i)| (n,H,W) and
@@ -493,6 +496,8 @@ def fast_filter(f, guide, centers, P, sigma_s, sigma_r, S=None,
     elif coef == "hard":
         C = np.zeros_like(B)
         C[np.arange(B.shape[0]), np.asarray(labels)] = 1.0
+    elif coef == "exact":
+        C = exact_ls(guide, mu, sigma_r, S, P=P)[0]
     else:
         raise ValueError(coef)
     F = f.reshape(n, -1)
@@ -643,6 +648,47 @@ def approx_error(guide, centers, sigma_r, S, P=None):
             fit = (Cimg[:, iy, ix] * Bimg[:, qy, qx]).sum(0)  # phi(x - mu_k) = b_k(q)
             err[iy, ix] += (exact - fit) ** 2
     return err, float(err.mean())
+
+
+def exact_ls(guide, centers, sigma_r, S, pixels=None, P=None):
+    """Eq. (10) solved at each pixel (Sec. II-A): c*(i) minimises
+        sum_{x in Theta_i} (phi(x - p(i)) - sum_k c_k phi(x - mu_k))^2
+    over the multiset Theta_i of the guide values of the in-image pixels of
+    the (2S+1)^2 window around i (the readings of :func:`approx_error`).
+    With the window's pixels q_1 .. q_m, row j of the design matrix M_i is
+    [phi(p(q_j) - mu_k)]_k = b(q_j) (eq. (12)'s weights at q_j) and the target
+    is y_j = phi(p(q_j) - p(i)); c*(i) = M_i^+ y_i, the minimum-norm minimiser,
+    with the pseudo-inverse of :func:`pinv` (the MATLAB default tolerance, as
+    for A^+).  ``pixels``: flat indices to solve (default: all).
+    Returns (C (len, K): c*(i); obj (len,): the minimum of eq. (10);
+    obj11 (len,): eq. (10) at the surrogate's coefficients c = A^+ b(i) of
+    eq. (11)), all FP64."""
+    p = _f64(guide)
+    rho, H, W = p.shape
+    mu = np.asarray(centers, dtype=np.float64).reshape(-1, rho)
+    K = mu.shape[0]
+    if P is None:
+        P, _, _ = pinv(kernel_matrix(mu, sigma_r))
+    P = np.asarray(P, dtype=np.float64)
+    X = p.reshape(rho, -1).T
+    B = range_weights(guide, mu, sigma_r)
+    idx = np.arange(H * W) if pixels is None else np.asarray(pixels, dtype=np.int64).ravel()
+    C = np.empty((len(idx), K))
+    obj = np.empty(len(idx))
+    obj11 = np.empty(len(idx))
+    for t, i in enumerate(idx):
+        iy, ix = divmod(int(i), W)
+        ys = np.arange(max(0, iy - S), min(H, iy + S + 1))
+        xs = np.arange(max(0, ix - S), min(W, ix + S + 1))
+        q = (ys[:, None] * W + xs[None, :]).ravel()
+        M = B[q]
+        y = phi(((X[q] - X[i]) ** 2).sum(1), sigma_r)
+        Mp, _, _ = pinv(M)
+        c = Mp @ y
+        C[t] = c
+        obj[t] = ((y - M @ c) ** 2).sum()
+        obj11[t] = ((y - M @ (P @ B[i])) ** 2).sum()
+    return C, obj, obj11
 
 
 def fast_filter_at(f, guide, centers, P, sigma_s, sigma_r, ys, xs, S=None,
