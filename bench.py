@@ -20,7 +20,8 @@ workload; beside it:
     sweep for the equal-PSNR comparison), nonlocal means at 1024x1024 (FP32,
     FP16, hard variant, K sweep), the ragged batch of 16 images (forward and
     forward + adjoint, HBM fraction), the window forms, the approximation
-    error, the 3-D domain;
+    error, the per-pixel least squares of eq. (10) against the surrogate
+    eq. (11), the 3-D domain;
   * the FP64 CPU oracle timed on the host (cpu_baseline).
 
 `--only LEG,...` runs the named legs only (for profiling); `--copy-calibration`
@@ -49,9 +50,10 @@ FP32_VECTOR_PEAK = 157.3     # TFLOP/s, MI355X published FP32 vector (packed FMA
 # written), for the kernels as they are in this tree (the assignment step:
 # the mean over all of a call's launches); None where the counters have not
 # been taken for the current version of the kernel.
-MEASURED_TRAFFIC = {"row": 2250091136, "col": 2494573909, "lloyd": 40183143}
+MEASURED_TRAFFIC = {"row": 2248301275, "col": 2506614357, "lloyd": 40183751}
 
-LEGS = ("c1", "quality", "c0", "fwd_bwd", "forms", "nlm", "batch", "window", "approx_error", "volume", "cpu")
+LEGS = ("c1", "quality", "c0", "fwd_bwd", "forms", "nlm", "batch", "window", "approx_error", "exact_ls", "volume",
+        "cpu")
 
 
 def parse():
@@ -493,6 +495,61 @@ def leg_approx_error(torch, fhd, synth):
     return legs
 
 
+def leg_exact_ls(torch, fhd, synth):
+    """Sec. II-A's comparison of the per-pixel fit eq. (10) with the surrogate
+    eq. (11), in the setting of the paper's grayscale study (256 x 256, sigma_s
+    2, sigma_r 20/255, K 4) and on the 256 x 256 RGB workload (K 16, S 9): time
+    and PSNR against the brute force of the filter with each set of
+    coefficients, the objective of eq. (10) averaged over the pixels at each
+    minimiser, and how far the surrogate's coefficients lie from the exact
+    ones (median and 90th percentile over the pixels of |A^+ b - c*| / |c*|,
+    and of both norms)."""
+    legs = {}
+    gray = synth.voronoi_rgb(256, 256, 24, 0.05, 1301)[:1].copy()
+    c0 = synth.WORKLOADS["bf_rgb_256"]
+    cases = (("gray_256", "256x256 grayscale (one Voronoi channel, noise 0.05), sigma_s 2 (S 6), sigma_r 20/255, "
+                          "K 4", gray, 4, 2.0, 20.0 / 255.0, None),
+             ("bf_rgb_256", "256x256 RGB, sigma_s 3 (S 9), sigma_r 0.1, K 16", synth.workload_input("bf_rgb_256"),
+              c0["K"], c0["sigma_s"], c0["sigma_r"], c0["S"]))
+    for name, desc, img, K, ss, sr, S in cases:
+        x = torch.from_numpy(img).cuda()
+        cen, _ = fhd.cluster(x, K)
+        kw = dict(sigma_s=ss, sigma_r=sr, radius=S)
+        ref = fhd.bruteforce(x, x, **kw)
+        row = {"workload": desc, "K_eff": int(cen.shape[0]),
+               "brute_force_ms": round(timed(torch, lambda: fhd.bruteforce(x, x, **kw), 3), 3)}
+        for coef, key in (("lsq", "eq11_surrogate"), ("exact", "eq10_exact")):
+            run = lambda: fhd.filter_centers(x, x, cen, coef=coef, **kw)
+            o = run()
+            row[key] = {"ms": round(timed(torch, run, 3), 3), "psnr_vs_brute_db": round(psnr(o, ref), 2)}
+        cf, o10, o11 = fhd.exact_ls(x, cen, sigma_r=sr, sigma_s=ss, radius=S)
+        row["eq10_objective_mean"] = {"at_exact": float(f"{float(o10.double().mean()):.4e}"),
+                                      "at_surrogate": float(f"{float(o11.double().mean()):.4e}")}
+        row["exact_ls_ms"] = round(timed(torch, lambda: fhd.exact_ls(x, cen, sigma_r=sr, sigma_s=ss, radius=S,
+                                                                     obj=False, obj11=False), 3), 3)
+        # the surrogate's coefficients A^+ b(i), formed here for the comparison
+        _, P, _, _ = fhd.pinv(cen, sr)
+        X = x.reshape(x.shape[0], -1).t().double()
+        mu = torch.as_tensor(cen, dtype=torch.float64, device=x.device)
+        B = torch.exp(-((X[:, None, :] - mu[None, :, :]) ** 2).sum(-1) / (2.0 * sr * sr))
+        Cs = B @ P.to(x.device).t()
+        Ce = cf.reshape(cf.shape[0], -1).t().double()
+        rel = (Cs - Ce).norm(dim=1) / Ce.norm(dim=1).clamp_min(1e-30)
+        qs = torch.tensor([0.5, 0.9], device=x.device)
+        q = torch.quantile(rel.float(), qs)
+        ne, ns = torch.quantile(Ce.norm(dim=1).float(), qs), torch.quantile(Cs.norm(dim=1).float(), qs)
+        row["coef_rel_diff"] = {"median": float(f"{float(q[0]):.3e}"), "p90": float(f"{float(q[1]):.3e}")}
+        # the minimum-norm fit of eq. (10) keeps every singular direction above
+        # the pseudo-inverse's tolerance; in near-flat windows the K basis
+        # functions are nearly dependent over the samples and its coefficients
+        # grow large while the fit itself changes little
+        row["coef_norm"] = {"exact_median": float(f"{float(ne[0]):.3e}"), "exact_p90": float(f"{float(ne[1]):.3e}"),
+                            "surrogate_median": float(f"{float(ns[0]):.3e}"),
+                            "surrogate_p90": float(f"{float(ns[1]):.3e}")}
+        legs[name] = row
+    return legs
+
+
 def leg_volume(torch, fhd, synth):
     """Algorithm 1 on a 3-D domain: a 64 x 256 x 256 three-component vector
     field (as many voxels as the 2048^2 image has pixels), window [-6,6]^3
@@ -640,6 +697,7 @@ def main():
     run("batch", "batch", lambda: leg_batch(torch, np, fhd, oracle, synth))
     run("window", "window", lambda: leg_window(torch, fhd, x, cfg["sigma_r"], cfg["K"]))
     run("approx_error", "approx_error", lambda: leg_approx_error(torch, fhd, synth))
+    run("exact_ls", "exact_ls", lambda: leg_exact_ls(torch, fhd, synth))
     run("volume", "volume", lambda: leg_volume(torch, fhd, synth))
     run("cpu", "cpu_baseline", lambda: leg_cpu(np, synth, f, cfg))
     print(json.dumps(res))

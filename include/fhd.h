@@ -67,7 +67,13 @@ enum { FHD_SPATIAL_GAUSSIAN = 0, FHD_SPATIAL_BOX = 1, FHD_SPATIAL_YOUNG = 2 };
 enum { FHD_CONTRACT_FP32 = 0, FHD_CONTRACT_BF16 = 1, FHD_CONTRACT_FP16 = 2 };
 /* Coefficients: least squares c = A^+ b (eqs. (11)-(12)) or the hard
  * cluster indicator of eq. (17), which gives eq. (18). */
-enum { FHD_COEF_LSQ = 0, FHD_COEF_HARD = 1 };
+/* Coefficients c(i) of the approximation eq. (9): LSQ, the surrogate fit
+ * eq. (11), c = A^+ b(i) (Algorithm 1); HARD, the cluster indicator of
+ * eq. (17); EXACT, the per-pixel fit of eq. (10) over the window's own guide
+ * samples (fhd_exact_ls; an accuracy study of Sec. II-A: K <= 32, FP32
+ * contraction, Gaussian or box window, fhd_filter and fhd_filter_centers
+ * only). */
+enum { FHD_COEF_LSQ = 0, FHD_COEF_HARD = 1, FHD_COEF_EXACT = 2 };
 
 /* Limits of this library. */
 #define FHD_MAX_K 128        /* clusters */
@@ -371,6 +377,36 @@ fhd_status fhd_filter_volume(fhd_ctx* ctx, const float* f, int n, const float* g
  * cost (2S+1)^3 (rho + n) per voxel.  Enqueued on the context's stream. */
 fhd_status fhd_bruteforce_volume(fhd_ctx* ctx, const float* f, int n, const float* guide, int rho, int D, int H,
                                  int W, const fhd_params* p, float* out, float* den);
+
+/* Eq. (10) solved at every pixel (Sec. II-A): the coefficients c*(i) of
+ * the least-squares fit
+ *   min_c sum_q (phi(p(q) - p(i)) - sum_k c_k phi(p(q) - mu_k))^2,
+ * q over the in-image pixels of the (2S+1)^2 window around i (Theta_i of
+ * eq. (10), with multiplicity), taken as the minimum-norm minimiser M_i^+ y_i
+ * of the window's design matrix (rows b(q), targets phi(p(q) - p(i))), with
+ * singular values at or below max(m, K) 2^-52 s_max dropped (the tolerance
+ * of the MATLAB pinv), m the window's in-image pixels.  The paper fits over
+ * the centers instead (eq. (11)) to share one K x K pseudo-inverse across
+ * all pixels; this call gives the fit it approximates, and the objective of
+ * eq. (10) at both.
+ *   guide    device rho x H x W;  centers host K x rho FP32, 1 <= K <= 32;
+ *   p        sigma_r, pinv_rtol (for A^+ in obj11) and the window as in
+ *            fhd_approx_error (the recursive Gaussian is rejected);
+ *   coef     device K x H x W FP32 (plane k = c*_k over the image) or NULL;
+ *   obj      device H x W FP32: the minimum of eq. (10), or NULL;
+ *   obj11    device H x W FP32: eq. (10) at c = A^+ b(i), or NULL.
+ * At least one output.  FP64 throughout (a streaming Givens QR of the
+ * design matrix and a Jacobi SVD of its K x K triangle, per pixel); cost
+ * ~ (2S+1)^2 K^2 per pixel.  Enqueued on the context's stream. */
+fhd_status fhd_exact_ls(fhd_ctx* ctx, const float* guide, int rho, int H, int W, const float* centers, int K,
+                        const fhd_params* p, float* coef, float* obj, float* obj11);
+
+/* Clusters used (K_eff) by the last call on this context that clustered
+ * (fhd_filter, fhd_filter_volume, fhd_cluster, fhd_filter_batch: its last
+ * image); 0 before any.  A caller that only wants the number of centers
+ * fhd_filter wrote can skip fhd_info, whose normaliser fields cost one device
+ * reduction and a synchronisation. */
+int fhd_last_k_eff(const fhd_ctx* ctx);
 
 /* Error of the kernel approximation at each pixel's own samples (Sec. II-A):
  * the objective of eq. (10) evaluated at the coefficients the method uses,

@@ -31,7 +31,7 @@ _STATUS = {0: "FHD_OK", -1: "FHD_EINVAL", -2: "FHD_ENOMEM", -3: "FHD_EHIP",
            -4: "FHD_ENUMERIC", -5: "FHD_EUNSUPPORTED"}
 SPATIAL = {"gaussian": 0, "box": 1, "young": 2}
 CONTRACT = {"fp32": 0, "bf16": 1, "fp16": 2}
-COEF = {"lsq": 0, "hard": 1}
+COEF = {"lsq": 0, "hard": 1, "exact": 2}
 
 # Every entry point declared in include/fhd.h.
 symbols = [
@@ -39,7 +39,7 @@ symbols = [
     "fhd_workspace_size", "fhd_saved_size", "fhd_saved_size_batch", "fhd_set_workspace", "fhd_cluster", "fhd_pinv",
     "fhd_filter_centers", "fhd_filter_centers_noalloc", "fhd_filter", "fhd_filter_backward", "fhd_filter_batch",
     "fhd_filter_batch_backward", "fhd_bruteforce", "fhd_nlm_guide", "fhd_scale_guide",
-    "fhd_approx_error", "fhd_filter_volume", "fhd_bruteforce_volume",
+    "fhd_approx_error", "fhd_exact_ls", "fhd_last_k_eff", "fhd_filter_volume", "fhd_bruteforce_volume",
     "fhd_timing_enable", "fhd_timing_read", "fhd_timing_units",
 ]
 STAGES = ("cluster", "weights", "row", "col", "brute", "lloyd")
@@ -118,6 +118,8 @@ def load():
             "fhd_nlm_guide": (I, [V, V, I, I, I, I, I, V, V]),
             "fhd_scale_guide": (I, [V, V, I, ctypes.c_longlong, V, V]),
             "fhd_approx_error": (I, [V, V, I, I, I, V, I, pp, V, P(D)]),
+            "fhd_exact_ls": (I, [V, V, I, I, I, V, I, pp, V, V, V]),
+            "fhd_last_k_eff": (I, [V]),
             "fhd_filter_volume": (I, [V, V, I, V, I, I, I, I, pp, V, V, V, pi]),
             "fhd_bruteforce_volume": (I, [V, V, I, V, I, I, I, I, pp, V, V]),
             "fhd_timing_enable": (I, [V, I]),
@@ -253,15 +255,16 @@ def filter(f, guide=None, sigma_s=3.0, sigma_r=0.1, K=16, spatial="gaussian", ra
     den = torch.empty((H, W), device=f.device, dtype=torch.float32) if return_den else None
     cen = torch.zeros((K, rho), dtype=torch.float32)
     inf = Info()
-    _check(load().fhd_filter(ctx, _dev(f, "f"), n, _dev(g, "guide"), rho, H, W, ctypes.byref(p),
-                             _dev(out, "out"), ctypes.c_void_p(cen.data_ptr()),
-                             _dev(den, "den") if den is not None else None,
-                             ctypes.byref(inf) if (info or return_centers) else None, sp, sb), ctx)
+    lib = load()
+    _check(lib.fhd_filter(ctx, _dev(f, "f"), n, _dev(g, "guide"), rho, H, W, ctypes.byref(p),
+                          _dev(out, "out"), ctypes.c_void_p(cen.data_ptr()),
+                          _dev(den, "den") if den is not None else None,
+                          ctypes.byref(inf) if info else None, sp, sb), ctx)
     res = [out]
     if return_den:
         res.append(den)
     if return_centers:
-        res.append(cen[:inf.K_eff].clone())
+        res.append(cen[:lib.fhd_last_k_eff(ctx)].clone())
     if info:
         res.append(inf.as_dict())
     return res[0] if len(res) == 1 else tuple(res)
@@ -670,6 +673,34 @@ def approx_error(guide, centers, sigma_r=0.1, sigma_s=3.0, radius=None, spatial=
                                    c.shape[0], ctypes.byref(p), _dev(err, "err") if err is not None else None,
                                    ctypes.byref(m)), ctx)
     return err, m.value
+
+
+def exact_ls(guide, centers, sigma_r=0.1, sigma_s=3.0, radius=None, spatial="gaussian", pinv_rtol=0.0,
+             coef=True, obj=True, obj11=True):
+    """Eq. (10) solved at every pixel (``fhd_exact_ls``): the minimum-norm
+    least-squares coefficients over the window's own guide samples (Sec.
+    II-A), the fit that eq. (11)'s c = A^+ b(i) stands in for.  ``guide``
+    (rho, H, W) on the device, ``centers`` (K, rho), K <= 32.  Returns
+    (coef (K, H, W), obj (H, W): the minimum of eq. (10), obj11 (H, W):
+    eq. (10) at A^+ b(i)); outputs not asked for are None."""
+    if not isinstance(guide, torch.Tensor) or not guide.is_cuda or guide.dim() != 3:
+        raise FHDError(FHD_EINVAL, "guide must be a (rho, H, W) CUDA (HIP) tensor")
+    rho, H, W = guide.shape
+    c = torch.as_tensor(centers, dtype=torch.float32).detach().cpu().contiguous()
+    if c.dim() != 2 or c.shape[1] != rho:
+        raise FHDError(FHD_EINVAL, "centers must be (K, rho)")
+    K = c.shape[0]
+    ctx = _ctx(guide.device.index)
+    p = make_params(sigma_s, sigma_r, K, spatial, radius, pinv_rtol=pinv_rtol)
+    dev = dict(device=guide.device, dtype=torch.float32)
+    cf = torch.empty((K, H, W), **dev) if coef else None
+    o10 = torch.empty((H, W), **dev) if obj else None
+    o11 = torch.empty((H, W), **dev) if obj11 else None
+    _check(load().fhd_exact_ls(ctx, _dev(guide, "guide"), rho, H, W, ctypes.c_void_p(c.data_ptr()), K,
+                               ctypes.byref(p), _dev(cf, "coef") if cf is not None else None,
+                               _dev(o10, "obj") if o10 is not None else None,
+                               _dev(o11, "obj11") if o11 is not None else None), ctx)
+    return cf, o10, o11
 
 
 class ScaleGuide(torch.autograd.Function):

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libfhd.so")
-SOURCES = ["kmeans.hip", "filter.hip", "nlm.hip", "api.hip", "linalg.cpp"]
+SOURCES = ["kmeans.hip", "filter.hip", "nlm.hip", "exact_ls.hip", "api.hip", "linalg.cpp"]
 ARCH = os.environ.get("FHD_OFFLOAD_ARCH", "gfx950")
 
 COMMON = [

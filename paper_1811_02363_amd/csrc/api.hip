@@ -198,7 +198,8 @@ void check_params(const fhd_params* p, int n, int rho, int H, int W) {
     FHD_REQUIRE(p->sigma_r > 0.0f && !std::isnan(p->sigma_r), FHD_EINVAL, "sigma_r must be > 0");
     FHD_REQUIRE(p->K >= 1 && p->K <= FHD_MAX_K, FHD_EINVAL, "K must be in [1, FHD_MAX_K]");
     FHD_REQUIRE((long long)p->K <= (long long)H * W, FHD_EINVAL, "K exceeds the number of pixels");
-    FHD_REQUIRE(p->coef == FHD_COEF_LSQ || p->coef == FHD_COEF_HARD, FHD_EINVAL, "unknown coef");
+    FHD_REQUIRE(p->coef == FHD_COEF_LSQ || p->coef == FHD_COEF_HARD || p->coef == FHD_COEF_EXACT, FHD_EINVAL,
+                "unknown coef");
     FHD_REQUIRE(p->contract == FHD_CONTRACT_FP32 || p->contract == FHD_CONTRACT_BF16 ||
                     p->contract == FHD_CONTRACT_FP16,
                 FHD_EINVAL, "unknown contraction precision");
@@ -222,8 +223,24 @@ FilterPlan make_plan(const fhd_params& p, int n, int rho, int H, int W, int K) {
     fp.sigma_r = p.sigma_r;
     fp.N = (long long)H * W;
     fp.Wp = (int)align_up((size_t)W, 4);
-    fp.materialize = rho > 8 || K > 32 || p.contract != FHD_CONTRACT_FP32 || p.spatial == FHD_SPATIAL_YOUNG;
+    fp.materialize = rho > 8 || K > 32 || p.contract != FHD_CONTRACT_FP32 || p.spatial == FHD_SPATIAL_YOUNG ||
+                     p.coef == FHD_COEF_EXACT;
     return fp;
+}
+
+// The per-pixel fit of eq. (10) as the filter's coefficients: the forms the
+// kernel covers, and only the calls that take it.
+void check_exact(const fhd_params* p, int K) {
+    if (p->coef != FHD_COEF_EXACT) return;
+    FHD_REQUIRE(K <= EXACT_LS_MAX_K, FHD_EUNSUPPORTED, "coefficients from eq. (10) take K <= 32");
+    FHD_REQUIRE(p->contract == FHD_CONTRACT_FP32, FHD_EUNSUPPORTED, "coefficients from eq. (10) take the FP32 form");
+    FHD_REQUIRE(p->spatial != FHD_SPATIAL_YOUNG, FHD_EUNSUPPORTED,
+                "coefficients from eq. (10) need a finite window (Gaussian or box)");
+}
+
+void reject_exact(const fhd_params* p, const char* call) {
+    FHD_REQUIRE(p->coef != FHD_COEF_EXACT, FHD_EUNSUPPORTED,
+                std::string(call) + " does not take coefficients from eq. (10) (fhd_filter, fhd_filter_centers do)");
 }
 
 bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
@@ -736,6 +753,7 @@ fhd_status fhd_cluster(fhd_ctx* ctx, const float* guide, int rho, int H, int W, 
         kmeans_run(c, ws, guide, rho, N, K, max_iter, labels, km);
         for (size_t q = 0; q < km.centers.size(); ++q) centers[q] = (float)km.centers[q];
         if (K_eff) *K_eff = km.K_eff;
+        c.last_keff = km.K_eff;
         FHD_HIP(hipStreamSynchronize(c.stream));
         if (info) {
             std::memset(info, 0, sizeof(*info));
@@ -776,6 +794,7 @@ fhd_status fhd_filter_centers(fhd_ctx* ctx, const float* f, int n, const float* 
         FHD_REQUIRE(f && guide && centers && out, FHD_EINVAL, "NULL pointer");
         FHD_REQUIRE(K >= 1 && K <= FHD_MAX_K, FHD_EINVAL, "K must be in [1, FHD_MAX_K]");
         FHD_REQUIRE(p->coef != FHD_COEF_HARD || labels != nullptr, FHD_EINVAL, "hard coefficients need labels");
+        check_exact(p, K);
         const long long N = (long long)H * W;
         FHD_REQUIRE(!ranges_overlap(out, sizeof(float) * N * n, f, sizeof(float) * N * n) &&
                         !ranges_overlap(out, sizeof(float) * N * n, guide, sizeof(float) * N * rho) &&
@@ -837,6 +856,7 @@ fhd_status fhd_filter_centers_noalloc(fhd_ctx* ctx, const float* f, int n, const
         FHD_REQUIRE(p->coef != FHD_COEF_HARD || labels != nullptr, FHD_EINVAL, "hard coefficients need labels");
         FHD_REQUIRE(c.noalloc_scratch != nullptr && c.noalloc_pinned != nullptr, FHD_EINVAL,
                     "context was not set up for the allocation-free call");
+        reject_exact(p, "fhd_filter_centers_noalloc");
         const long long N = (long long)H * W;
         FHD_REQUIRE(!ranges_overlap(out, sizeof(float) * N * n, f, sizeof(float) * N * n) &&
                         !ranges_overlap(out, sizeof(float) * N * n, guide, sizeof(float) * N * rho) &&
@@ -886,6 +906,7 @@ fhd_status fhd_filter(fhd_ctx* ctx, const float* f, int n, const float* guide, i
                       size_t saved_bytes) {
     return guarded(ctx, [&](Ctx& c) {
         check_params(p, n, rho, H, W);
+        check_exact(p, p->K);
         FHD_REQUIRE(f && guide && out, FHD_EINVAL, "NULL pointer");
         const long long N = (long long)H * W;
         FHD_REQUIRE(!ranges_overlap(out, sizeof(float) * N * n, f, sizeof(float) * N * n) &&
@@ -924,6 +945,7 @@ fhd_status fhd_filter(fhd_ctx* ctx, const float* f, int n, const float* guide, i
         }
         const double ms_cluster = ms_since(t0);
         const int K = km.K_eff;
+        c.last_keff = K;
         std::vector<float> c32((size_t)K * rho);
         for (size_t q = 0; q < c32.size(); ++q) c32[q] = (float)km.centers[q];
         if (centers_out) std::memcpy(centers_out, c32.data(), sizeof(float) * c32.size());
@@ -1019,6 +1041,7 @@ fhd_status fhd_filter_batch(fhd_ctx* ctx, int B, const int* H, const int* W, con
     return guarded(ctx, [&](Ctx& c) {
         const std::vector<long long> cnt = batch_counts(B, H, W, px_offset);
         for (int b = 0; b < B; ++b) check_params(p, n, rho, H[b], W[b]);
+        reject_exact(p, "fhd_filter_batch");
         FHD_REQUIRE(f && guide && out, FHD_EINVAL, "NULL pointer");
         long long N = 0;
         for (long long q : cnt) N += q;
@@ -1076,6 +1099,7 @@ fhd_status fhd_filter_batch(fhd_ctx* ctx, int B, const int* H, const int* W, con
         const auto t1 = clk::now();
         parallel_for(B, [&](int b) {
             const int Kb = km[b].K_eff;
+            c.last_keff = Kb;
             std::vector<float> c32((size_t)Kb * rho);
             for (size_t q = 0; q < c32.size(); ++q) c32[q] = (float)km[b].centers[q];
             if (centers_out) std::memcpy(centers_out + (size_t)b * K * rho, c32.data(), sizeof(float) * c32.size());
@@ -1340,6 +1364,7 @@ fhd_status fhd_filter_volume(fhd_ctx* ctx, const float* f, int n, const float* g
         FHD_REQUIRE(p->spatial != FHD_SPATIAL_YOUNG, FHD_EUNSUPPORTED,
                     "volumes take the Gaussian or box window (finite, separable over [-S,S]^3)");
         FHD_REQUIRE(p->contract == FHD_CONTRACT_FP32, FHD_EUNSUPPORTED, "volumes take the FP32 form");
+        reject_exact(p, "fhd_filter_volume");
         FHD_REQUIRE(f && guide && out, FHD_EINVAL, "NULL pointer");
         const long long N = (long long)D * H * W;
         FHD_REQUIRE(!ranges_overlap(out, sizeof(float) * N * n, f, sizeof(float) * N * n) &&
@@ -1369,6 +1394,7 @@ fhd_status fhd_filter_volume(fhd_ctx* ctx, const float* f, int n, const float* g
         }
         const double ms_cluster = ms_since(t0);
         const int K = km.K_eff;
+        c.last_keff = K;
         std::vector<float> c32((size_t)K * rho);
         for (size_t q = 0; q < c32.size(); ++q) c32[q] = (float)km.centers[q];
         if (centers_out) std::memcpy(centers_out, c32.data(), sizeof(float) * c32.size());
@@ -1445,6 +1471,52 @@ fhd_status fhd_approx_error(fhd_ctx* ctx, const float* guide, int rho, int H, in
         approx_error_run(c, ws, guide, rho, H, W, centers, P32.data(), K, S, p->sigma_r, err, mean);
     });
 }
+
+fhd_status fhd_exact_ls(fhd_ctx* ctx, const float* guide, int rho, int H, int W, const float* centers, int K,
+                        const fhd_params* p, float* coef, float* obj, float* obj11) {
+    return guarded(ctx, [&](Ctx& c) {
+        FHD_REQUIRE(p != nullptr, FHD_EINVAL, "params is NULL");
+        FHD_REQUIRE(guide != nullptr && centers != nullptr, FHD_EINVAL, "NULL pointer");
+        FHD_REQUIRE(coef != nullptr || obj != nullptr || obj11 != nullptr, FHD_EINVAL, "no output requested");
+        FHD_REQUIRE(rho >= 1 && H >= 1 && W >= 1, FHD_EINVAL, "rho, H, W must be >= 1");
+        FHD_REQUIRE(rho <= FHD_MAX_RHO, FHD_EUNSUPPORTED, "rho exceeds FHD_MAX_RHO");
+        FHD_REQUIRE((long long)H * W < (1LL << 31), FHD_EUNSUPPORTED, "image has 2^31 pixels or more");
+        FHD_REQUIRE(K >= 1, FHD_EINVAL, "K must be >= 1");
+        FHD_REQUIRE(K <= EXACT_LS_MAX_K, FHD_EUNSUPPORTED, "the per-pixel least squares takes at most 32 clusters");
+        FHD_REQUIRE(p->sigma_r > 0.0f && !std::isnan(p->sigma_r), FHD_EINVAL, "sigma_r must be > 0");
+        FHD_REQUIRE(p->spatial == FHD_SPATIAL_GAUSSIAN || p->spatial == FHD_SPATIAL_BOX, FHD_EINVAL,
+                    "the window of eq. (10) needs the Gaussian (radius from sigma_s) or box spatial kernel");
+        if (p->spatial == FHD_SPATIAL_GAUSSIAN && p->radius < 0)
+            FHD_REQUIRE(p->sigma_s > 0.0f && std::isfinite(p->sigma_s), FHD_EINVAL, "sigma_s must be > 0");
+        if (p->spatial == FHD_SPATIAL_BOX) FHD_REQUIRE(p->radius >= 0, FHD_EINVAL, "the box kernel needs radius >= 0");
+        const int S = resolve_radius(*p);
+        FHD_REQUIRE(S >= 0 && S <= FHD_MAX_RADIUS, FHD_EUNSUPPORTED, "radius exceeds FHD_MAX_RADIUS");
+        const long long N = (long long)H * W;
+        FHD_REQUIRE(!ranges_overlap(coef, sizeof(float) * N * K, guide, sizeof(float) * N * rho) &&
+                        !ranges_overlap(obj, sizeof(float) * N, guide, sizeof(float) * N * rho) &&
+                        !ranges_overlap(obj11, sizeof(float) * N, guide, sizeof(float) * N * rho) &&
+                        !ranges_overlap(obj, sizeof(float) * N, coef, sizeof(float) * N * K) &&
+                        !ranges_overlap(obj11, sizeof(float) * N, coef, sizeof(float) * N * K) &&
+                        !ranges_overlap(obj, sizeof(float) * N, obj11, sizeof(float) * N),
+                    FHD_EINVAL, "outputs alias an input or each other");
+        // A^+ in FP64 (eq. (10) at the surrogate's coefficients), the centers
+        std::vector<double> A((size_t)K * K), P((size_t)K * K);
+        kernel_matrix(centers, K, rho, p->sigma_r, A.data());
+        pinv_symmetric(A.data(), K, p->pinv_rtol, P.data());
+        const size_t mb = align_up(sizeof(float) * K * rho, 256), pb = sizeof(double) * K * K;
+        Arena ws = c.arena(mb + pb + 512);
+        char* dev = ws.take<char>(mb + pb);
+        char* hs = static_cast<char*>(c.host_stage(1, mb + pb));
+        std::memcpy(hs, centers, sizeof(float) * K * rho);
+        std::memcpy(hs + mb, P.data(), pb);
+        FHD_HIP(hipMemcpyAsync(dev, hs, mb + pb, hipMemcpyHostToDevice, c.stream));
+        c.stage_done(1);
+        exact_ls_run(c, guide, rho, H, W, reinterpret_cast<const float*>(dev), K,
+                     reinterpret_cast<const double*>(dev + mb), p->sigma_r, S, coef, N, W, obj, obj11);
+    });
+}
+
+int fhd_last_k_eff(const fhd_ctx* ctx) { return ctx == nullptr ? 0 : ctx->impl.last_keff; }
 
 fhd_status fhd_scale_guide(fhd_ctx* ctx, const float* guide, int rho, long long N, const float* sigma_d,
                            float* out) {

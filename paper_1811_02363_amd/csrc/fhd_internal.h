@@ -119,6 +119,14 @@ void filter_run(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, const f
                 float* out, float* den, const SavedPlanes* sv = nullptr);
 // Device copies of one image's constants: centers (K x rho), A^+ (K x K) and
 // the contraction offset (rho), FP32, in one block of filter_consts_bytes.
+// Eq. (10) per pixel (exact_ls.hip): c*(i) into `coef` (K planes, plane
+// stride cstride, row pitch cpitch) and the objective at c* (obj) and at
+// A^+ b(i) (obj11, needs P_dev: K x K FP64); any output may be null.
+constexpr int EXACT_LS_MAX_K = 32;
+void exact_ls_run(Ctx& c, const float* guide, int rho, int H, int W, const float* mu_dev, int K,
+                  const double* P_dev, double sigma_r, int S, float* coef, long long cstride, int cpitch, float* obj,
+                  float* obj11);
+
 struct FilterConsts {
     const float* mu;
     const float* P;
@@ -235,6 +243,7 @@ struct Ctx {
 
     // stage timing (fhd_timing_enable)
     bool timing = false;
+    int last_keff = 0;  // K_eff of the last call that clustered
     std::vector<hipEvent_t> ev_pool;
     struct EvPair {
         hipEvent_t begin, end;

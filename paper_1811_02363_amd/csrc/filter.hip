@@ -2597,6 +2597,18 @@ void filter_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, cons
         FHD_HIP(hipGetLastError());
         a.Bpl = Bpl;
         a.Cpl = Cpl;
+        if (fp.coef == FHD_COEF_EXACT) {
+            // the per-pixel fit of eq. (10) replaces c = A^+ b.  The passes
+            // convolve c_l [f, 1] and recombine with b_l(i), which equals
+            // eqs. (13)-(16) only for c = A^+ b with A^+ symmetric; here they
+            // run as written: the row pass convolves b_k [f, 1] (the B planes
+            // as its factor) and the column pass recombines with c*_k(i)
+            // (the C planes as its weights).
+            exact_ls_run(c, guide, fp.rho, fp.H, fp.W, mu, fp.K, nullptr, fp.sigma_r, fp.S, Cpl, Np, fp.Wp, nullptr,
+                         nullptr);
+            a.Bpl = Cpl;
+            a.Cpl = Bpl;
+        }
     }
 
     if (fp.spatial == FHD_SPATIAL_YOUNG) {  // recursive Gaussian (materialised weights, S = 0)
