@@ -1961,81 +1961,92 @@ __global__ __launch_bounds__(RT) void weights_mfma(FA a, float* Bpl, float* Cpl,
 }
 
 // ---------------------------------------------------------------------------
-// Brute force, eqs. (1)-(2): one thread per output pixel, window read from a
-// 16 x 16-output LDS tile with halo when it fits, else from global memory.
-__global__ __launch_bounds__(RT) void brute_lds(FA a) {
-    extern __shared__ float lds[];
-    const int S = a.S, n = a.n, rho = a.rho;
-    const int T = 16, L = T + 2 * S;
-    const int bx = blockIdx.x * T, by = blockIdx.y * T;
-    const int C = rho + n;
-    for (int t = threadIdx.x; t < L * L; t += RT) {
-        const int yy = by - S + t / L, xx = bx - S + t % L;
-        const bool in = yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
-        const long long off = (long long)yy * a.W + xx;
-        for (int c = 0; c < rho; ++c) lds[c * L * L + t] = in ? a.p[(long long)c * a.N + off] : 0.0f;
-        for (int c = 0; c < n; ++c) lds[(rho + c) * L * L + t] = in ? a.f[(long long)c * a.N + off] : 0.0f;
-        if (!in) lds[C * L * L + t] = 0.0f; else lds[C * L * L + t] = 1.0f;
+// Brute force, eqs. (1)-(2), in FP32: each thread takes one column and R
+// consecutive output rows.  For each horizontal offset jx it walks the R + 2S
+// neighbour rows of its column once, loading each neighbour's guide (and
+// image) values once for all of its R outputs whose window holds that
+// neighbour; the sums stay in registers.  A wave's 64 lanes take 64
+// consecutive columns (coalesced loads, served by the caches across
+// offsets), the block's four waves consecutive groups of R rows.  RM, NM
+// bound the guide and image channels (EXACT: exactly RM, NM); SAME: the
+// image is the guide (one load serves both); beyond 32 channels (DIRECT)
+// the values are read per use instead of staged in registers.
+template <int R, int RM, int NM, bool EXACT, bool SAME>
+__global__ __launch_bounds__(RT) void brute_strip(FA a) {
+    constexpr bool DIRECT = RM > 32 || NM > 32;
+    constexpr int RS = DIRECT ? 1 : RM, NS = DIRECT || SAME ? 1 : NM;
+    const int S = a.S;
+    const int rho = EXACT ? RM : a.rho, n = EXACT ? NM : a.n;
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y0 = (blockIdx.y * (RT / 64) + (threadIdx.x >> 6)) * R;  // uniform per wave
+    if (y0 >= a.H) return;
+    const bool colin = x < a.W;
+    const int xc = colin ? x : a.W - 1;  // out-of-image lanes read a valid column and store nothing
+    float pc[R][RM], num[R][NM], eta[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const long long off = (long long)min(y0 + r, a.H - 1) * a.W + xc;
+#pragma unroll
+        for (int c = 0; c < RM; ++c) pc[r][c] = c < rho ? a.p[(long long)c * a.N + off] : 0.0f;
+#pragma unroll
+        for (int c = 0; c < NM; ++c) num[r][c] = 0.0f;
+        eta[r] = 0.0f;
     }
-    __syncthreads();
-    const int ly = threadIdx.x / T, lx = threadIdx.x % T;
-    const int y = by + ly, x = bx + lx;
-    if (y >= a.H || x >= a.W) return;
-    const int ci = (ly + S) * L + (lx + S);
-    float pc[FHD_MAX_RHO > 16 ? 16 : FHD_MAX_RHO];
-    for (int c = 0; c < rho && c < 16; ++c) pc[c] = lds[c * L * L + ci];
-    float num[16];
-    for (int c = 0; c < 16; ++c) num[c] = 0.0f;
-    float eta = 0.0f;
-    for (int jy = -S; jy <= S; ++jy) {
-        const float wy = a.w[jy < 0 ? -jy : jy];
-        const int rowi = (ly + S - jy) * L;
-        for (int jx = -S; jx <= S; ++jx) {
-            const int q = rowi + (lx + S - jx);
-            const float inside = lds[C * L * L + q];
-            float d2 = 0.0f;
-            for (int c = 0; c < rho; ++c) {
-                const float d = lds[c * L * L + q] - pc[c];
-                d2 = fmaf(d, d, d2);
+    // neighbour rows y0 - S + t inside the image
+    const int t0 = max(0, S - y0), t1 = min(R + 2 * S, a.H - y0 + S);
+    for (int jx = -S; jx <= S; ++jx) {
+        const int xx = xc - jx;
+        const bool inx = colin && xx >= 0 && xx < a.W;
+        const int xq = min(max(xx, 0), a.W - 1);
+        const float wx = a.w[jx < 0 ? -jx : jx];
+        for (int t = t0; t < t1; ++t) {
+            const long long q = (long long)(y0 - S + t) * a.W + xq;
+            float pq[RS], fq[NS];
+            if (!DIRECT) {
+#pragma unroll
+                for (int c = 0; c < RS; ++c) pq[c] = c < rho ? a.p[(long long)c * a.N + q] : 0.0f;
+                if (!SAME) {
+#pragma unroll
+                    for (int c = 0; c < NS; ++c) fq[c] = c < n ? a.f[(long long)c * a.N + q] : 0.0f;
+                }
             }
-            const float wgt = inside * wy * a.w[jx < 0 ? -jx : jx] * __expf(-d2 * a.inv2s2);
-            for (int c = 0; c < n; ++c) num[c] = fmaf(wgt, lds[(rho + c) * L * L + q], num[c]);
-            eta += wgt;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int jy = r + S - t;  // output row y0 + r minus the neighbour row
+                if (jy < -S || jy > S) continue;  // uniform
+                float d2 = 0.0f;
+#pragma unroll
+                for (int c = 0; c < RM; ++c) {
+                    if (c < rho) {
+                        const float v = DIRECT ? a.p[(long long)c * a.N + q] : pq[DIRECT ? 0 : c];
+                        const float d = v - pc[r][c];
+                        d2 = fmaf(d, d, d2);
+                    }
+                }
+                const float wgt = inx ? wx * a.w[jy < 0 ? -jy : jy] * __expf(-d2 * a.inv2s2) : 0.0f;
+#pragma unroll
+                for (int c = 0; c < NM; ++c) {
+                    if (c < n) {
+                        const float v = DIRECT ? a.f[(long long)c * a.N + q]
+                                               : (SAME ? pq[c < RS ? c : 0] : fq[c < NS ? c : 0]);
+                        num[r][c] = fmaf(wgt, v, num[r][c]);
+                    }
+                }
+                eta[r] += wgt;
+            }
         }
     }
-    const long long off = (long long)y * a.W + x;
-    for (int c = 0; c < n; ++c) a.out[(long long)c * a.N + off] = num[c] / eta;
-    if (a.den) a.den[off] = eta;
-}
-
-__global__ __launch_bounds__(RT) void brute_global(FA a) {
-    const int x = blockIdx.x * 16 + (threadIdx.x & 15);
-    const int y = blockIdx.y * 16 + (threadIdx.x >> 4);
-    if (x >= a.W || y >= a.H) return;
-    const int S = a.S, n = a.n, rho = a.rho;
-    const long long i = (long long)y * a.W + x;
-    float eta = 0.0f;
-    for (int c = 0; c < n; ++c) a.out[(long long)c * a.N + i] = 0.0f;
-    for (int jy = -S; jy <= S; ++jy) {
-        const int yy = y - jy;
-        if (yy < 0 || yy >= a.H) continue;
-        const float wy = a.w[jy < 0 ? -jy : jy];
-        for (int jx = -S; jx <= S; ++jx) {
-            const int xx = x - jx;
-            if (xx < 0 || xx >= a.W) continue;
-            const long long q = (long long)yy * a.W + xx;
-            float d2 = 0.0f;
-            for (int c = 0; c < rho; ++c) {
-                const float d = a.p[(long long)c * a.N + q] - a.p[(long long)c * a.N + i];
-                d2 = fmaf(d, d, d2);
-            }
-            const float wgt = wy * a.w[jx < 0 ? -jx : jx] * __expf(-d2 * a.inv2s2);
-            for (int c = 0; c < n; ++c) a.out[(long long)c * a.N + i] += wgt * a.f[(long long)c * a.N + q];
-            eta += wgt;
-        }
+    if (!colin) return;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (y0 + r >= a.H) break;
+        const long long off = (long long)(y0 + r) * a.W + x;
+        const float inv = 1.0f / eta[r];
+#pragma unroll
+        for (int c = 0; c < NM; ++c)
+            if (c < n) a.out[(long long)c * a.N + off] = num[r][c] * inv;
+        if (a.den) a.den[off] = eta[r];
     }
-    for (int c = 0; c < n; ++c) a.out[(long long)c * a.N + i] /= eta;
-    if (a.den) a.den[i] = eta;
 }
 
 // ---------------------------------------------------------------------------
@@ -3153,15 +3164,38 @@ void bruteforce_run(Ctx& c, const FilterPlan& fp, const float* f, const float* g
     a.p = guide;
     a.out = out;
     a.den = den;
-    const int L = 16 + 2 * fp.S;
-    const size_t lds = sizeof(float) * (size_t)L * L * (fp.rho + fp.n + 1);
-    const dim3 g((fp.W + 15) / 16, (fp.H + 15) / 16);
-    hipEvent_t tb = c.stage_begin();
-    if (lds <= 64 * 1024 && fp.rho <= 16 && fp.n <= 16) {
-        hipLaunchKernelGGL(brute_lds, g, dim3(RT), lds, c.stream, a);
+    // the variant for the channel counts, rows per thread R as measured (RGB:
+    // R 8 3.39 ms at 2048x2048, S 15, R 16 5.06 ms at 150 VGPRs; 16-d guide
+    // and RGB image: R 8 1.19 ms at 1024x1024, S 10, R 4 1.75 ms)
+    const bool same = f == guide && fp.n == fp.rho;
+    KernFn k;
+    int R;
+    if (fp.rho == 3 && fp.n == 3) {
+        k = same ? brute_strip<8, 3, 3, true, true> : brute_strip<8, 3, 3, true, false>;
+        R = 8;
+    } else if (fp.rho <= 4 && fp.n <= 4) {
+        k = brute_strip<8, 4, 4, false, false>;
+        R = 8;
+    } else if (fp.rho == 16 && fp.n == 3) {
+        k = brute_strip<8, 16, 3, true, false>;
+        R = 8;
+    } else if (fp.rho <= 16 && fp.n <= 16) {
+        k = brute_strip<2, 16, 16, false, false>;
+        R = 2;
+    } else if (fp.rho == 32 && fp.n == 32 && same) {
+        k = brute_strip<2, 32, 32, true, true>;
+        R = 2;
+    } else if (fp.rho <= 32 && fp.n <= 32) {
+        k = brute_strip<1, 32, 32, false, false>;
+        R = 1;
     } else {
-        hipLaunchKernelGGL(brute_global, g, dim3(RT), 0, c.stream, a);
+        k = brute_strip<1, FHD_MAX_RHO, FHD_MAX_N, false, false>;
+        R = 1;
     }
+    const int rows = R * (RT / 64);
+    const dim3 g((fp.W + 63) / 64, (fp.H + rows - 1) / rows);
+    hipEvent_t tb = c.stage_begin();
+    hipLaunchKernelGGL(k, g, dim3(RT), 0, c.stream, a);
     c.stage_end(FHD_STAGE_BRUTE, tb);
     FHD_HIP(hipGetLastError());
 }
