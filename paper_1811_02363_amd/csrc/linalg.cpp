@@ -40,11 +40,20 @@ void kernel_matrix(const float* centers, int K, int rho, double sigma_r, double*
 // false when the off-diagonal band has not vanished after 64 n QR steps (a
 // matrix with non-finite entries never converges); the caller then rejects
 // the result.
+// sqrt(a^2 + b^2) without the cost of std::hypot; the library's matrices
+// (kernel matrices, covariances) stay far from overflow, hypot covers the rest
+static inline double norm2(double a, double b) {
+    const double m = std::max(std::fabs(a), std::fabs(b));
+    return m < 1e150 && (m == 0.0 || m > 1e-150) ? std::sqrt(a * a + b * b) : std::hypot(a, b);
+}
+
 bool sym_eigen(std::vector<double>& t, int n, std::vector<double>& lam, std::vector<double>& v) {
     auto T = [&](int i, int j) -> double& { return t[(size_t)i * n + j]; };
-    v.assign((size_t)n * n, 0.0);
-    for (int i = 0; i < n; ++i) v[(size_t)i * n + i] = 1.0;
-    auto Q = [&](int i, int j) -> double& { return v[(size_t)i * n + j]; };
+    // the orthogonal factor is accumulated transposed (row c = column c of
+    // the factor) so that every update runs along contiguous memory
+    std::vector<double> qt((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) qt[(size_t)i * n + i] = 1.0;
+    auto Q = [&](int i, int j) -> double& { return qt[(size_t)j * n + i]; };
     // --- Householder: T <- H T H on the trailing block, Q <- Q H
     std::vector<double> x(n), p(n), q(n);
     for (int k = 0; k + 2 < n; ++k) {
@@ -75,11 +84,19 @@ bool sym_eigen(std::vector<double>& t, int n, std::vector<double>& lam, std::vec
             for (int j = 0; j < m; ++j) T(k + 1 + i, k + 1 + j) -= x[i] * q[j] + q[i] * x[j];
         T(k + 1, k) = T(k, k + 1) = alpha;
         for (int i = 1; i < m; ++i) T(k + 1 + i, k) = T(k, k + 1 + i) = 0.0;
-        for (int r = 0; r < n; ++r) {
-            double s = 0.0;
-            for (int j = 0; j < m; ++j) s += Q(r, k + 1 + j) * x[j];
-            s *= beta;
-            for (int j = 0; j < m; ++j) Q(r, k + 1 + j) -= s * x[j];
+        // Q <- Q H: columns k+1.. of Q (rows of qt) minus beta (Q x) x^T
+        std::vector<double>& w = p;  // reused: w = beta Q x, over the n rows of Q
+        std::fill(w.begin(), w.end(), 0.0);
+        if ((int)w.size() < n) w.resize(n);
+        for (int j = 0; j < m; ++j) {
+            const double* qc = &qt[(size_t)(k + 1 + j) * n];
+            const double xj = x[j];
+            for (int r = 0; r < n; ++r) w[r] += qc[r] * xj;
+        }
+        for (int j = 0; j < m; ++j) {
+            double* qc = &qt[(size_t)(k + 1 + j) * n];
+            const double bx = beta * x[j];
+            for (int r = 0; r < n; ++r) qc[r] -= w[r] * bx;
         }
     }
     // --- implicit symmetric QR with Wilkinson shifts
@@ -97,10 +114,12 @@ bool sym_eigen(std::vector<double>& t, int n, std::vector<double>& lam, std::vec
             T(i, k) = c * a - s * b;
             T(i, k + 1) = s * a + c * b;
         }
+        double* qa = &qt[(size_t)k * n];
+        double* qb = &qt[(size_t)(k + 1) * n];
         for (int r = 0; r < n; ++r) {
-            const double a = Q(r, k), b = Q(r, k + 1);
-            Q(r, k) = c * a - s * b;
-            Q(r, k + 1) = s * a + c * b;
+            const double a = qa[r], b = qb[r];
+            qa[r] = c * a - s * b;
+            qb[r] = s * a + c * b;
         }
     };
     int hi = n - 1, guard = 0;
@@ -116,11 +135,11 @@ bool sym_eigen(std::vector<double>& t, int n, std::vector<double>& lam, std::vec
         ++guard;
         const double dd = 0.5 * (T(hi - 1, hi - 1) - T(hi, hi));
         const double ee = T(hi, hi - 1);
-        const double den = dd + (dd >= 0.0 ? 1.0 : -1.0) * std::hypot(dd, ee);
+        const double den = dd + (dd >= 0.0 ? 1.0 : -1.0) * norm2(dd, ee);
         const double mu = T(hi, hi) - ee * ee / den;
         double xx = T(lo, lo) - mu, zz = T(lo + 1, lo);
         for (int k = lo; k < hi; ++k) {
-            const double r = std::hypot(xx, zz);
+            const double r = norm2(xx, zz);
             const double c = r == 0.0 ? 1.0 : xx / r, s = r == 0.0 ? 0.0 : -zz / r;
             rot(k, lo, hi, c, s);
             if (k + 1 < hi) {
@@ -131,6 +150,9 @@ bool sym_eigen(std::vector<double>& t, int n, std::vector<double>& lam, std::vec
     }
     lam.resize(n);
     for (int i = 0; i < n; ++i) lam[i] = T(i, i);
+    v.resize((size_t)n * n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) v[(size_t)i * n + j] = qt[(size_t)j * n + i];
     if (hi > 0) return false;
     for (int i = 0; i < n; ++i)
         if (!std::isfinite(lam[i])) return false;
