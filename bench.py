@@ -454,16 +454,20 @@ def leg_batch(torch, np, fhd, oracle, synth):
 
 
 def leg_window(torch, fhd, x, sr, K):
-    """The 2048x2048 RGB workload with the truncated-Gaussian FIR window and
-    with the recursive Gaussian (the paper's O(1) convolution), at sigma_s 5
-    and 20: Mpix/s and PSNR against the GPU brute force with the truncated
-    window of radius 3 sigma_s."""
+    """The 2048x2048 RGB workload over sigma_s 2 .. 20 (the paper's sweep of
+    the spatial scale): the fast filter with the truncated-Gaussian FIR
+    window (S = 3 sigma_s) and with the recursive Gaussian (the paper's O(1)
+    convolution), each with its Mpix/s and PSNR against the GPU brute force
+    of the truncated window, and that brute force's own Mpix/s: where the
+    clustered filter overtakes the direct sum on this GPU."""
     N = x.shape[1] * x.shape[2]
-    leg = {"workload": "bf_rgb_2048, sigma_r 0.12, K 32: window forms at sigma_s 5 and 20"}
-    for ss in (5.0, 20.0):
+    leg = {"workload": "bf_rgb_2048, sigma_r 0.12, K 32: window forms and the brute force over sigma_s"}
+    for ss in (2.0, 3.0, 5.0, 8.0, 12.0, 20.0):
         S = int(round(3 * ss))
-        brute = fhd.bruteforce(x, sigma_s=ss, sigma_r=sr, radius=S)
-        ent = {}
+        bf = lambda: fhd.bruteforce(x, sigma_s=ss, sigma_r=sr, radius=S)
+        brute = bf()
+        ms_b = timed(torch, bf, 3)
+        ent = {"brute_force": {"mpix_s": round(N / ms_b / 1e3, 2), "ms": round(ms_b, 3)}}
         for name, kw in (("fir", dict(spatial="gaussian", radius=S)), ("recursive", dict(spatial="young"))):
             run = lambda: fhd.filter(x, sigma_s=ss, sigma_r=sr, K=K, **kw)
             o = run()

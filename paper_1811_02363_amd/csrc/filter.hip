@@ -2244,6 +2244,27 @@ size_t row_lds_bytes(const FilterPlan& fp, int tx) {
     return fl * sizeof(float);
 }
 
+// The row pass's run length and LDS bytes.  With inline weights every halo
+// pixel costs its weights and coefficients, so runs stay long (row_tx); with
+// weight planes the halo costs only loads (a few % of the plane writes), so
+// runs are shortened until three blocks share a CU's LDS (a 40 KB cap for
+// four blocks measured no faster: 44.0 against 44.7 Mpix/s at 512x512x32).
+int row_run(const FilterPlan& fp, int R, size_t& lds) {
+    int tx = row_tx(fp.K, fp.S, R, fp.W);
+    lds = row_lds_bytes(fp, tx);
+    const size_t cap = fp.materialize ? 52 * 1024 : 150 * 1024;
+    while (lds > cap && tx > 4 * R) {
+        tx = std::max(4 * R, tx / 2 / R * R);
+        lds = row_lds_bytes(fp, tx);
+    }
+    while (lds > 150 * 1024 && tx > 4 * R) {
+        tx = std::max(4 * R, tx / 2 / R * R);
+        lds = row_lds_bytes(fp, tx);
+    }
+    FHD_REQUIRE(lds <= 160 * 1024, FHD_EUNSUPPORTED, "row pass does not fit in LDS");
+    return tx;
+}
+
 // ---------------------------------------------------------------------------
 // 3-D domain (D slices of H x W, flattened to D H rows of the planes): the
 // (n+1)K convolutions over the window [-S,S]^3 as three 1-D passes, zero
@@ -2646,13 +2667,8 @@ void filter_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, cons
     // window with every tap 1); the generic kernels cover the rest
     const bool unrolled = fp.S >= 1 && fp.S <= MAXS_T;
     const int rR = unrolled ? R_ROW : 16;
-    int tx = row_tx(fp.K, fp.S, rR, fp.W);
-    size_t lds = row_lds_bytes(fp, tx);
-    while (lds > 150 * 1024 && tx > 4 * rR) {
-        tx = std::max(4 * rR, tx / 2 / rR * rR);
-        lds = row_lds_bytes(fp, tx);
-    }
-    FHD_REQUIRE(lds <= 160 * 1024, FHD_EUNSUPPORTED, "row pass does not fit in LDS");
+    size_t lds = 0;
+    const int tx = row_run(fp, rR, lds);
     a.tx = tx;
     FHD_REQUIRE(fp.H + 2 * fp.S <= 65535, FHD_EUNSUPPORTED, "image height plus 2 radius exceeds 65535");
     const dim3 rg((fp.W + tx - 1) / tx, fp.H + 2 * fp.S);
@@ -2737,13 +2753,8 @@ void filter_passes_batch(Ctx& c, Arena& ws, int B, const FilterPlan* plans, cons
         a.Csave = sv != nullptr ? sv[b].C : nullptr;
         a.out = out[b];
         a.den = den ? den[b] : nullptr;
-        int tx = row_tx(fp.K, fp.S, R_ROW, fp.W);
-        size_t l = row_lds_bytes(fp, tx);
-        while (l > 150 * 1024 && tx > 4 * R_ROW) {
-            tx = std::max(4 * R_ROW, tx / 2 / R_ROW * R_ROW);
-            l = row_lds_bytes(fp, tx);
-        }
-        FHD_REQUIRE(l <= 160 * 1024, FHD_EUNSUPPORTED, "row pass does not fit in LDS");
+        size_t l = 0;
+        const int tx = row_run(fp, R_ROW, l);
         lds = std::max(lds, l);
         a.tx = tx;
         pre_row[b + 1] = pre_row[b] + ((fp.W + tx - 1) / tx) * (fp.H + 2 * fp.S);
@@ -2910,13 +2921,8 @@ void adjoint_passes(Ctx& c, Arena& ws, const FilterPlan& fp, const float* f, con
     a.Cpl = inl ? nullptr : Cpl;   // row passes: null = factors formed inline
     FilterPlan rp = fp;
     rp.materialize = !inl;
-    int tx = row_tx(fp.K, fp.S, R_ROW, fp.W);
-    size_t lds = row_lds_bytes(rp, tx);
-    while (lds > 150 * 1024 && tx > 4 * R_ROW) {
-        tx = std::max(4 * R_ROW, tx / 2 / R_ROW * R_ROW);
-        lds = row_lds_bytes(rp, tx);
-    }
-    FHD_REQUIRE(lds <= 160 * 1024, FHD_EUNSUPPORTED, "row pass does not fit in LDS");
+    size_t lds = 0;
+    const int tx = row_run(rp, R_ROW, lds);
     a.tx = tx;
     FHD_REQUIRE(fp.H + 2 * fp.S <= 65535, FHD_EUNSUPPORTED, "image height plus 2 radius exceeds 65535");
     const dim3 rg((fp.W + tx - 1) / tx, fp.H + 2 * fp.S);
@@ -3069,13 +3075,8 @@ void adjoint_passes_batch(Ctx& c, Arena& ws, int B, const FilterPlan* plans, con
         a.Cpl = nullptr;
         FilterPlan rp = fp;
         rp.materialize = false;
-        int tx = row_tx(fp.K, fp.S, R_ROW, fp.W);
-        size_t l = row_lds_bytes(rp, tx);
-        while (l > 150 * 1024 && tx > 4 * R_ROW) {
-            tx = std::max(4 * R_ROW, tx / 2 / R_ROW * R_ROW);
-            l = row_lds_bytes(rp, tx);
-        }
-        FHD_REQUIRE(l <= 160 * 1024, FHD_EUNSUPPORTED, "row pass does not fit in LDS");
+        size_t l = 0;
+        const int tx = row_run(rp, R_ROW, l);
         rlds = std::max(rlds, l);
         wlds = std::max(wlds, weights_fp32_lds(fp.K, fp.rho, npx));
         a.tx = tx;
