@@ -222,7 +222,7 @@ FilterPlan make_plan(const fhd_params& p, int n, int rho, int H, int W, int K) {
     fp.sigma_s = p.sigma_s;
     fp.sigma_r = p.sigma_r;
     fp.N = (long long)H * W;
-    fp.Wp = (int)align_up((size_t)W, 4);
+    fp.Wp = (int)align_up((size_t)W, 32);  // plane rows start on 128-byte lines
     fp.materialize = rho > 8 || K > 32 || p.contract != FHD_CONTRACT_FP32 || p.spatial == FHD_SPATIAL_YOUNG ||
                      p.coef == FHD_COEF_EXACT;
     return fp;
