@@ -122,7 +122,10 @@ template <int RH>
 __device__ __forceinline__ void coef_run(const FA& a, int g0, bool in, const float (&pr)[RH], int hw, int csp,
                                          float* cs, const float* smu, const float* sP) {
     const int lane = threadIdx.x & 63, pl = lane & 31, kh = lane >> 5;
-    const f32x16 acc = inline_coef_mfma<RH>(a, pr, in, smu, sP);
+    // guides of at most 4 dimensions sum 4 entries per distance (the first 4
+    // of pr; the rest are zero)
+    const f32x16 acc = a.rho <= 4 ? inline_coef_mfma<4>(a, reinterpret_cast<const float(&)[4]>(pr), in, smu, sP)
+                                  : inline_coef_mfma<RH>(a, pr, in, smu, sP);
     if (pl < a.K) {
         if (g0 + 32 <= hw) {  // uniform: a full run of 32 pixels
 #pragma unroll
@@ -140,8 +143,8 @@ __device__ __forceinline__ void coef_run(const FA& a, int g0, bool in, const flo
 // b_m of one halo pixel for every center, into cs (the hard variant's
 // factor, and the adjoint's b_l Y).
 template <int RH>
-__device__ __forceinline__ void bfactor_pixel(const FA& a, int h, bool in, const float (&pr)[RH], int csp, float* cs,
-                                              const float* smu) {
+__device__ __forceinline__ void bfactor_loop(const FA& a, int h, bool in, const float (&pr)[RH], int csp, float* cs,
+                                             const float* smu) {
     for (int m = 0; m < a.K; ++m) {
         float d2 = 0.0f;
 #pragma unroll
@@ -151,6 +154,15 @@ __device__ __forceinline__ void bfactor_pixel(const FA& a, int h, bool in, const
         }
         cs[m * csp + pidx(h)] = in ? __expf(-d2 * a.inv2s2) : 0.0f;
     }
+}
+
+template <int RH>
+__device__ __forceinline__ void bfactor_pixel(const FA& a, int h, bool in, const float (&pr)[RH], int csp, float* cs,
+                                              const float* smu) {
+    if (a.rho <= 4)
+        bfactor_loop<4>(a, h, in, reinterpret_cast<const float(&)[4]>(pr), csp, cs, smu);
+    else
+        bfactor_loop<RH>(a, h, in, pr, csp, cs, smu);
 }
 
 template <int RH>
@@ -297,9 +309,7 @@ __device__ __forceinline__ void row_factors_rh(const FA& a, int y, int x0, int h
     __syncthreads();
 }
 
-// One width for every inline guide: a second copy summing 4 dimensions
-// (RGB) measured slower at radius 9 and 15 than the 8-wide sum alone.
-__device__ void row_factors(const FA& a, int y, int x0, int hw, int csp, float* cs, float* fs, float* smu,
+__device__ __forceinline__ void row_factors(const FA& a, int y, int x0, int hw, int csp, float* cs, float* fs, float* smu,
                             float* sP) {
     row_factors_rh<RHO_INLINE>(a, y, x0, hw, csp, cs, fs, smu, sP);
 }
@@ -1414,7 +1424,8 @@ __device__ __forceinline__ float ld_off(const float* base, unsigned byte_off) {
     return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + byte_off);
 }
 
-__device__ __forceinline__ void adj_final_mfma_body(const FA& a, const float* __restrict__ Md, float sig3inv,
+template <int RH>
+__device__ __forceinline__ void adj_final_mfma_rh(const FA& a, const float* __restrict__ Md, float sig3inv,
                                                     float* __restrict__ gradp, double* part_slot,
                                                     double* parts_slot, int blk) {
     __shared__ float smu[KMAX_INLINE * RHO_INLINE];
@@ -1462,9 +1473,9 @@ __device__ __forceinline__ void adj_final_mfma_body(const FA& a, const float* __
             gv[s2] = (valid && m < K) ? v : 0.0f;
             og += 2u * np4;
         }
-        float pr[RHO_INLINE];
+        float pr[RH];
 #pragma unroll
-        for (int r = 0; r < RHO_INLINE; ++r) {
+        for (int r = 0; r < RH; ++r) {
             const float v = ld_off(a.p, pi4 + (unsigned)min(r, rho - 1) * n4);
             pr[r] = (valid && r < rho) ? v : 0.0f;
         }
@@ -1491,18 +1502,18 @@ __device__ __forceinline__ void adj_final_mfma_body(const FA& a, const float* __
                 bs[r] = (valid && l < K) ? vs : 0.0f;
             }
         }
-        float wsum = 0.0f, sw[RHO_INLINE];
+        float wsum = 0.0f, sw[RH];
 #pragma unroll
-        for (int r = 0; r < RHO_INLINE; ++r) sw[r] = 0.0f;
+        for (int r = 0; r < RH; ++r) sw[r] = 0.0f;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int l = 8 * (r >> 2) + 4 * kh + (r & 3);
-            float mu8[RHO_INLINE];
+            float mu8[RH];
 #pragma unroll
-            for (int q = 0; q < RHO_INLINE; ++q) mu8[q] = smq[l * RHO_INLINE + q];
+            for (int q = 0; q < RH; ++q) mu8[q] = smq[l * RHO_INLINE + q];
             float d2 = 0.0f;
 #pragma unroll
-            for (int q = 0; q < RHO_INLINE; ++q) {  // padded entries: (0 - 0)^2
+            for (int q = 0; q < RH; ++q) {  // padded entries: (0 - 0)^2
                 const float d = pr[q] - mu8[q];
                 d2 = fmaf(d, d, d2);
             }
@@ -1513,15 +1524,15 @@ __device__ __forceinline__ void adj_final_mfma_body(const FA& a, const float* __
             sigs += (double)bl * bs[r];
             wsum += w;
 #pragma unroll
-            for (int q = 0; q < RHO_INLINE; ++q) sw[q] = fmaf(w, mu8[q], sw[q]);
+            for (int q = 0; q < RH; ++q) sw[q] = fmaf(w, mu8[q], sw[q]);
         }
         // the pixel's other 16 clusters sit in the lane 32 apart
         wsum += __shfl_xor(wsum, 32, 64);
 #pragma unroll
-        for (int q = 0; q < RHO_INLINE; ++q) sw[q] += __shfl_xor(sw[q], 32, 64);
+        for (int q = 0; q < RH; ++q) sw[q] += __shfl_xor(sw[q], 32, 64);
         if (valid && kh == 0 && gradp != nullptr) {
 #pragma unroll
-            for (int q = 0; q < RHO_INLINE; ++q)
+            for (int q = 0; q < RH; ++q)
                 if (q < rho) gradp[(long long)q * a.N + ii] = m2s * (pr[q] * wsum - sw[q]);
         }
     }
@@ -1544,6 +1555,17 @@ __device__ __forceinline__ void adj_final_mfma_body(const FA& a, const float* __
         *part_slot = t;
         if (parts_slot != nullptr) *parts_slot = ts;
     }
+}
+
+// RH: guide dimensions summed per distance (4 for guides of at most 4
+// dimensions: the entries past rho are zero on both sides).
+__device__ __forceinline__ void adj_final_mfma_body(const FA& a, const float* __restrict__ Md, float sig3inv,
+                                                    float* __restrict__ gradp, double* part_slot,
+                                                    double* parts_slot, int blk) {
+    if (a.rho <= 4)
+        adj_final_mfma_rh<4>(a, Md, sig3inv, gradp, part_slot, parts_slot, blk);
+    else
+        adj_final_mfma_rh<RHO_INLINE>(a, Md, sig3inv, gradp, part_slot, parts_slot, blk);
 }
 
 __global__ __launch_bounds__(RT) void adj_final_mfma(FA a, const float* __restrict__ Md, float sig3inv,

@@ -11,7 +11,9 @@ through the C ABI, against the FP64 oracle fed the same FP32 centers.
   1..32, with inline weights (3-d guide), materialised weight planes (12-d
   guide) and the hard variant of eq. (17), on ragged sizes, some smaller than
   the window.
-* Radius 0 (the window is the pixel itself: g_hat = f wherever r_hat != 0).
+* Radius 0 (the window is the pixel itself: g_hat = f wherever r_hat != 0),
+  and radii above 96, where a row-pass block's halo run is longer than its
+  threads.
 * The normaliser diagnostics of fhd_info (den_min, den_nonpos, den_small,
   nonfinite) against the returned r_hat and output, and strict mode's
   FHD_ENUMERIC on a nonlocal-means crop whose r_hat goes through zero, with
@@ -84,6 +86,12 @@ GENERIC = [
     ("gauss_S0_inline_41x57", 41, 57, 3, 6, "gaussian", 0, 1.0, 0.15, "lsq"),
     ("box_S0_planes_33x45", 33, 45, 12, 8, "box", 0, None, 0.3, "lsq"),
     ("gauss_S0_hard_39x50", 39, 50, 3, 6, "gaussian", 0, 1.0, 0.15, "hard"),
+    # radii above 96: the row pass's halo run (run + 2S) exceeds the block's
+    # 256 threads, so its first phase takes the remaining halo pixels and
+    # coefficient runs in loops
+    ("gauss_S100_inline_48x300", 48, 300, 3, 8, "gaussian", 100, 33.3, 0.2, "lsq"),
+    ("gauss_S128_hard_40x270", 40, 270, 3, 7, "gaussian", 128, 42.7, 0.15, "hard"),
+    ("box_S110_planes_36x270", 36, 270, 12, 9, "box", 110, None, 0.3, "lsq"),
 ]
 
 
