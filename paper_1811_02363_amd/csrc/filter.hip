@@ -957,29 +957,16 @@ __device__ __forceinline__ void col_body(const FA& a, int blk) {
         for (int l = 0; l < K; ++l) {
             float hl[R];
             recomb_weights<R, MODE>(a, l, x, y0, ly0, lx, TY, sp, lab, hl);
-            // one copy of the plane loop (a uniform switch picks the
-            // accumulator), so only one window is ever live
-#pragma unroll 1
-            for (int c = 0; c < nc; ++c) {
-                float s[R];
-                filter_plane(s);
-                switch (c) {
-                    case 0:
+            // the channel loop unrolled, each channel's accumulator fixed;
+            // the barriers inside filter_plane keep the next window's LDS
+            // reads after this one's FIR, so one window is live at a time
 #pragma unroll
-                        for (int t = 0; t < R; ++t) acc[0][t] = fmaf(hl[t], s[t], acc[0][t]);
-                        break;
-                    case 1:
+            for (int c = 0; c < CG; ++c) {
+                if (c < nc) {  // uniform
+                    float s[R];
+                    filter_plane(s);
 #pragma unroll
-                        for (int t = 0; t < R; ++t) acc[1][t] = fmaf(hl[t], s[t], acc[1][t]);
-                        break;
-                    case 2:
-#pragma unroll
-                        for (int t = 0; t < R; ++t) acc[2][t] = fmaf(hl[t], s[t], acc[2][t]);
-                        break;
-                    default:
-#pragma unroll
-                        for (int t = 0; t < R; ++t) acc[3][t] = fmaf(hl[t], s[t], acc[3][t]);
-                        break;
+                    for (int t = 0; t < R; ++t) acc[c][t] = fmaf(hl[t], s[t], acc[c][t]);
                 }
             }
         }
@@ -1168,7 +1155,8 @@ __device__ __forceinline__ void col_adj_body(const FA& a, int blk) {
                             : 0.0f;
             }
             // one copy of the plane loop (a uniform switch picks the
-            // channel's registers), one LDS copy of a plane
+            // channel's registers: unrolled, the GAMMA pass took 264 VGPRs),
+            // one LDS copy of a plane
             auto upd = [&](const float (&v)[R], float (&fb)[R], int gi, const float (&sv)[R],
                            const float (&sd)[R]) {
 #pragma unroll
