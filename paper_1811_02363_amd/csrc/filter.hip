@@ -957,16 +957,47 @@ __device__ __forceinline__ void col_body(const FA& a, int blk) {
         for (int l = 0; l < K; ++l) {
             float hl[R];
             recomb_weights<R, MODE>(a, l, x, y0, ly0, lx, TY, sp, lab, hl);
-            // the channel loop unrolled, each channel's accumulator fixed;
-            // the barriers inside filter_plane keep the next window's LDS
-            // reads after this one's FIR, so one window is live at a time
+            if constexpr (MODE != WM_PLANES) {
+                // the channel loop unrolled, each channel's accumulator
+                // fixed; the barriers inside filter_plane keep the next
+                // window's LDS reads after this one's FIR, so one window is
+                // live at a time
 #pragma unroll
-            for (int c = 0; c < CG; ++c) {
-                if (c < nc) {  // uniform
+                for (int c = 0; c < CG; ++c) {
+                    if (c < nc) {  // uniform
+                        float s[R];
+                        filter_plane(s);
+#pragma unroll
+                        for (int t = 0; t < R; ++t) acc[c][t] = fmaf(hl[t], s[t], acc[c][t]);
+                    }
+                }
+            } else {
+                // with weight planes the unrolled loop takes 145-161 VGPRs
+                // (three waves per SIMD instead of four) and measured slower
+                // on the 32-band image: one copy of the plane loop, a
+                // uniform switch picking the accumulator
+#pragma unroll 1
+                for (int c = 0; c < nc; ++c) {
                     float s[R];
                     filter_plane(s);
+                    switch (c) {
+                        case 0:
 #pragma unroll
-                    for (int t = 0; t < R; ++t) acc[c][t] = fmaf(hl[t], s[t], acc[c][t]);
+                            for (int t = 0; t < R; ++t) acc[0][t] = fmaf(hl[t], s[t], acc[0][t]);
+                            break;
+                        case 1:
+#pragma unroll
+                            for (int t = 0; t < R; ++t) acc[1][t] = fmaf(hl[t], s[t], acc[1][t]);
+                            break;
+                        case 2:
+#pragma unroll
+                            for (int t = 0; t < R; ++t) acc[2][t] = fmaf(hl[t], s[t], acc[2][t]);
+                            break;
+                        default:
+#pragma unroll
+                            for (int t = 0; t < R; ++t) acc[3][t] = fmaf(hl[t], s[t], acc[3][t]);
+                            break;
+                    }
                 }
             }
         }
