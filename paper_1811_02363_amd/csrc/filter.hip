@@ -2371,18 +2371,18 @@ size_t plane_floats(const FilterPlan& fp) {
 // starts on a 128-byte line.  A run boundary inside a line leaves that line
 // written in two parts by two blocks; the row pass's store pattern alone
 // measured 0.73 ms for 2.15 GB with 232-pixel runs against 0.48 ms with
-// 256-pixel ones.  From radius 8 (K <= 32) the runs are 256 pixels and the
-// halo run is longer than the block (its first phase takes the rest in
+// 256-pixel ones.  At radius 8..16 (K <= 32) the runs are 256 pixels and
+// the halo run is longer than the block (its first phase takes the rest in
 // loops): fewer blocks per row measured 7 % faster at radius 9 and 15.
-// Below radius 8 the runs are the longest whose halo run fits the 256
-// threads (224 pixels); 256-pixel runs were 5 % slower at radius 1.  A row
-// takes the fewest runs of that length, of equal length in units of 32
-// pixels.
+// Elsewhere the runs are the longest whose halo run fits the 256 threads:
+// 256-pixel runs were 5 % slower at radius 1 and 13 % slower at radius 36
+// and 60 (the generic kernels).  A row takes the fewest runs of that
+// length, of equal length in units of 32 pixels.
 constexpr int RUN_ALIGN = 32;
 
 int row_tx(int K, int S, int R, int W) {
     FHD_REQUIRE(RUN_ALIGN % R == 0, FHD_EINVAL, "internal: row task length must divide the run alignment");
-    int tx = (K <= 32 && S >= 8) ? 256 : (RT - 2 * S) / RUN_ALIGN * RUN_ALIGN;
+    int tx = (K <= 32 && S >= 8 && S <= 16) ? 256 : (RT - 2 * S) / RUN_ALIGN * RUN_ALIGN;
     if (tx < 64) tx = K <= 32 ? 256 : 128;
     const int runs = (W + tx - 1) / tx;
     return std::min(tx, (W + runs * RUN_ALIGN - 1) / (runs * RUN_ALIGN) * RUN_ALIGN);
